@@ -1,0 +1,156 @@
+"""The H-matrix split Z = Z_N + Z_F of eq. (13).
+
+Everything is indexed in *tree order* (position p holds RWG unknown perm[p]):
+
+* groups (leaves) g = 0..M-1 own the contiguous ranges [lo_g, hi_g);
+* near blocks (t, s), t <= s, touching leaves, hold the dense Galerkin block
+  Z[perm[t], perm[s]]; the (s, t) block is its transpose (Z = Z^T);
+* far blocks (t, s), admissible cluster pairs with t before s in depth-first
+  order, hold ACA factors with Z[perm[t], perm[s]] ~= U V^T; the (s, t)
+  block is V U^T.
+"""
+
+import numpy as np
+
+from .aca import aca
+from .cluster import build_tree, block_partition
+from .efie import EFIEOperator
+from .rwg import build_rwg, edge_midpoints
+
+
+class HMatrix:
+    def __init__(self, N, perm, groups, near, far):
+        self.N = N
+        self.perm = np.asarray(perm, dtype=np.int64)
+        self.groups = np.asarray(groups, dtype=np.int64)        # (M, 2) lo, hi
+        self.near = near    # dict (t, s) -> block, t <= s
+        self.far = far      # list of (tlo, thi, slo, shi, U, V)
+
+    @property
+    def M(self):
+        return len(self.groups)
+
+    def group_slice(self, g):
+        lo, hi = self.groups[g]
+        return slice(int(lo), int(hi))
+
+    # ------------------------------------------------------------- products
+    def near_matvec(self, x):
+        """Z_N x in tree order; x is (N,) or (N, R)."""
+        y = np.zeros_like(x, dtype=np.complex128)
+        for (t, s), B in self.near.items():
+            st, ss = self.group_slice(t), self.group_slice(s)
+            y[st] += B @ x[ss]
+            if t != s:
+                y[ss] += B.T @ x[st]
+        return y
+
+    def far_matvec(self, x):
+        """Z_F x in tree order (both directions of every stored block)."""
+        y = np.zeros_like(x, dtype=np.complex128)
+        for tlo, thi, slo, shi, U, V in self.far:
+            y[tlo:thi] += U @ (V.T @ x[slo:shi])
+            y[slo:shi] += V @ (U.T @ x[tlo:thi])
+        return y
+
+    def matvec(self, x):
+        return self.near_matvec(x) + self.far_matvec(x)
+
+    def dense_near(self):
+        Z = np.zeros((self.N, self.N), dtype=np.complex128)
+        for (t, s), B in self.near.items():
+            st, ss = self.group_slice(t), self.group_slice(s)
+            Z[st, ss] = B
+            Z[ss, st] = B.T
+        return Z
+
+    def dense_far(self):
+        Z = np.zeros((self.N, self.N), dtype=np.complex128)
+        for tlo, thi, slo, shi, U, V in self.far:
+            B = U @ V.T
+            Z[tlo:thi, slo:shi] = B
+            Z[slo:shi, tlo:thi] = B.T
+        return Z
+
+    def to_tree(self, x_rwg):
+        return np.asarray(x_rwg)[self.perm]
+
+    def to_rwg(self, x_tree):
+        out = np.empty_like(x_tree)
+        out[self.perm] = x_tree
+        return out
+
+    def far_entries(self):
+        """sum over both triangles of r (m + n): the applied far entries."""
+        return sum(2 * U.shape[1] * (U.shape[0] + V.shape[0]) for _, _, _, _, U, V in self.far)
+
+
+_JOB = {}
+
+
+def _near_job(pairs):
+    op, perm = _JOB["op"], _JOB["perm"]
+    return [op.block(perm[tlo:thi], perm[slo:shi]) for tlo, thi, slo, shi in pairs]
+
+
+def _far_job(pairs):
+    op, perm, eps = _JOB["op"], _JOB["perm"], _JOB["eps"]
+    out = []
+    for tlo, thi, slo, shi in pairs:
+        rows, cols = perm[tlo:thi], perm[slo:shi]
+        out.append(aca(lambda i: op.entries(rows[i], cols),
+                       lambda j: op.entries(rows, cols[j]),
+                       lambda: op.block(rows, cols),
+                       len(rows), len(cols), eps))
+    return out
+
+
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _run(job, items, workers, chunk=64):
+    chunks = [items[i:i + chunk] for i in range(0, len(items), chunk)]
+    if workers <= 1:
+        res = [job(c) for c in chunks]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers, initializer=_one_blas_thread) as pool:
+            res = pool.map(job, chunks)
+    return [r for c in res for r in c]
+
+
+def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1):
+    """Mesh -> RWG -> octree -> near blocks (quadrature) + far blocks (ACA).
+
+    With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
+    near block (Z_F = 0), used to pin the series against a dense LU solve.
+    ``workers`` > 1 evaluates independent blocks in forked processes (the
+    arithmetic of each block is unchanged).
+    """
+    rwg = build_rwg(xyz, tri)
+    op = EFIEOperator(rwg, freq_hz)
+    tree = build_tree(edge_midpoints(rwg), leaf_max)
+    perm = tree["perm"]
+    leaves = tree["leaves"]
+    groups = np.array([(nd.lo, nd.hi) for nd in leaves], dtype=np.int64)
+    near_pairs, far_pairs = block_partition(tree)
+    if not eta_far:
+        near_pairs = [(a, b) for a in leaves for b in leaves if a.leaf_id <= b.leaf_id]
+        far_pairs = []
+    _JOB.update(op=op, perm=perm, eps=aca_tol)
+    try:
+        nb = _run(_near_job, [(t.lo, t.hi, s.lo, s.hi) for t, s in near_pairs], workers)
+        fb = _run(_far_job, [(t.lo, t.hi, s.lo, s.hi) for t, s in far_pairs], workers, chunk=16)
+    finally:
+        _JOB.clear()
+    near = {(t.leaf_id, s.leaf_id): B for (t, s), B in zip(near_pairs, nb)}
+    far = [(t.lo, t.hi, s.lo, s.hi, U, V) for (t, s), (U, V) in zip(far_pairs, fb)]
+    H = HMatrix(rwg["N"], perm, groups, near, far)
+    H.rwg, H.op, H.tree = rwg, op, tree
+    H.near_pairs, H.far_pairs = near_pairs, far_pairs
+    return H

@@ -1,0 +1,94 @@
+"""Pins for the oracle's cluster tree, admissibility split and ACA."""
+
+import numpy as np
+
+from oracle.aca import aca, recompress
+from oracle.cluster import build_tree, block_partition, touch, Node, DEPTH_MAX
+from oracle.rwg import build_rwg, edge_midpoints
+from workloads import icosphere
+from conftest import rel
+
+
+def test_tree_is_a_partition():
+    xyz, tri = icosphere(3)
+    rwg = build_rwg(xyz, tri)
+    for leaf_max in (16, 64, 200):
+        tree = build_tree(edge_midpoints(rwg), leaf_max)
+        perm = tree["perm"]
+        assert np.array_equal(np.sort(perm), np.arange(rwg["N"]))
+        lo = 0
+        for nd in tree["leaves"]:
+            assert nd.lo == lo and nd.hi - nd.lo <= leaf_max
+            assert np.all(np.diff(perm[nd.lo:nd.hi]) > 0)      # RWG order inside a leaf
+            lo = nd.hi
+        assert lo == rwg["N"]
+
+
+def test_near_far_cover_every_pair_once():
+    xyz, tri = icosphere(3)
+    rwg = build_rwg(xyz, tri)
+    tree = build_tree(edge_midpoints(rwg), 32)
+    near, far = block_partition(tree)
+    N = rwg["N"]
+    cover = np.zeros((N, N), dtype=np.int32)
+    for t, s in near:
+        cover[t.lo:t.hi, s.lo:s.hi] += 1
+        if t is not s:
+            cover[s.lo:s.hi, t.lo:t.hi] += 1
+        assert touch(t, s)
+    for t, s in far:
+        cover[t.lo:t.hi, s.lo:s.hi] += 1
+        cover[s.lo:s.hi, t.lo:t.hi] += 1
+        assert not touch(t, s)
+    assert np.all(cover == 1)
+
+
+def test_touch_integer_geometry():
+    def node(depth, ijk):
+        return Node(depth, ijk, np.zeros(0, dtype=np.int64))
+    a = node(3, (2, 2, 2))
+    assert touch(a, node(3, (3, 3, 3)))          # corner contact
+    assert not touch(a, node(3, (4, 2, 2)))      # one cell gap
+    assert touch(a, node(2, (1, 1, 1)))          # parent contains it
+    assert touch(a, node(4, (6, 4, 4)))          # finer cell on the face
+    assert not touch(a, node(4, (7, 4, 4)))
+    assert DEPTH_MAX == 21
+
+
+def test_aca_recovers_exact_low_rank():
+    rng = np.random.default_rng(3)
+    m, n, r = 60, 45, 4
+    A = (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))) @ \
+        (rng.standard_normal((r, n)) + 1j * rng.standard_normal((r, n)))
+    U, V = aca(lambda i: A[i], lambda j: A[:, j], lambda: A, m, n, 1e-10)
+    assert U.shape[1] == r
+    assert rel(U @ V.T, A) < 1e-12
+
+
+def test_aca_dense_fallback_and_recompress():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    U, V = aca(lambda i: A[i], lambda j: A[:, j], lambda: A, 8, 8, 1e-3)
+    assert rel(U @ V.T, A) < 1e-3
+    # recompression of an exact rank-2 pair padded with dependent columns
+    B = rng.standard_normal((20, 2)) + 0j
+    C = rng.standard_normal((15, 2)) + 0j
+    U2, V2 = recompress(np.hstack([B, B]), np.hstack([C, C]), 1e-12)
+    assert U2.shape[1] == 2 and rel(U2 @ V2.T, 2 * B @ C.T) < 1e-12
+
+
+def test_hmatrix_vs_dense(c0_hmatrix, c0_dense):
+    """||Z - H||_F <= 2 eps ||Z||_F and H x within 2 eps of Z x (eps = 1e-3)."""
+    H = c0_hmatrix
+    P = H.perm
+    Zt = c0_dense[np.ix_(P, P)]
+    assert rel(H.dense_near() + H.dense_far(), Zt) <= 2e-3
+    x = np.random.default_rng(0).standard_normal((H.N, 3)) + 0j
+    assert rel(H.matvec(x), Zt @ x) <= 2e-3
+    # near blocks are the exact Galerkin entries
+    for (t, s), B in list(H.near.items())[::17]:
+        assert np.array_equal(B, Zt[H.group_slice(t), H.group_slice(s)])
+    # per block the partial-pivoting stopping rule is a heuristic, so eq. (12)
+    # holds only approximately block by block (observed max ~2.1 eps)
+    errs = [rel(U @ V.T, Zt[tlo:thi, slo:shi]) for tlo, thi, slo, shi, U, V in H.far[::3]]
+    assert max(errs) <= 5e-3 and np.median(errs) <= 1e-3

@@ -1,0 +1,123 @@
+"""Named workloads: geometry, frequency, leaf size, ACA tolerance and the
+plane-wave sweep of each scattering problem.
+
+Angles follow the usual spherical convention: r_hat(theta, phi) =
+(sin t cos p, sin t sin p, cos t), theta_hat = (cos t cos p, cos t sin p, -sin t).
+A monostatic look from (theta, phi) illuminates the body with a plane wave
+travelling along k_hat = -r_hat(theta, phi), polarised along theta_hat (VV).
+"""
+
+import math
+
+import numpy as np
+
+from .meshes import icosphere, geodesic_sphere, ellipsoid_mesh
+
+C0_LIGHT = 299792458.0
+
+
+def r_hat(theta, phi):
+    return np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi),
+                     np.cos(theta)], axis=-1)
+
+
+def theta_hat(theta, phi):
+    return np.stack([np.cos(theta) * np.cos(phi), np.cos(theta) * np.sin(phi),
+                     -np.sin(theta)], axis=-1)
+
+
+def monostatic_angles(theta_deg, phi_deg):
+    """(khat, pol) arrays (R, 3) for monostatic looks at the given angles."""
+    t = np.deg2rad(np.asarray(theta_deg, dtype=np.float64))
+    p = np.deg2rad(np.asarray(phi_deg, dtype=np.float64))
+    t, p = np.broadcast_arrays(t, p)
+    return -r_hat(t, p), theta_hat(t, p)
+
+
+def plane_wave_dirs(kind, **kw):
+    if kind == "single_minus_z":
+        return np.array([[0.0, 0.0, -1.0]]), np.array([[1.0, 0.0, 0.0]])
+    if kind == "theta_sweep":
+        th = np.arange(kw.get("start", 0.0), kw.get("stop", 180.0) + 1e-9, kw.get("step", 1.0))
+        return monostatic_angles(th, np.zeros_like(th))
+    if kind == "phi_sweep":
+        ph = np.arange(kw.get("start", 0.0), kw.get("stop", 360.0) + 1e-9, kw.get("step", 0.5))
+        return monostatic_angles(np.full_like(ph, 90.0), ph)
+    if kind == "phi_list":
+        ph = np.asarray(kw["phi"], dtype=np.float64)
+        return monostatic_angles(np.full_like(ph, 90.0), ph)
+    raise ValueError(kind)
+
+
+def _thomsen_area(a, b, c, p=1.6075):
+    return 4.0 * math.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3.0) ** (1.0 / p)
+
+
+def batch_ellipsoids(count=32, freq_hz=600e6, seed=0, n_lo=2000, n_hi=40000):
+    """Seed-drawn axis-aligned ellipsoids for the batched workload: semi-axes
+    log-uniform in [0.5, 2] m (drawn x, y, z), aspect <= 4, meshed as geodesic
+    spheres of frequency nu sized for lambda/10 edges, mapped affinely."""
+    rng = np.random.default_rng(seed)
+    lam = C0_LIGHT / freq_hz
+    out = []
+    while len(out) < count:
+        ax = np.exp(rng.uniform(math.log(0.5), math.log(2.0), 3))
+        if ax.max() / ax.min() > 4.0:
+            continue
+        s = _thomsen_area(*ax)
+        n_target = 1.5 * s / (math.sqrt(3.0) / 4.0 * (lam / 10.0) ** 2)
+        nu = max(1, int(round(math.sqrt(n_target / 30.0))))
+        n = 30 * nu * nu
+        if not (n_lo <= n <= n_hi):
+            continue
+        out.append((tuple(float(x) for x in ax), nu))
+    return out
+
+
+WORKLOADS = {
+    "sphere_s3_200MHz": dict(
+        desc="PEC sphere r=1 m, icosphere subdiv 3 (1,280 tris, 1,920 RWG), EFIE 200 MHz, "
+             "leaf<=64, ACA 1e-3, 1 RHS x-pol along -z",
+        mesh=("icosphere", 3, 1.0), freq_hz=200e6, leaf_max=64, aca_tol=1e-3,
+        rhs=("single_minus_z", {}), precision=0),
+    "sphere_s5_790MHz": dict(
+        desc="PEC sphere r=1 m, icosphere subdiv 5 (20,480 tris, 30,720 RWG), EFIE 790 MHz, "
+             "leaf<=128, ACA 1e-3, 181 monostatic RHS theta=0..180 step 1, phi=0, theta-pol",
+        mesh=("icosphere", 5, 1.0), freq_hz=790e6, leaf_max=128, aca_tol=1e-3,
+        rhs=("theta_sweep", {"start": 0.0, "stop": 180.0, "step": 1.0}), precision=0),
+    "sphere_s5_790MHz_mixed": dict(
+        desc="as sphere_s5_790MHz in the precision form: BF16 far factors with per-block "
+             "FP32 scale, FP32 D^-1 and scaling blocks, FP64 setup, one FP32 residual pass",
+        mesh=("icosphere", 5, 1.0), freq_hz=790e6, leaf_max=128, aca_tol=1e-3,
+        rhs=("theta_sweep", {"start": 0.0, "stop": 180.0, "step": 1.0}), precision=1),
+    "ellipsoid_4x2x1_300MHz": dict(
+        desc="PEC ellipsoid 4x2x1 m, icosphere subdiv 7 mapped affinely (327,680 tris, "
+             "491,520 RWG), 300 MHz, leaf<=256, ACA 1e-3, 721 RHS theta=90, phi=0..360 step 0.5",
+        mesh=("ellipsoid", 7, (4.0, 2.0, 1.0)), freq_hz=300e6, leaf_max=256, aca_tol=1e-3,
+        rhs=("phi_sweep", {"start": 0.0, "stop": 360.0, "step": 0.5}), precision=1),
+}
+
+
+def workload_mesh(spec):
+    kind = spec[0]
+    if kind == "icosphere":
+        return icosphere(spec[1], spec[2])
+    if kind == "geodesic":
+        return geodesic_sphere(spec[1], spec[2])
+    if kind == "ellipsoid":
+        xyz, tri = icosphere(spec[1], 1.0)
+        return ellipsoid_mesh(xyz, tri, spec[2])
+    if kind == "geodesic_ellipsoid":
+        xyz, tri = geodesic_sphere(spec[1], 1.0)
+        return ellipsoid_mesh(xyz, tri, spec[2])
+    raise ValueError(kind)
+
+
+def workload(name):
+    """Return dict(xyz, tri, freq_hz, leaf_max, aca_tol, khat, pol, ...)."""
+    w = dict(WORKLOADS[name])
+    xyz, tri = workload_mesh(w["mesh"])
+    kind, kw = w["rhs"]
+    khat, pol = plane_wave_dirs(kind, **kw)
+    w.update(xyz=xyz, tri=tri, khat=khat, pol=pol, name=name)
+    return w
