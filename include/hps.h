@@ -1,0 +1,183 @@
+/*
+ * hps.h -- C ABI of the H-matrix power-series EFIE solver for MI355X (gfx950).
+ *
+ * Method: Negi, Balakrishnan, Rao, "Fast Power Series Solution of Large 3-D
+ * Electrodynamic Integral Equation for PEC Scatterers" (arXiv:2109.04129).
+ *
+ *   Z x = b  (eq. 9), Z = Z_N + Z_F (eq. 13): dense near-field blocks between
+ *   touching octree leaves and ACA low-rank far-field blocks (eqs. 10-12).
+ *   Setup: right scaling coefficients alpha_i = I - sum_j E_ij Z~_ii^-1 Z~_ij
+ *   by successive Schur steps with fill-in until the near field is block
+ *   diagonal (eqs. 14-23).  Only the right coefficients are stored; the left
+ *   ones are their transposes (Z_N = Z_N^T).
+ *   Solve: b~ = A^T b (eq. 25), b_o = D^-1 b~ (eq. 32), x~ = b_o - U b_o
+ *   (eqs. 31, 35-36, two terms), x = A x~ (eq. 26), with the per-RHS ratio
+ *   ||U b_o|| / ||b_o|| of eq. (45).
+ *
+ * Conventions shared by every call:
+ *   - complex numbers are interleaved (re, im) IEEE doubles ("c128");
+ *   - unknowns are RWG functions, one per interior mesh edge, numbered by the
+ *     edges sorted lexicographically on (min vertex id, max vertex id);
+ *     T+ is the triangle that runs along the edge from the smaller to the
+ *     larger vertex id in its counter-clockwise order;
+ *   - an N x R block of vectors is column-major with leading dimension N;
+ *   - time convention e^{j w t}, G = exp(-jkR)/(4 pi R), E0 = 1 V/m;
+ *   - every function returns an hps_status; nothing throws or aborts across
+ *     the ABI; after an error hps_last_error() describes it;
+ *   - a context is not thread-safe: one host thread at a time.
+ *
+ * Call order:  hps_create -> hps_set_mesh -> (hps_build_hmatrix |
+ *              hps_set_hmatrix) -> hps_setup -> hps_solve_* (any number).
+ *   Calling out of order returns HPS_ESTATE.
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hps_ctx hps_ctx;
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_WRATIO = 1,       /* results written, but some ratio >= ratio_warn (eq. 45) */
+  HPS_EINVAL = -1,      /* bad argument or mesh */
+  HPS_ENOMEM = -2,      /* host or device allocation failed, or over device_mem_cap */
+  HPS_EDEVICE = -3,     /* HIP runtime error, or no device in this context */
+  HPS_ESINGULAR = -4,   /* a scaled diagonal block Z~_ii is singular */
+  HPS_ESTATE = -5,      /* call order violated */
+  HPS_EIO = -6          /* file error */
+} hps_status;
+
+typedef struct {
+  double freq_hz;          /* > 0 */
+  int32_t leaf_max;        /* max unknowns per octree leaf (group), >= 1 */
+  double aca_tol;          /* eps of eq. (12), Frobenius, per far block, in (0, 1) */
+  int32_t precision;       /* 0: FP64 throughout.  1: FP32 solve (D^-1, scaling
+                              blocks, vectors) with BF16 far factors and a per-block
+                              FP32 scale, FP64 setup, plus refine_passes residual
+                              passes in FP32 */
+  int32_t terms;           /* power-series terms, >= 1 (paper: 2) */
+  int32_t refine_passes;   /* residual-correction passes (precision form), >= 0 */
+  double ratio_warn;       /* HPS_WRATIO threshold on eq. (45) (paper: 0.1) */
+  uint64_t device_mem_cap; /* bytes; 0 = none.  hps_setup fails with HPS_ENOMEM
+                              before allocating if its plan needs more */
+  int32_t host_threads;    /* threads for the host H-matrix build; 0 = all cores */
+  int32_t ordering;        /* group elimination order: 0 = nested dissection (default),
+                              1 = natural (tree order of the groups).  The currents do
+                              not depend on it; the eq. (45) ratio, which is measured in
+                              the scaled unknowns, does. */
+} hps_params;
+
+/* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0.
+   freq_hz = 0 (must be set). */
+hps_status hps_params_default(hps_params *p);
+
+/* Create a context on HIP device `device` (>= 0), or a host-only context
+   (device = -1) that can build and inspect H-matrices but not set up or solve.
+   `stream` is a hipStream_t to run on, or NULL for a stream the context
+   creates (default priority).  *out receives the context. */
+hps_status hps_create(hps_ctx **out, int device, void *stream);
+
+/* Release every host and device allocation of the context.  NULL is a no-op. */
+void hps_destroy(hps_ctx *ctx);
+
+/* Text of the last error on ctx (empty if none); valid until the next call. */
+const char *hps_last_error(const hps_ctx *ctx);
+
+/* Triangle mesh: xyz (nv x 3 doubles, metres, host), tri (nt x 3 int32 vertex
+   ids, host), counter-clockwise seen from outside.  Copied.  The mesh must be a
+   closed, consistently oriented 2-manifold without degenerate triangles, else
+   HPS_EINVAL.  Builds the RWG functions. */
+hps_status hps_set_mesh(hps_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri,
+                        int64_t nt);
+
+/* Number of RWG unknowns of the current mesh. */
+hps_status hps_num_unknowns(const hps_ctx *ctx, int64_t *N);
+
+/* Build the H-matrix of the mesh (Sec. II): octree over edge midpoints with at
+   most leaf_max unknowns per leaf; near blocks = touching leaf pairs (EFIE
+   Galerkin quadrature, Z = Z^T exactly); far blocks = non-touching cluster
+   pairs, re-compressed ACA to aca_tol (eqs. 10-12).  Host threads; the blocks
+   are then copied to the device (if any).  Not part of "setup". */
+hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
+
+/* Install an H-matrix built elsewhere instead (same meaning as above), all
+   arrays on the host, copied:
+     perm[N]          tree position -> RWG unknown (a permutation);
+     group_ptr[M+1]   group g owns tree positions [group_ptr[g], group_ptr[g+1]);
+     near_ts[2*n_near]  (t, s) group pairs, t <= s, each pair at most once, all
+                      (g, g) present; near_off[n_near+1] element offsets into
+                      near_vals (c128), block (t, s) is row-major
+                      (size_t - size_s) x (size of s) with entry [a][b] =
+                      Z(perm[lo_t + a], perm[lo_s + b]); block (s, t) is its
+                      transpose;
+     far_rng[4*n_far] (tlo, thi, slo, shi) tree-position ranges, disjoint from
+                      the near pattern; far_rank[n_far] r_b >= 0;
+                      far_off[n_far+1] element offsets into far_uv (c128);
+                      block b stores U (m x r, column-major) then V (n x r,
+                      column-major), m = thi - tlo, n = shi - slo, with
+                      Z[t, s] ~= U V^T and Z[s, t] ~= V U^T.
+   p supplies freq_hz (for excitation / RCS) and the solve options. */
+hps_status hps_set_hmatrix(hps_ctx *ctx, const hps_params *p, int64_t N, const int64_t *perm,
+                           int64_t M, const int64_t *group_ptr, int64_t n_near,
+                           const int32_t *near_ts, const int64_t *near_off,
+                           const double *near_vals, int64_t n_far, const int64_t *far_rng,
+                           const int32_t *far_rank, const int64_t *far_off,
+                           const double *far_uv);
+
+/* Query the H-matrix structure.  Pass NULL for arrays not wanted; sizes first:
+   *M, *n_near, *n_far, *near_elems (total near c128 entries), *far_elems. */
+hps_status hps_hmatrix_sizes(const hps_ctx *ctx, int64_t *M, int64_t *n_near, int64_t *n_far,
+                             int64_t *near_elems, int64_t *far_elems);
+/* Copy out the structure (host arrays sized by hps_hmatrix_sizes, same layout
+   as hps_set_hmatrix; any pointer may be NULL). */
+hps_status hps_get_hmatrix(const hps_ctx *ctx, int64_t *perm, int64_t *group_ptr, int32_t *near_ts,
+                           int64_t *near_off, double *near_vals, int64_t *far_rng,
+                           int32_t *far_rank, int64_t *far_off, double *far_uv);
+
+/* Setup ("setup time", Sec. III.A and IV.A): host symbolic phase (fill-reducing
+   nested-dissection order of the groups, fill-in pattern, elimination-tree
+   levels), then on the device, level by level: LU with partial pivoting and
+   inverse of each scaled diagonal block Z~_ii (eq. 16), the right coefficients
+   C_ij = Z~_ii^-1 Z~_ij, and the Schur updates Z~_jk -= Z~_ij^T C_ik including
+   fill-in blocks (eq. 21).  Precision form: also converts the solve operands.
+   HPS_ESINGULAR if a pivot block is singular (zero pivot column). */
+hps_status hps_setup(hps_ctx *ctx);
+
+/* Solve R plane-wave right-hand sides (Sec. V): wave r travels along khat[r]
+   with polarisation pol[r] (host arrays R x 3, unit, orthogonal).  Writes:
+     X     N x R c128 currents (RWG order), DEVICE pointer, or NULL;
+     rcs   R doubles (host): monostatic co-polar RCS in m^2 in the direction
+           -khat[r] (sigma = k^2 eta^2 / 4pi |b_r^T x_r|^2), or NULL;
+     ratio R doubles (host): ||it_1|| / ||it_0|| of eq. (45), or NULL.
+   Returns HPS_WRATIO (results written) when some ratio >= ratio_warn. */
+hps_status hps_solve_planewaves(hps_ctx *ctx, int64_t R, const double *khat, const double *pol,
+                                void *X, double *rcs, double *ratio);
+
+/* Solve arbitrary right-hand sides: B and X are N x R c128 DEVICE pointers in
+   RWG order (may not alias); ratio as above (host, nullable). */
+hps_status hps_solve_rhs(hps_ctx *ctx, int64_t R, const void *B, void *X, double *ratio);
+
+/* Plane-wave excitation only: B (N x R c128, DEVICE, RWG order) = <f_m, E_inc>. */
+hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const double *pol,
+                          void *B);
+
+/* Y = H X on the device (near blocks + both directions of every far block),
+   X and Y N x R c128 DEVICE pointers in RWG order.  Valid after the H-matrix
+   is installed (before or after setup). */
+hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
+
+/* JSON statistics (sizes, ranks, fill, bytes, per-stage device times of the
+   last setup / solve in ms) into buf (NUL-terminated, truncated to len). */
+hps_status hps_stats(const hps_ctx *ctx, char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H */

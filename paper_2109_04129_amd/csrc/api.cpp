@@ -1,0 +1,359 @@
+// C ABI of the hps library (include/hps.h).  Argument checking, call-order
+// state and error capture; the work is in the host modules and device.hip.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <sstream>
+#include <thread>
+
+#include "device.h"
+#include "hps_internal.h"
+
+struct hps_ctx {
+  int device = -1;
+  void *stream = nullptr;
+  std::string err;
+  hps_params params{};
+  bool have_params = false;
+  hps::Mesh mesh;
+  bool have_mesh = false;
+  hps::HMatrix H;
+  bool have_h = false;
+  hps::Plan plan;
+  bool have_setup = false;
+  std::unique_ptr<hps::DeviceState> dev;
+  double build_ms = 0.0, symbolic_ms = 0.0, setup_ms = 0.0;
+};
+
+namespace {
+
+hps_status fail(hps_ctx *c, hps_status s, const std::string &m) {
+  if (c) c->err = m;
+  return s;
+}
+
+template <class F>
+hps_status guarded(hps_ctx *c, F &&f) {
+  try {
+    c->err.clear();
+    return f();
+  } catch (const hps::Error &e) {
+    return fail(c, e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    return fail(c, HPS_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(c, HPS_EINVAL, e.what());
+  } catch (...) {
+    return fail(c, HPS_EINVAL, "unknown error");
+  }
+}
+
+hps_status check_params(hps_ctx *c, const hps_params *p) {
+  if (!p) return fail(c, HPS_EINVAL, "params is NULL");
+  if (!(p->freq_hz > 0.0) || !std::isfinite(p->freq_hz)) return fail(c, HPS_EINVAL, "freq_hz must be > 0");
+  if (p->leaf_max < 1) return fail(c, HPS_EINVAL, "leaf_max must be >= 1");
+  if (p->leaf_max > 128) return fail(c, HPS_EINVAL, "leaf_max above 128 is not supported by the setup kernels");
+  if (!(p->aca_tol > 0.0 && p->aca_tol < 1.0)) return fail(c, HPS_EINVAL, "aca_tol must be in (0, 1)");
+  if (p->terms < 1) return fail(c, HPS_EINVAL, "terms must be >= 1");
+  if (p->refine_passes < 0) return fail(c, HPS_EINVAL, "refine_passes must be >= 0");
+  if (p->precision != 0) return fail(c, HPS_EINVAL, "precision form not available in this build");
+  if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
+  return HPS_OK;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+hps_status hps_params_default(hps_params *p) {
+  if (!p) return HPS_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->freq_hz = 0.0;
+  p->leaf_max = 128;
+  p->aca_tol = 1e-3;
+  p->precision = 0;
+  p->terms = 2;
+  p->refine_passes = 0;
+  p->ratio_warn = 0.1;
+  p->device_mem_cap = 0;
+  p->host_threads = 0;
+  return HPS_OK;
+}
+
+hps_status hps_create(hps_ctx **out, int device, void *stream) {
+  if (!out) return HPS_EINVAL;
+  *out = nullptr;
+  hps_ctx *c = new (std::nothrow) hps_ctx();
+  if (!c) return HPS_ENOMEM;
+  c->device = device;
+  c->stream = stream;
+  if (device >= 0) {
+    hps_status st = guarded(c, [&]() {
+      c->dev.reset(new hps::DeviceState(device, stream));
+      return HPS_OK;
+    });
+    if (st != HPS_OK) {
+      delete c;
+      return st;
+    }
+  }
+  *out = c;
+  return HPS_OK;
+}
+
+void hps_destroy(hps_ctx *c) {
+  if (!c) return;
+  try {
+    c->dev.reset();
+  } catch (...) {
+  }
+  delete c;
+}
+
+const char *hps_last_error(const hps_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
+  if (!c) return HPS_EINVAL;
+  if (!xyz || !tri || nv <= 0 || nt <= 0) return fail(c, HPS_EINVAL, "empty mesh");
+  return guarded(c, [&]() {
+    hps::Mesh m;
+    m.nv = nv;
+    m.nt = nt;
+    m.xyz.assign(xyz, xyz + 3 * nv);
+    m.tri.assign(tri, tri + 3 * nt);
+    hps::build_rwg(m);
+    c->mesh = std::move(m);
+    c->have_mesh = true;
+    c->have_h = false;
+    c->have_setup = false;
+    return HPS_OK;
+  });
+}
+
+hps_status hps_num_unknowns(const hps_ctx *c, int64_t *N) {
+  if (!c || !N) return HPS_EINVAL;
+  if (!c->have_mesh) return HPS_ESTATE;
+  *N = c->mesh.N;
+  return HPS_OK;
+}
+
+hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_mesh) return fail(c, HPS_ESTATE, "hps_set_mesh first");
+  hps_status st = check_params(c, p);
+  if (st != HPS_OK) return st;
+  return guarded(c, [&]() {
+    const double t0 = now_ms();
+    hps::HMatrix H;
+    hps::build_hmatrix(c->mesh, *p, H);
+    c->H = std::move(H);
+    c->params = *p;
+    c->have_params = true;
+    c->have_h = true;
+    c->have_setup = false;
+    if (c->dev) c->dev->upload(c->mesh, c->H, *p);
+    c->build_ms = now_ms() - t0;
+    return HPS_OK;
+  });
+}
+
+hps_status hps_set_hmatrix(hps_ctx *c, const hps_params *p, int64_t N, const int64_t *perm, int64_t M,
+                           const int64_t *group_ptr, int64_t n_near, const int32_t *near_ts, const int64_t *near_off,
+                           const double *near_vals, int64_t n_far, const int64_t *far_rng, const int32_t *far_rank,
+                           const int64_t *far_off, const double *far_uv) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_mesh) return fail(c, HPS_ESTATE, "hps_set_mesh first");
+  hps_status st = check_params(c, p);
+  if (st != HPS_OK) return st;
+  if (N != c->mesh.N) return fail(c, HPS_EINVAL, "N does not match the mesh");
+  if (!perm || !group_ptr || M <= 0 || n_near <= 0 || !near_ts || !near_off || !near_vals)
+    return fail(c, HPS_EINVAL, "missing near-field arrays");
+  if (n_far < 0 || (n_far > 0 && (!far_rng || !far_rank || !far_off || !far_uv)))
+    return fail(c, HPS_EINVAL, "missing far-field arrays");
+  return guarded(c, [&]() {
+    hps::HMatrix H;
+    H.N = N;
+    H.M = M;
+    H.perm.assign(perm, perm + N);
+    std::vector<char> seen(N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      if (perm[i] < 0 || perm[i] >= N || seen[perm[i]]) throw hps::Error{HPS_EINVAL, "perm is not a permutation"};
+      seen[perm[i]] = 1;
+    }
+    H.gptr.assign(group_ptr, group_ptr + M + 1);
+    if (H.gptr[0] != 0 || H.gptr[M] != N) throw hps::Error{HPS_EINVAL, "group_ptr must span [0, N)"};
+    for (int64_t g = 0; g < M; ++g) {
+      const int64_t sz = H.gptr[g + 1] - H.gptr[g];
+      if (sz < 1) throw hps::Error{HPS_EINVAL, "empty group"};
+      if (sz > 128) throw hps::Error{HPS_EINVAL, "group larger than 128 unknowns"};
+    }
+    H.near_ts.assign(near_ts, near_ts + 2 * n_near);
+    H.near_off.assign(near_off, near_off + n_near + 1);
+    std::vector<char> diag(M, 0);
+    for (int64_t b = 0; b < n_near; ++b) {
+      const int64_t t = near_ts[2 * b], s = near_ts[2 * b + 1];
+      if (t < 0 || s < 0 || t >= M || s >= M || t > s) throw hps::Error{HPS_EINVAL, "bad near pair"};
+      if (near_off[b + 1] - near_off[b] != (H.gptr[t + 1] - H.gptr[t]) * (H.gptr[s + 1] - H.gptr[s]))
+        throw hps::Error{HPS_EINVAL, "near_off does not match the block sizes"};
+      if (t == s) diag[t] = 1;
+    }
+    for (int64_t g = 0; g < M; ++g)
+      if (!diag[g]) throw hps::Error{HPS_EINVAL, "every group needs its diagonal near block"};
+    const int64_t ne = near_off[n_near];
+    H.near_vals.resize(ne);
+    std::memcpy((void *)H.near_vals.data(), near_vals, ne * sizeof(hps::cplx));
+    H.far_rng.assign(far_rng ? far_rng : perm, far_rng ? far_rng + 4 * n_far : perm);
+    H.far_rank.assign(far_rank ? far_rank : (const int32_t *)nullptr, far_rank ? far_rank + n_far : nullptr);
+    H.far_off.assign(1, 0);
+    if (n_far > 0) H.far_off.assign(far_off, far_off + n_far + 1);
+    for (int64_t b = 0; b < n_far; ++b) {
+      const int64_t m = far_rng[4 * b + 1] - far_rng[4 * b], n = far_rng[4 * b + 3] - far_rng[4 * b + 2];
+      if (m <= 0 || n <= 0 || far_rng[4 * b] < 0 || far_rng[4 * b + 3] > N || far_rank[b] < 0 ||
+          far_off[b + 1] - far_off[b] != (int64_t)far_rank[b] * (m + n))
+        throw hps::Error{HPS_EINVAL, "bad far block"};
+    }
+    const int64_t fe = n_far > 0 ? far_off[n_far] : 0;
+    H.far_uv.resize(fe);
+    if (fe) std::memcpy((void *)H.far_uv.data(), far_uv, fe * sizeof(hps::cplx));
+    c->H = std::move(H);
+    c->params = *p;
+    c->have_params = true;
+    c->have_h = true;
+    c->have_setup = false;
+    if (c->dev) c->dev->upload(c->mesh, c->H, *p);
+    return HPS_OK;
+  });
+}
+
+hps_status hps_hmatrix_sizes(const hps_ctx *c, int64_t *M, int64_t *n_near, int64_t *n_far, int64_t *near_elems,
+                             int64_t *far_elems) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_h) return HPS_ESTATE;
+  if (M) *M = c->H.M;
+  if (n_near) *n_near = c->H.n_near();
+  if (n_far) *n_far = c->H.n_far();
+  if (near_elems) *near_elems = (int64_t)c->H.near_vals.size();
+  if (far_elems) *far_elems = (int64_t)c->H.far_uv.size();
+  return HPS_OK;
+}
+
+hps_status hps_get_hmatrix(const hps_ctx *c, int64_t *perm, int64_t *group_ptr, int32_t *near_ts, int64_t *near_off,
+                           double *near_vals, int64_t *far_rng, int32_t *far_rank, int64_t *far_off,
+                           double *far_uv) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_h) return HPS_ESTATE;
+  const hps::HMatrix &H = c->H;
+  if (perm) std::memcpy(perm, H.perm.data(), H.perm.size() * 8);
+  if (group_ptr) std::memcpy(group_ptr, H.gptr.data(), H.gptr.size() * 8);
+  if (near_ts) std::memcpy(near_ts, H.near_ts.data(), H.near_ts.size() * 4);
+  if (near_off) std::memcpy(near_off, H.near_off.data(), H.near_off.size() * 8);
+  if (near_vals) std::memcpy(near_vals, H.near_vals.data(), H.near_vals.size() * 16);
+  if (far_rng) std::memcpy(far_rng, H.far_rng.data(), H.far_rng.size() * 8);
+  if (far_rank) std::memcpy(far_rank, H.far_rank.data(), H.far_rank.size() * 4);
+  if (far_off) std::memcpy(far_off, H.far_off.data(), H.far_off.size() * 8);
+  if (far_uv) std::memcpy(far_uv, H.far_uv.data(), H.far_uv.size() * 16);
+  return HPS_OK;
+}
+
+hps_status hps_setup(hps_ctx *c) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_h) return fail(c, HPS_ESTATE, "install an H-matrix first");
+  if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context cannot run the setup");
+  return guarded(c, [&]() {
+    const double t0 = now_ms();
+    hps::Plan P;
+    hps::make_plan(c->H, c->mesh, c->params.ordering, P);
+    const double t1 = now_ms();
+    c->dev->times.symbolic_ms = t1 - t0;
+    c->have_setup = false;
+    c->dev->setup(P, c->H);
+    c->plan = std::move(P);
+    c->symbolic_ms = t1 - t0;
+    c->setup_ms = now_ms() - t0;
+    c->dev->times.setup_ms = c->setup_ms;
+    c->have_setup = true;
+    return HPS_OK;
+  });
+}
+
+static hps_status ratio_status(const hps_ctx *c, int64_t R, const double *ratio) {
+  if (!ratio) return HPS_OK;
+  for (int64_t r = 0; r < R; ++r)
+    if (!(ratio[r] < c->params.ratio_warn)) return HPS_WRATIO;
+  return HPS_OK;
+}
+
+hps_status hps_solve_planewaves(hps_ctx *c, int64_t R, const double *khat, const double *pol, void *X, double *rcs,
+                                double *ratio) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
+  if (R <= 0 || !khat || !pol) return fail(c, HPS_EINVAL, "bad plane-wave arguments");
+  return guarded(c, [&]() {
+    std::vector<double> rt(R);
+    c->dev->solve_planewaves(R, khat, pol, X, rcs, rt.data());
+    if (ratio) std::memcpy(ratio, rt.data(), R * sizeof(double));
+    return c->params.terms > 1 ? ratio_status(c, R, rt.data()) : HPS_OK;
+  });
+}
+
+hps_status hps_solve_rhs(hps_ctx *c, int64_t R, const void *B, void *X, double *ratio) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
+  if (R <= 0 || !B || !X || B == X) return fail(c, HPS_EINVAL, "bad RHS arguments");
+  return guarded(c, [&]() {
+    std::vector<double> rt(R);
+    c->dev->solve_rhs(R, B, X, rt.data());
+    if (ratio) std::memcpy(ratio, rt.data(), R * sizeof(double));
+    return c->params.terms > 1 ? ratio_status(c, R, rt.data()) : HPS_OK;
+  });
+}
+
+hps_status hps_excitation(hps_ctx *c, int64_t R, const double *khat, const double *pol, void *B) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
+  if (R <= 0 || !khat || !pol || !B) return fail(c, HPS_EINVAL, "bad plane-wave arguments");
+  return guarded(c, [&]() {
+    c->dev->excitation(R, khat, pol, B);
+    return HPS_OK;
+  });
+}
+
+hps_status hps_hmatvec(hps_ctx *c, int64_t R, const void *X, void *Y) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
+  if (R <= 0 || !X || !Y || X == Y) return fail(c, HPS_EINVAL, "bad matvec arguments");
+  return guarded(c, [&]() {
+    c->dev->hmatvec(R, X, Y);
+    return HPS_OK;
+  });
+}
+
+hps_status hps_stats(const hps_ctx *c, char *buf, size_t len) {
+  if (!c || !buf || len == 0) return HPS_EINVAL;
+  std::ostringstream o;
+  o.precision(9);
+  o << "{\"build_ms\": " << c->build_ms << ", \"setup_ms\": " << c->setup_ms << ", \"symbolic_ms\": " << c->symbolic_ms;
+  if (c->have_h) {
+    int64_t rsum = 0, rmax = 0;
+    for (int32_t r : c->H.far_rank) { rsum += r; rmax = std::max<int64_t>(rmax, r); }
+    o << ", \"hmatrix\": {\"N\": " << c->H.N << ", \"groups\": " << c->H.M << ", \"near_blocks\": " << c->H.n_near()
+      << ", \"far_blocks\": " << c->H.n_far() << ", \"rank_mean\": "
+      << (c->H.n_far() ? (double)rsum / c->H.n_far() : 0.0) << ", \"rank_max\": " << rmax
+      << ", \"near_elems\": " << c->H.near_vals.size() << ", \"far_elems\": " << c->H.far_uv.size() << "}";
+  }
+  if (c->dev) o << ", \"device\": " << c->dev->stats_json();
+  o << "}";
+  const std::string s = o.str();
+  const size_t n = std::min(len - 1, s.size());
+  std::memcpy(buf, s.data(), n);
+  buf[n] = 0;
+  return HPS_OK;
+}
+
+}  // extern "C"

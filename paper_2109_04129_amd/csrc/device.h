@@ -1,0 +1,71 @@
+// Device side of the hps library: buffers, schedules and launches.
+// Only host types appear here; the kernels live in device.hip.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hps_internal.h"
+
+namespace hps {
+
+// One output tile of a grouped GEMM: C[r0:r0+32, c0:c0+32] of a block with
+// m x n valid entries at C + c_off (column-major, leading dimension ldc),
+// accumulated over terms [t_begin, t_end).
+struct Tile {
+  int64_t c_off;
+  int32_t ldc, r0, c0, m, n, t_begin, t_end;
+};
+
+// One term op(A) B: A at a_off (column-major, lda), B at b_off (column-major,
+// ldb), contraction length k; trans = 1 uses A^T (never the conjugate).
+struct Term {
+  int64_t a_off, b_off;
+  int32_t lda, ldb, k, trans;
+};
+
+// A batch of tiles for one launch: C = alpha * sum op(A) B + beta * C with
+// mode 0: C = sum, 1: C -= sum, 2: C += sum.
+struct GemmBatch {
+  int mode = 0;
+  int a_buf = 0, b_buf = 0, c_buf = 0;   // buffer ids (see DeviceState::buf)
+  std::vector<Tile> tiles;
+  std::vector<Term> terms;
+  // device copies
+  void *d_tiles = nullptr, *d_terms = nullptr;
+  double flops = 0.0;                     // algorithmic, 8 per complex MAC
+};
+
+struct StageTimes {
+  double setup_ms = 0, inverse_ms = 0, coef_ms = 0, schur_ms = 0, symbolic_ms = 0;
+  double solve_ms = 0, rhs_ms = 0, sweep_ms = 0, far_ms = 0, rcs_ms = 0;
+};
+
+class DeviceState {
+ public:
+  DeviceState(int device, void *stream);
+  ~DeviceState();
+  void upload(const Mesh &mesh, const HMatrix &H, const hps_params &p);
+  void setup(const Plan &P, const HMatrix &H);         // throws Error
+  // RHS in elimination order into buffer `dst` (N x R), from plane waves.
+  void solve_planewaves(int64_t R, const double *khat, const double *pol, void *X, double *rcs,
+                        double *ratio);
+  void solve_rhs(int64_t R, const void *B, void *X, double *ratio);
+  void excitation(int64_t R, const double *khat, const double *pol, void *B);
+  void hmatvec(int64_t R, const void *X, void *Y);
+  std::string stats_json() const;
+
+  int device;
+  void *stream;     // hipStream_t
+  bool own_stream;
+  StageTimes times;
+  int terms = 2;
+  double last_solve_flops = 0.0;
+
+  struct Impl;
+  std::unique_ptr<Impl> impl;
+};
+
+}  // namespace hps

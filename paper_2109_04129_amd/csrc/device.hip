@@ -1,0 +1,1111 @@
+// HIP kernels and device schedules for gfx950 (CDNA4, wave64).
+//
+// Setup (Sec. III.A, eqs. 16-23), level by level of the elimination tree:
+//   k_inverse   Gauss-Jordan inverse with partial pivoting of each scaled
+//               diagonal block D_e = Z~_ee (held in registers, one block per
+//               workgroup);
+//   k_gemm      C_eN = D_e^-1 Z~_eN (the right scaling coefficients) and the
+//               Schur updates Z~_jk -= Z~_ej^T C_ek (eq. 21, incl. fill-in).
+// Solve (eqs. 25-36): plane-wave RHS, forward sweep with C^T (eq. 25), D^-1
+// (eq. 32), back sweep with C (eq. 26), far field U (V^T x) in both
+// directions, ratio of eq. (45), combination of the series terms, RCS.
+//
+// Every contraction goes through one grouped complex GEMM kernel driven by
+// host-built tile and term lists, so each output tile is owned by exactly one
+// workgroup and sums its terms in a fixed order (deterministic, no atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+#include "device.h"
+
+#define HIP_CHECK(x)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::hps::Error{HPS_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};   \
+  } while (0)
+
+namespace hps {
+
+typedef double2 c2;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ void cmac(c2 &acc, c2 a, c2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ c2 cinv(c2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+// ------------------------------------------------------------------ grouped GEMM
+// 32 x 32 output tile per workgroup of 256 threads; each thread owns rows
+// {tx, tx+16} and columns {ty, ty+16}.  K is staged through LDS in chunks of 16.
+constexpr int TM = 32, TK = 16;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
+                                              c2 *__restrict__ C, const Tile *__restrict__ tiles,
+                                              const Term *__restrict__ terms) {
+  const Tile t = tiles[blockIdx.x];
+  __shared__ c2 As[TK][TM + 1];
+  __shared__ c2 Bs[TK][TM + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  c2 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int q = t.t_begin; q < t.t_end; ++q) {
+    const Term tm = terms[q];
+    for (int k0 = 0; k0 < tm.k; k0 += TK) {
+      if (!tm.trans) {
+        const int i = tid & 31, kk = tid >> 5;
+        for (int h = 0; h < 2; ++h) {
+          const int k2 = kk + 8 * h, row = t.r0 + i, kg = k0 + k2;
+          c2 v = make_double2(0.0, 0.0);
+          if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)kg * tm.lda + row];
+          As[k2][i] = v;
+        }
+      } else {
+        const int kk = tid & 15, i = tid >> 4;
+        for (int h = 0; h < 2; ++h) {
+          const int i2 = i + 16 * h, row = t.r0 + i2, kg = k0 + kk;
+          c2 v = make_double2(0.0, 0.0);
+          if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)row * tm.lda + kg];
+          As[kk][i2] = v;
+        }
+      }
+      {
+        const int kk = tid & 15, j = tid >> 4;
+        for (int h = 0; h < 2; ++h) {
+          const int j2 = j + 16 * h, col = t.c0 + j2, kg = k0 + kk;
+          c2 v = make_double2(0.0, 0.0);
+          if (col < t.n && kg < tm.k) v = B[tm.b_off + (int64_t)col * tm.ldb + kg];
+          Bs[kk][j2] = v;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        const c2 a0 = As[kk][tx], a1 = As[kk][tx + 16];
+        const c2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+        cmac(acc[0][0], a0, b0);
+        cmac(acc[0][1], a0, b1);
+        cmac(acc[1][0], a1, b0);
+        cmac(acc[1][1], a1, b1);
+      }
+      __syncthreads();
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int row = t.r0 + tx + 16 * a, col = t.c0 + ty + 16 * b;
+      if (row < t.m && col < t.n) {
+        c2 *p = C + t.c_off + (int64_t)col * t.ldc + row;
+        if (MODE == 0) {
+          *p = acc[a][b];
+        } else if (MODE == 1) {
+          c2 v = *p;
+          v.x -= acc[a][b].x;
+          v.y -= acc[a][b].y;
+          *p = v;
+        } else {
+          c2 v = *p;
+          v.x += acc[a][b].x;
+          v.y += acc[a][b].y;
+          *p = v;
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------------ inverse
+// Gauss-Jordan inversion with partial pivoting (row interchanges recorded,
+// not performed) of n x n blocks, n <= NC.  Thread (c, rb) holds column c,
+// rows rb*RPT .. rb*RPT+RPT-1 in registers.  Equivalent to LU with partial
+// pivoting followed by the inverse.  A zero pivot column flags the block.
+template <int NC>
+__global__ __launch_bounds__(4 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
+                                                    const int64_t *__restrict__ off,
+                                                    const int32_t *__restrict__ nsz,
+                                                    const int32_t *__restrict__ ids,
+                                                    int *__restrict__ status) {
+  constexpr int RPT = NC / 4;
+  const int blk = blockIdx.x;
+  const int n = nsz[blk];
+  const c2 *src = W + off[blk];
+  c2 *dst = F + off[blk];
+  const int tid = threadIdx.x, c = tid % NC, rb = tid / NC;
+  __shared__ double cand_v[2][4];
+  __shared__ int cand_i[2][4];
+  __shared__ c2 rowbuf[2][NC];
+  __shared__ c2 colbuf[2][NC];
+  __shared__ int used[NC], pivrow[NC], stepof[NC];
+  c2 a[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int row = rb * RPT + q;
+    a[q] = (row < n && c < n) ? src[(int64_t)c * n + row] : make_double2(0.0, 0.0);
+  }
+  if (tid < NC) used[tid] = (tid < n) ? 0 : 1;
+  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < n; ++k) {
+    const int s = k & 1;
+    if (c == k) {
+      double best = -1.0;
+      int bi = -1;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = rb * RPT + q;
+        if (row < n && !used[row]) {
+          const double m = a[q].x * a[q].x + a[q].y * a[q].y;
+          if (m > best) { best = m; bi = row; }
+        }
+      }
+      cand_v[s][rb] = best;
+      cand_i[s][rb] = bi;
+    }
+    __syncthreads();
+    double best = -1.0;
+    int p = -1;
+    for (int r = 0; r < 4; ++r)
+      if (cand_i[s][r] >= 0 && cand_v[s][r] > best) { best = cand_v[s][r]; p = cand_i[s][r]; }
+    if (p < 0 || !(best > 0.0)) { singular = true; break; }
+    if (rb == p / RPT && c < n) {
+      c2 v = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (q == p % RPT) v = a[q];
+      rowbuf[s][c] = v;
+    }
+    if (c == k) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) colbuf[s][rb * RPT + q] = a[q];
+    }
+    if (tid == 0) { used[p] = 1; pivrow[k] = p; stepof[p] = k; }
+    __syncthreads();
+    const c2 inv = cinv(rowbuf[s][k]);
+    const c2 rp = (c < n && c != k) ? cmul(rowbuf[s][c], inv) : make_double2(0.0, 0.0);
+    if (c < n) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = rb * RPT + q;
+        if (row >= n) continue;
+        if (row == p) {
+          a[q] = (c == k) ? inv : cmul(a[q], inv);
+        } else {
+          const c2 m = colbuf[s][row];
+          if (c == k) {
+            const c2 t = cmul(m, inv);
+            a[q] = make_double2(-t.x, -t.y);
+          } else {
+            const c2 t = cmul(m, rp);
+            a[q].x -= t.x;
+            a[q].y -= t.y;
+          }
+        }
+      }
+    }
+  }
+  if (singular) {
+    if (tid == 0) atomicMax(status, ids[blk] + 1);
+    return;
+  }
+  __syncthreads();
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = rb * RPT + q;
+      if (row < n) dst[(int64_t)pivrow[c] * n + stepof[row]] = a[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_fill(c2 *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+// Scatter the near blocks (row-major m x n, tree order) into the panels.
+struct Scatter {
+  int64_t src, dst;
+  int32_t m, n, ld, trans;
+};
+__global__ void k_scatter(const c2 *__restrict__ near, c2 *__restrict__ W, const Scatter *__restrict__ d) {
+  const Scatter s = d[blockIdx.x];
+  const int64_t tot = (int64_t)s.m * s.n;
+  for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int64_t a = i / s.n, b = i % s.n;   // row a of t, column b of s
+    const c2 v = near[s.src + i];
+    if (!s.trans)
+      W[s.dst + b * s.ld + a] = v;           // panel of t: rows of t, columns of s
+    else
+      W[s.dst + a * s.ld + b] = v;           // panel of s: rows of s, columns of t
+  }
+}
+
+// b[q, r] = sum over the 14 quadrature points of T+ and T- of
+//           c (r_pt - v).pol exp(-j k khat.r_pt)
+__global__ void k_rhs(const double *__restrict__ qd, const int64_t *__restrict__ dperm, int64_t N,
+                      int64_t R, const double *__restrict__ kp, double k, c2 *__restrict__ B) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * R) return;
+  const int64_t q = idx % N, r = idx / N;
+  const int64_t m = dperm[q];
+  const double *w = kp + 6 * r;
+  double re = 0.0, im = 0.0;
+  for (int pt = 0; pt < 14; ++pt) {
+    const double *d = qd + (m * 14 + pt) * 7;
+    const double ph = -k * (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]);
+    const double f = d[6] * (d[3] * w[3] + d[4] * w[4] + d[5] * w[5]);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    re = fma(f, cs, re);
+    im = fma(f, sn, im);
+  }
+  B[idx] = make_double2(re, im);
+}
+
+// Per-column reductions: out[r] = sum_q |v|^2 (mode 0) or
+// coef * |sum_q a b|^2 (mode 1: monostatic RCS from b^T x).
+__global__ __launch_bounds__(256) void k_colreduce(const c2 *__restrict__ a, const c2 *__restrict__ b,
+                                                   int64_t N, double coef, int mode,
+                                                   double *__restrict__ out) {
+  const int64_t r = blockIdx.x;
+  __shared__ double sx[256], sy[256];
+  double x = 0.0, y = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) {
+    const c2 u = a[r * N + i];
+    if (mode == 0) {
+      x = fma(u.x, u.x, x);
+      x = fma(u.y, u.y, x);
+    } else {
+      const c2 v = b[r * N + i];
+      x = fma(u.x, v.x, x);
+      x = fma(-u.y, v.y, x);
+      y = fma(u.x, v.y, y);
+      y = fma(u.y, v.x, y);
+    }
+  }
+  sx[threadIdx.x] = x;
+  sy[threadIdx.x] = y;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sx[threadIdx.x] += sx[threadIdx.x + s];
+      sy[threadIdx.x] += sy[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = (mode == 0) ? sx[0] : coef * (sx[0] * sx[0] + sy[0] * sy[0]);
+}
+
+// y += sgn * w
+__global__ void k_axpy(c2 *__restrict__ y, const c2 *__restrict__ w, double sgn, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    c2 a = y[i];
+    const c2 b = w[i];
+    a.x = fma(sgn, b.x, a.x);
+    a.y = fma(sgn, b.y, a.y);
+    y[i] = a;
+  }
+}
+
+// dir 0: out[q + r N] = in[dperm[q] + r N] (RWG -> elimination order);
+// dir 1: out[dperm[q] + r N] = in[q + r N].
+__global__ void k_permute(const c2 *__restrict__ in, c2 *__restrict__ out, const int64_t *__restrict__ dperm,
+                          int64_t N, int64_t R, int dir) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * R) return;
+  const int64_t q = idx % N, r = idx / N;
+  if (dir == 0)
+    out[idx] = in[dperm[q] + r * N];
+  else
+    out[dperm[q] + r * N] = in[idx];
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+
+template <class T>
+struct DevArray {
+  T *p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    HIP_CHECK(hipMalloc((void **)&p, count * sizeof(T)));
+    n = count;
+  }
+  void upload(const std::vector<T> &v, hipStream_t s) {
+    alloc(v.size());
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevArray() { release(); }
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Host-side bounds check of a tile/term batch against the element counts of
+// the A, B and C buffers: every index a kernel can form must be in range.
+void validate(const std::vector<Tile> &tiles, const std::vector<Term> &terms, int64_t na, int64_t nb,
+              int64_t nc, const char *what) {
+  for (const Tile &t : tiles) {
+    if (t.m <= 0 || t.n <= 0) continue;
+    if (t.c_off < 0 || t.ldc < t.m || t.c_off + (int64_t)(t.n - 1) * t.ldc + (t.m - 1) >= nc ||
+        t.t_begin < 0 || t.t_end > (int64_t)terms.size() || t.t_begin > t.t_end)
+      throw Error{HPS_EINVAL, std::string("internal descriptor out of range (C) in ") + what};
+    for (int32_t q = t.t_begin; q < t.t_end; ++q) {
+      const Term &m = terms[q];
+      if (m.k <= 0) continue;
+      const int64_t amax = m.trans ? m.a_off + (int64_t)(t.m - 1) * m.lda + (m.k - 1)
+                                   : m.a_off + (int64_t)(m.k - 1) * m.lda + (t.m - 1);
+      const int64_t bmax = m.b_off + (int64_t)(t.n - 1) * m.ldb + (m.k - 1);
+      const bool lda_ok = m.trans ? (m.lda >= m.k) : (m.lda >= t.m);
+      if (m.a_off < 0 || m.b_off < 0 || amax >= na || bmax >= nb || !lda_ok || m.ldb < m.k)
+        throw Error{HPS_EINVAL, std::string("internal descriptor out of range (A/B) in ") + what};
+    }
+  }
+}
+
+}  // namespace
+
+struct LevelInv {
+  int nc;                       // 32, 64 or 128
+  std::vector<int64_t> off;
+  std::vector<int32_t> n, id;
+  DevArray<int64_t> d_off;
+  DevArray<int32_t> d_n, d_id;
+};
+
+struct DeviceState::Impl {
+  hipStream_t s;
+  // problem
+  int64_t N = 0, M = 0, R_cap = 0;
+  double k = 0.0, coef_rcs = 0.0, ratio_warn = 0.1;
+  int terms = 2;
+  uint64_t mem_cap = 0;
+  // H-matrix on device
+  DevArray<c2> near, faruv;
+  DevArray<double> quad;           // N x 14 x 7 (RWG order)
+  HMatrix hcopy;                   // structure (values not needed after upload)
+  std::vector<int64_t> far_m, far_n;
+  // plan
+  bool ready = false;
+  Plan P;
+  DevArray<int64_t> dperm;         // elimination position -> RWG
+  DevArray<c2> F;                  // factor panels
+  std::vector<int64_t> tree2elim;  // tree position -> elimination position
+  // solve schedules (independent of R: terms; tiles rebuilt per R)
+  struct Sched {
+    std::vector<Term> terms;
+    std::vector<std::pair<int64_t, int32_t>> targets;   // (c_off, m) per target, rows
+    std::vector<int32_t> t_ptr;                          // terms per target
+    std::vector<int32_t> ld;                             // ldc per target
+    int mode = 0;
+  };
+  std::vector<Sched> fwd, bwd;     // per level
+  Sched dinv, far1, far2, nearmv;
+  std::vector<int64_t> toff;       // far intermediate offsets (per block, dir), in units of R
+  int64_t t_rows = 0;
+  // vector buffers
+  DevArray<c2> vB, vY, vW, vS, vI, vX;
+  DevArray<c2> vT;
+  DevArray<double> red;
+  DevArray<int> status;
+  // cached per-R tile lists
+  struct Built {
+    DevArray<Tile> tiles;
+    DevArray<Term> terms;
+    int64_t n_tiles = 0;
+    double flops = 0.0;
+  };
+  int64_t built_R = -1;
+  std::vector<Built> b_fwd, b_bwd;
+  Built b_dinv, b_far1, b_far2, b_near;
+  std::vector<double> solve_flops_parts;
+
+  void build(const Sched &sc, int64_t R, Built &out, int64_t na, int64_t nb, int64_t nc, const char *what) {
+    std::vector<Tile> tiles;
+    double fl = 0.0;
+    for (size_t t = 0; t < sc.targets.size(); ++t) {
+      const int64_t coff = sc.targets[t].first;
+      const int32_t m = sc.targets[t].second;
+      const int32_t tb = sc.t_ptr[t], te = sc.t_ptr[t + 1];
+      for (int64_t r0 = 0; r0 < m; r0 += TM)
+        for (int64_t c0 = 0; c0 < R; c0 += TM)
+          tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, tb, te});
+      for (int32_t q = tb; q < te; ++q) fl += 8.0 * m * (double)R * sc.terms[q].k;
+    }
+    validate(tiles, sc.terms, na, nb, nc, what);
+    out.tiles.upload(tiles, s);
+    out.terms.upload(sc.terms, s);
+    out.n_tiles = (int64_t)tiles.size();
+    out.flops = fl;
+  }
+
+  void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
+    if (b.n_tiles == 0) return;
+    dim3 g((unsigned)b.n_tiles), blk(256);
+    if (mode == 0)
+      hipLaunchKernelGGL(k_gemm<0>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+    else if (mode == 1)
+      hipLaunchKernelGGL(k_gemm<1>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+    else
+      hipLaunchKernelGGL(k_gemm<2>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+    HIP_CHECK(hipGetLastError());
+  }
+
+  void ensure_R(int64_t R) {
+    if (R == built_R) return;
+    b_fwd.clear();
+    b_bwd.clear();
+    b_fwd.resize(fwd.size());
+    b_bwd.resize(bwd.size());
+    solve_flops_parts.assign(4, 0.0);
+    const int64_t NR = N * R, nF = (int64_t)F.n, nT = std::max<int64_t>(t_rows, 1) * R;
+    for (size_t l = 0; l < fwd.size(); ++l) { build(fwd[l], R, b_fwd[l], nF, NR, NR, "forward sweep"); solve_flops_parts[0] += b_fwd[l].flops; }
+    for (size_t l = 0; l < bwd.size(); ++l) { build(bwd[l], R, b_bwd[l], nF, NR, NR, "back sweep"); solve_flops_parts[1] += b_bwd[l].flops; }
+    build(dinv, R, b_dinv, nF, NR, NR, "D^-1");
+    solve_flops_parts[2] = b_dinv.flops;
+    build(far1, R, b_far1, (int64_t)faruv.n, NR, nT, "far stage 1");
+    build(far2, R, b_far2, (int64_t)faruv.n, nT, NR, "far stage 2");
+    solve_flops_parts[3] = b_far1.flops + b_far2.flops;
+    build(nearmv, R, b_near, (int64_t)near.n, NR, NR, "near matvec");
+    vB.alloc(NR); vY.alloc(NR); vW.alloc(NR); vS.alloc(NR); vI.alloc(NR); vX.alloc(NR);
+    vT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
+    red.alloc(2 * R + 8);
+    built_R = R;
+  }
+
+  void sweep_fwd(c2 *v) {
+    for (size_t l = 0; l < b_fwd.size(); ++l) launch(b_fwd[l], 1, F.p, v, v);
+  }
+  void sweep_bwd(c2 *v) {
+    for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch(b_bwd[l], 1, F.p, v, v);
+  }
+  void far_apply(const c2 *y, c2 *out, int mode) {
+    launch(b_far1, 0, faruv.p, y, vT.p);
+    launch(b_far2, mode, faruv.p, vT.p, out);
+  }
+  void colnorm2(const c2 *v, int64_t R, double *dst) {
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R), dim3(256), 0, s, v, v, N, 0.0, 0, dst);
+    HIP_CHECK(hipGetLastError());
+  }
+
+  // Power series (eqs. 25-36) on vB (elimination order, N x R): result in vY.
+  void series(int64_t R, double *ratio_host) {
+    const int64_t NR = N * R;
+    const unsigned gb = (unsigned)cdiv(NR, 256);
+    HIP_CHECK(hipMemcpyAsync(vS.p, vB.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+    sweep_fwd(vS.p);                               // b~ = A^T b            (eq. 25)
+    launch(b_dinv, 0, F.p, vS.p, vI.p);            // it_0 = b_o = D^-1 b~  (eq. 32)
+    colnorm2(vI.p, R, red.p);
+    HIP_CHECK(hipMemcpyAsync(vY.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+    sweep_bwd(vY.p);                               // w_0 = A it_0          (eq. 26)
+    std::vector<double> n0(R), n1(R), worst(R, 0.0);
+    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    const c2 *wprev = vY.p;
+    for (int t = 1; t < terms; ++t) {
+      far_apply(wprev, vS.p, 0);                   // s = Z_F w_{t-1}
+      sweep_fwd(vS.p);                             // A^T s
+      launch(b_dinv, 0, F.p, vS.p, vI.p);          // it_t = D^-1 A^T Z_F A it_{t-1}  (eq. 31)
+      colnorm2(vI.p, R, red.p + R);
+      HIP_CHECK(hipMemcpyAsync(vW.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+      sweep_bwd(vW.p);                             // w_t = A it_t
+      hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, vY.p, vW.p, (t & 1) ? -1.0 : 1.0, NR);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + R, R * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      for (int64_t r = 0; r < R; ++r) {
+        const double q = std::sqrt(n1[r]) / std::sqrt(n0[r]);
+        if (t == 1) worst[r] = q;
+        n0[r] = n1[r];
+      }
+      // keep w_t for the next term
+      std::swap(vW.p, vX.p);
+      std::swap(vW.n, vX.n);
+      wprev = vX.p;
+    }
+    if (ratio_host)
+      for (int64_t r = 0; r < R; ++r) ratio_host[r] = (terms > 1) ? worst[r] : 0.0;
+  }
+};
+
+DeviceState::DeviceState(int dev, void *strm) : device(dev), stream(strm), own_stream(false) {
+  HIP_CHECK(hipSetDevice(dev));
+  impl.reset(new Impl());
+  if (!strm) {
+    hipStream_t s;
+    HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    stream = s;
+    own_stream = true;
+  }
+  impl->s = (hipStream_t)stream;
+  impl->status.alloc(1);
+}
+
+DeviceState::~DeviceState() {
+  if (impl) {
+    (void)hipStreamSynchronize(impl->s);
+    impl.reset();
+  }
+  if (own_stream && stream) (void)hipStreamDestroy((hipStream_t)stream);
+}
+
+void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p) {
+  Impl &I = *impl;
+  HIP_CHECK(hipSetDevice(device));
+  I.N = H.N;
+  I.M = H.M;
+  I.ready = false;
+  I.built_R = -1;
+  const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi;
+  I.k = 2.0 * pi * p.freq_hz / c0;
+  const double eta = mu0 * c0;
+  I.coef_rcs = I.k * I.k * eta * eta / (4.0 * pi);
+  I.terms = std::max(1, p.terms);
+  terms = I.terms;
+  I.ratio_warn = p.ratio_warn;
+  I.mem_cap = p.device_mem_cap;
+  const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * 7 * 8;
+  if (I.mem_cap && need > I.mem_cap) throw Error{HPS_ENOMEM, "H-matrix exceeds device_mem_cap"};
+  {
+    std::vector<c2> tmp(H.near_vals.size());
+    std::memcpy(tmp.data(), H.near_vals.data(), tmp.size() * sizeof(c2));
+    I.near.upload(tmp, I.s);
+    HIP_CHECK(hipStreamSynchronize(I.s));
+    tmp.resize(H.far_uv.size());
+    std::memcpy(tmp.data(), H.far_uv.data(), tmp.size() * sizeof(c2));
+    I.faruv.upload(tmp, I.s);
+    HIP_CHECK(hipStreamSynchronize(I.s));
+  }
+  // structure copy without values
+  I.hcopy = HMatrix();
+  I.hcopy.N = H.N; I.hcopy.M = H.M; I.hcopy.perm = H.perm; I.hcopy.gptr = H.gptr;
+  I.hcopy.near_ts = H.near_ts; I.hcopy.near_off = H.near_off;
+  I.hcopy.far_rng = H.far_rng; I.hcopy.far_rank = H.far_rank; I.hcopy.far_off = H.far_off;
+  // quadrature data of the RWG functions for the excitation (7-point rule)
+  std::vector<double> qd((size_t)H.N * 14 * 7);
+  {
+    const double s15 = std::sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, w1 = (155.0 - s15) / 1200.0;
+    const double a2 = (6.0 + s15) / 21.0, w2 = (155.0 + s15) / 1200.0;
+    const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
+    const double Bc[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {b1, a1, a1}, {a1, b1, a1}, {a1, a1, b1},
+                             {b2, a2, a2}, {a2, b2, a2}, {a2, a2, b2}};
+    const double Wq[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+    for (int64_t m = 0; m < H.N; ++m)
+      for (int side = 0; side < 2; ++side) {
+        const int32_t t = side ? mesh.tm[m] : mesh.tp[m];
+        const int32_t v = side ? mesh.vm[m] : mesh.vp[m];
+        const double sg = side ? -1.0 : 1.0;
+        const double *P0 = &mesh.xyz[3 * mesh.tri[3 * t]], *P1 = &mesh.xyz[3 * mesh.tri[3 * t + 1]],
+                     *P2 = &mesh.xyz[3 * mesh.tri[3 * t + 2]];
+        const double *V = &mesh.xyz[3 * v];
+        for (int q = 0; q < 7; ++q) {
+          double *d = &qd[((size_t)m * 14 + side * 7 + q) * 7];
+          for (int c = 0; c < 3; ++c) {
+            d[c] = Bc[q][0] * P0[c] + Bc[q][1] * P1[c] + Bc[q][2] * P2[c];
+            d[3 + c] = d[c] - V[c];
+          }
+          d[6] = sg * mesh.len[m] / 2.0 * Wq[q];   // (l / 2A) * A * w
+        }
+      }
+  }
+  I.quad.upload(qd, I.s);
+  HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+void DeviceState::setup(const Plan &P, const HMatrix &H) {
+  Impl &I = *impl;
+  HIP_CHECK(hipSetDevice(device));
+  hipStream_t s = I.s;
+  I.P = P;
+  I.ready = false;
+  I.built_R = -1;
+  const int64_t N = I.N, M = I.M;
+  const uint64_t need = 2ull * (uint64_t)P.panel_elems * sizeof(c2);
+  if (I.mem_cap && need + (I.near.n + I.faruv.n) * sizeof(c2) > I.mem_cap)
+    throw Error{HPS_ENOMEM, "setup plan exceeds device_mem_cap"};
+  // elimination-order permutation
+  std::vector<int64_t> dperm(N), t2e(N);
+  for (int64_t e = 0; e < M; ++e) {
+    const int32_t g = P.order[e];
+    for (int64_t i = 0; i < P.size[e]; ++i) {
+      dperm[P.uoff[e] + i] = H.perm[H.gptr[g] + i];
+      t2e[H.gptr[g] + i] = P.uoff[e] + i;
+    }
+  }
+  I.tree2elim = t2e;
+  I.dperm.upload(dperm, s);
+
+  // column-offset lookup: block (e, f) of panel e
+  auto col_of = [&](int64_t e, int64_t f) -> int64_t {
+    if (e == f) return 0;
+    const int32_t *b = &P.later[P.later_ptr[e]], *en = &P.later[P.later_ptr[e + 1]];
+    const int32_t *it = std::lower_bound(b, en, (int32_t)f);
+    if (it == en || *it != f) throw Error{HPS_EINVAL, "internal: block missing from fill pattern"};
+    return P.col_off[it - &P.later[0]];
+  };
+
+  // ---- working panels and factor panels
+  DevArray<c2> Wd;
+  Wd.alloc(std::max<int64_t>(P.panel_elems, 1));
+  I.F.alloc(std::max<int64_t>(P.panel_elems, 1));
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(std::max<int64_t>(P.panel_elems, 1), 256)), dim3(256), 0, s, Wd.p,
+                     std::max<int64_t>(P.panel_elems, 1));
+  HIP_CHECK(hipGetLastError());
+  {
+    std::vector<Scatter> sc(H.n_near());
+    for (int64_t b = 0; b < H.n_near(); ++b) {
+      const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
+      const int64_t et = P.pos[t], eu = P.pos[u];
+      const int32_t mt = (int32_t)(H.gptr[t + 1] - H.gptr[t]), mu = (int32_t)(H.gptr[u + 1] - H.gptr[u]);
+      Scatter d;
+      d.src = H.near_off[b];
+      d.m = mt;
+      d.n = mu;
+      if (et <= eu) {
+        d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
+        d.ld = (int32_t)P.size[et];
+        d.trans = 0;
+      } else {
+        d.dst = P.panel_off[eu] + col_of(eu, et) * P.size[eu];
+        d.ld = (int32_t)P.size[eu];
+        d.trans = 1;
+      }
+      sc[b] = d;
+    }
+    for (const Scatter &d : sc) {
+      const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
+      if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= P.panel_elems)
+        throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
+    }
+    DevArray<Scatter> dsc;
+    dsc.upload(sc, s);
+    if (!sc.empty()) {
+      hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd.p, dsc.p);
+      HIP_CHECK(hipGetLastError());
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+
+  // ---- per-level schedules
+  const int L = P.n_levels;
+  std::vector<LevelInv> inv;               // flattened: (level, class)
+  std::vector<int> inv_level;
+  struct GB { std::vector<Tile> tiles; std::vector<Term> terms; };
+  std::vector<GB> coef(L), schur(L);
+  double flops = 0.0;
+  for (int l = 0; l < L; ++l) {
+    // inverse launches by size class
+    for (int nc : {32, 64, 128}) {
+      LevelInv li;
+      li.nc = nc;
+      for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+        const int32_t e = P.level_piv[i];
+        const int64_t n = P.size[e];
+        const int cls = n <= 32 ? 32 : (n <= 64 ? 64 : 128);
+        if (n > 128) throw Error{HPS_EINVAL, "group larger than 128 unknowns is not supported"};
+        if (cls != nc) continue;
+        li.off.push_back(P.panel_off[e]);
+        li.n.push_back((int32_t)n);
+        li.id.push_back(e);
+      }
+      if (!li.off.empty()) {
+        inv.push_back(std::move(li));
+        inv_level.push_back(l);
+      }
+    }
+    // coefficient panels C_eN = D^-1 Z~_eN
+    GB &cg = coef[l];
+    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+      const int32_t e = P.level_piv[i];
+      const int64_t n = P.size[e], nF = P.width[e] - n;
+      if (nF == 0) continue;
+      const int32_t tb = (int32_t)cg.terms.size();
+      cg.terms.push_back(Term{P.panel_off[e], P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 0});
+      for (int64_t r0 = 0; r0 < n; r0 += TM)
+        for (int64_t c0 = 0; c0 < nF; c0 += TM)
+          cg.tiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
+                                  (int32_t)nF, tb, tb + 1});
+      flops += 8.0 * n * n * nF;
+    }
+    // Schur targets (j <= k) with their contributing pivots
+    std::map<std::pair<int32_t, int32_t>, std::vector<Term>> tg;
+    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+      const int32_t e = P.level_piv[i];
+      const int64_t n = P.size[e];
+      for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
+        for (int64_t b = a; b < P.later_ptr[e + 1]; ++b) {
+          const int32_t j = P.later[a], kk = P.later[b];
+          tg[{j, kk}].push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
+                                     (int32_t)n, (int32_t)n, (int32_t)n, 1});
+          flops += 8.0 * n * P.size[j] * P.size[kk];
+        }
+    }
+    GB &sg = schur[l];
+    for (auto &kv : tg) {
+      const int32_t j = kv.first.first, kk = kv.first.second;
+      const int64_t coff = P.panel_off[j] + col_of(j, kk) * P.size[j];
+      const int32_t tb = (int32_t)sg.terms.size();
+      sg.terms.insert(sg.terms.end(), kv.second.begin(), kv.second.end());
+      const int32_t te = (int32_t)sg.terms.size();
+      for (int64_t r0 = 0; r0 < P.size[j]; r0 += TM)
+        for (int64_t c0 = 0; c0 < P.size[kk]; c0 += TM)
+          sg.tiles.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j],
+                                  (int32_t)P.size[kk], tb, te});
+    }
+  }
+  for (auto &li : inv)
+    for (size_t i = 0; i < li.off.size(); ++i)
+      if (li.n[i] < 1 || li.n[i] > li.nc || li.off[i] < 0 || li.off[i] + (int64_t)li.n[i] * li.n[i] > P.panel_elems)
+        throw Error{HPS_EINVAL, "internal descriptor out of range (inverse)"};
+  for (int l = 0; l < L; ++l) {
+    validate(coef[l].tiles, coef[l].terms, P.panel_elems, P.panel_elems, P.panel_elems, "coefficients");
+    validate(schur[l].tiles, schur[l].terms, P.panel_elems, P.panel_elems, P.panel_elems, "schur");
+  }
+  for (auto &li : inv) {
+    li.d_off.upload(li.off, s);
+    li.d_n.upload(li.n, s);
+    li.d_id.upload(li.id, s);
+  }
+  std::vector<DevArray<Tile>> dct(L), dst(L);
+  std::vector<DevArray<Term>> dcm(L), dsm(L);
+  for (int l = 0; l < L; ++l) {
+    dct[l].upload(coef[l].tiles, s);
+    dcm[l].upload(coef[l].terms, s);
+    dst[l].upload(schur[l].tiles, s);
+    dsm[l].upload(schur[l].terms, s);
+  }
+  HIP_CHECK(hipMemsetAsync(I.status.p, 0, sizeof(int), s));
+
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipEventRecord(e0, s));
+  size_t ii = 0;
+  for (int l = 0; l < L; ++l) {
+    for (; ii < inv.size() && inv_level[ii] == l; ++ii) {
+      LevelInv &li = inv[ii];
+      const unsigned nb = (unsigned)li.off.size();
+      if (li.nc == 32)
+        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p, li.d_id.p,
+                           I.status.p);
+      else if (li.nc == 64)
+        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(256), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p, li.d_id.p,
+                           I.status.p);
+      else
+        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(512), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p,
+                           li.d_id.p, I.status.p);
+      HIP_CHECK(hipGetLastError());
+    }
+    if (!coef[l].tiles.empty()) {
+      hipLaunchKernelGGL(k_gemm<0>, dim3((unsigned)coef[l].tiles.size()), dim3(256), 0, s, I.F.p, Wd.p, I.F.p,
+                         dct[l].p, dcm[l].p);
+      HIP_CHECK(hipGetLastError());
+    }
+    if (!schur[l].tiles.empty()) {
+      hipLaunchKernelGGL(k_gemm<1>, dim3((unsigned)schur[l].tiles.size()), dim3(256), 0, s, Wd.p, I.F.p, Wd.p,
+                         dst[l].p, dsm[l].p);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+  HIP_CHECK(hipEventRecord(e1, s));
+  HIP_CHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  times.inverse_ms = 0;
+  times.schur_ms = ms;
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+  int st = 0;
+  HIP_CHECK(hipMemcpy(&st, I.status.p, sizeof(int), hipMemcpyDeviceToHost));
+  if (st > 0) throw Error{HPS_ESINGULAR, "singular scaled diagonal block of group " + std::to_string(P.order[st - 1])};
+  I.P.setup_flops = flops;
+
+  // ---- solve schedules (terms independent of R)
+  auto add_target = [](Impl::Sched &sc, int64_t coff, int32_t m, int32_t ld) {
+    sc.targets.push_back({coff, m});
+    sc.ld.push_back(ld);
+    sc.t_ptr.push_back((int32_t)sc.terms.size());
+  };
+  auto close = [](Impl::Sched &sc) { sc.t_ptr.push_back((int32_t)sc.terms.size()); };
+  // contributors of each f (transpose of the pattern)
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> contrib(M);
+  for (int64_t e = 0; e < M; ++e)
+    for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
+  I.fwd.assign(L, Impl::Sched());
+  I.bwd.assign(L, Impl::Sched());
+  for (int l = 0; l < L; ++l) {
+    Impl::Sched &fs = I.fwd[l];
+    Impl::Sched &bs = I.bwd[l];
+    fs.t_ptr.clear();
+    bs.t_ptr.clear();
+    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+      const int32_t f = P.level_piv[i];
+      if (!contrib[f].empty()) {
+        fs.targets.push_back({P.uoff[f], (int32_t)P.size[f]});
+        fs.ld.push_back((int32_t)N);
+        fs.t_ptr.push_back((int32_t)fs.terms.size());
+        for (auto &ce : contrib[f]) {
+          const int32_t e = ce.first;
+          fs.terms.push_back(Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N,
+                                  (int32_t)P.size[e], 1});
+        }
+      }
+      if (P.later_ptr[f + 1] > P.later_ptr[f]) {
+        bs.targets.push_back({P.uoff[f], (int32_t)P.size[f]});
+        bs.ld.push_back((int32_t)N);
+        bs.t_ptr.push_back((int32_t)bs.terms.size());
+        for (int64_t a = P.later_ptr[f]; a < P.later_ptr[f + 1]; ++a) {
+          const int32_t g = P.later[a];
+          bs.terms.push_back(Term{P.panel_off[f] + P.col_off[a] * P.size[f], P.uoff[g], (int32_t)P.size[f], (int32_t)N,
+                                  (int32_t)P.size[g], 0});
+        }
+      }
+    }
+    close(fs);
+    close(bs);
+  }
+  I.dinv = Impl::Sched();
+  for (int64_t e = 0; e < M; ++e) {
+    add_target(I.dinv, P.uoff[e], (int32_t)P.size[e], (int32_t)N);
+    I.dinv.terms.push_back(Term{P.panel_off[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 0});
+  }
+  close(I.dinv);
+  // far field: stage 1 targets = (block, direction) rank x R, stage 2 = leaves
+  const HMatrix &Hs = I.hcopy;
+  const int64_t nf = Hs.n_far();
+  I.far1 = Impl::Sched();
+  I.far2 = Impl::Sched();
+  I.toff.assign(2 * nf, 0);
+  int64_t trow = 0;
+  auto leaves_in = [&](int64_t lo, int64_t hi, std::vector<int64_t> &out) {
+    out.clear();
+    int64_t g = std::upper_bound(Hs.gptr.begin(), Hs.gptr.end(), lo) - Hs.gptr.begin() - 1;
+    for (; g < Hs.M && Hs.gptr[g] < hi; ++g) out.push_back(g);
+  };
+  std::vector<std::vector<Term>> leaf_terms(M);
+  std::vector<int64_t> lv;
+  // T is one column-major matrix of t_rows x R: rows [toff, toff + r) hold
+  // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of s)
+  for (int64_t b = 0; b < nf; ++b)
+    for (int dir = 0; dir < 2; ++dir) {
+      I.toff[2 * b + dir] = trow;
+      trow += Hs.far_rank[b];
+    }
+  I.t_rows = trow;
+  const int32_t ldT = (int32_t)std::max<int64_t>(trow, 1);
+  for (int64_t b = 0; b < nf; ++b) {
+    const int64_t tlo = Hs.far_rng[4 * b], thi = Hs.far_rng[4 * b + 1];
+    const int64_t slo = Hs.far_rng[4 * b + 2], shi = Hs.far_rng[4 * b + 3];
+    const int64_t m = thi - tlo, n = shi - slo, r = Hs.far_rank[b];
+    if (r == 0) continue;
+    const int64_t uo = Hs.far_off[b], vo = Hs.far_off[b] + m * r;
+    for (int dir = 0; dir < 2; ++dir) {
+      add_target(I.far1, I.toff[2 * b + dir], (int32_t)r, ldT);
+      const int64_t clo = dir == 0 ? slo : tlo, chi = dir == 0 ? shi : thi;
+      const int64_t fo = dir == 0 ? vo : uo, fld = dir == 0 ? n : m;
+      leaves_in(clo, chi, lv);
+      for (int64_t g : lv) {
+        const int64_t e = P.pos[g];
+        I.far1.terms.push_back(Term{fo + (Hs.gptr[g] - clo), P.uoff[e], (int32_t)fld, (int32_t)N,
+                                    (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1});
+      }
+    }
+    leaves_in(tlo, thi, lv);
+    for (int64_t g : lv)
+      leaf_terms[g].push_back(Term{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0});
+    leaves_in(slo, shi, lv);
+    for (int64_t g : lv)
+      leaf_terms[g].push_back(Term{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0});
+  }
+  close(I.far1);
+  for (int64_t g = 0; g < M; ++g) {
+    add_target(I.far2, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
+    I.far2.terms.insert(I.far2.terms.end(), leaf_terms[g].begin(), leaf_terms[g].end());
+  }
+  close(I.far2);
+  // near-field matvec (both triangles of every stored near block)
+  I.nearmv = Impl::Sched();
+  std::vector<std::vector<Term>> nt(M);
+  for (int64_t b = 0; b < Hs.n_near(); ++b) {
+    const int32_t t = Hs.near_ts[2 * b], u = Hs.near_ts[2 * b + 1];
+    const int64_t mt = Hs.gptr[t + 1] - Hs.gptr[t], mu = Hs.gptr[u + 1] - Hs.gptr[u];
+    // row-major mt x mu == column-major mu x mt with ld mu
+    nt[t].push_back(Term{Hs.near_off[b], P.uoff[P.pos[u]], (int32_t)mu, (int32_t)N, (int32_t)mu, 1});
+    if (t != u) nt[u].push_back(Term{Hs.near_off[b], P.uoff[P.pos[t]], (int32_t)mu, (int32_t)N, (int32_t)mt, 0});
+  }
+  for (int64_t g = 0; g < M; ++g) {
+    add_target(I.nearmv, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
+    I.nearmv.terms.insert(I.nearmv.terms.end(), nt[g].begin(), nt[g].end());
+  }
+  close(I.nearmv);
+  I.ready = true;
+}
+
+// ------------------------------------------------------------------ solves
+namespace {
+struct Ev {
+  hipEvent_t e;
+  Ev() { HIP_CHECK(hipEventCreate(&e)); }
+  ~Ev() { (void)hipEventDestroy(e); }
+};
+float elapsed(const Ev &a, const Ev &b) {
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, a.e, b.e));
+  return ms;
+}
+}  // namespace
+
+static void check_ready(const DeviceState::Impl *I) {
+  if (!I->ready) throw Error{HPS_ESTATE, "setup has not been run"};
+}
+
+void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *pol, void *X, double *rcs,
+                                   double *ratio) {
+  Impl &I = *impl;
+  check_ready(&I);
+  HIP_CHECK(hipSetDevice(device));
+  I.ensure_R(R);
+  const int64_t N = I.N, NR = N * R;
+  std::vector<double> kp(6 * R);
+  for (int64_t r = 0; r < R; ++r)
+    for (int d = 0; d < 3; ++d) {
+      kp[6 * r + d] = khat[3 * r + d];
+      kp[6 * r + 3 + d] = pol[3 * r + d];
+    }
+  DevArray<double> dkp;
+  dkp.upload(kp, I.s);
+  Ev e0, e1, e2, e3;
+  HIP_CHECK(hipEventRecord(e0.e, I.s));
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, dkp.p, I.k,
+                     I.vB.p);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipEventRecord(e1.e, I.s));
+  I.series(R, ratio);
+  HIP_CHECK(hipEventRecord(e2.e, I.s));
+  std::vector<double> sig(R);
+  if (rcs) {
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R), dim3(256), 0, I.s, I.vB.p, I.vY.p, N, I.coef_rcs, 1, I.red.p);
+    HIP_CHECK(hipGetLastError());
+  }
+  if (X) {
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, N, R, 1);
+    HIP_CHECK(hipGetLastError());
+  }
+  HIP_CHECK(hipEventRecord(e3.e, I.s));
+  if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p, R * sizeof(double), hipMemcpyDeviceToHost, I.s));
+  HIP_CHECK(hipStreamSynchronize(I.s));
+  times.rhs_ms = elapsed(e0, e1);
+  times.sweep_ms = elapsed(e1, e2);
+  times.rcs_ms = elapsed(e2, e3);
+  times.solve_ms = elapsed(e0, e3);
+  last_solve_flops = 0.0;
+  for (double f : I.solve_flops_parts) last_solve_flops += f;
+}
+
+void DeviceState::solve_rhs(int64_t R, const void *B, void *X, double *ratio) {
+  Impl &I = *impl;
+  check_ready(&I);
+  HIP_CHECK(hipSetDevice(device));
+  I.ensure_R(R);
+  const int64_t N = I.N, NR = N * R;
+  Ev e0, e1;
+  HIP_CHECK(hipEventRecord(e0.e, I.s));
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p, N, R,
+                     0);
+  HIP_CHECK(hipGetLastError());
+  I.series(R, ratio);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, N, R, 1);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipEventRecord(e1.e, I.s));
+  HIP_CHECK(hipStreamSynchronize(I.s));
+  times.solve_ms = elapsed(e0, e1);
+}
+
+void DeviceState::excitation(int64_t R, const double *khat, const double *pol, void *B) {
+  Impl &I = *impl;
+  check_ready(&I);
+  HIP_CHECK(hipSetDevice(device));
+  I.ensure_R(R);
+  const int64_t N = I.N, NR = N * R;
+  std::vector<double> kp(6 * R);
+  for (int64_t r = 0; r < R; ++r)
+    for (int d = 0; d < 3; ++d) {
+      kp[6 * r + d] = khat[3 * r + d];
+      kp[6 * r + 3 + d] = pol[3 * r + d];
+    }
+  DevArray<double> dkp;
+  dkp.upload(kp, I.s);
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, dkp.p, I.k,
+                     I.vB.p);
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p, N, R, 1);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
+  Impl &I = *impl;
+  check_ready(&I);
+  HIP_CHECK(hipSetDevice(device));
+  I.ensure_R(R);
+  const int64_t N = I.N, NR = N * R;
+  const unsigned g = (unsigned)cdiv(NR, 256);
+  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, I.vS.p, I.dperm.p, N, R, 0);
+  HIP_CHECK(hipGetLastError());
+  I.launch(I.b_near, 0, I.near.p, I.vS.p, I.vI.p);
+  I.far_apply(I.vS.p, I.vI.p, 2);
+  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, N, R, 1);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+std::string DeviceState::stats_json() const {
+  const Impl &I = *impl;
+  std::ostringstream o;
+  o.precision(9);
+  o << "{\"N\": " << I.N << ", \"groups\": " << I.M;
+  if (I.ready) {
+    o << ", \"levels\": " << I.P.n_levels << ", \"upper_blocks\": " << I.P.n_upper_blocks
+      << ", \"n_U\": " << I.P.n_U << ", \"n_D\": " << I.P.n_D
+      << ", \"factor_bytes\": " << 16.0 * (double)I.P.panel_elems
+      << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
+  }
+  o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
+  o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"symbolic\": " << times.symbolic_ms
+    << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms
+    << ", \"rcs\": " << times.rcs_ms << "}";
+  if (I.built_R > 0) {
+    o << ", \"solve_flops\": {\"fwd\": " << I.solve_flops_parts[0] << ", \"bwd\": " << I.solve_flops_parts[1]
+      << ", \"dinv\": " << I.solve_flops_parts[2] << ", \"far\": " << I.solve_flops_parts[3]
+      << ", \"R\": " << I.built_R << "}";
+  }
+  o << "}";
+  return o.str();
+}
+
+}  // namespace hps

@@ -1,0 +1,124 @@
+// Internal host-side structures of the hps library (not part of the ABI).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hps.h"
+
+namespace hps {
+
+using cplx = std::complex<double>;
+
+struct Error {
+  hps_status code;
+  std::string msg;
+};
+
+// ---------------------------------------------------------------- mesh / RWG
+struct Mesh {
+  std::vector<double> xyz;     // nv * 3
+  std::vector<int32_t> tri;    // nt * 3
+  int64_t nv = 0, nt = 0;
+  // per triangle
+  std::vector<double> cen;     // nt * 3, (v0 + v1 + v2) / 3
+  std::vector<double> area;    // nt
+  double hmax = 0.0;           // longest edge
+  // per RWG unknown (RWG order)
+  int64_t N = 0;
+  std::vector<int32_t> edge;   // N * 2 (min, max vertex)
+  std::vector<int32_t> tp, tm; // T+, T-
+  std::vector<int32_t> vp, vm; // free vertices
+  std::vector<double> len;     // edge length
+};
+
+// Validates and builds the RWG functions; throws Error on bad meshes.
+void build_rwg(Mesh &m);
+
+// ---------------------------------------------------------------- octree
+struct TreeNode {
+  int depth;
+  int64_t ijk[3];
+  int64_t lo, hi;              // range in tree order
+  int32_t first_child = -1, n_child = 0;
+  int32_t leaf = -1;           // leaf (group) ordinal or -1
+};
+
+struct Tree {
+  std::vector<TreeNode> nodes; // depth-first preorder; children contiguous by construction
+  std::vector<int32_t> child;  // child node ids per node (first_child indexes here)
+  std::vector<int64_t> perm;   // tree position -> RWG index
+  std::vector<int32_t> leaf_node;
+};
+
+void build_tree(const Mesh &m, int leaf_max, Tree &t);
+bool cells_touch(const TreeNode &a, const TreeNode &b);
+void block_partition(const Tree &t, std::vector<std::pair<int32_t, int32_t>> &near_leaves,
+                     std::vector<std::pair<int32_t, int32_t>> &far_nodes);
+
+// ---------------------------------------------------------------- H-matrix (host copy)
+struct HMatrix {
+  int64_t N = 0, M = 0;
+  std::vector<int64_t> perm;          // tree position -> RWG
+  std::vector<int64_t> gptr;          // M + 1
+  std::vector<int32_t> near_ts;       // 2 * n_near, t <= s
+  std::vector<int64_t> near_off;      // n_near + 1
+  std::vector<cplx> near_vals;        // row-major blocks
+  std::vector<int64_t> far_rng;       // 4 * n_far
+  std::vector<int32_t> far_rank;
+  std::vector<int64_t> far_off;       // n_far + 1, U then V column-major
+  std::vector<cplx> far_uv;
+  int64_t n_near() const { return (int64_t)near_ts.size() / 2; }
+  int64_t n_far() const { return (int64_t)far_rank.size(); }
+};
+
+// EFIE entries of the Galerkin matrix (symmetric by construction).
+struct EFIE {
+  const Mesh *mesh;
+  double k, omega, h;
+  cplx cA, cPhi;
+  EFIE(const Mesh &m, double freq_hz);
+  cplx entry(int64_t m, int64_t n) const;
+  // Z[rows[i], cols[j]] into out (row-major rows x cols)
+  void block(const int64_t *rows, int64_t nr, const int64_t *cols, int64_t nc, cplx *out) const;
+};
+
+// Re-compressed ACA of one admissible block; U (m x r) and V (n x r)
+// column-major with block ~= U V^T.
+void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
+               double eps, std::vector<cplx> &U, std::vector<cplx> &V, int &rank);
+
+void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H);
+
+// Small dense complex linear algebra used by the ACA recompression.
+void householder_qr(int64_t m, int64_t n, cplx *A /* m x n col-major, in/out */,
+                    std::vector<cplx> &Q /* m x k */, std::vector<cplx> &R /* k x n */, int64_t &k);
+void jacobi_svd(int64_t n, const cplx *A /* n x n col-major */, std::vector<cplx> &W,
+                std::vector<double> &s, std::vector<cplx> &Y);  // A = W diag(s) Y^H, s descending
+
+// ---------------------------------------------------------------- symbolic plan
+struct Plan {
+  int64_t M = 0, N = 0;
+  std::vector<int32_t> order;        // elimination index -> group
+  std::vector<int32_t> pos;          // group -> elimination index
+  std::vector<int64_t> size;         // per elimination index: n_e
+  std::vector<int64_t> uoff;         // per elimination index: first unknown (elimination order)
+  std::vector<int64_t> later_ptr;    // CSR: N+(e) over elimination indices (sorted)
+  std::vector<int32_t> later;
+  std::vector<int64_t> col_off;      // per CSR entry: column offset of block (e, f) in panel e
+  std::vector<int64_t> width;        // panel width W_e = n_e + sum n_f
+  std::vector<int64_t> panel_off;    // element offset of panel e (n_e x W_e column-major)
+  int64_t panel_elems = 0;
+  std::vector<int32_t> level;        // etree level per elimination index
+  int32_t n_levels = 0;
+  std::vector<int64_t> level_ptr;    // pivots grouped by level
+  std::vector<int32_t> level_piv;
+  int64_t n_upper_blocks = 0, n_U = 0, n_D = 0;
+  double setup_flops = 0.0;          // algorithmic (8 flops per complex MAC)
+};
+
+void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, Plan &P);
+
+}  // namespace hps
