@@ -87,7 +87,8 @@ hps_status hps_create(hps_ctx **out, int device, void *stream);
 /* Release every host and device allocation of the context.  NULL is a no-op. */
 void hps_destroy(hps_ctx *ctx);
 
-/* Text of the last error on ctx (empty if none); valid until the next call. */
+/* Text of the last error on ctx (empty if none); valid until the next call.
+   With ctx = NULL: the reason the last failed hps_create on this thread failed. */
 const char *hps_last_error(const hps_ctx *ctx);
 
 /* Triangle mesh: xyz (nv x 3 doubles, metres, host), tri (nt x 3 int32 vertex

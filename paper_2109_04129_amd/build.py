@@ -39,6 +39,8 @@ def _run(cmd):
 
 def build(verbose=False):
     os.makedirs(OUT, exist_ok=True)
+    if os.path.exists(LIB):          # never leave a stale library behind a failed build
+        os.remove(LIB)
     jobs = []
     for f in HOST_SRC:
         obj = os.path.join(OUT, f + ".o")

@@ -29,6 +29,8 @@ struct hps_ctx {
 
 namespace {
 
+thread_local std::string g_create_error;
+
 hps_status fail(hps_ctx *c, hps_status s, const std::string &m) {
   if (c) c->err = m;
   return s;
@@ -99,6 +101,7 @@ hps_status hps_create(hps_ctx **out, int device, void *stream) {
       return HPS_OK;
     });
     if (st != HPS_OK) {
+      g_create_error = c->err;
       delete c;
       return st;
     }
@@ -116,7 +119,7 @@ void hps_destroy(hps_ctx *c) {
   delete c;
 }
 
-const char *hps_last_error(const hps_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *hps_last_error(const hps_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
   if (!c) return HPS_EINVAL;

@@ -46,8 +46,8 @@ __device__ __forceinline__ void cmac(c2 &acc, c2 a, c2 b) {
   acc.y = fma(a.y, b.x, acc.y);
 }
 __device__ __forceinline__ c2 cinv(c2 a) {
-  const double d = a.x * a.x + a.y * a.y;
-  return make_double2(a.x / d, -a.y / d);
+  const double r = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * r, -a.y * r);
 }
 
 // ------------------------------------------------------------------ grouped GEMM
@@ -63,174 +63,213 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
   __shared__ c2 As[TK][TM + 1];
   __shared__ c2 Bs[TK][TM + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  c2 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
-  for (int q = t.t_begin; q < t.t_end; ++q) {
-    const Term tm = terms[q];
-    for (int k0 = 0; k0 < tm.k; k0 += TK) {
-      if (!tm.trans) {
-        const int i = tid & 31, kk = tid >> 5;
-        for (int h = 0; h < 2; ++h) {
-          const int k2 = kk + 8 * h, row = t.r0 + i, kg = k0 + k2;
-          c2 v = make_double2(0.0, 0.0);
-          if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)kg * tm.lda + row];
-          As[k2][i] = v;
-        }
-      } else {
-        const int kk = tid & 15, i = tid >> 4;
-        for (int h = 0; h < 2; ++h) {
-          const int i2 = i + 16 * h, row = t.r0 + i2, kg = k0 + kk;
-          c2 v = make_double2(0.0, 0.0);
-          if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)row * tm.lda + kg];
-          As[kk][i2] = v;
-        }
-      }
-      {
-        const int kk = tid & 15, j = tid >> 4;
-        for (int h = 0; h < 2; ++h) {
-          const int j2 = j + 16 * h, col = t.c0 + j2, kg = k0 + kk;
-          c2 v = make_double2(0.0, 0.0);
-          if (col < t.n && kg < tm.k) v = B[tm.b_off + (int64_t)col * tm.ldb + kg];
-          Bs[kk][j2] = v;
-        }
-      }
-      __syncthreads();
+  // r0 < 0: the tile stands for the whole m x n block and blockIdx.y picks
+  // its 32 x 32 sub-tile (surplus y indices exit); else one explicit tile.
+  int rb = t.r0, cb = t.c0;
+  if (t.r0 < 0) {
+    const int nsc = (t.n + TM - 1) / TM, nsr = (t.m + TM - 1) / TM;
+    if ((int)blockIdx.y >= nsr * nsc) return;
+    rb = (blockIdx.y / nsc) * TM;
+    cb = (blockIdx.y % nsc) * TM;
+  } else if (blockIdx.y > 0) {
+    return;
+  }
+  {
+    const int r0 = rb, c0 = cb;
+    {
+      c2 acc[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+      for (int q = t.t_begin; q < t.t_end; ++q) {
+        const Term tm = terms[q];
+        for (int k0 = 0; k0 < tm.k; k0 += TK) {
+          if (!tm.trans) {
+            const int i = tid & 31, kk = tid >> 5;
+            for (int h = 0; h < 2; ++h) {
+              const int k2 = kk + 8 * h, row = r0 + i, kg = k0 + k2;
+              c2 v = make_double2(0.0, 0.0);
+              if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)kg * tm.lda + row];
+              As[k2][i] = v;
+            }
+          } else {
+            const int kk = tid & 15, i = tid >> 4;
+            for (int h = 0; h < 2; ++h) {
+              const int i2 = i + 16 * h, row = r0 + i2, kg = k0 + kk;
+              c2 v = make_double2(0.0, 0.0);
+              if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)row * tm.lda + kg];
+              As[kk][i2] = v;
+            }
+          }
+          {
+            const int kk = tid & 15, j = tid >> 4;
+            for (int h = 0; h < 2; ++h) {
+              const int j2 = j + 16 * h, col = c0 + j2, kg = k0 + kk;
+              c2 v = make_double2(0.0, 0.0);
+              if (col < t.n && kg < tm.k) v = B[tm.b_off + (int64_t)col * tm.ldb + kg];
+              Bs[kk][j2] = v;
+            }
+          }
+          __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < TK; ++kk) {
-        const c2 a0 = As[kk][tx], a1 = As[kk][tx + 16];
-        const c2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
-        cmac(acc[0][0], a0, b0);
-        cmac(acc[0][1], a0, b1);
-        cmac(acc[1][0], a1, b0);
-        cmac(acc[1][1], a1, b1);
+          for (int kk = 0; kk < TK; ++kk) {
+            const c2 a0 = As[kk][tx], a1 = As[kk][tx + 16];
+            const c2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+            cmac(acc[0][0], a0, b0);
+            cmac(acc[0][1], a0, b1);
+            cmac(acc[1][0], a1, b0);
+            cmac(acc[1][1], a1, b1);
+          }
+          __syncthreads();
+        }
       }
-      __syncthreads();
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          const int row = r0 + tx + 16 * a, col = c0 + ty + 16 * b;
+          if (row < t.m && col < t.n) {
+            c2 *p = C + t.c_off + (int64_t)col * t.ldc + row;
+            if (MODE == 0) {
+              *p = acc[a][b];
+            } else if (MODE == 1) {
+              c2 v = *p;
+              v.x -= acc[a][b].x;
+              v.y -= acc[a][b].y;
+              *p = v;
+            } else {
+              c2 v = *p;
+              v.x += acc[a][b].x;
+              v.y += acc[a][b].y;
+              *p = v;
+            }
+          }
+        }
     }
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int row = t.r0 + tx + 16 * a, col = t.c0 + ty + 16 * b;
-      if (row < t.m && col < t.n) {
-        c2 *p = C + t.c_off + (int64_t)col * t.ldc + row;
-        if (MODE == 0) {
-          *p = acc[a][b];
-        } else if (MODE == 1) {
-          c2 v = *p;
-          v.x -= acc[a][b].x;
-          v.y -= acc[a][b].y;
-          *p = v;
-        } else {
-          c2 v = *p;
-          v.x += acc[a][b].x;
-          v.y += acc[a][b].y;
-          *p = v;
-        }
-      }
-    }
 }
 
 // ------------------------------------------------------------------ inverse
 // Gauss-Jordan inversion with partial pivoting (row interchanges recorded,
-// not performed) of n x n blocks, n <= NC.  Thread (c, rb) holds column c,
-// rows rb*RPT .. rb*RPT+RPT-1 in registers.  Equivalent to LU with partial
-// pivoting followed by the inverse.  A zero pivot column flags the block.
+// not performed) of n x n blocks, n <= NC, one block per workgroup of 4 NC
+// threads.  Equivalent to LU with partial pivoting followed by the inverse.
+// A zero pivot column flags the block as singular.
+//
+// Tile layout: thread (rg, cg) with tid = rg + RB*cg owns rows rg*4..rg*4+3 and
+// columns cg*CT..cg*CT+CT-1 (RB = NC/4 row groups, 16 column groups, CT = NC/16).
+// One barrier per elimination step.
 template <int NC>
 __global__ __launch_bounds__(4 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
                                                     const int64_t *__restrict__ off,
                                                     const int32_t *__restrict__ nsz,
                                                     const int32_t *__restrict__ ids,
                                                     int *__restrict__ status) {
-  constexpr int RPT = NC / 4;
+  constexpr int RT = 4, RB = NC / RT, CT = NC / 16;
   const int blk = blockIdx.x;
   const int n = nsz[blk];
   const c2 *src = W + off[blk];
   c2 *dst = F + off[blk];
-  const int tid = threadIdx.x, c = tid % NC, rb = tid / NC;
-  __shared__ double cand_v[2][4];
-  __shared__ int cand_i[2][4];
-  __shared__ c2 rowbuf[2][NC];
+  const int tid = threadIdx.x, rg = tid % RB, cg = tid / RB;
+  const int lane = tid & 63;
+  const int gbase = lane - rg;          // first lane of my column group (RB divides 64)
   __shared__ c2 colbuf[2][NC];
-  __shared__ int used[NC], pivrow[NC], stepof[NC];
-  c2 a[RPT];
+  __shared__ int pbuf[2];
+  __shared__ int pivrow[NC], stepof[NC];
+  c2 a[RT][CT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int row = rb * RPT + q;
-    a[q] = (row < n && c < n) ? src[(int64_t)c * n + row] : make_double2(0.0, 0.0);
-  }
-  if (tid < NC) used[tid] = (tid < n) ? 0 : 1;
-  __syncthreads();
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int row = rg * RT + r, col = cg * CT + j;
+      a[r][j] = (row < n && col < n) ? src[(int64_t)col * n + row] : make_double2(0.0, 0.0);
+    }
+  uint32_t used = 0;
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+    if (rg * RT + r >= n) used |= 1u << r;
   bool singular = false;
   for (int k = 0; k < n; ++k) {
     const int s = k & 1;
-    if (c == k) {
+    if (cg == k / CT) {
+      const int kc = k % CT;
       double best = -1.0;
-      int bi = -1;
+      int bi = 0x7fffffff;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int row = rb * RPT + q;
-        if (row < n && !used[row]) {
-          const double m = a[q].x * a[q].x + a[q].y * a[q].y;
-          if (m > best) { best = m; bi = row; }
+      for (int r = 0; r < RT; ++r) {
+        c2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          const double w = (j == kc) ? 1.0 : 0.0;
+          v.x = fma(w, a[r][j].x, v.x);
+          v.y = fma(w, a[r][j].y, v.y);
         }
+        colbuf[s][rg * RT + r] = v;
+        const double m = v.x * v.x + v.y * v.y;
+        const bool ok = !((used >> r) & 1u) && m > best;
+        best = ok ? m : best;
+        bi = ok ? rg * RT + r : bi;
       }
-      cand_v[s][rb] = best;
-      cand_i[s][rb] = bi;
+      // reduce (max value, lowest row on ties) over the RB lanes of the group
+#pragma unroll
+      for (int w = 1; w < RB; w <<= 1) {
+        const double ob = __shfl_xor(best, w, 64);
+        const int oi = __shfl_xor(bi, w, 64);
+        const bool take = (ob > best) || (ob == best && oi < bi);
+        best = take ? ob : best;
+        bi = take ? oi : bi;
+      }
+      if (rg == 0) {
+        const int p = (best > 0.0 && bi < n) ? bi : -1;
+        pbuf[s] = p;
+        if (p >= 0) { pivrow[k] = p; stepof[p] = k; }
+      }
     }
     __syncthreads();
-    double best = -1.0;
-    int p = -1;
-    for (int r = 0; r < 4; ++r)
-      if (cand_i[s][r] >= 0 && cand_v[s][r] > best) { best = cand_v[s][r]; p = cand_i[s][r]; }
-    if (p < 0 || !(best > 0.0)) { singular = true; break; }
-    if (rb == p / RPT && c < n) {
+    const int p = pbuf[s];
+    if (p < 0) { singular = true; break; }
+    const c2 inv = cinv(colbuf[s][p]);
+    c2 m[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) m[r] = colbuf[s][rg * RT + r];
+    const int pr = p % RT, src_lane = gbase + p / RT;
+    const bool ownp = (rg == p / RT);
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
       c2 v = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == p % RPT) v = a[q];
-      rowbuf[s][c] = v;
-    }
-    if (c == k) {
+      for (int r = 0; r < RT; ++r) {
+        const double w = (r == pr) ? 1.0 : 0.0;
+        v.x = fma(w, a[r][j].x, v.x);
+        v.y = fma(w, a[r][j].y, v.y);
+      }
+      c2 rowp;
+      rowp.x = __shfl(v.x, src_lane, 64);
+      rowp.y = __shfl(v.y, src_lane, 64);
+      const c2 rp = cmul(rowp, inv);
+      const bool isk = (cg * CT + j == k);
+      const double delta = isk ? 0.0 : 1.0;
+      const c2 beta = isk ? inv : rp;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) colbuf[s][rb * RPT + q] = a[q];
-    }
-    if (tid == 0) { used[p] = 1; pivrow[k] = p; stepof[p] = k; }
-    __syncthreads();
-    const c2 inv = cinv(rowbuf[s][k]);
-    const c2 rp = (c < n && c != k) ? cmul(rowbuf[s][c], inv) : make_double2(0.0, 0.0);
-    if (c < n) {
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int row = rb * RPT + q;
-        if (row >= n) continue;
-        if (row == p) {
-          a[q] = (c == k) ? inv : cmul(a[q], inv);
-        } else {
-          const c2 m = colbuf[s][row];
-          if (c == k) {
-            const c2 t = cmul(m, inv);
-            a[q] = make_double2(-t.x, -t.y);
-          } else {
-            const c2 t = cmul(m, rp);
-            a[q].x -= t.x;
-            a[q].y -= t.y;
-          }
-        }
+      for (int r = 0; r < RT; ++r) {
+        c2 t;
+        t.x = fma(-m[r].x, beta.x, fma(m[r].y, beta.y, a[r][j].x * delta));
+        t.y = fma(-m[r].x, beta.y, fma(-m[r].y, beta.x, a[r][j].y * delta));
+        const bool isp = ownp && (r == pr);
+        a[r][j].x = isp ? beta.x : t.x;
+        a[r][j].y = isp ? beta.y : t.y;
       }
     }
+    if (ownp) used |= 1u << pr;
   }
   if (singular) {
     if (tid == 0) atomicMax(status, ids[blk] + 1);
     return;
   }
   __syncthreads();
-  if (c < n) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int row = rb * RPT + q;
-      if (row < n) dst[(int64_t)pivrow[c] * n + stepof[row]] = a[q];
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int row = rg * RT + r, col = cg * CT + j;
+      if (row < n && col < n) dst[(int64_t)pivrow[col] * n + stepof[row]] = a[r][j];
     }
-  }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -368,9 +407,10 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Host-side bounds check of a tile/term batch against the element counts of
 // the A, B and C buffers: every index a kernel can form must be in range.
-void validate(const std::vector<Tile> &tiles, const std::vector<Term> &terms, int64_t na, int64_t nb,
+void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, int64_t na, int64_t nb,
               int64_t nc, const char *what) {
-  for (const Tile &t : tiles) {
+  for (size_t it = 0; it < ntiles; ++it) {
+    const Tile &t = tiles[it];
     if (t.m <= 0 || t.n <= 0) continue;
     if (t.c_off < 0 || t.ldc < t.m || t.c_off + (int64_t)(t.n - 1) * t.ldc + (t.m - 1) >= nc ||
         t.t_begin < 0 || t.t_end > (int64_t)terms.size() || t.t_begin > t.t_end)
@@ -415,6 +455,7 @@ struct DeviceState::Impl {
   Plan P;
   DevArray<int64_t> dperm;         // elimination position -> RWG
   DevArray<c2> F;                  // factor panels
+  DevArray<c2> Wk;                 // working panels (Z~ during the setup)
   std::vector<int64_t> tree2elim;  // tree position -> elimination position
   // solve schedules (independent of R: terms; tiles rebuilt per R)
   struct Sched {
@@ -433,20 +474,38 @@ struct DeviceState::Impl {
   DevArray<c2> vT;
   DevArray<double> red;
   DevArray<int> status;
-  // cached per-R tile lists
+  // Flat tile / term arrays shared by many launches: one upload each.
+  struct Pool {
+    std::vector<Tile> tiles;
+    std::vector<Term> terms;
+    DevArray<Tile> dtiles;
+    DevArray<Term> dterms;
+    void clear() {
+      tiles.clear();
+      terms.clear();
+    }
+    void upload(hipStream_t st) {
+      dtiles.upload(tiles, st);
+      dterms.upload(terms, st);
+    }
+  };
   struct Built {
-    DevArray<Tile> tiles;
-    DevArray<Term> terms;
-    int64_t n_tiles = 0;
+    int64_t t0 = 0, n_tiles = 0;
     double flops = 0.0;
   };
+  Pool spool;                      // solve schedules for the current R
   int64_t built_R = -1;
   std::vector<Built> b_fwd, b_bwd;
   Built b_dinv, b_far1, b_far2, b_near;
   std::vector<double> solve_flops_parts;
 
-  void build(const Sched &sc, int64_t R, Built &out, int64_t na, int64_t nb, int64_t nc, const char *what) {
-    std::vector<Tile> tiles;
+  // Append the tiles of schedule sc for R right-hand sides (32 x 32 tiles
+  // over target rows and RHS columns) and its terms to pool pl.
+  void build(const Sched &sc, int64_t R, Pool &pl, Built &out, int64_t na, int64_t nb, int64_t nc,
+             const char *what) {
+    const int32_t base = (int32_t)pl.terms.size();
+    pl.terms.insert(pl.terms.end(), sc.terms.begin(), sc.terms.end());
+    out.t0 = (int64_t)pl.tiles.size();
     double fl = 0.0;
     for (size_t t = 0; t < sc.targets.size(); ++t) {
       const int64_t coff = sc.targets[t].first;
@@ -454,26 +513,28 @@ struct DeviceState::Impl {
       const int32_t tb = sc.t_ptr[t], te = sc.t_ptr[t + 1];
       for (int64_t r0 = 0; r0 < m; r0 += TM)
         for (int64_t c0 = 0; c0 < R; c0 += TM)
-          tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, tb, te});
+          pl.tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, base + tb, base + te});
       for (int32_t q = tb; q < te; ++q) fl += 8.0 * m * (double)R * sc.terms[q].k;
     }
-    validate(tiles, sc.terms, na, nb, nc, what);
-    out.tiles.upload(tiles, s);
-    out.terms.upload(sc.terms, s);
-    out.n_tiles = (int64_t)tiles.size();
+    out.n_tiles = (int64_t)pl.tiles.size() - out.t0;
     out.flops = fl;
+    validate(pl.tiles.data() + out.t0, (size_t)out.n_tiles, pl.terms, na, nb, nc, what);
   }
 
-  void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
-    if (b.n_tiles == 0) return;
-    dim3 g((unsigned)b.n_tiles), blk(256);
+  void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
+                    c2 *C, int sub = 1) {
+    if (n_tiles == 0) return;
+    dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
     if (mode == 0)
-      hipLaunchKernelGGL(k_gemm<0>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+      hipLaunchKernelGGL(k_gemm<0>, g, blk, 0, s, A, B, C, tiles, terms);
     else if (mode == 1)
-      hipLaunchKernelGGL(k_gemm<1>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+      hipLaunchKernelGGL(k_gemm<1>, g, blk, 0, s, A, B, C, tiles, terms);
     else
-      hipLaunchKernelGGL(k_gemm<2>, g, blk, 0, s, A, B, C, b.tiles.p, b.terms.p);
+      hipLaunchKernelGGL(k_gemm<2>, g, blk, 0, s, A, B, C, tiles, terms);
     HIP_CHECK(hipGetLastError());
+  }
+  void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
+    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C);
   }
 
   void ensure_R(int64_t R) {
@@ -483,15 +544,23 @@ struct DeviceState::Impl {
     b_fwd.resize(fwd.size());
     b_bwd.resize(bwd.size());
     solve_flops_parts.assign(4, 0.0);
+    spool.clear();
     const int64_t NR = N * R, nF = (int64_t)F.n, nT = std::max<int64_t>(t_rows, 1) * R;
-    for (size_t l = 0; l < fwd.size(); ++l) { build(fwd[l], R, b_fwd[l], nF, NR, NR, "forward sweep"); solve_flops_parts[0] += b_fwd[l].flops; }
-    for (size_t l = 0; l < bwd.size(); ++l) { build(bwd[l], R, b_bwd[l], nF, NR, NR, "back sweep"); solve_flops_parts[1] += b_bwd[l].flops; }
-    build(dinv, R, b_dinv, nF, NR, NR, "D^-1");
+    for (size_t l = 0; l < fwd.size(); ++l) {
+      build(fwd[l], R, spool, b_fwd[l], nF, NR, NR, "forward sweep");
+      solve_flops_parts[0] += b_fwd[l].flops;
+    }
+    for (size_t l = 0; l < bwd.size(); ++l) {
+      build(bwd[l], R, spool, b_bwd[l], nF, NR, NR, "back sweep");
+      solve_flops_parts[1] += b_bwd[l].flops;
+    }
+    build(dinv, R, spool, b_dinv, nF, NR, NR, "D^-1");
     solve_flops_parts[2] = b_dinv.flops;
-    build(far1, R, b_far1, (int64_t)faruv.n, NR, nT, "far stage 1");
-    build(far2, R, b_far2, (int64_t)faruv.n, nT, NR, "far stage 2");
+    build(far1, R, spool, b_far1, (int64_t)faruv.n, NR, nT, "far stage 1");
+    build(far2, R, spool, b_far2, (int64_t)faruv.n, nT, NR, "far stage 2");
     solve_flops_parts[3] = b_far1.flops + b_far2.flops;
-    build(nearmv, R, b_near, (int64_t)near.n, NR, NR, "near matvec");
+    build(nearmv, R, spool, b_near, (int64_t)near.n, NR, NR, "near matvec");
+    spool.upload(s);
     vB.alloc(NR); vY.alloc(NR); vW.alloc(NR); vS.alloc(NR); vI.alloc(NR); vX.alloc(NR);
     vT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
     red.alloc(2 * R + 8);
@@ -669,137 +738,163 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     return P.col_off[it - &P.later[0]];
   };
 
-  // ---- working panels and factor panels
-  DevArray<c2> Wd;
-  Wd.alloc(std::max<int64_t>(P.panel_elems, 1));
-  I.F.alloc(std::max<int64_t>(P.panel_elems, 1));
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(std::max<int64_t>(P.panel_elems, 1), 256)), dim3(256), 0, s, Wd.p,
-                     std::max<int64_t>(P.panel_elems, 1));
+  // ---- working panels and factor panels (kept across setups, grow-only)
+  const int64_t PE = std::max<int64_t>(P.panel_elems, 1);
+  I.Wk.alloc(PE);
+  I.F.alloc(PE);
+  c2 *Wd = I.Wk.p;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, Wd, PE);
   HIP_CHECK(hipGetLastError());
-  {
-    std::vector<Scatter> sc(H.n_near());
-    for (int64_t b = 0; b < H.n_near(); ++b) {
-      const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
-      const int64_t et = P.pos[t], eu = P.pos[u];
-      const int32_t mt = (int32_t)(H.gptr[t + 1] - H.gptr[t]), mu = (int32_t)(H.gptr[u + 1] - H.gptr[u]);
-      Scatter d;
-      d.src = H.near_off[b];
-      d.m = mt;
-      d.n = mu;
-      if (et <= eu) {
-        d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
-        d.ld = (int32_t)P.size[et];
-        d.trans = 0;
-      } else {
-        d.dst = P.panel_off[eu] + col_of(eu, et) * P.size[eu];
-        d.ld = (int32_t)P.size[eu];
-        d.trans = 1;
-      }
-      sc[b] = d;
+  std::vector<Scatter> sc(H.n_near());
+  for (int64_t b = 0; b < H.n_near(); ++b) {
+    const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
+    const int64_t et = P.pos[t], eu = P.pos[u];
+    Scatter d;
+    d.src = H.near_off[b];
+    d.m = (int32_t)(H.gptr[t + 1] - H.gptr[t]);
+    d.n = (int32_t)(H.gptr[u + 1] - H.gptr[u]);
+    if (et <= eu) {
+      d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
+      d.ld = (int32_t)P.size[et];
+      d.trans = 0;
+    } else {
+      d.dst = P.panel_off[eu] + col_of(eu, et) * P.size[eu];
+      d.ld = (int32_t)P.size[eu];
+      d.trans = 1;
     }
-    for (const Scatter &d : sc) {
-      const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
-      if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= P.panel_elems)
-        throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
-    }
-    DevArray<Scatter> dsc;
-    dsc.upload(sc, s);
-    if (!sc.empty()) {
-      hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd.p, dsc.p);
-      HIP_CHECK(hipGetLastError());
-    }
-    HIP_CHECK(hipStreamSynchronize(s));
+    const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
+    if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= P.panel_elems)
+      throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
+    sc[b] = d;
+  }
+  DevArray<Scatter> dsc;
+  dsc.upload(sc, s);
+  if (!sc.empty()) {
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd, dsc.p);
+    HIP_CHECK(hipGetLastError());
   }
 
-  // ---- per-level schedules
+  // ---- per-level schedules, flattened into one pool
+  const auto th0 = std::chrono::steady_clock::now();
   const int L = P.n_levels;
-  std::vector<LevelInv> inv;               // flattened: (level, class)
-  std::vector<int> inv_level;
-  struct GB { std::vector<Tile> tiles; std::vector<Term> terms; };
-  std::vector<GB> coef(L), schur(L);
+  struct InvLaunch { int nc; int64_t start, count; int level; };
+  std::vector<InvLaunch> invl;
+  std::vector<int64_t> inv_off;
+  std::vector<int32_t> inv_n, inv_id;
+  struct GemmLaunch { int64_t t0, n; int sub = 1; };
+  std::vector<GemmLaunch> coefl(L), schurl(L);
+  Impl::Pool pool;
   double flops = 0.0;
+  const int64_t n_up = P.n_upper_blocks;
+  std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
+  std::vector<Term> pair_term;
+  std::vector<std::vector<Term>> bucket;
   for (int l = 0; l < L; ++l) {
-    // inverse launches by size class
     for (int nc : {32, 64, 128}) {
-      LevelInv li;
-      li.nc = nc;
+      InvLaunch li{nc, (int64_t)inv_off.size(), 0, l};
       for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
         const int32_t e = P.level_piv[i];
         const int64_t n = P.size[e];
-        const int cls = n <= 32 ? 32 : (n <= 64 ? 64 : 128);
         if (n > 128) throw Error{HPS_EINVAL, "group larger than 128 unknowns is not supported"};
+        const int cls = n <= 32 ? 32 : (n <= 64 ? 64 : 128);
         if (cls != nc) continue;
-        li.off.push_back(P.panel_off[e]);
-        li.n.push_back((int32_t)n);
-        li.id.push_back(e);
+        if (P.panel_off[e] + n * n > P.panel_elems) throw Error{HPS_EINVAL, "internal descriptor out of range (inverse)"};
+        inv_off.push_back(P.panel_off[e]);
+        inv_n.push_back((int32_t)n);
+        inv_id.push_back(e);
       }
-      if (!li.off.empty()) {
-        inv.push_back(std::move(li));
-        inv_level.push_back(l);
-      }
+      li.count = (int64_t)inv_off.size() - li.start;
+      if (li.count) invl.push_back(li);
     }
-    // coefficient panels C_eN = D^-1 Z~_eN
-    GB &cg = coef[l];
+    // right scaling coefficients C_eN = D_e^-1 Z~_eN (eq. 16)
+    coefl[l].t0 = (int64_t)pool.tiles.size();
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
       const int32_t e = P.level_piv[i];
       const int64_t n = P.size[e], nF = P.width[e] - n;
       if (nF == 0) continue;
-      const int32_t tb = (int32_t)cg.terms.size();
-      cg.terms.push_back(Term{P.panel_off[e], P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 0});
+      const int32_t tb = (int32_t)pool.terms.size();
+      pool.terms.push_back(Term{P.panel_off[e], P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 0});
       for (int64_t r0 = 0; r0 < n; r0 += TM)
         for (int64_t c0 = 0; c0 < nF; c0 += TM)
-          cg.tiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
-                                  (int32_t)nF, tb, tb + 1});
+          pool.tiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
+                                    (int32_t)nF, tb, tb + 1});
       flops += 8.0 * n * n * nF;
     }
-    // Schur targets (j <= k) with their contributing pivots
-    std::map<std::pair<int32_t, int32_t>, std::vector<Term>> tg;
+    coefl[l].n = (int64_t)pool.tiles.size() - coefl[l].t0;
+    // Schur targets (j <= k), eq. (21): id = CSR index of (j, k), or n_up + j
+    // for (j, j).  Terms are grouped per target by a counting sort in the
+    // order of first touch; one whole-block tile per target.
+    pair_id.clear();
+    pair_term.clear();
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
       const int32_t e = P.level_piv[i];
       const int64_t n = P.size[e];
-      for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
+      for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) {
+        const int32_t j = P.later[a];
+        int64_t q = P.later_ptr[j];
         for (int64_t b = a; b < P.later_ptr[e + 1]; ++b) {
-          const int32_t j = P.later[a], kk = P.later[b];
-          tg[{j, kk}].push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
-                                     (int32_t)n, (int32_t)n, (int32_t)n, 1});
+          const int32_t kk = P.later[b];
+          int64_t id;
+          if (b == a) {
+            id = n_up + j;
+          } else {
+            while (q < P.later_ptr[j + 1] && P.later[q] < kk) ++q;
+            if (q >= P.later_ptr[j + 1] || P.later[q] != kk)
+              throw Error{HPS_EINVAL, "internal: fill pattern not closed"};
+            id = q;
+          }
+          if (slot[id] < 0) {
+            slot[id] = (int32_t)tgt.size();
+            tgt.push_back((int32_t)id);
+            tcount.push_back(0);
+            tjrow.push_back(j);
+          }
+          tcount[slot[id]]++;
+          pair_id.push_back(slot[id]);
+          pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
+                                   (int32_t)n, (int32_t)n, (int32_t)n, 1});
           flops += 8.0 * n * P.size[j] * P.size[kk];
         }
+      }
     }
-    GB &sg = schur[l];
-    for (auto &kv : tg) {
-      const int32_t j = kv.first.first, kk = kv.first.second;
-      const int64_t coff = P.panel_off[j] + col_of(j, kk) * P.size[j];
-      const int32_t tb = (int32_t)sg.terms.size();
-      sg.terms.insert(sg.terms.end(), kv.second.begin(), kv.second.end());
-      const int32_t te = (int32_t)sg.terms.size();
-      for (int64_t r0 = 0; r0 < P.size[j]; r0 += TM)
-        for (int64_t c0 = 0; c0 < P.size[kk]; c0 += TM)
-          sg.tiles.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j],
-                                  (int32_t)P.size[kk], tb, te});
+    schurl[l].t0 = (int64_t)pool.tiles.size();
+    {
+      const int32_t base = (int32_t)pool.terms.size();
+      std::vector<int32_t> start(tgt.size() + 1, 0);
+      for (size_t x = 0; x < tgt.size(); ++x) start[x + 1] = start[x] + tcount[x];
+      pool.terms.resize(base + start[tgt.size()]);
+      std::vector<int32_t> fillp(start.begin(), start.end() - 1);
+      for (size_t x = 0; x < pair_id.size(); ++x) pool.terms[base + fillp[pair_id[x]]++] = pair_term[x];
+      for (size_t x = 0; x < tgt.size(); ++x) {
+        const int64_t id = tgt[x], j = tjrow[x];
+        int64_t coff, cols;
+        if (id >= n_up) {
+          coff = P.panel_off[j];
+          cols = P.size[j];
+        } else {
+          coff = P.panel_off[j] + P.col_off[id] * P.size[j];
+          cols = P.size[P.later[id]];
+        }
+        pool.tiles.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols,
+                                  base + start[x], base + start[x + 1]});
+        schurl[l].sub = std::max<int>(schurl[l].sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
+        slot[id] = -1;
+      }
     }
+    tgt.clear();
+    tcount.clear();
+    tjrow.clear();
+    schurl[l].n = (int64_t)pool.tiles.size() - schurl[l].t0;
   }
-  for (auto &li : inv)
-    for (size_t i = 0; i < li.off.size(); ++i)
-      if (li.n[i] < 1 || li.n[i] > li.nc || li.off[i] < 0 || li.off[i] + (int64_t)li.n[i] * li.n[i] > P.panel_elems)
-        throw Error{HPS_EINVAL, "internal descriptor out of range (inverse)"};
-  for (int l = 0; l < L; ++l) {
-    validate(coef[l].tiles, coef[l].terms, P.panel_elems, P.panel_elems, P.panel_elems, "coefficients");
-    validate(schur[l].tiles, schur[l].terms, P.panel_elems, P.panel_elems, P.panel_elems, "schur");
-  }
-  for (auto &li : inv) {
-    li.d_off.upload(li.off, s);
-    li.d_n.upload(li.n, s);
-    li.d_id.upload(li.id, s);
-  }
-  std::vector<DevArray<Tile>> dct(L), dst(L);
-  std::vector<DevArray<Term>> dcm(L), dsm(L);
-  for (int l = 0; l < L; ++l) {
-    dct[l].upload(coef[l].tiles, s);
-    dcm[l].upload(coef[l].terms, s);
-    dst[l].upload(schur[l].tiles, s);
-    dsm[l].upload(schur[l].terms, s);
-  }
+  validate(pool.tiles.data(), pool.tiles.size(), pool.terms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
+  pool.upload(s);
+  DevArray<int64_t> d_inv_off;
+  DevArray<int32_t> d_inv_n, d_inv_id;
+  d_inv_off.upload(inv_off, s);
+  d_inv_n.upload(inv_n, s);
+  d_inv_id.upload(inv_id, s);
   HIP_CHECK(hipMemsetAsync(I.status.p, 0, sizeof(int), s));
+  times.inverse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
 
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
@@ -807,36 +902,26 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   HIP_CHECK(hipEventRecord(e0, s));
   size_t ii = 0;
   for (int l = 0; l < L; ++l) {
-    for (; ii < inv.size() && inv_level[ii] == l; ++ii) {
-      LevelInv &li = inv[ii];
-      const unsigned nb = (unsigned)li.off.size();
+    for (; ii < invl.size() && invl[ii].level == l; ++ii) {
+      const InvLaunch &li = invl[ii];
+      const unsigned nb = (unsigned)li.count;
+      const int64_t *po = d_inv_off.p + li.start;
+      const int32_t *pn = d_inv_n.p + li.start, *pi = d_inv_id.p + li.start;
       if (li.nc == 32)
-        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p, li.d_id.p,
-                           I.status.p);
+        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else if (li.nc == 64)
-        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(256), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p, li.d_id.p,
-                           I.status.p);
+        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else
-        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(512), 0, s, Wd.p, I.F.p, li.d_off.p, li.d_n.p,
-                           li.d_id.p, I.status.p);
+        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       HIP_CHECK(hipGetLastError());
     }
-    if (!coef[l].tiles.empty()) {
-      hipLaunchKernelGGL(k_gemm<0>, dim3((unsigned)coef[l].tiles.size()), dim3(256), 0, s, I.F.p, Wd.p, I.F.p,
-                         dct[l].p, dcm[l].p);
-      HIP_CHECK(hipGetLastError());
-    }
-    if (!schur[l].tiles.empty()) {
-      hipLaunchKernelGGL(k_gemm<1>, dim3((unsigned)schur[l].tiles.size()), dim3(256), 0, s, Wd.p, I.F.p, Wd.p,
-                         dst[l].p, dsm[l].p);
-      HIP_CHECK(hipGetLastError());
-    }
+    I.launch_tiles(pool.dtiles.p + coefl[l].t0, pool.dterms.p, coefl[l].n, 0, I.F.p, Wd, I.F.p);
+    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd, schurl[l].sub);
   }
   HIP_CHECK(hipEventRecord(e1, s));
   HIP_CHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-  times.inverse_ms = 0;
   times.schur_ms = ms;
   HIP_CHECK(hipEventDestroy(e0));
   HIP_CHECK(hipEventDestroy(e1));
@@ -852,42 +937,51 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     sc.t_ptr.push_back((int32_t)sc.terms.size());
   };
   auto close = [](Impl::Sched &sc) { sc.t_ptr.push_back((int32_t)sc.terms.size()); };
-  // contributors of each f (transpose of the pattern)
+  // Right-looking (push) sweeps: the launch of level l applies the blocks of
+  // the pivots at level l to every group they couple to, one term per pivot,
+  // so a launch has many short tiles instead of a few long ones.
+  //   forward (eq. 25), levels ascending:   b_f -= C_ef^T b_e, e at level l, f in N+(e);
+  //   back (eq. 26), levels descending:     x_e -= C_ef x_f,  f at level l, f in N+(e).
   std::vector<std::vector<std::pair<int32_t, int64_t>>> contrib(M);
   for (int64_t e = 0; e < M; ++e)
     for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
   I.fwd.assign(L, Impl::Sched());
   I.bwd.assign(L, Impl::Sched());
+  slot.assign(M, -1);
+  tgt.clear();
+  bucket.assign(M, std::vector<Term>());
+  auto flush = [&](Impl::Sched &sc) {
+    for (int32_t g : tgt) {
+      add_target(sc, P.uoff[g], (int32_t)P.size[g], (int32_t)N);
+      std::vector<Term> &bk = bucket[slot[g]];
+      sc.terms.insert(sc.terms.end(), bk.begin(), bk.end());
+      bk.clear();
+    }
+    for (int32_t g : tgt) slot[g] = -1;
+    tgt.clear();
+    close(sc);
+  };
+  auto put = [&](int32_t g, const Term &t) {
+    if (slot[g] < 0) { slot[g] = (int32_t)tgt.size(); tgt.push_back(g); }
+    bucket[slot[g]].push_back(t);
+  };
   for (int l = 0; l < L; ++l) {
-    Impl::Sched &fs = I.fwd[l];
-    Impl::Sched &bs = I.bwd[l];
-    fs.t_ptr.clear();
-    bs.t_ptr.clear();
+    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+      const int32_t e = P.level_piv[i];
+      for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
+        put(P.later[a], Term{P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N,
+                             (int32_t)P.size[e], 1});
+    }
+    flush(I.fwd[l]);
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
       const int32_t f = P.level_piv[i];
-      if (!contrib[f].empty()) {
-        fs.targets.push_back({P.uoff[f], (int32_t)P.size[f]});
-        fs.ld.push_back((int32_t)N);
-        fs.t_ptr.push_back((int32_t)fs.terms.size());
-        for (auto &ce : contrib[f]) {
-          const int32_t e = ce.first;
-          fs.terms.push_back(Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N,
-                                  (int32_t)P.size[e], 1});
-        }
-      }
-      if (P.later_ptr[f + 1] > P.later_ptr[f]) {
-        bs.targets.push_back({P.uoff[f], (int32_t)P.size[f]});
-        bs.ld.push_back((int32_t)N);
-        bs.t_ptr.push_back((int32_t)bs.terms.size());
-        for (int64_t a = P.later_ptr[f]; a < P.later_ptr[f + 1]; ++a) {
-          const int32_t g = P.later[a];
-          bs.terms.push_back(Term{P.panel_off[f] + P.col_off[a] * P.size[f], P.uoff[g], (int32_t)P.size[f], (int32_t)N,
-                                  (int32_t)P.size[g], 0});
-        }
+      for (auto &ce : contrib[f]) {
+        const int32_t e = ce.first;
+        put(e, Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[f], (int32_t)P.size[e], (int32_t)N,
+                    (int32_t)P.size[f], 0});
       }
     }
-    close(fs);
-    close(bs);
+    flush(I.bwd[l]);
   }
   I.dinv = Impl::Sched();
   for (int64_t e = 0; e < M; ++e) {
@@ -1096,7 +1190,8 @@ std::string DeviceState::stats_json() const {
       << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
-  o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"symbolic\": " << times.symbolic_ms
+  o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms
+    << ", \"symbolic\": " << times.symbolic_ms
     << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms
     << ", \"rcs\": " << times.rcs_ms << "}";
   if (I.built_R > 0) {

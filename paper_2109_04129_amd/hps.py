@@ -44,6 +44,13 @@ def lib():
     """Load libhps.so; raise if it has not been built (no fallback exists)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime (same soname as the system one).
+        # Importing it first makes libhps bind to that copy, so device
+        # pointers and streams from torch are valid in the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libhps.so is not built; run python -m paper_2109_04129_amd.build")
         L = ctypes.CDLL(LIB_PATH)
@@ -98,7 +105,7 @@ def hps_create(device=0, stream=None):
     c = ctypes.c_void_p()
     st = lib().hps_create(ctypes.byref(c), int(device), stream)
     if st < 0:
-        raise HpsError(st, "hps_create failed")
+        raise HpsError(st, "hps_create failed: " + lib().hps_last_error(None).decode())
     return c
 
 
