@@ -27,6 +27,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+# dominant kernel: the grouped complex GEMM in subtract mode (Schur updates of
+# the setup, forward and back sweeps of the solve), FP64 MFMA 16x16x4 (4M)
+DOMINANT = "gemm_sub"
+
+
+def kernel_hash():
+    """sha256 prefix of the k_gemm source, to tie the counted traffic to it."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2109_04129_amd", "csrc", "device.hip")).read()
+    a = src.index("template <int MODE>\n__global__ __launch_bounds__(256) void k_gemm(")
+    b = src.index("// ------------------------------------------------------------------", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def counted_traffic(workload):
+    """HBM bytes per k_gemm<1> launch from the committed rocprofv3 --pmc
+    summary of this workload, or None if absent or taken on other code."""
+    path = os.path.join(ROOT, "profiles", "k_gemm_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sha256_prefix"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("kernel_sha256_prefix") != kernel_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in vals else None
 
 
 def parse():
@@ -37,6 +65,8 @@ def parse():
     ap.add_argument("--workload", default="sphere_s5_790MHz")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rhs", type=int, default=8, help="RHS in the oracle's timed sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 256 MiB device copy first (scale reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -45,6 +75,12 @@ def gpu_leg(args, w):
     from paper_2109_04129_amd import hps
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)                   # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
     hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
@@ -70,6 +106,7 @@ def gpu_leg(args, w):
         step()
         print("[bench] warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    hps.hps_profile(ctx, True)          # HIP events around every kernel launch of the timed steps
     setup_t, solve_t = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -84,6 +121,35 @@ def gpu_leg(args, w):
                 ratio=ratio, stats=stats, build_s=build_s)
 
 
+def cpu_leg(args, w):
+    """The oracle, untuned, on the host cores: its own H-matrix (untimed),
+    its setup (timed) and the solve of the first --cpu-rhs RHS (timed)."""
+    from threadpoolctl import threadpool_info
+    from oracle.hmatrix import build_hmatrix
+    from oracle.planewave import excitation
+    from oracle.scaling import group_graph, min_degree_order, schur_scaling
+    from oracle.series import PowerSeries
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"], workers=workers)
+    print("[bench] oracle H-matrix built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    S = schur_scaling(H, min_degree_order(group_graph(H)))
+    setup_s = time.perf_counter() - t0
+    print("[bench] oracle setup %.1f s" % setup_s, file=sys.stderr, flush=True)
+    R = args.cpu_rhs
+    b = excitation(H.rwg, w["freq_hz"], w["khat"][:R], w["pol"][:R])
+    t0 = time.perf_counter()
+    PowerSeries(H, S).solve_rwg(b, 2)
+    solve_s = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": R / solve_s, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of the %d RHS (theta = 0..%d deg) of the same workload, two-term solve "
+                      "after the oracle's own H-matrix build (%d worker processes, untimed) and setup"
+                      % (R, len(w["khat"]), R - 1, workers),
+            "setup_s": setup_s, "host_cpus": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -96,6 +162,16 @@ def main():
     R, K = g["R"], args.steps
     ms_per_step = 1e3 * g["total"] / K
     dev = g["stats"].get("device", {})
+    k = dev.get("kernels", {}).get(DOMINANT, {})
+    achieved = k["flops"] / (k["ms"] * 1e-3) if k.get("ms") else None
+    roofline = {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": "mfma",
+                "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["fp64"] / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"] if achieved else None,
+                "traffic": counted_traffic(args.workload),
+                "algorithmic_bytes_per_launch": k["bytes"] / k["launches"] if k.get("launches") else None,
+                "launches_per_step": k.get("launches", 0) / K,
+                "avg_launch_us": 1e3 * k["ms"] / k["launches"] if k.get("launches") else None,
+                "flops_per_launch": k["flops"] / k["launches"] if k.get("launches") else None}
     out = {
         "metric": "RHS solved/sec + setup s at <=1e-3 rel err vs FP64; mixed/batched vs plain FP64",
         "value": R * K / g["total"],
@@ -107,7 +183,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 (fp64)",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": g["N"], "rhs": R, "leaf_max": w["leaf_max"],
                    "aca_tol": w["aca_tol"], "freq_hz": w["freq_hz"], "form": "plain fp64", "terms": 2},
@@ -115,6 +191,8 @@ def main():
         "solve_rhs_per_s": float(R / np.median(g["solve"])),
         "hmatrix_build_s": g["build_s"],
         "ratio_max": float(np.max(g["ratio"])),
+        "roofline": roofline,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_leg(args, w),
         "device_stats": dev,
     }
     print(json.dumps(out), flush=True)

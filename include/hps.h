@@ -174,6 +174,13 @@ hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const dou
    is installed (before or after setup). */
 hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
+/* Per-launch kernel timing: with enable != 0 every grouped-GEMM and inverse
+   launch is bracketed by HIP events on the context's stream; hps_stats then
+   reports launches, summed device ms and algorithmic flops per kernel class
+   since the call.  Counters reset on every call.  Adds two event records per
+   launch. */
+hps_status hps_profile(hps_ctx *ctx, int enable);
+
 /* JSON statistics (sizes, ranks, fill, bytes, per-stage device times of the
    last setup / solve in ms) into buf (NUL-terminated, truncated to len). */
 hps_status hps_stats(const hps_ctx *ctx, char *buf, size_t len);

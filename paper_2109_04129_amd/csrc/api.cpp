@@ -337,6 +337,15 @@ hps_status hps_hmatvec(hps_ctx *c, int64_t R, const void *X, void *Y) {
   });
 }
 
+hps_status hps_profile(hps_ctx *c, int enable) {
+  if (!c) return HPS_EINVAL;
+  if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context");
+  return guarded(c, [&]() {
+    c->dev->set_profiling(enable != 0);
+    return HPS_OK;
+  });
+}
+
 hps_status hps_stats(const hps_ctx *c, char *buf, size_t len) {
   if (!c || !buf || len == 0) return HPS_EINVAL;
   std::ostringstream o;

@@ -56,6 +56,7 @@ class DeviceState {
   void excitation(int64_t R, const double *khat, const double *pol, void *B);
   void hmatvec(int64_t R, const void *X, void *Y);
   std::string stats_json() const;
+  void set_profiling(bool on);
 
   int device;
   void *stream;     // hipStream_t

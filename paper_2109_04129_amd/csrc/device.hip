@@ -51,18 +51,23 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 }
 
 // ------------------------------------------------------------------ grouped GEMM
-// 32 x 32 output tile per workgroup of 256 threads; each thread owns rows
-// {tx, tx+16} and columns {ty, ty+16}.  K is staged through LDS in chunks of 16.
-constexpr int TM = 32, TK = 16;
+// Complex FP64 on the matrix cores: each wave owns one 16 x 16 block of a
+// 32 x 32 workgroup tile and accumulates op(A) B with V_MFMA_F64_16X16X4_F64
+// in the real 4M split (Ar Br, Ai Bi, Ar Bi, Ai Br in four independent
+// accumulators; re = rr - ii, im = ri + ir).  Operand layout of the
+// instruction: lane l supplies A[l % 16][k slot l / 16] and B[k slot
+// l / 16][l % 16]; result register r of lane l is D[l / 16 + 4 r][l % 16].
+// The contraction index is permuted so that each lane reads four
+// consecutive k (k = k0 + 4 (l / 16) + s in step s) for both operands; the
+// sum over k is unchanged.  Operands come straight from L2 (no LDS).
+constexpr int TM = 32;
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
                                               const Term *__restrict__ terms) {
   const Tile t = tiles[blockIdx.x];
-  __shared__ c2 As[TK][TM + 1];
-  __shared__ c2 Bs[TK][TM + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   // r0 < 0: the tile stands for the whole m x n block and blockIdx.y picks
   // its 32 x 32 sub-tile (surplus y indices exit); else one explicit tile.
   int rb = t.r0, cb = t.c0;
@@ -74,74 +79,57 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
   } else if (blockIdx.y > 0) {
     return;
   }
-  {
-    const int r0 = rb, c0 = cb;
-    {
-      c2 acc[2][2];
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
-      for (int q = t.t_begin; q < t.t_end; ++q) {
-        const Term tm = terms[q];
-        for (int k0 = 0; k0 < tm.k; k0 += TK) {
-          if (!tm.trans) {
-            const int i = tid & 31, kk = tid >> 5;
-            for (int h = 0; h < 2; ++h) {
-              const int k2 = kk + 8 * h, row = r0 + i, kg = k0 + k2;
-              c2 v = make_double2(0.0, 0.0);
-              if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)kg * tm.lda + row];
-              As[k2][i] = v;
-            }
-          } else {
-            const int kk = tid & 15, i = tid >> 4;
-            for (int h = 0; h < 2; ++h) {
-              const int i2 = i + 16 * h, row = r0 + i2, kg = k0 + kk;
-              c2 v = make_double2(0.0, 0.0);
-              if (row < t.m && kg < tm.k) v = A[tm.a_off + (int64_t)row * tm.lda + kg];
-              As[kk][i2] = v;
-            }
-          }
-          {
-            const int kk = tid & 15, j = tid >> 4;
-            for (int h = 0; h < 2; ++h) {
-              const int j2 = j + 16 * h, col = c0 + j2, kg = k0 + kk;
-              c2 v = make_double2(0.0, 0.0);
-              if (col < t.n && kg < tm.k) v = B[tm.b_off + (int64_t)col * tm.ldb + kg];
-              Bs[kk][j2] = v;
-            }
-          }
-          __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * (wave & 1);
+  if (row0 >= t.m || col0 >= t.n) return;            // wave-uniform
+  const int li = lane & 15, lg = lane >> 4;
+  const int arow = row0 + li, bcol = col0 + li;
+  const bool arow_ok = arow < t.m, bcol_ok = bcol < t.n;
+  d4 rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
+  for (int q = t.t_begin; q < t.t_end; ++q) {
+    const Term tm = terms[q];
+    const c2 *Ab = A + tm.a_off;
+    const c2 *Bb = B + tm.b_off + (int64_t)bcol * tm.ldb;
+    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+      c2 av[4], bv[4];
 #pragma unroll
-          for (int kk = 0; kk < TK; ++kk) {
-            const c2 a0 = As[kk][tx], a1 = As[kk][tx + 16];
-            const c2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
-            cmac(acc[0][0], a0, b0);
-            cmac(acc[0][1], a0, b1);
-            cmac(acc[1][0], a1, b0);
-            cmac(acc[1][1], a1, b1);
-          }
-          __syncthreads();
-        }
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * lg + s;
+        const bool kok = k < tm.k;
+        av[s] = make_double2(0.0, 0.0);
+        bv[s] = make_double2(0.0, 0.0);
+        if (kok && arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+        if (kok && bcol_ok) bv[s] = Bb[k];
       }
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-          const int row = r0 + tx + 16 * a, col = c0 + ty + 16 * b;
-          if (row < t.m && col < t.n) {
-            c2 *p = C + t.c_off + (int64_t)col * t.ldc + row;
-            if (MODE == 0) {
-              *p = acc[a][b];
-            } else if (MODE == 1) {
-              c2 v = *p;
-              v.x -= acc[a][b].x;
-              v.y -= acc[a][b].y;
-              *p = v;
-            } else {
-              c2 v = *p;
-              v.x += acc[a][b].x;
-              v.y += acc[a][b].y;
-              *p = v;
-            }
-          }
-        }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        rr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[s].x, rr, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[s].y, ii, 0, 0, 0);
+        ri = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[s].y, ri, 0, 0, 0);
+        ir = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[s].x, ir, 0, 0, 0);
+      }
+    }
+  }
+  const int ccol = col0 + li;
+  if (ccol >= t.n) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int crow = row0 + lg + 4 * r;
+    if (crow >= t.m) continue;
+    const c2 acc = make_double2(rr[r] - ii[r], ri[r] + ir[r]);
+    c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+    if (MODE == 0) {
+      *p = acc;
+    } else if (MODE == 1) {
+      c2 v = *p;
+      v.x -= acc.x;
+      v.y -= acc.y;
+      *p = v;
+    } else {
+      c2 v = *p;
+      v.x += acc.x;
+      v.y += acc.y;
+      *p = v;
     }
   }
 }
@@ -491,7 +479,7 @@ struct DeviceState::Impl {
   };
   struct Built {
     int64_t t0 = 0, n_tiles = 0;
-    double flops = 0.0;
+    double flops = 0.0, bytes = 0.0;   // algorithmic: each term's A and B blocks once, C read + written once
   };
   Pool spool;                      // solve schedules for the current R
   int64_t built_R = -1;
@@ -506,6 +494,7 @@ struct DeviceState::Impl {
     const int32_t base = (int32_t)pl.terms.size();
     pl.terms.insert(pl.terms.end(), sc.terms.begin(), sc.terms.end());
     out.t0 = (int64_t)pl.tiles.size();
+    out.bytes = 0.0;
     double fl = 0.0;
     for (size_t t = 0; t < sc.targets.size(); ++t) {
       const int64_t coff = sc.targets[t].first;
@@ -514,17 +503,64 @@ struct DeviceState::Impl {
       for (int64_t r0 = 0; r0 < m; r0 += TM)
         for (int64_t c0 = 0; c0 < R; c0 += TM)
           pl.tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, base + tb, base + te});
-      for (int32_t q = tb; q < te; ++q) fl += 8.0 * m * (double)R * sc.terms[q].k;
+      double by = 32.0 * m * (double)R;
+      for (int32_t q = tb; q < te; ++q) {
+        fl += 8.0 * m * (double)R * sc.terms[q].k;
+        by += 16.0 * sc.terms[q].k * ((double)m + (double)R);
+      }
+      out.bytes += by;
     }
     out.n_tiles = (int64_t)pl.tiles.size() - out.t0;
     out.flops = fl;
     validate(pl.tiles.data() + out.t0, (size_t)out.n_tiles, pl.terms, na, nb, nc, what);
   }
 
+  // ---- optional per-launch timing with HIP events on the library stream
+  // kinds: 0..2 = k_gemm<mode>, 3 = k_inverse
+  bool prof = false;
+  struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_free;
+  struct KStat { int64_t launches = 0; double ms = 0.0, flops = 0.0, bytes = 0.0; };
+  KStat kstat[4];
+  hipEvent_t ev_get() {
+    if (ev_free.empty()) {
+      hipEvent_t e;
+      HIP_CHECK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = ev_free.back();
+    ev_free.pop_back();
+    return e;
+  }
+  ProfRec *prof_begin(int kind, double flops, double bytes = 0.0) {
+    if (!prof) return nullptr;
+    prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes});
+    HIP_CHECK(hipEventRecord(prof_recs.back().a, s));
+    return &prof_recs.back();
+  }
+  void prof_end(ProfRec *r) {
+    if (r) HIP_CHECK(hipEventRecord(r->b, s));
+  }
+  void prof_collect() {     // after a stream synchronisation
+    for (ProfRec &r : prof_recs) {
+      float ms = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      kstat[r.kind].launches += 1;
+      kstat[r.kind].ms += ms;
+      kstat[r.kind].flops += r.flops;
+      kstat[r.kind].bytes += r.bytes;
+      ev_free.push_back(r.a);
+      ev_free.push_back(r.b);
+    }
+    prof_recs.clear();
+  }
+
   void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
-                    c2 *C, int sub = 1) {
+                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0) {
     if (n_tiles == 0) return;
     dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
+    ProfRec *pr = prof_begin(mode, flops, bytes);
     if (mode == 0)
       hipLaunchKernelGGL(k_gemm<0>, g, blk, 0, s, A, B, C, tiles, terms);
     else if (mode == 1)
@@ -532,9 +568,10 @@ struct DeviceState::Impl {
     else
       hipLaunchKernelGGL(k_gemm<2>, g, blk, 0, s, A, B, C, tiles, terms);
     HIP_CHECK(hipGetLastError());
+    prof_end(pr);
   }
   void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
-    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C);
+    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, 1, b.flops, b.bytes);
   }
 
   void ensure_R(int64_t R) {
@@ -777,11 +814,11 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // ---- per-level schedules, flattened into one pool
   const auto th0 = std::chrono::steady_clock::now();
   const int L = P.n_levels;
-  struct InvLaunch { int nc; int64_t start, count; int level; };
+  struct InvLaunch { int nc; int64_t start, count; int level; double flops; };
   std::vector<InvLaunch> invl;
   std::vector<int64_t> inv_off;
   std::vector<int32_t> inv_n, inv_id;
-  struct GemmLaunch { int64_t t0, n; int sub = 1; };
+  struct GemmLaunch { int64_t t0, n; int sub = 1; double flops = 0.0, bytes = 0.0; };
   std::vector<GemmLaunch> coefl(L), schurl(L);
   Impl::Pool pool;
   double flops = 0.0;
@@ -791,7 +828,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   std::vector<std::vector<Term>> bucket;
   for (int l = 0; l < L; ++l) {
     for (int nc : {32, 64, 128}) {
-      InvLaunch li{nc, (int64_t)inv_off.size(), 0, l};
+      InvLaunch li{nc, (int64_t)inv_off.size(), 0, l, 0.0};
       for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
         const int32_t e = P.level_piv[i];
         const int64_t n = P.size[e];
@@ -802,6 +839,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         inv_off.push_back(P.panel_off[e]);
         inv_n.push_back((int32_t)n);
         inv_id.push_back(e);
+        li.flops += 8.0 * n * n * n;
       }
       li.count = (int64_t)inv_off.size() - li.start;
       if (li.count) invl.push_back(li);
@@ -819,6 +857,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
           pool.tiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
                                     (int32_t)nF, tb, tb + 1});
       flops += 8.0 * n * n * nF;
+      coefl[l].flops += 8.0 * n * n * nF;
+      coefl[l].bytes += 16.0 * (n * n + 2.0 * n * nF);
     }
     coefl[l].n = (int64_t)pool.tiles.size() - coefl[l].t0;
     // Schur targets (j <= k), eq. (21): id = CSR index of (j, k), or n_up + j
@@ -854,6 +894,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
           pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
                                    (int32_t)n, (int32_t)n, (int32_t)n, 1});
           flops += 8.0 * n * P.size[j] * P.size[kk];
+          schurl[l].flops += 8.0 * n * P.size[j] * P.size[kk];
+          schurl[l].bytes += 16.0 * n * (P.size[j] + P.size[kk]);
         }
       }
     }
@@ -877,6 +919,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         }
         pool.tiles.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols,
                                   base + start[x], base + start[x + 1]});
+        schurl[l].bytes += 32.0 * P.size[j] * cols;
         schurl[l].sub = std::max<int>(schurl[l].sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
         slot[id] = -1;
       }
@@ -907,6 +950,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       const unsigned nb = (unsigned)li.count;
       const int64_t *po = d_inv_off.p + li.start;
       const int32_t *pn = d_inv_n.p + li.start, *pi = d_inv_id.p + li.start;
+      Impl::ProfRec *pr = I.prof_begin(3, li.flops);
       if (li.nc == 32)
         hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else if (li.nc == 64)
@@ -914,15 +958,19 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       else
         hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       HIP_CHECK(hipGetLastError());
+      I.prof_end(pr);
     }
-    I.launch_tiles(pool.dtiles.p + coefl[l].t0, pool.dterms.p, coefl[l].n, 0, I.F.p, Wd, I.F.p);
-    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd, schurl[l].sub);
+    I.launch_tiles(pool.dtiles.p + coefl[l].t0, pool.dterms.p, coefl[l].n, 0, I.F.p, Wd, I.F.p, 1, coefl[l].flops,
+                   coefl[l].bytes);
+    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd, schurl[l].sub,
+                   schurl[l].flops, schurl[l].bytes);
   }
   HIP_CHECK(hipEventRecord(e1, s));
   HIP_CHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
   times.schur_ms = ms;
+  I.prof_collect();
   HIP_CHECK(hipEventDestroy(e0));
   HIP_CHECK(hipEventDestroy(e1));
   int st = 0;
@@ -1113,6 +1161,7 @@ void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *
   HIP_CHECK(hipEventRecord(e3.e, I.s));
   if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p, R * sizeof(double), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
+  I.prof_collect();
   times.rhs_ms = elapsed(e0, e1);
   times.sweep_ms = elapsed(e1, e2);
   times.rcs_ms = elapsed(e2, e3);
@@ -1178,6 +1227,14 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
+void DeviceState::set_profiling(bool on) {
+  Impl &I = *impl;
+  HIP_CHECK(hipStreamSynchronize(I.s));
+  I.prof_collect();
+  I.prof = on;
+  for (auto &k : I.kstat) k = Impl::KStat();
+}
+
 std::string DeviceState::stats_json() const {
   const Impl &I = *impl;
   std::ostringstream o;
@@ -1194,6 +1251,15 @@ std::string DeviceState::stats_json() const {
     << ", \"symbolic\": " << times.symbolic_ms
     << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms
     << ", \"rcs\": " << times.rcs_ms << "}";
+  {
+    const char *names[4] = {"gemm_store", "gemm_sub", "gemm_add", "inverse"};
+    o << ", \"kernels\": {";
+    for (int k = 0; k < 4; ++k)
+      o << (k ? ", " : "") << "\"" << names[k] << "\": {\"launches\": " << I.kstat[k].launches
+        << ", \"ms\": " << I.kstat[k].ms << ", \"flops\": " << I.kstat[k].flops
+        << ", \"bytes\": " << I.kstat[k].bytes << "}";
+    o << ", \"profiling\": " << (I.prof ? 1 : 0) << "}";
+  }
   if (I.built_R > 0) {
     o << ", \"solve_flops\": {\"fwd\": " << I.solve_flops_parts[0] << ", \"bwd\": " << I.solve_flops_parts[1]
       << ", \"dinv\": " << I.solve_flops_parts[2] << ", \"far\": " << I.solve_flops_parts[3]
