@@ -64,13 +64,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere_s5_790MHz")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--cpu-rhs", type=int, default=8, help="RHS in the oracle's timed sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
     return ap.parse_args()
 
 
-def gpu_leg(args, w):
+def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
     import torch
     from paper_2109_04129_amd import hps
 
@@ -84,7 +85,8 @@ def gpu_leg(args, w):
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
     hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
-    p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2)
+    p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
+                               precision=precision, refine_passes=refine)
     t0 = time.perf_counter()
     hps.hps_build_hmatrix(ctx, p)
     build_s = time.perf_counter() - t0
@@ -116,9 +118,30 @@ def gpu_leg(args, w):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     stats = hps.hps_stats(ctx)
+    err = None
+    if reference_terms:
+        # full-size accuracy of this form against the plain FP64 path (parity-
+        # tested against the oracle) on the same H-matrix, at the matching
+        # number of series terms
+        Xm = X.cpu().numpy()
+        p.precision, p.refine_passes, p.terms = 0, 0, reference_terms
+        ref = hps.hps_create(0, stream.cuda_stream)
+        hps.hps_set_mesh(ref, w["xyz"], w["tri"])
+        g = hps.hps_get_hmatrix(ctx)
+        hps.hps_set_hmatrix(ref, p, N, g["perm"], g["group_ptr"], g["near_ts"], g["near_off"], g["near_vals"],
+                            g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
+        hps.hps_setup(ref)
+        Xr = torch.zeros_like(X)
+        _, rcs_r, _ = hps.hps_solve_planewaves(ref, khat, pol, Xr.data_ptr())
+        torch.cuda.synchronize()
+        Xr = Xr.cpu().numpy()
+        hps.hps_destroy(ref)
+        err = {"terms_of_reference": reference_terms,
+               "current_rel_err_max": float(np.max(np.linalg.norm(Xm - Xr, axis=1) / np.linalg.norm(Xr, axis=1))),
+               "rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs / rcs_r))))}
     hps.hps_destroy(ctx)
     return dict(N=N, R=R, total=total, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
-                ratio=ratio, stats=stats, build_s=build_s)
+                ratio=ratio, stats=stats, build_s=build_s, err=err)
 
 
 def cpu_leg(args, w):
@@ -159,6 +182,18 @@ def main():
     from workloads import workload
     w = workload(args.workload)
     g = gpu_leg(args, w)
+    mixed = None
+    if not args.no_mixed:
+        forms = {}
+        for prec, name in ((1, "bf16_far"), (2, "fp16_far")):
+            gm = gpu_leg(args, w, precision=prec, refine=1, reference_terms=4)
+            forms[name] = {"rhs_per_s_step": gm["R"] * args.steps / gm["total"],
+                           "setup_s": float(np.median(gm["setup"])),
+                           "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
+                           "speedup_solve_vs_plain_fp64": float(np.median(g["solve"]) / np.median(gm["solve"])),
+                           "accuracy_vs_fp64": gm["err"]}
+        mixed = {"form": "FP32 near operands on MFMA, 16-bit far factors with per-block FP32 scale, "
+                         "FP64 setup, one FP32 residual pass (= four-term series)", "variants": forms}
     R, K = g["R"], args.steps
     ms_per_step = 1e3 * g["total"] / K
     dev = g["stats"].get("device", {})
@@ -192,6 +227,7 @@ def main():
         "hmatrix_build_s": g["build_s"],
         "ratio_max": float(np.max(g["ratio"])),
         "roofline": roofline,
+        "precision_form": mixed,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_leg(args, w),
         "device_stats": dev,
     }

@@ -60,7 +60,7 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (!(p->aca_tol > 0.0 && p->aca_tol < 1.0)) return fail(c, HPS_EINVAL, "aca_tol must be in (0, 1)");
   if (p->terms < 1) return fail(c, HPS_EINVAL, "terms must be >= 1");
   if (p->refine_passes < 0) return fail(c, HPS_EINVAL, "refine_passes must be >= 0");
-  if (p->precision != 0) return fail(c, HPS_EINVAL, "precision form not available in this build");
+  if (p->precision < 0 || p->precision > 2) return fail(c, HPS_EINVAL, "precision must be 0, 1 or 2");
   if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
   return HPS_OK;
 }

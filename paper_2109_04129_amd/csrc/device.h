@@ -21,9 +21,12 @@ struct Tile {
 
 // One term op(A) B: A at a_off (column-major, lda), B at b_off (column-major,
 // ldb), contraction length k; trans = 1 uses A^T (never the conjugate).
+// sidx >= 0: A is a 16-bit far factor whose values are multiplied by
+// scales[sidx] (precision form); -1 otherwise.
 struct Term {
   int64_t a_off, b_off;
   int32_t lda, ldb, k, trans;
+  int32_t sidx = -1, pad = 0;
 };
 
 // A batch of tiles for one launch: C = alpha * sum op(A) B + beta * C with
@@ -49,6 +52,8 @@ class DeviceState {
   ~DeviceState();
   void upload(const Mesh &mesh, const HMatrix &H, const hps_params &p);
   void setup(const Plan &P, const HMatrix &H);         // throws Error
+  int precision = 0;        // 0 FP64; 1 FP32 + BF16 far; 2 FP32 + FP16 far
+  int refine = 0;           // residual-correction passes (precision form)
   // RHS in elimination order into buffer `dst` (N x R), from plane waves.
   void solve_planewaves(int64_t R, const double *khat, const double *pol, void *X, double *rcs,
                         double *ratio);

@@ -13,6 +13,7 @@
 // Every contraction goes through one grouped complex GEMM kernel driven by
 // host-built tile and term lists, so each output tile is owned by exactly one
 // workgroup and sums its terms in a fixed order (deterministic, no atomics).
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -131,6 +132,176 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
       v.y += acc.y;
       *p = v;
     }
+  }
+}
+
+// ------------------------------------------------------------------ precision form
+// Complex FP32 products on V_MFMA_F32_16X16X4_F32 (4M split, FP32
+// accumulation).  Same tile/term scheme and k permutation as k_gemm; the
+// result register r of lane l is D[4 (l / 16) + r][l % 16] for this
+// instruction.  AT selects the A operand: 0 complex FP32, 1 BF16 pairs,
+// 2 FP16 pairs (16-bit far factors, multiplied by their block scale).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int AT>
+__device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) {
+  if (AT == 0) return reinterpret_cast<const float2 *>(A)[i];
+  const uint32_t w = reinterpret_cast<const uint32_t *>(A)[i];
+  if (AT == 1) return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+  const __half2 h = *reinterpret_cast<const __half2 *>(&w);
+  return make_float2(__low2float(h), __high2float(h));
+}
+
+template <int MODE, int AT>
+__global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
+                                                float2 *__restrict__ C, const Tile *__restrict__ tiles,
+                                                const Term *__restrict__ terms, const float *__restrict__ scales) {
+  const Tile t = tiles[blockIdx.x];
+  int rb = t.r0, cb = t.c0;
+  if (t.r0 < 0) {
+    const int nsc = (t.n + TM - 1) / TM, nsr = (t.m + TM - 1) / TM;
+    if ((int)blockIdx.y >= nsr * nsc) return;
+    rb = (blockIdx.y / nsc) * TM;
+    cb = (blockIdx.y % nsc) * TM;
+  } else if (blockIdx.y > 0) {
+    return;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * (wave & 1);
+  if (row0 >= t.m || col0 >= t.n) return;
+  const int li = lane & 15, lg = lane >> 4;
+  const int arow = row0 + li, bcol = col0 + li;
+  const bool arow_ok = arow < t.m, bcol_ok = bcol < t.n;
+  f4 rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
+  for (int q = t.t_begin; q < t.t_end; ++q) {
+    const Term tm = terms[q];
+    const float sc = (AT != 0 && tm.sidx >= 0) ? scales[tm.sidx] : 1.0f;
+    const float2 *Bb = B + tm.b_off + (int64_t)bcol * tm.ldb;
+    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+      float2 av[4], bv[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * lg + s;
+        const bool kok = k < tm.k;
+        av[s] = make_float2(0.f, 0.f);
+        bv[s] = make_float2(0.f, 0.f);
+        if (kok && arow_ok) {
+          const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+          av[s] = load_a<AT>(A, idx);
+          av[s].x *= sc;
+          av[s].y *= sc;
+        }
+        if (kok && bcol_ok) bv[s] = Bb[k];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        rr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[s].x, rr, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[s].y, ii, 0, 0, 0);
+        ri = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[s].y, ri, 0, 0, 0);
+        ir = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[s].x, ir, 0, 0, 0);
+      }
+    }
+  }
+  const int ccol = col0 + li;
+  if (ccol >= t.n) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int crow = row0 + 4 * lg + r;
+    if (crow >= t.m) continue;
+    const float2 acc = make_float2(rr[r] - ii[r], ri[r] + ir[r]);
+    float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+    if (MODE == 0) {
+      *p = acc;
+    } else if (MODE == 1) {
+      float2 v = *p;
+      v.x -= acc.x;
+      v.y -= acc.y;
+      *p = v;
+    } else {
+      float2 v = *p;
+      v.x += acc.x;
+      v.y += acc.y;
+      *p = v;
+    }
+  }
+}
+
+__global__ void k_to32(const c2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+__global__ void k_to64(const float2 *__restrict__ in, c2 *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+// y = a - b  (FP32 residual)
+__global__ void k_sub32(const float2 *__restrict__ a, const float2 *__restrict__ b, float2 *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = make_float2(a[i].x - b[i].x, a[i].y - b[i].y);
+}
+// y += sgn * w  (FP32)
+__global__ void k_axpy32(float2 *__restrict__ y, const float2 *__restrict__ w, float sgn, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = make_float2(fmaf(sgn, w[i].x, y[i].x), fmaf(sgn, w[i].y, y[i].y));
+}
+// per-column sum of |v|^2 (FP32 input, FP64 accumulation)
+__global__ __launch_bounds__(256) void k_colnorm32(const float2 *__restrict__ a, int64_t N, double *__restrict__ out) {
+  const int64_t r = blockIdx.x;
+  __shared__ double sx[256];
+  double x = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) {
+    const float2 u = a[r * N + i];
+    x += (double)u.x * u.x + (double)u.y * u.y;
+  }
+  sx[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sx[threadIdx.x] += sx[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = sx[0];
+}
+
+// Far factors to 16-bit pairs with one FP32 scale per factor per block:
+// scale = largest |component|, stored values = component / scale.
+struct FarPart {
+  int64_t off, len;
+};
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+template <int AT>
+__global__ __launch_bounds__(256) void k_far16(const c2 *__restrict__ in, uint32_t *__restrict__ out,
+                                               float *__restrict__ scales, const FarPart *__restrict__ parts) {
+  const FarPart pt = parts[blockIdx.x];
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < pt.len; i += 256) {
+    const c2 v = in[pt.off + i];
+    m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double sc = sm[0] > 0.0 ? sm[0] : 1.0;
+  if (threadIdx.x == 0) scales[blockIdx.x] = (float)sc;
+  const double inv = 1.0 / sc;
+  for (int64_t i = threadIdx.x; i < pt.len; i += 256) {
+    const c2 v = in[pt.off + i];
+    const float re = (float)(v.x * inv), im = (float)(v.y * inv);
+    uint32_t w;
+    if (AT == 1) {
+      w = bf16_rne(re) | (bf16_rne(im) << 16);
+    } else {
+      const __half2 h = __floats2half2_rn(re, im);
+      w = *reinterpret_cast<const uint32_t *>(&h);
+    }
+    out[pt.off + i] = w;
   }
 }
 
@@ -604,6 +775,117 @@ struct DeviceState::Impl {
     built_R = R;
   }
 
+  // ---- precision form (FP32 solve operands, 16-bit far factors)
+  int precision = 0, refine = 0;
+  DevArray<float2> F32, near32;
+  DevArray<uint32_t> far16;
+  DevArray<float> fscale;
+  DevArray<float2> wB, wY, wW, wS, wI, wX, wT, wR, wZ;
+
+  template <int MODE>
+  void g32(const Tile *tiles, const Term *terms, int64_t n, int at, const void *A, const float2 *B, float2 *C,
+           double flops, double bytes) {
+    if (n == 0) return;
+    ProfRec *pr = prof_begin(MODE, flops, bytes);
+    dim3 g((unsigned)n), blk(256);
+    if (at == 0)
+      hipLaunchKernelGGL((k_gemm32<MODE, 0>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+    else if (at == 1)
+      hipLaunchKernelGGL((k_gemm32<MODE, 1>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+    else
+      hipLaunchKernelGGL((k_gemm32<MODE, 2>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+    HIP_CHECK(hipGetLastError());
+    prof_end(pr);
+  }
+  void launch32(const Built &b, int mode, int at, const void *A, const float2 *B, float2 *C) {
+    const Tile *t = spool.dtiles.p + b.t0;
+    if (mode == 0) g32<0>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
+    else if (mode == 1) g32<1>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
+    else g32<2>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
+  }
+  void ensure32(int64_t R) {
+    const int64_t NR = N * R;
+    wB.alloc(NR); wY.alloc(NR); wW.alloc(NR); wS.alloc(NR); wI.alloc(NR); wX.alloc(NR); wR.alloc(NR); wZ.alloc(NR);
+    wT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
+  }
+  void far32(const float2 *y, float2 *out, int mode) {
+    launch32(b_far1, 0, precision, far16.p, y, wT.p);
+    launch32(b_far2, mode, precision, far16.p, wT.p, out);
+  }
+  // out = two-term series applied to in (FP32); in is kept
+  void series32(int64_t R, const float2 *in, float2 *out, double *ratio_host) {
+    const int64_t NR = N * R;
+    const unsigned gb = (unsigned)cdiv(NR, 256);
+    HIP_CHECK(hipMemcpyAsync(wS.p, in, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
+    launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
+    hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R), dim3(256), 0, s, wI.p, N, red.p);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(out, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, out, out);
+    std::vector<double> n0(R), n1(R);
+    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    const float2 *wprev = out;
+    float2 *wa = wW.p, *wb = wX.p;
+    for (int t = 1; t < terms; ++t) {
+      far32(wprev, wS.p, 0);
+      for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
+      launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
+      hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R), dim3(256), 0, s, wI.p, N, red.p + R);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(wa, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+      for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, wa, wa);
+      hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, out, wa, (t & 1) ? -1.0f : 1.0f, NR);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + R, R * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      for (int64_t r = 0; r < R; ++r) {
+        if (t == 1 && ratio_host) ratio_host[r] = std::sqrt(n1[r]) / std::sqrt(n0[r]);
+        n0[r] = n1[r];
+      }
+      wprev = wa;
+      std::swap(wa, wb);
+    }
+    if (terms == 1 && ratio_host)
+      for (int64_t r = 0; r < R; ++r) ratio_host[r] = 0.0;
+  }
+  // out = H x with FP32 near blocks and 16-bit far factors
+  void hmatvec32(const float2 *x, float2 *out) {
+    launch32(b_near, 0, 0, near32.p, x, out);
+    far32(x, out, 2);
+  }
+  // Precision form of the solve: x = P b, then refine passes
+  // x <- x + P (b - H x); b in wB, x left in wY.
+  void solve32(int64_t R, double *ratio_host) {
+    const int64_t NR = N * R;
+    const unsigned gb = (unsigned)cdiv(NR, 256);
+    series32(R, wB.p, wY.p, ratio_host);
+    for (int it = 0; it < refine; ++it) {
+      hmatvec32(wY.p, wZ.p);
+      hipLaunchKernelGGL(k_sub32, dim3(gb), dim3(256), 0, s, wB.p, wZ.p, wR.p, NR);
+      HIP_CHECK(hipGetLastError());
+      series32(R, wR.p, wZ.p, nullptr);
+      hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, wY.p, wZ.p, 1.0f, NR);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+
+  // FP64 series (plain) or precision form; B in vB, x in vY (FP64)
+  void solve_any(int64_t R, double *ratio_host) {
+    if (precision == 0) {
+      series(R, ratio_host);
+      return;
+    }
+    const int64_t NR = N * R;
+    const unsigned gb = (unsigned)cdiv(NR, 256);
+    ensure32(R);
+    hipLaunchKernelGGL(k_to32, dim3(gb), dim3(256), 0, s, vB.p, wB.p, NR);
+    HIP_CHECK(hipGetLastError());
+    solve32(R, ratio_host);
+    hipLaunchKernelGGL(k_to64, dim3(gb), dim3(256), 0, s, wY.p, vY.p, NR);
+    HIP_CHECK(hipGetLastError());
+  }
+
   void sweep_fwd(c2 *v) {
     for (size_t l = 0; l < b_fwd.size(); ++l) launch(b_fwd[l], 1, F.p, v, v);
   }
@@ -692,6 +974,10 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   I.coef_rcs = I.k * I.k * eta * eta / (4.0 * pi);
   I.terms = std::max(1, p.terms);
   terms = I.terms;
+  I.precision = p.precision;
+  I.refine = std::max(0, p.refine_passes);
+  precision = I.precision;
+  refine = I.refine;
   I.ratio_warn = p.ratio_warn;
   I.mem_cap = p.device_mem_cap;
   const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * 7 * 8;
@@ -978,6 +1264,39 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   if (st > 0) throw Error{HPS_ESINGULAR, "singular scaled diagonal block of group " + std::to_string(P.order[st - 1])};
   I.P.setup_flops = flops;
 
+  // ---- precision form: FP32 copies of the factor panels and near blocks,
+  // far factors to 16-bit pairs with one FP32 scale per factor per block
+  if (I.precision > 0) {
+    I.F32.alloc(PE);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PE);
+    HIP_CHECK(hipGetLastError());
+    const int64_t nn = std::max<int64_t>((int64_t)I.near.n, 1);
+    I.near32.alloc(nn);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, s, I.near.p, I.near32.p, (int64_t)I.near.n);
+    HIP_CHECK(hipGetLastError());
+    const HMatrix &Hf = I.hcopy;
+    std::vector<FarPart> parts(2 * Hf.n_far());
+    for (int64_t b = 0; b < Hf.n_far(); ++b) {
+      const int64_t m = Hf.far_rng[4 * b + 1] - Hf.far_rng[4 * b], n = Hf.far_rng[4 * b + 3] - Hf.far_rng[4 * b + 2];
+      const int64_t r = Hf.far_rank[b];
+      parts[2 * b] = FarPart{Hf.far_off[b], m * r};
+      parts[2 * b + 1] = FarPart{Hf.far_off[b] + m * r, n * r};
+      if (Hf.far_off[b] + (m + n) * r > (int64_t)I.faruv.n) throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
+    }
+    I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
+    I.fscale.alloc(std::max<size_t>(parts.size(), 1));
+    if (!parts.empty()) {
+      DevArray<FarPart> dparts;
+      dparts.upload(parts, s);
+      if (I.precision == 1)
+        hipLaunchKernelGGL(k_far16<1>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
+      else
+        hipLaunchKernelGGL(k_far16<2>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+  }
+
   // ---- solve schedules (terms independent of R)
   auto add_target = [](Impl::Sched &sc, int64_t coff, int32_t m, int32_t ld) {
     sc.targets.push_back({coff, m});
@@ -1073,16 +1392,23 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       leaves_in(clo, chi, lv);
       for (int64_t g : lv) {
         const int64_t e = P.pos[g];
-        I.far1.terms.push_back(Term{fo + (Hs.gptr[g] - clo), P.uoff[e], (int32_t)fld, (int32_t)N,
-                                    (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1});
+        Term tmv{fo + (Hs.gptr[g] - clo), P.uoff[e], (int32_t)fld, (int32_t)N, (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
+        tmv.sidx = (int32_t)(2 * b + (dir == 0 ? 1 : 0));
+        I.far1.terms.push_back(tmv);
       }
     }
     leaves_in(tlo, thi, lv);
-    for (int64_t g : lv)
-      leaf_terms[g].push_back(Term{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0});
+    for (int64_t g : lv) {
+      Term tmu{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0};
+      tmu.sidx = (int32_t)(2 * b);
+      leaf_terms[g].push_back(tmu);
+    }
     leaves_in(slo, shi, lv);
-    for (int64_t g : lv)
-      leaf_terms[g].push_back(Term{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0});
+    for (int64_t g : lv) {
+      Term tmv{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0};
+      tmv.sidx = (int32_t)(2 * b + 1);
+      leaf_terms[g].push_back(tmv);
+    }
   }
   close(I.far1);
   for (int64_t g = 0; g < M; ++g) {
@@ -1147,9 +1473,8 @@ void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *
                      I.vB.p);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventRecord(e1.e, I.s));
-  I.series(R, ratio);
+  I.solve_any(R, ratio);
   HIP_CHECK(hipEventRecord(e2.e, I.s));
-  std::vector<double> sig(R);
   if (rcs) {
     hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R), dim3(256), 0, I.s, I.vB.p, I.vY.p, N, I.coef_rcs, 1, I.red.p);
     HIP_CHECK(hipGetLastError());
@@ -1181,7 +1506,7 @@ void DeviceState::solve_rhs(int64_t R, const void *B, void *X, double *ratio) {
   hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p, N, R,
                      0);
   HIP_CHECK(hipGetLastError());
-  I.series(R, ratio);
+  I.solve_any(R, ratio);
   hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventRecord(e1.e, I.s));
@@ -1220,8 +1545,16 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   const unsigned g = (unsigned)cdiv(NR, 256);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, I.vS.p, I.dperm.p, N, R, 0);
   HIP_CHECK(hipGetLastError());
-  I.launch(I.b_near, 0, I.near.p, I.vS.p, I.vI.p);
-  I.far_apply(I.vS.p, I.vI.p, 2);
+  if (I.precision == 0) {
+    I.launch(I.b_near, 0, I.near.p, I.vS.p, I.vI.p);
+    I.far_apply(I.vS.p, I.vI.p, 2);
+  } else {                                  // FP32 near blocks, 16-bit far factors
+    I.ensure32(R);
+    hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, I.s, I.vS.p, I.wS.p, NR);
+    I.hmatvec32(I.wS.p, I.wI.p);
+    hipLaunchKernelGGL(k_to64, dim3(g), dim3(256), 0, I.s, I.wI.p, I.vI.p, NR);
+    HIP_CHECK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(I.s));

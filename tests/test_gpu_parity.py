@@ -159,3 +159,35 @@ def test_singular_block_reported(small):
         assert ei.value.status == -4
     finally:
         hps.hps_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision,refine,bar", [(2, 0, 1e-3), (2, 1, 1e-3), (1, 0, 5e-3), (1, 1, 5e-3)])
+def test_precision_form(c0_workload, c0_hmatrix, precision, refine, bar):
+    """Precision form (FP32 solve on MFMA, 16-bit far factors with per-block
+    FP32 scale, optional FP32 residual pass) against the FP64 oracle at the
+    matching number of terms: one residual pass with the two-term operator P
+    gives x + P(b - Hx) = (I - K + K^2 - K^3) Z_N^-1 b, the four-term series.
+    FP16 far factors meet 1e-3 / 0.1 dB; BF16 (unit roundoff 2^-9) reaches
+    about 2.5e-3 on the currents, so its current bar is 5e-3."""
+    w, H = c0_workload, c0_hmatrix
+    print("case: sphere 1,920, precision %d, refine %d" % (precision, refine), flush=True)
+    khat, pol = monostatic_angles(np.linspace(0.0, 180.0, 7), np.zeros(7))
+    ctx = _ctx()
+    try:
+        hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=64, aca_tol=1e-3, terms=2, ordering=1,
+                                   precision=precision, refine_passes=refine)
+        a = hmatrix_arrays(H)
+        hps.hps_set_hmatrix(ctx, p, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
+                            a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(ctx)
+        st, X, rcs, ratio = _solve(ctx, H.N, khat, pol)
+    finally:
+        hps.hps_destroy(ctx)
+    x, ratios, sig = _oracle(H, w["freq_hz"], khat, pol, 4 if refine else 2, order="natural")
+    err = per_rhs_rel(X, x).max()
+    db = np.max(np.abs(10 * np.log10(rcs / sig)))
+    print("precision %d refine %d: max rel current err %.3e, max RCS err %.4f dB" % (precision, refine, err, db))
+    assert err < bar
+    assert db < 0.1
+    assert np.allclose(ratio, ratios[0], rtol=1e-2)
