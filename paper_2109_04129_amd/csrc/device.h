@@ -69,6 +69,7 @@ class DeviceState {
   StageTimes times;
   int terms = 2;
   double last_solve_flops = 0.0;
+  double sched_split[5] = {0, 0, 0, 0, 0};
 
   struct Impl;
   std::unique_ptr<Impl> impl;

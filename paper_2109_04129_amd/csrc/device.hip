@@ -22,6 +22,8 @@
 #include <cstring>
 #include <map>
 #include <sstream>
+#include <atomic>
+#include <thread>
 
 #include "device.h"
 
@@ -62,75 +64,107 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // consecutive k (k = k0 + 4 (l / 16) + s in step s) for both operands; the
 // sum over k is unchanged.  Operands come straight from L2 (no LDS).
 constexpr int TM = 32;
+constexpr int NB_SOLVE = 1, TN_SOLVE = 32 * NB_SOLVE;   // solve tiles: 32 rows x 32 RHS
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int MODE>
+template <int MODE, int NB>
 __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
                                               const Term *__restrict__ terms) {
+  // workgroup tile: 32 rows x (32 NB) columns; wave w owns rows 16 (w / 2)
+  // and NB column blocks of 16 starting at 16 NB (w % 2)
+  constexpr int TN = 32 * NB;
   const Tile t = tiles[blockIdx.x];
   // r0 < 0: the tile stands for the whole m x n block and blockIdx.y picks
-  // its 32 x 32 sub-tile (surplus y indices exit); else one explicit tile.
+  // its sub-tile (surplus y indices exit); else one explicit tile.
   int rb = t.r0, cb = t.c0;
   if (t.r0 < 0) {
-    const int nsc = (t.n + TM - 1) / TM, nsr = (t.m + TM - 1) / TM;
+    const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
     if ((int)blockIdx.y >= nsr * nsc) return;
     rb = (blockIdx.y / nsc) * TM;
-    cb = (blockIdx.y % nsc) * TM;
+    cb = (blockIdx.y % nsc) * TN;
   } else if (blockIdx.y > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * (wave & 1);
+  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
   if (row0 >= t.m || col0 >= t.n) return;            // wave-uniform
   const int li = lane & 15, lg = lane >> 4;
-  const int arow = row0 + li, bcol = col0 + li;
-  const bool arow_ok = arow < t.m, bcol_ok = bcol < t.n;
-  d4 rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
+  const int arow = row0 + li;
+  const bool arow_ok = arow < t.m;
+  d4 rr[NB], ii[NB], ri[NB], ir[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = d4{0.0, 0.0, 0.0, 0.0};
   for (int q = t.t_begin; q < t.t_end; ++q) {
     const Term tm = terms[q];
     const c2 *Ab = A + tm.a_off;
-    const c2 *Bb = B + tm.b_off + (int64_t)bcol * tm.ldb;
-    for (int k0 = 0; k0 < tm.k; k0 += 16) {
-      c2 av[4], bv[4];
+    // full chunks of 16: lane group g reads k = k0 + 4 g + s (four consecutive)
+    const int kfull = tm.k & ~15;
+    for (int k0 = 0; k0 < kfull; k0 += 16) {
+      c2 av[4], bv[NB][4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = k0 + 4 * lg + s;
-        const bool kok = k < tm.k;
         av[s] = make_double2(0.0, 0.0);
-        bv[s] = make_double2(0.0, 0.0);
-        if (kok && arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
-        if (kok && bcol_ok) bv[s] = Bb[k];
+        if (arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int bcol = col0 + 16 * j + li;
+          bv[j][s] = make_double2(0.0, 0.0);
+          if (bcol < t.n) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        }
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        rr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[s].x, rr, 0, 0, 0);
-        ii = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[s].y, ii, 0, 0, 0);
-        ri = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[s].y, ri, 0, 0, 0);
-        ir = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[s].x, ir, 0, 0, 0);
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
+          ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
+          ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
+          ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+        }
+    }
+    // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
+    for (int kt = kfull; kt < tm.k; kt += 4) {
+      const int k = kt + lg;
+      const bool kok = k < tm.k;
+      c2 av = make_double2(0.0, 0.0);
+      if (kok && arow_ok) av = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int bcol = col0 + 16 * j + li;
+        c2 bv = make_double2(0.0, 0.0);
+        if (kok && bcol < t.n) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
+        ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
+        ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ri[j], 0, 0, 0);
+        ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, ir[j], 0, 0, 0);
       }
     }
   }
-  const int ccol = col0 + li;
-  if (ccol >= t.n) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int crow = row0 + lg + 4 * r;
-    if (crow >= t.m) continue;
-    const c2 acc = make_double2(rr[r] - ii[r], ri[r] + ir[r]);
-    c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
-    if (MODE == 0) {
-      *p = acc;
-    } else if (MODE == 1) {
-      c2 v = *p;
-      v.x -= acc.x;
-      v.y -= acc.y;
-      *p = v;
-    } else {
-      c2 v = *p;
-      v.x += acc.x;
-      v.y += acc.y;
-      *p = v;
+  for (int j = 0; j < NB; ++j) {
+    const int ccol = col0 + 16 * j + li;
+    if (ccol >= t.n) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int crow = row0 + lg + 4 * r;
+      if (crow >= t.m) continue;
+      const c2 acc = make_double2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
+      c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+      if (MODE == 0) {
+        *p = acc;
+      } else if (MODE == 1) {
+        c2 v = *p;
+        v.x -= acc.x;
+        v.y -= acc.y;
+        *p = v;
+      } else {
+        c2 v = *p;
+        v.x += acc.x;
+        v.y += acc.y;
+        *p = v;
+      }
     }
   }
 }
@@ -152,76 +186,108 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
   return make_float2(__low2float(h), __high2float(h));
 }
 
-template <int MODE, int AT>
+template <int MODE, int AT, int NB>
 __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
                                                 const Term *__restrict__ terms, const float *__restrict__ scales) {
+  constexpr int TN = 32 * NB;
   const Tile t = tiles[blockIdx.x];
   int rb = t.r0, cb = t.c0;
   if (t.r0 < 0) {
-    const int nsc = (t.n + TM - 1) / TM, nsr = (t.m + TM - 1) / TM;
+    const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
     if ((int)blockIdx.y >= nsr * nsc) return;
     rb = (blockIdx.y / nsc) * TM;
-    cb = (blockIdx.y % nsc) * TM;
+    cb = (blockIdx.y % nsc) * TN;
   } else if (blockIdx.y > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * (wave & 1);
+  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
   if (row0 >= t.m || col0 >= t.n) return;
   const int li = lane & 15, lg = lane >> 4;
-  const int arow = row0 + li, bcol = col0 + li;
-  const bool arow_ok = arow < t.m, bcol_ok = bcol < t.n;
-  f4 rr = {0.f, 0.f, 0.f, 0.f}, ii = rr, ri = rr, ir = rr;
+  const int arow = row0 + li;
+  const bool arow_ok = arow < t.m;
+  f4 rr[NB], ii[NB], ri[NB], ir[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int q = t.t_begin; q < t.t_end; ++q) {
     const Term tm = terms[q];
     const float sc = (AT != 0 && tm.sidx >= 0) ? scales[tm.sidx] : 1.0f;
-    const float2 *Bb = B + tm.b_off + (int64_t)bcol * tm.ldb;
-    for (int k0 = 0; k0 < tm.k; k0 += 16) {
-      float2 av[4], bv[4];
+    const int kfull = tm.k & ~15;
+    for (int k0 = 0; k0 < kfull; k0 += 16) {
+      float2 av[4], bv[NB][4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = k0 + 4 * lg + s;
-        const bool kok = k < tm.k;
         av[s] = make_float2(0.f, 0.f);
-        bv[s] = make_float2(0.f, 0.f);
-        if (kok && arow_ok) {
+        if (arow_ok) {
           const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
           av[s] = load_a<AT>(A, idx);
           av[s].x *= sc;
           av[s].y *= sc;
         }
-        if (kok && bcol_ok) bv[s] = Bb[k];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int bcol = col0 + 16 * j + li;
+          bv[j][s] = make_float2(0.f, 0.f);
+          if (bcol < t.n) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        }
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        rr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[s].x, rr, 0, 0, 0);
-        ii = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[s].y, ii, 0, 0, 0);
-        ri = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[s].y, ri, 0, 0, 0);
-        ir = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[s].x, ir, 0, 0, 0);
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
+          ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
+          ri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
+          ir[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+        }
+    }
+    for (int kt = kfull; kt < tm.k; kt += 4) {
+      const int k = kt + lg;
+      const bool kok = k < tm.k;
+      float2 av = make_float2(0.f, 0.f);
+      if (kok && arow_ok) {
+        const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+        av = load_a<AT>(A, idx);
+        av.x *= sc;
+        av.y *= sc;
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int bcol = col0 + 16 * j + li;
+        float2 bv = make_float2(0.f, 0.f);
+        if (kok && bcol < t.n) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, rr[j], 0, 0, 0);
+        ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, ii[j], 0, 0, 0);
+        ri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, ri[j], 0, 0, 0);
+        ir[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.x, ir[j], 0, 0, 0);
       }
     }
   }
-  const int ccol = col0 + li;
-  if (ccol >= t.n) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int crow = row0 + 4 * lg + r;
-    if (crow >= t.m) continue;
-    const float2 acc = make_float2(rr[r] - ii[r], ri[r] + ir[r]);
-    float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
-    if (MODE == 0) {
-      *p = acc;
-    } else if (MODE == 1) {
-      float2 v = *p;
-      v.x -= acc.x;
-      v.y -= acc.y;
-      *p = v;
-    } else {
-      float2 v = *p;
-      v.x += acc.x;
-      v.y += acc.y;
-      *p = v;
+  for (int j = 0; j < NB; ++j) {
+    const int ccol = col0 + 16 * j + li;
+    if (ccol >= t.n) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int crow = row0 + 4 * lg + r;
+      if (crow >= t.m) continue;
+      const float2 acc = make_float2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
+      float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+      if (MODE == 0) {
+        *p = acc;
+      } else if (MODE == 1) {
+        float2 v = *p;
+        v.x -= acc.x;
+        v.y -= acc.y;
+        *p = v;
+      } else {
+        float2 v = *p;
+        v.x += acc.x;
+        v.y += acc.y;
+        *p = v;
+      }
     }
   }
 }
@@ -672,7 +738,7 @@ struct DeviceState::Impl {
       const int32_t m = sc.targets[t].second;
       const int32_t tb = sc.t_ptr[t], te = sc.t_ptr[t + 1];
       for (int64_t r0 = 0; r0 < m; r0 += TM)
-        for (int64_t c0 = 0; c0 < R; c0 += TM)
+        for (int64_t c0 = 0; c0 < R; c0 += TN_SOLVE)
           pl.tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, base + tb, base + te});
       double by = 32.0 * m * (double)R;
       for (int32_t q = tb; q < te; ++q) {
@@ -728,21 +794,30 @@ struct DeviceState::Impl {
   }
 
   void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
-                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0) {
+                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false) {
     if (n_tiles == 0) return;
     dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
     ProfRec *pr = prof_begin(mode, flops, bytes);
-    if (mode == 0)
-      hipLaunchKernelGGL(k_gemm<0>, g, blk, 0, s, A, B, C, tiles, terms);
-    else if (mode == 1)
-      hipLaunchKernelGGL(k_gemm<1>, g, blk, 0, s, A, B, C, tiles, terms);
-    else
-      hipLaunchKernelGGL(k_gemm<2>, g, blk, 0, s, A, B, C, tiles, terms);
+    if (wide) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+      else if (mode == 1)
+        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+      else
+        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+    } else {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+      else if (mode == 1)
+        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+      else
+        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+    }
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
   void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
-    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, 1, b.flops, b.bytes);
+    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, 1, b.flops, b.bytes, true);
   }
 
   void ensure_R(int64_t R) {
@@ -789,11 +864,11 @@ struct DeviceState::Impl {
     ProfRec *pr = prof_begin(MODE, flops, bytes);
     dim3 g((unsigned)n), blk(256);
     if (at == 0)
-      hipLaunchKernelGGL((k_gemm32<MODE, 0>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
     else if (at == 1)
-      hipLaunchKernelGGL((k_gemm32<MODE, 1>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
     else
-      hipLaunchKernelGGL((k_gemm32<MODE, 2>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
@@ -1097,56 +1172,53 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     HIP_CHECK(hipGetLastError());
   }
 
-  // ---- per-level schedules, flattened into one pool
+  // ---- per-level schedules: built per level on host threads (levels are
+  // independent), then concatenated in level order into one pool
   const auto th0 = std::chrono::steady_clock::now();
   const int L = P.n_levels;
   struct InvLaunch { int nc; int64_t start, count; int level; double flops; };
-  std::vector<InvLaunch> invl;
-  std::vector<int64_t> inv_off;
-  std::vector<int32_t> inv_n, inv_id;
   struct GemmLaunch { int64_t t0, n; int sub = 1; double flops = 0.0, bytes = 0.0; };
-  std::vector<GemmLaunch> coefl(L), schurl(L);
-  Impl::Pool pool;
-  double flops = 0.0;
+  struct LevelOut {
+    std::vector<int64_t> inv_off[3];
+    std::vector<int32_t> inv_n[3], inv_id[3];
+    double inv_flops[3] = {0, 0, 0};
+    std::vector<Tile> ctiles, stiles;
+    std::vector<Term> cterms, sterms;
+    GemmLaunch coef, schur;
+    double flops = 0.0;
+    std::string err;
+  };
+  std::vector<LevelOut> lv_out(L);
   const int64_t n_up = P.n_upper_blocks;
-  std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
-  std::vector<Term> pair_term;
-  std::vector<std::vector<Term>> bucket;
-  for (int l = 0; l < L; ++l) {
-    for (int nc : {32, 64, 128}) {
-      InvLaunch li{nc, (int64_t)inv_off.size(), 0, l, 0.0};
-      for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
-        const int32_t e = P.level_piv[i];
-        const int64_t n = P.size[e];
-        if (n > 128) throw Error{HPS_EINVAL, "group larger than 128 unknowns is not supported"};
-        const int cls = n <= 32 ? 32 : (n <= 64 ? 64 : 128);
-        if (cls != nc) continue;
-        if (P.panel_off[e] + n * n > P.panel_elems) throw Error{HPS_EINVAL, "internal descriptor out of range (inverse)"};
-        inv_off.push_back(P.panel_off[e]);
-        inv_n.push_back((int32_t)n);
-        inv_id.push_back(e);
-        li.flops += 8.0 * n * n * n;
-      }
-      li.count = (int64_t)inv_off.size() - li.start;
-      if (li.count) invl.push_back(li);
+  auto build_level = [&](int l, std::vector<int32_t> &slot, std::vector<int32_t> &tgt, std::vector<int32_t> &tcount,
+                         std::vector<int32_t> &tjrow, std::vector<int32_t> &pair_id, std::vector<Term> &pair_term) {
+    LevelOut &o = lv_out[l];
+    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+      const int32_t e = P.level_piv[i];
+      const int64_t n = P.size[e];
+      if (n > 128) throw Error{HPS_EINVAL, "group larger than 128 unknowns is not supported"};
+      const int cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+      if (P.panel_off[e] + n * n > P.panel_elems) throw Error{HPS_EINVAL, "internal descriptor out of range (inverse)"};
+      o.inv_off[cls].push_back(P.panel_off[e]);
+      o.inv_n[cls].push_back((int32_t)n);
+      o.inv_id[cls].push_back(e);
+      o.inv_flops[cls] += 8.0 * n * n * n;
     }
     // right scaling coefficients C_eN = D_e^-1 Z~_eN (eq. 16)
-    coefl[l].t0 = (int64_t)pool.tiles.size();
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
       const int32_t e = P.level_piv[i];
       const int64_t n = P.size[e], nF = P.width[e] - n;
       if (nF == 0) continue;
-      const int32_t tb = (int32_t)pool.terms.size();
-      pool.terms.push_back(Term{P.panel_off[e], P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 0});
+      const int32_t tb = (int32_t)o.cterms.size();
+      o.cterms.push_back(Term{P.panel_off[e], P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 0});
       for (int64_t r0 = 0; r0 < n; r0 += TM)
         for (int64_t c0 = 0; c0 < nF; c0 += TM)
-          pool.tiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
-                                    (int32_t)nF, tb, tb + 1});
-      flops += 8.0 * n * n * nF;
-      coefl[l].flops += 8.0 * n * n * nF;
-      coefl[l].bytes += 16.0 * (n * n + 2.0 * n * nF);
+          o.ctiles.push_back(Tile{P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
+                                  (int32_t)nF, tb, tb + 1});
+      o.flops += 8.0 * n * n * nF;
+      o.coef.flops += 8.0 * n * n * nF;
+      o.coef.bytes += 16.0 * (n * n + 2.0 * n * nF);
     }
-    coefl[l].n = (int64_t)pool.tiles.size() - coefl[l].t0;
     // Schur targets (j <= k), eq. (21): id = CSR index of (j, k), or n_up + j
     // for (j, j).  Terms are grouped per target by a counting sort in the
     // order of first touch; one whole-block tile per target.
@@ -1179,44 +1251,116 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
           pair_id.push_back(slot[id]);
           pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
                                    (int32_t)n, (int32_t)n, (int32_t)n, 1});
-          flops += 8.0 * n * P.size[j] * P.size[kk];
-          schurl[l].flops += 8.0 * n * P.size[j] * P.size[kk];
-          schurl[l].bytes += 16.0 * n * (P.size[j] + P.size[kk]);
+          const double f = 8.0 * n * P.size[j] * P.size[kk];
+          o.flops += f;
+          o.schur.flops += f;
+          o.schur.bytes += 16.0 * n * (P.size[j] + P.size[kk]);
         }
       }
     }
-    schurl[l].t0 = (int64_t)pool.tiles.size();
-    {
-      const int32_t base = (int32_t)pool.terms.size();
-      std::vector<int32_t> start(tgt.size() + 1, 0);
-      for (size_t x = 0; x < tgt.size(); ++x) start[x + 1] = start[x] + tcount[x];
-      pool.terms.resize(base + start[tgt.size()]);
-      std::vector<int32_t> fillp(start.begin(), start.end() - 1);
-      for (size_t x = 0; x < pair_id.size(); ++x) pool.terms[base + fillp[pair_id[x]]++] = pair_term[x];
-      for (size_t x = 0; x < tgt.size(); ++x) {
-        const int64_t id = tgt[x], j = tjrow[x];
-        int64_t coff, cols;
-        if (id >= n_up) {
-          coff = P.panel_off[j];
-          cols = P.size[j];
-        } else {
-          coff = P.panel_off[j] + P.col_off[id] * P.size[j];
-          cols = P.size[P.later[id]];
-        }
-        pool.tiles.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols,
-                                  base + start[x], base + start[x + 1]});
-        schurl[l].bytes += 32.0 * P.size[j] * cols;
-        schurl[l].sub = std::max<int>(schurl[l].sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
-        slot[id] = -1;
+    std::vector<int32_t> start(tgt.size() + 1, 0);
+    for (size_t x = 0; x < tgt.size(); ++x) start[x + 1] = start[x] + tcount[x];
+    o.sterms.resize(start[tgt.size()]);
+    std::vector<int32_t> fillp(start.begin(), start.end() - 1);
+    for (size_t x = 0; x < pair_id.size(); ++x) o.sterms[fillp[pair_id[x]]++] = pair_term[x];
+    for (size_t x = 0; x < tgt.size(); ++x) {
+      const int64_t id = tgt[x], j = tjrow[x];
+      int64_t coff, cols;
+      if (id >= n_up) {
+        coff = P.panel_off[j];
+        cols = P.size[j];
+      } else {
+        coff = P.panel_off[j] + P.col_off[id] * P.size[j];
+        cols = P.size[P.later[id]];
       }
+      o.stiles.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols, start[x],
+                              start[x + 1]});
+      o.schur.bytes += 32.0 * P.size[j] * cols;
+      o.schur.sub = std::max<int>(o.schur.sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
+      slot[id] = -1;
     }
     tgt.clear();
     tcount.clear();
     tjrow.clear();
-    schurl[l].n = (int64_t)pool.tiles.size() - schurl[l].t0;
+  };
+  {
+    const int nthreads = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16));
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+      std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
+      std::vector<Term> pair_term;
+      while (true) {
+        const int l = next.fetch_add(1);
+        if (l >= L) break;
+        try {
+          build_level(l, slot, tgt, tcount, tjrow, pair_id, pair_term);
+        } catch (const Error &e) {
+          lv_out[l].err = e.msg;
+        }
+      }
+    };
+    std::vector<std::thread> pool_threads;
+    for (int t = 1; t < nthreads; ++t) pool_threads.emplace_back(worker);
+    worker();
+    for (auto &th : pool_threads) th.join();
+    for (int l = 0; l < L; ++l)
+      if (!lv_out[l].err.empty()) throw Error{HPS_EINVAL, lv_out[l].err};
   }
+  // concatenate in level order
+  std::vector<InvLaunch> invl;
+  std::vector<int64_t> inv_off;
+  std::vector<int32_t> inv_n, inv_id;
+  std::vector<GemmLaunch> coefl(L), schurl(L);
+  Impl::Pool pool;
+  double flops = 0.0;
+  {
+    size_t nt = 0, nm = 0;
+    for (auto &o : lv_out) {
+      nt += o.ctiles.size() + o.stiles.size();
+      nm += o.cterms.size() + o.sterms.size();
+    }
+    pool.tiles.reserve(nt);
+    pool.terms.reserve(nm);
+  }
+  const int ncls[3] = {32, 64, 128};
+  for (int l = 0; l < L; ++l) {
+    LevelOut &o = lv_out[l];
+    for (int c = 0; c < 3; ++c) {
+      if (o.inv_off[c].empty()) continue;
+      invl.push_back(InvLaunch{ncls[c], (int64_t)inv_off.size(), (int64_t)o.inv_off[c].size(), l, o.inv_flops[c]});
+      inv_off.insert(inv_off.end(), o.inv_off[c].begin(), o.inv_off[c].end());
+      inv_n.insert(inv_n.end(), o.inv_n[c].begin(), o.inv_n[c].end());
+      inv_id.insert(inv_id.end(), o.inv_id[c].begin(), o.inv_id[c].end());
+    }
+    auto append = [&](std::vector<Tile> &tl, std::vector<Term> &tm, GemmLaunch &dst, const GemmLaunch &src) {
+      const int32_t base = (int32_t)pool.terms.size();
+      pool.terms.insert(pool.terms.end(), tm.begin(), tm.end());
+      dst = src;
+      dst.t0 = (int64_t)pool.tiles.size();
+      for (Tile t : tl) {
+        t.t_begin += base;
+        t.t_end += base;
+        pool.tiles.push_back(t);
+      }
+      dst.n = (int64_t)tl.size();
+      std::vector<Tile>().swap(tl);
+      std::vector<Term>().swap(tm);
+    };
+    append(o.ctiles, o.cterms, coefl[l], o.coef);
+    append(o.stiles, o.sterms, schurl[l], o.schur);
+    flops += o.flops;
+  }
+  const auto th1 = std::chrono::steady_clock::now();
   validate(pool.tiles.data(), pool.tiles.size(), pool.terms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
+  const auto th2 = std::chrono::steady_clock::now();
   pool.upload(s);
+  HIP_CHECK(hipStreamSynchronize(s));
+  const auto th3 = std::chrono::steady_clock::now();
+  sched_split[0] = std::chrono::duration<double, std::milli>(th1 - th0).count();
+  sched_split[1] = std::chrono::duration<double, std::milli>(th2 - th1).count();
+  sched_split[2] = std::chrono::duration<double, std::milli>(th3 - th2).count();
+  sched_split[3] = (double)pool.tiles.size();
+  sched_split[4] = (double)pool.terms.size();
   DevArray<int64_t> d_inv_off;
   DevArray<int32_t> d_inv_n, d_inv_id;
   d_inv_off.upload(inv_off, s);
@@ -1314,9 +1458,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
   I.fwd.assign(L, Impl::Sched());
   I.bwd.assign(L, Impl::Sched());
-  slot.assign(M, -1);
-  tgt.clear();
-  bucket.assign(M, std::vector<Term>());
+  std::vector<int32_t> slot(M, -1), tgt;
+  std::vector<std::vector<Term>> bucket(M);
   auto flush = [&](Impl::Sched &sc) {
     for (int32_t g : tgt) {
       add_target(sc, P.uoff[g], (int32_t)P.size[g], (int32_t)N);
@@ -1580,6 +1723,8 @@ std::string DeviceState::stats_json() const {
       << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
+  o << ", \"schedule_split\": {\"build_ms\": " << sched_split[0] << ", \"validate_ms\": " << sched_split[1]
+    << ", \"upload_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
   o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms
     << ", \"symbolic\": " << times.symbolic_ms
     << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms
