@@ -185,6 +185,53 @@ hps_status hps_profile(hps_ctx *ctx, int enable);
    last setup / solve in ms) into buf (NUL-terminated, truncated to len). */
 hps_status hps_stats(const hps_ctx *ctx, char *buf, size_t len);
 
+/* ------------------------------------------------------------------ batches
+ * A batch context holds P independent scattering problems (separate meshes,
+ * one set of parameters).  Their H-matrices are kept apart (no block couples
+ * two problems) but the setup and the solve treat them as one block-diagonal
+ * system: every elimination-tree level of every problem is processed in the
+ * same launches, and every solve stage is one launch over all problems.
+ * Results per problem are those of a single-problem context on the same
+ * problem, up to rounding.
+ *
+ * Call order:  hps_batch_create -> hps_batch_set_mesh for p = 0..P-1 ->
+ *   (hps_build_hmatrix | hps_batch_set_hmatrix for every p) -> hps_setup ->
+ *   hps_solve_* ; hps_set_mesh / hps_set_hmatrix return HPS_EINVAL on a
+ *   batch context.
+ * Layouts on a batch context (all R plane waves or RHS columns apply to every
+ *   problem): X, B and Y hold, for p = 0..P-1 in turn, problem p's N_p x R
+ *   column-major block (RWG order of that mesh, leading dimension N_p),
+ *   starting at element R * (N_0 + ... + N_{p-1}); rcs and ratio hold P x R
+ *   doubles, problem-major (entry p * R + r).  hps_num_unknowns returns
+ *   N_0 + ... + N_{P-1}; hps_get_hmatrix returns the merged block-diagonal
+ *   H-matrix (tree positions and groups of problem p follow those of
+ *   problems 0..p-1).  A single-problem context behaves as a batch of one. */
+
+/* Create a batch context for n_problems (1..65535) problems; device and
+   stream as in hps_create. */
+hps_status hps_batch_create(hps_ctx **out, int device, void *hip_stream, int32_t n_problems);
+
+/* Mesh of problem p (0 <= p < P); same rules as hps_set_mesh.  Invalidates
+   the H-matrix and setup of the whole batch. */
+hps_status hps_batch_set_mesh(hps_ctx *ctx, int32_t p, const double *xyz, int64_t nv,
+                              const int32_t *tri, int64_t nt);
+
+/* Install problem p's H-matrix (arguments as in hps_set_hmatrix, positions
+   local to problem p).  params must be identical for every problem.  The
+   batch becomes ready for hps_setup once every problem has one. */
+hps_status hps_batch_set_hmatrix(hps_ctx *ctx, int32_t p, const hps_params *params, int64_t N,
+                                 const int64_t *perm, int64_t M, const int64_t *group_ptr,
+                                 int64_t n_near, const int32_t *near_ts, const int64_t *near_off,
+                                 const double *near_vals, int64_t n_far, const int64_t *far_rng,
+                                 const int32_t *far_rank, const int64_t *far_off,
+                                 const double *far_uv);
+
+/* Number of problems (1 for a single-problem context). */
+hps_status hps_num_problems(const hps_ctx *ctx, int32_t *n_problems);
+
+/* Unknowns N_p of problem p (after its mesh is set). */
+hps_status hps_problem_unknowns(const hps_ctx *ctx, int32_t p, int64_t *N);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libhps.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SRC = ["mesh.cpp", "tree.cpp", "efie.cpp", "aca.cpp", "symbolic.cpp", "api.cpp"]
+HOST_SRC = ["mesh.cpp", "tree.cpp", "efie.cpp", "aca.cpp", "symbolic.cpp", "batch.cpp", "api.cpp"]
 DEVICE_SRC = ["device.hip"]
 
 HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-pthread", "-Wall",

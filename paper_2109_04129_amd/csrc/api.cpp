@@ -1,5 +1,6 @@
 // C ABI of the hps library (include/hps.h).  Argument checking, call-order
 // state and error capture; the work is in the host modules and device.hip.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -25,6 +26,14 @@ struct hps_ctx {
   bool have_setup = false;
   std::unique_ptr<hps::DeviceState> dev;
   double build_ms = 0.0, symbolic_ms = 0.0, setup_ms = 0.0;
+  // batch of independent problems (n_prob > 0): per-problem meshes and
+  // H-matrices, merged into mesh / H above once all are present
+  int32_t n_prob = 0;
+  std::vector<hps::Mesh> pmesh;
+  std::vector<hps::HMatrix> pH;
+  std::vector<char> pmesh_ok, pH_ok;
+  std::vector<int64_t> nseg, gseg;   // unknown / group offsets per problem
+  int32_t problems() const { return n_prob > 0 ? n_prob : 1; }
 };
 
 namespace {
@@ -63,6 +72,79 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (p->precision < 0 || p->precision > 2) return fail(c, HPS_EINVAL, "precision must be 0, 1 or 2");
   if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
   return HPS_OK;
+}
+
+void single_segments(hps_ctx *c) {
+  c->nseg = {0, c->H.N};
+  c->gseg = {0, c->H.M};
+}
+
+void merge_batch(hps_ctx *c) {
+  hps::Mesh m;
+  hps::HMatrix H;
+  hps::merge_problems(c->pmesh, c->pH, m, H, c->nseg, c->gseg);
+  c->mesh = std::move(m);
+  c->H = std::move(H);
+}
+
+// Checked copy of an H-matrix given as flat arrays (layout in hps.h).
+hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64_t *group_ptr, int64_t n_near,
+                                 const int32_t *near_ts, const int64_t *near_off, const double *near_vals,
+                                 int64_t n_far, const int64_t *far_rng, const int32_t *far_rank,
+                                 const int64_t *far_off, const double *far_uv) {
+  if (!perm || !group_ptr || M <= 0 || n_near <= 0 || !near_ts || !near_off || !near_vals)
+    throw hps::Error{HPS_EINVAL, "missing near-field arrays"};
+  if (n_far < 0 || (n_far > 0 && (!far_rng || !far_rank || !far_off || !far_uv)))
+    throw hps::Error{HPS_EINVAL, "missing far-field arrays"};
+  hps::HMatrix H;
+  H.N = N;
+  H.M = M;
+  H.perm.assign(perm, perm + N);
+  std::vector<char> seen(N, 0);
+  for (int64_t i = 0; i < N; ++i) {
+    if (perm[i] < 0 || perm[i] >= N || seen[perm[i]]) throw hps::Error{HPS_EINVAL, "perm is not a permutation"};
+    seen[perm[i]] = 1;
+  }
+  H.gptr.assign(group_ptr, group_ptr + M + 1);
+  if (H.gptr[0] != 0 || H.gptr[M] != N) throw hps::Error{HPS_EINVAL, "group_ptr must span [0, N)"};
+  for (int64_t g = 0; g < M; ++g) {
+    const int64_t sz = H.gptr[g + 1] - H.gptr[g];
+    if (sz < 1) throw hps::Error{HPS_EINVAL, "empty group"};
+    if (sz > 128) throw hps::Error{HPS_EINVAL, "group larger than 128 unknowns"};
+  }
+  H.near_ts.assign(near_ts, near_ts + 2 * n_near);
+  H.near_off.assign(near_off, near_off + n_near + 1);
+  if (near_off[0] != 0) throw hps::Error{HPS_EINVAL, "near_off must start at 0"};
+  std::vector<char> diag(M, 0);
+  for (int64_t b = 0; b < n_near; ++b) {
+    const int64_t t = near_ts[2 * b], s = near_ts[2 * b + 1];
+    if (t < 0 || s < 0 || t >= M || s >= M || t > s) throw hps::Error{HPS_EINVAL, "bad near pair"};
+    if (near_off[b + 1] - near_off[b] != (H.gptr[t + 1] - H.gptr[t]) * (H.gptr[s + 1] - H.gptr[s]))
+      throw hps::Error{HPS_EINVAL, "near_off does not match the block sizes"};
+    if (t == s) diag[t] = 1;
+  }
+  for (int64_t g = 0; g < M; ++g)
+    if (!diag[g]) throw hps::Error{HPS_EINVAL, "every group needs its diagonal near block"};
+  const int64_t ne = near_off[n_near];
+  H.near_vals.resize(ne);
+  std::memcpy((void *)H.near_vals.data(), near_vals, ne * sizeof(hps::cplx));
+  H.far_off.assign(1, 0);
+  if (n_far > 0) {
+    H.far_rng.assign(far_rng, far_rng + 4 * n_far);
+    H.far_rank.assign(far_rank, far_rank + n_far);
+    H.far_off.assign(far_off, far_off + n_far + 1);
+    if (far_off[0] != 0) throw hps::Error{HPS_EINVAL, "far_off must start at 0"};
+  }
+  for (int64_t b = 0; b < n_far; ++b) {
+    const int64_t m = far_rng[4 * b + 1] - far_rng[4 * b], n = far_rng[4 * b + 3] - far_rng[4 * b + 2];
+    if (m <= 0 || n <= 0 || far_rng[4 * b] < 0 || far_rng[4 * b + 3] > N || far_rng[4 * b + 1] > N ||
+        far_rng[4 * b + 2] < 0 || far_rank[b] < 0 || far_off[b + 1] - far_off[b] != (int64_t)far_rank[b] * (m + n))
+      throw hps::Error{HPS_EINVAL, "bad far block"};
+  }
+  const int64_t fe = n_far > 0 ? far_off[n_far] : 0;
+  H.far_uv.resize(fe);
+  if (fe) std::memcpy((void *)H.far_uv.data(), far_uv, fe * sizeof(hps::cplx));
+  return H;
 }
 
 double now_ms() {
@@ -123,6 +205,7 @@ const char *hps_last_error(const hps_ctx *c) { return c ? c->err.c_str() : g_cre
 
 hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
   if (!c) return HPS_EINVAL;
+  if (c->n_prob) return fail(c, HPS_EINVAL, "batch context: use hps_batch_set_mesh");
   if (!xyz || !tri || nv <= 0 || nt <= 0) return fail(c, HPS_EINVAL, "empty mesh");
   return guarded(c, [&]() {
     hps::Mesh m;
@@ -142,25 +225,143 @@ hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t
 hps_status hps_num_unknowns(const hps_ctx *c, int64_t *N) {
   if (!c || !N) return HPS_EINVAL;
   if (!c->have_mesh) return HPS_ESTATE;
-  *N = c->mesh.N;
+  if (c->n_prob) {
+    int64_t t = 0;
+    for (const hps::Mesh &m : c->pmesh) t += m.N;
+    *N = t;
+  } else {
+    *N = c->mesh.N;
+  }
   return HPS_OK;
+}
+
+hps_status hps_batch_create(hps_ctx **out, int device, void *stream, int32_t n_problems) {
+  if (!out) return HPS_EINVAL;
+  *out = nullptr;
+  if (n_problems < 1 || n_problems > 65535) {
+    g_create_error = "n_problems must be in [1, 65535]";
+    return HPS_EINVAL;
+  }
+  hps_status st = hps_create(out, device, stream);
+  if (st != HPS_OK) return st;
+  hps_ctx *c = *out;
+  try {
+    c->n_prob = n_problems;
+    c->pmesh.resize(n_problems);
+    c->pH.resize(n_problems);
+    c->pmesh_ok.assign(n_problems, 0);
+    c->pH_ok.assign(n_problems, 0);
+  } catch (...) {
+    hps_destroy(c);
+    *out = nullptr;
+    g_create_error = "host allocation failed";
+    return HPS_ENOMEM;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_num_problems(const hps_ctx *c, int32_t *n_problems) {
+  if (!c || !n_problems) return HPS_EINVAL;
+  *n_problems = c->problems();
+  return HPS_OK;
+}
+
+hps_status hps_problem_unknowns(const hps_ctx *c, int32_t p, int64_t *N) {
+  if (!c || !N || p < 0 || p >= c->problems()) return HPS_EINVAL;
+  if (c->n_prob) {
+    if (!c->pmesh_ok[p]) return HPS_ESTATE;
+    *N = c->pmesh[p].N;
+  } else {
+    if (!c->have_mesh) return HPS_ESTATE;
+    *N = c->mesh.N;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_batch_set_mesh(hps_ctx *c, int32_t p, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
+  if (!c) return HPS_EINVAL;
+  if (!c->n_prob) return fail(c, HPS_EINVAL, "not a batch context: use hps_set_mesh");
+  if (p < 0 || p >= c->n_prob) return fail(c, HPS_EINVAL, "problem index out of range");
+  if (!xyz || !tri || nv <= 0 || nt <= 0) return fail(c, HPS_EINVAL, "empty mesh");
+  return guarded(c, [&]() {
+    hps::Mesh m;
+    m.nv = nv;
+    m.nt = nt;
+    m.xyz.assign(xyz, xyz + 3 * nv);
+    m.tri.assign(tri, tri + 3 * nt);
+    hps::build_rwg(m);
+    c->pmesh[p] = std::move(m);
+    c->pmesh_ok[p] = 1;
+    c->pH_ok[p] = 0;
+    c->pH[p] = hps::HMatrix();
+    c->have_mesh = std::all_of(c->pmesh_ok.begin(), c->pmesh_ok.end(), [](char x) { return x != 0; });
+    c->have_h = false;
+    c->have_setup = false;
+    return HPS_OK;
+  });
+}
+
+hps_status hps_batch_set_hmatrix(hps_ctx *c, int32_t p, const hps_params *prm, int64_t N, const int64_t *perm,
+                                 int64_t M, const int64_t *group_ptr, int64_t n_near, const int32_t *near_ts,
+                                 const int64_t *near_off, const double *near_vals, int64_t n_far,
+                                 const int64_t *far_rng, const int32_t *far_rank, const int64_t *far_off,
+                                 const double *far_uv) {
+  if (!c) return HPS_EINVAL;
+  if (!c->n_prob) return fail(c, HPS_EINVAL, "not a batch context: use hps_set_hmatrix");
+  if (p < 0 || p >= c->n_prob) return fail(c, HPS_EINVAL, "problem index out of range");
+  if (!c->pmesh_ok[p]) return fail(c, HPS_ESTATE, "hps_batch_set_mesh for this problem first");
+  hps_status st = check_params(c, prm);
+  if (st != HPS_OK) return st;
+  if (N != c->pmesh[p].N) return fail(c, HPS_EINVAL, "N does not match the mesh of this problem");
+  for (int32_t q = 0; q < c->n_prob; ++q)
+    if (c->pH_ok[q] && q != p && std::memcmp(&c->params, prm, sizeof(hps_params)) != 0)
+      return fail(c, HPS_EINVAL, "every problem of a batch takes the same parameters");
+  return guarded(c, [&]() {
+    hps::HMatrix H = read_hmatrix(N, perm, M, group_ptr, n_near, near_ts, near_off, near_vals, n_far, far_rng,
+                                  far_rank, far_off, far_uv);
+    c->have_h = false;
+    c->have_setup = false;
+    c->pH[p] = std::move(H);
+    c->pH_ok[p] = 1;
+    c->params = *prm;
+    c->have_params = true;
+    if (c->have_mesh && std::all_of(c->pH_ok.begin(), c->pH_ok.end(), [](char x) { return x != 0; })) {
+      merge_batch(c);
+      if (c->dev) c->dev->upload(c->mesh, c->H, *prm, c->nseg);
+      c->have_h = true;
+    }
+    return HPS_OK;
+  });
 }
 
 hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
   if (!c) return HPS_EINVAL;
-  if (!c->have_mesh) return fail(c, HPS_ESTATE, "hps_set_mesh first");
+  if (!c->have_mesh) return fail(c, HPS_ESTATE, c->n_prob ? "hps_batch_set_mesh for every problem first"
+                                                         : "hps_set_mesh first");
   hps_status st = check_params(c, p);
   if (st != HPS_OK) return st;
   return guarded(c, [&]() {
     const double t0 = now_ms();
-    hps::HMatrix H;
-    hps::build_hmatrix(c->mesh, *p, H);
-    c->H = std::move(H);
+    c->have_h = false;
+    c->have_setup = false;
+    if (c->n_prob) {
+      for (int32_t q = 0; q < c->n_prob; ++q) {
+        hps::HMatrix H;
+        hps::build_hmatrix(c->pmesh[q], *p, H);
+        c->pH[q] = std::move(H);
+        c->pH_ok[q] = 1;
+      }
+      merge_batch(c);
+    } else {
+      hps::HMatrix H;
+      hps::build_hmatrix(c->mesh, *p, H);
+      c->H = std::move(H);
+      single_segments(c);
+    }
     c->params = *p;
     c->have_params = true;
+    if (c->dev) c->dev->upload(c->mesh, c->H, *p, c->nseg);
     c->have_h = true;
-    c->have_setup = false;
-    if (c->dev) c->dev->upload(c->mesh, c->H, *p);
     c->build_ms = now_ms() - t0;
     return HPS_OK;
   });
@@ -171,65 +372,22 @@ hps_status hps_set_hmatrix(hps_ctx *c, const hps_params *p, int64_t N, const int
                            const double *near_vals, int64_t n_far, const int64_t *far_rng, const int32_t *far_rank,
                            const int64_t *far_off, const double *far_uv) {
   if (!c) return HPS_EINVAL;
+  if (c->n_prob) return fail(c, HPS_EINVAL, "batch context: use hps_batch_set_hmatrix");
   if (!c->have_mesh) return fail(c, HPS_ESTATE, "hps_set_mesh first");
   hps_status st = check_params(c, p);
   if (st != HPS_OK) return st;
   if (N != c->mesh.N) return fail(c, HPS_EINVAL, "N does not match the mesh");
-  if (!perm || !group_ptr || M <= 0 || n_near <= 0 || !near_ts || !near_off || !near_vals)
-    return fail(c, HPS_EINVAL, "missing near-field arrays");
-  if (n_far < 0 || (n_far > 0 && (!far_rng || !far_rank || !far_off || !far_uv)))
-    return fail(c, HPS_EINVAL, "missing far-field arrays");
   return guarded(c, [&]() {
-    hps::HMatrix H;
-    H.N = N;
-    H.M = M;
-    H.perm.assign(perm, perm + N);
-    std::vector<char> seen(N, 0);
-    for (int64_t i = 0; i < N; ++i) {
-      if (perm[i] < 0 || perm[i] >= N || seen[perm[i]]) throw hps::Error{HPS_EINVAL, "perm is not a permutation"};
-      seen[perm[i]] = 1;
-    }
-    H.gptr.assign(group_ptr, group_ptr + M + 1);
-    if (H.gptr[0] != 0 || H.gptr[M] != N) throw hps::Error{HPS_EINVAL, "group_ptr must span [0, N)"};
-    for (int64_t g = 0; g < M; ++g) {
-      const int64_t sz = H.gptr[g + 1] - H.gptr[g];
-      if (sz < 1) throw hps::Error{HPS_EINVAL, "empty group"};
-      if (sz > 128) throw hps::Error{HPS_EINVAL, "group larger than 128 unknowns"};
-    }
-    H.near_ts.assign(near_ts, near_ts + 2 * n_near);
-    H.near_off.assign(near_off, near_off + n_near + 1);
-    std::vector<char> diag(M, 0);
-    for (int64_t b = 0; b < n_near; ++b) {
-      const int64_t t = near_ts[2 * b], s = near_ts[2 * b + 1];
-      if (t < 0 || s < 0 || t >= M || s >= M || t > s) throw hps::Error{HPS_EINVAL, "bad near pair"};
-      if (near_off[b + 1] - near_off[b] != (H.gptr[t + 1] - H.gptr[t]) * (H.gptr[s + 1] - H.gptr[s]))
-        throw hps::Error{HPS_EINVAL, "near_off does not match the block sizes"};
-      if (t == s) diag[t] = 1;
-    }
-    for (int64_t g = 0; g < M; ++g)
-      if (!diag[g]) throw hps::Error{HPS_EINVAL, "every group needs its diagonal near block"};
-    const int64_t ne = near_off[n_near];
-    H.near_vals.resize(ne);
-    std::memcpy((void *)H.near_vals.data(), near_vals, ne * sizeof(hps::cplx));
-    H.far_rng.assign(far_rng ? far_rng : perm, far_rng ? far_rng + 4 * n_far : perm);
-    H.far_rank.assign(far_rank ? far_rank : (const int32_t *)nullptr, far_rank ? far_rank + n_far : nullptr);
-    H.far_off.assign(1, 0);
-    if (n_far > 0) H.far_off.assign(far_off, far_off + n_far + 1);
-    for (int64_t b = 0; b < n_far; ++b) {
-      const int64_t m = far_rng[4 * b + 1] - far_rng[4 * b], n = far_rng[4 * b + 3] - far_rng[4 * b + 2];
-      if (m <= 0 || n <= 0 || far_rng[4 * b] < 0 || far_rng[4 * b + 3] > N || far_rank[b] < 0 ||
-          far_off[b + 1] - far_off[b] != (int64_t)far_rank[b] * (m + n))
-        throw hps::Error{HPS_EINVAL, "bad far block"};
-    }
-    const int64_t fe = n_far > 0 ? far_off[n_far] : 0;
-    H.far_uv.resize(fe);
-    if (fe) std::memcpy((void *)H.far_uv.data(), far_uv, fe * sizeof(hps::cplx));
+    hps::HMatrix H = read_hmatrix(N, perm, M, group_ptr, n_near, near_ts, near_off, near_vals, n_far, far_rng,
+                                  far_rank, far_off, far_uv);
+    c->have_h = false;
+    c->have_setup = false;
     c->H = std::move(H);
+    single_segments(c);
     c->params = *p;
     c->have_params = true;
+    if (c->dev) c->dev->upload(c->mesh, c->H, *p, c->nseg);
     c->have_h = true;
-    c->have_setup = false;
-    if (c->dev) c->dev->upload(c->mesh, c->H, *p);
     return HPS_OK;
   });
 }
@@ -271,7 +429,7 @@ hps_status hps_setup(hps_ctx *c) {
   return guarded(c, [&]() {
     const double t0 = now_ms();
     hps::Plan P;
-    hps::make_plan(c->H, c->mesh, c->params.ordering, P);
+    hps::make_plan(c->H, c->mesh, c->params.ordering, c->gseg, P);
     const double t1 = now_ms();
     c->dev->times.symbolic_ms = t1 - t0;
     c->have_setup = false;
@@ -298,10 +456,11 @@ hps_status hps_solve_planewaves(hps_ctx *c, int64_t R, const double *khat, const
   if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
   if (R <= 0 || !khat || !pol) return fail(c, HPS_EINVAL, "bad plane-wave arguments");
   return guarded(c, [&]() {
-    std::vector<double> rt(R);
+    const int64_t RP = R * c->problems();
+    std::vector<double> rt(RP);
     c->dev->solve_planewaves(R, khat, pol, X, rcs, rt.data());
-    if (ratio) std::memcpy(ratio, rt.data(), R * sizeof(double));
-    return c->params.terms > 1 ? ratio_status(c, R, rt.data()) : HPS_OK;
+    if (ratio) std::memcpy(ratio, rt.data(), RP * sizeof(double));
+    return c->params.terms > 1 ? ratio_status(c, RP, rt.data()) : HPS_OK;
   });
 }
 
@@ -310,10 +469,11 @@ hps_status hps_solve_rhs(hps_ctx *c, int64_t R, const void *B, void *X, double *
   if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
   if (R <= 0 || !B || !X || B == X) return fail(c, HPS_EINVAL, "bad RHS arguments");
   return guarded(c, [&]() {
-    std::vector<double> rt(R);
+    const int64_t RP = R * c->problems();
+    std::vector<double> rt(RP);
     c->dev->solve_rhs(R, B, X, rt.data());
-    if (ratio) std::memcpy(ratio, rt.data(), R * sizeof(double));
-    return c->params.terms > 1 ? ratio_status(c, R, rt.data()) : HPS_OK;
+    if (ratio) std::memcpy(ratio, rt.data(), RP * sizeof(double));
+    return c->params.terms > 1 ? ratio_status(c, RP, rt.data()) : HPS_OK;
   });
 }
 
@@ -350,7 +510,7 @@ hps_status hps_stats(const hps_ctx *c, char *buf, size_t len) {
   if (!c || !buf || len == 0) return HPS_EINVAL;
   std::ostringstream o;
   o.precision(9);
-  o << "{\"build_ms\": " << c->build_ms << ", \"setup_ms\": " << c->setup_ms << ", \"symbolic_ms\": " << c->symbolic_ms;
+  o << "{\"problems\": " << c->problems() << ", \"build_ms\": " << c->build_ms << ", \"setup_ms\": " << c->setup_ms << ", \"symbolic_ms\": " << c->symbolic_ms;
   if (c->have_h) {
     int64_t rsum = 0, rmax = 0;
     for (int32_t r : c->H.far_rank) { rsum += r; rmax = std::max<int64_t>(rmax, r); }

@@ -50,7 +50,9 @@ class DeviceState {
  public:
   DeviceState(int device, void *stream);
   ~DeviceState();
-  void upload(const Mesh &mesh, const HMatrix &H, const hps_params &p);
+  // nseg[P+1]: unknown offsets of the P independent problems of a batch
+  // ({0, N} for one problem); outputs are laid out per problem.
+  void upload(const Mesh &mesh, const HMatrix &H, const hps_params &p, const std::vector<int64_t> &nseg);
   void setup(const Plan &P, const HMatrix &H);         // throws Error
   int precision = 0;        // 0 FP64; 1 FP32 + BF16 far; 2 FP32 + FP16 far
   int refine = 0;           // residual-correction passes (precision form)

@@ -310,12 +310,25 @@ __global__ void k_axpy32(float2 *__restrict__ y, const float2 *__restrict__ w, f
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = make_float2(fmaf(sgn, w[i].x, y[i].x), fmaf(sgn, w[i].y, y[i].y));
 }
-// per-column sum of |v|^2 (FP32 input, FP64 accumulation)
-__global__ __launch_bounds__(256) void k_colnorm32(const float2 *__restrict__ a, int64_t N, double *__restrict__ out) {
-  const int64_t r = blockIdx.x;
+// Problem p of a batch owns unknowns [soff[p], soff[p + 1]) (elimination
+// order and RWG order alike); nseg problems.
+__device__ __forceinline__ int seg_of(const int64_t *__restrict__ soff, int nseg, int64_t q) {
+  int lo = 0, hi = nseg;                  // soff[lo] <= q < soff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (soff[mid] <= q) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// per-column, per-problem sum of |v|^2 (FP32 input, FP64 accumulation):
+// block (r, p) writes out[p R + r]
+__global__ __launch_bounds__(256) void k_colnorm32(const float2 *__restrict__ a, int64_t N,
+                                                   const int64_t *__restrict__ soff, double *__restrict__ out) {
+  const int64_t r = blockIdx.x, R = gridDim.x, p = blockIdx.y;
   __shared__ double sx[256];
   double x = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += 256) {
+  for (int64_t i = soff[p] + threadIdx.x; i < soff[p + 1]; i += 256) {
     const float2 u = a[r * N + i];
     x += (double)u.x * u.x + (double)u.y * u.y;
   }
@@ -325,7 +338,7 @@ __global__ __launch_bounds__(256) void k_colnorm32(const float2 *__restrict__ a,
     if (threadIdx.x < s) sx[threadIdx.x] += sx[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = sx[0];
+  if (threadIdx.x == 0) out[p * R + r] = sx[0];
 }
 
 // Far factors to 16-bit pairs with one FP32 scale per factor per block:
@@ -543,15 +556,16 @@ __global__ void k_rhs(const double *__restrict__ qd, const int64_t *__restrict__
   B[idx] = make_double2(re, im);
 }
 
-// Per-column reductions: out[r] = sum_q |v|^2 (mode 0) or
-// coef * |sum_q a b|^2 (mode 1: monostatic RCS from b^T x).
+// Per-column, per-problem reductions, block (r, p) -> out[p R + r]:
+// sum_q |a|^2 (mode 0) or coef * |sum_q a b|^2 (mode 1: monostatic RCS
+// from b^T x), q over the unknowns of problem p.
 __global__ __launch_bounds__(256) void k_colreduce(const c2 *__restrict__ a, const c2 *__restrict__ b,
-                                                   int64_t N, double coef, int mode,
-                                                   double *__restrict__ out) {
-  const int64_t r = blockIdx.x;
+                                                   int64_t N, const int64_t *__restrict__ soff, double coef,
+                                                   int mode, double *__restrict__ out) {
+  const int64_t r = blockIdx.x, R = gridDim.x, p = blockIdx.y;
   __shared__ double sx[256], sy[256];
   double x = 0.0, y = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += 256) {
+  for (int64_t i = soff[p] + threadIdx.x; i < soff[p + 1]; i += 256) {
     const c2 u = a[r * N + i];
     if (mode == 0) {
       x = fma(u.x, u.x, x);
@@ -574,7 +588,7 @@ __global__ __launch_bounds__(256) void k_colreduce(const c2 *__restrict__ a, con
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = (mode == 0) ? sx[0] : coef * (sx[0] * sx[0] + sy[0] * sy[0]);
+  if (threadIdx.x == 0) out[p * R + r] = (mode == 0) ? sx[0] : coef * (sx[0] * sx[0] + sy[0] * sy[0]);
 }
 
 // y += sgn * w
@@ -589,17 +603,24 @@ __global__ void k_axpy(c2 *__restrict__ y, const c2 *__restrict__ w, double sgn,
   }
 }
 
-// dir 0: out[q + r N] = in[dperm[q] + r N] (RWG -> elimination order);
-// dir 1: out[dperm[q] + r N] = in[q + r N].
+// Between the internal N x R block (elimination order, leading dimension N)
+// and the caller's layout, where problem p's N_p x R block (RWG order within
+// the problem, leading dimension N_p) starts at element R soff[p]; for one
+// problem that is the plain N x R block in RWG order.
+// dir 0: caller -> internal; dir 1: internal -> caller.
 __global__ void k_permute(const c2 *__restrict__ in, c2 *__restrict__ out, const int64_t *__restrict__ dperm,
-                          int64_t N, int64_t R, int dir) {
+                          const int64_t *__restrict__ soff, int nseg, int64_t N, int64_t R, int dir) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N * R) return;
   const int64_t q = idx % N, r = idx / N;
+  const int64_t n = dperm[q];
+  const int p = seg_of(soff, nseg, n);
+  const int64_t lo = soff[p];
+  const int64_t o = R * lo + r * (soff[p + 1] - lo) + (n - lo);
   if (dir == 0)
-    out[idx] = in[dperm[q] + r * N];
+    out[idx] = in[o];
   else
-    out[dperm[q] + r * N] = in[idx];
+    out[o] = in[idx];
 }
 
 // ------------------------------------------------------------------ host side
@@ -667,6 +688,9 @@ struct DeviceState::Impl {
   hipStream_t s;
   // problem
   int64_t N = 0, M = 0, R_cap = 0;
+  int nseg = 1;                    // independent problems (batch)
+  std::vector<int64_t> soff;       // nseg + 1 unknown offsets
+  DevArray<int64_t> dsoff;
   double k = 0.0, coef_rcs = 0.0, ratio_warn = 0.1;
   int terms = 2;
   uint64_t mem_cap = 0;
@@ -846,7 +870,7 @@ struct DeviceState::Impl {
     spool.upload(s);
     vB.alloc(NR); vY.alloc(NR); vW.alloc(NR); vS.alloc(NR); vI.alloc(NR); vX.alloc(NR);
     vT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
-    red.alloc(2 * R + 8);
+    red.alloc(2 * R * nseg + 8);
     built_R = R;
   }
 
@@ -889,32 +913,33 @@ struct DeviceState::Impl {
   }
   // out = two-term series applied to in (FP32); in is kept
   void series32(int64_t R, const float2 *in, float2 *out, double *ratio_host) {
-    const int64_t NR = N * R;
+    const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
     HIP_CHECK(hipMemcpyAsync(wS.p, in, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
     for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
     launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-    hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R), dim3(256), 0, s, wI.p, N, red.p);
+    hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, wI.p, N, dsoff.p, red.p);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(out, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
     for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, out, out);
-    std::vector<double> n0(R), n1(R);
-    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> n0(RP), n1(RP);
+    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, RP * sizeof(double), hipMemcpyDeviceToHost, s));
     const float2 *wprev = out;
     float2 *wa = wW.p, *wb = wX.p;
     for (int t = 1; t < terms; ++t) {
       far32(wprev, wS.p, 0);
       for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
       launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-      hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R), dim3(256), 0, s, wI.p, N, red.p + R);
+      hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, wI.p, N, dsoff.p,
+                         red.p + RP);
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipMemcpyAsync(wa, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
       for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, wa, wa);
       hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, out, wa, (t & 1) ? -1.0f : 1.0f, NR);
       HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + R, R * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + RP, RP * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
-      for (int64_t r = 0; r < R; ++r) {
+      for (int64_t r = 0; r < RP; ++r) {
         if (t == 1 && ratio_host) ratio_host[r] = std::sqrt(n1[r]) / std::sqrt(n0[r]);
         n0[r] = n1[r];
       }
@@ -922,7 +947,7 @@ struct DeviceState::Impl {
       std::swap(wa, wb);
     }
     if (terms == 1 && ratio_host)
-      for (int64_t r = 0; r < R; ++r) ratio_host[r] = 0.0;
+      for (int64_t r = 0; r < RP; ++r) ratio_host[r] = 0.0;
   }
   // out = H x with FP32 near blocks and 16-bit far factors
   void hmatvec32(const float2 *x, float2 *out) {
@@ -971,14 +996,15 @@ struct DeviceState::Impl {
     launch(b_far1, 0, faruv.p, y, vT.p);
     launch(b_far2, mode, faruv.p, vT.p, out);
   }
-  void colnorm2(const c2 *v, int64_t R, double *dst) {
-    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R), dim3(256), 0, s, v, v, N, 0.0, 0, dst);
+  void colnorm2(const c2 *v, int64_t R, double *dst) {     // nseg x R values
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, v, v, N, dsoff.p, 0.0, 0,
+                       dst);
     HIP_CHECK(hipGetLastError());
   }
 
   // Power series (eqs. 25-36) on vB (elimination order, N x R): result in vY.
   void series(int64_t R, double *ratio_host) {
-    const int64_t NR = N * R;
+    const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
     HIP_CHECK(hipMemcpyAsync(vS.p, vB.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
     sweep_fwd(vS.p);                               // b~ = A^T b            (eq. 25)
@@ -986,21 +1012,21 @@ struct DeviceState::Impl {
     colnorm2(vI.p, R, red.p);
     HIP_CHECK(hipMemcpyAsync(vY.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
     sweep_bwd(vY.p);                               // w_0 = A it_0          (eq. 26)
-    std::vector<double> n0(R), n1(R), worst(R, 0.0);
-    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> n0(RP), n1(RP), worst(RP, 0.0);
+    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, RP * sizeof(double), hipMemcpyDeviceToHost, s));
     const c2 *wprev = vY.p;
     for (int t = 1; t < terms; ++t) {
       far_apply(wprev, vS.p, 0);                   // s = Z_F w_{t-1}
       sweep_fwd(vS.p);                             // A^T s
       launch(b_dinv, 0, F.p, vS.p, vI.p);          // it_t = D^-1 A^T Z_F A it_{t-1}  (eq. 31)
-      colnorm2(vI.p, R, red.p + R);
+      colnorm2(vI.p, R, red.p + RP);
       HIP_CHECK(hipMemcpyAsync(vW.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
       sweep_bwd(vW.p);                             // w_t = A it_t
       hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, vY.p, vW.p, (t & 1) ? -1.0 : 1.0, NR);
       HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + R, R * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + RP, RP * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
-      for (int64_t r = 0; r < R; ++r) {
+      for (int64_t r = 0; r < RP; ++r) {
         const double q = std::sqrt(n1[r]) / std::sqrt(n0[r]);
         if (t == 1) worst[r] = q;
         n0[r] = n1[r];
@@ -1011,7 +1037,7 @@ struct DeviceState::Impl {
       wprev = vX.p;
     }
     if (ratio_host)
-      for (int64_t r = 0; r < R; ++r) ratio_host[r] = (terms > 1) ? worst[r] : 0.0;
+      for (int64_t r = 0; r < RP; ++r) ratio_host[r] = (terms > 1) ? worst[r] : 0.0;
   }
 };
 
@@ -1036,11 +1062,17 @@ DeviceState::~DeviceState() {
   if (own_stream && stream) (void)hipStreamDestroy((hipStream_t)stream);
 }
 
-void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p) {
+void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p, const std::vector<int64_t> &nseg) {
   Impl &I = *impl;
   HIP_CHECK(hipSetDevice(device));
+  if (nseg.size() < 2 || nseg.front() != 0 || nseg.back() != H.N) throw Error{HPS_EINVAL, "internal: bad problem offsets"};
+  for (size_t q = 0; q + 1 < nseg.size(); ++q)
+    if (nseg[q + 1] <= nseg[q]) throw Error{HPS_EINVAL, "internal: empty problem in a batch"};
   I.N = H.N;
   I.M = H.M;
+  I.nseg = (int)nseg.size() - 1;
+  I.soff = nseg;
+  I.dsoff.upload(nseg, I.s);
   I.ready = false;
   I.built_R = -1;
   const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi;
@@ -1123,6 +1155,15 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       dperm[P.uoff[e] + i] = H.perm[H.gptr[g] + i];
       t2e[H.gptr[g] + i] = P.uoff[e] + i;
     }
+  }
+  // every problem of a batch must own one contiguous range of elimination
+  // positions (the per-problem reductions and layouts rely on it)
+  for (int64_t e = 0; e < M; ++e) {
+    const int64_t lo = H.gptr[P.order[e]];
+    const int64_t p = std::upper_bound(I.soff.begin(), I.soff.end(), lo) - I.soff.begin() - 1;
+    if (p < 0 || p >= I.nseg || P.uoff[e] < I.soff[p] || P.uoff[e] + P.size[e] > I.soff[p + 1] ||
+        H.gptr[P.order[e] + 1] > I.soff[p + 1])
+      throw Error{HPS_EINVAL, "internal: a problem of the batch is not contiguous in elimination order"};
   }
   I.tree2elim = t2e;
   I.dperm.upload(dperm, s);
@@ -1619,15 +1660,16 @@ void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *
   I.solve_any(R, ratio);
   HIP_CHECK(hipEventRecord(e2.e, I.s));
   if (rcs) {
-    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R), dim3(256), 0, I.s, I.vB.p, I.vY.p, N, I.coef_rcs, 1, I.red.p);
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)I.nseg), dim3(256), 0, I.s, I.vB.p, I.vY.p, N,
+                       I.dsoff.p, I.coef_rcs, 1, I.red.p);
     HIP_CHECK(hipGetLastError());
   }
   if (X) {
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, N, R, 1);
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
     HIP_CHECK(hipGetLastError());
   }
   HIP_CHECK(hipEventRecord(e3.e, I.s));
-  if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p, R * sizeof(double), hipMemcpyDeviceToHost, I.s));
+  if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p, R * I.nseg * sizeof(double), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
   I.prof_collect();
   times.rhs_ms = elapsed(e0, e1);
@@ -1646,11 +1688,11 @@ void DeviceState::solve_rhs(int64_t R, const void *B, void *X, double *ratio) {
   const int64_t N = I.N, NR = N * R;
   Ev e0, e1;
   HIP_CHECK(hipEventRecord(e0.e, I.s));
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p, N, R,
-                     0);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p, I.dsoff.p,
+                     I.nseg, N, R, 0);
   HIP_CHECK(hipGetLastError());
   I.solve_any(R, ratio);
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, N, R, 1);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventRecord(e1.e, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
@@ -1674,7 +1716,7 @@ void DeviceState::excitation(int64_t R, const double *khat, const double *pol, v
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, dkp.p, I.k,
                      I.vB.p);
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p, N, R, 1);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
@@ -1686,7 +1728,7 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   I.ensure_R(R);
   const int64_t N = I.N, NR = N * R;
   const unsigned g = (unsigned)cdiv(NR, 256);
-  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, I.vS.p, I.dperm.p, N, R, 0);
+  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, I.vS.p, I.dperm.p, I.dsoff.p, I.nseg, N, R, 0);
   HIP_CHECK(hipGetLastError());
   if (I.precision == 0) {
     I.launch(I.b_near, 0, I.near.p, I.vS.p, I.vI.p);
@@ -1698,7 +1740,7 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
     hipLaunchKernelGGL(k_to64, dim3(g), dim3(256), 0, I.s, I.wI.p, I.vI.p, NR);
     HIP_CHECK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, N, R, 1);
+  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(I.s));
 }

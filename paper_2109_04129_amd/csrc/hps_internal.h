@@ -119,6 +119,18 @@ struct Plan {
   double setup_flops = 0.0;          // algorithmic (8 flops per complex MAC)
 };
 
-void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, Plan &P);
+// gseg[P+1]: the groups of problem p are [gseg[p], gseg[p+1]) (one entry pair
+// {0, M} for a single problem).  Each problem is ordered on its own and the
+// problems follow each other, so every problem owns a contiguous range of
+// elimination positions; the elimination-tree levels are shared.
+void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, const std::vector<int64_t> &gseg, Plan &P);
+
+// ---------------------------------------------------------------- batches
+// Several independent problems as one block-diagonal system: vertices,
+// triangles, RWG unknowns, tree positions and groups of problem p follow
+// those of problems 0..p-1, and no near or far block couples two problems.
+// nseg[P+1] / gseg[P+1] receive the unknown / group offsets.
+void merge_problems(const std::vector<Mesh> &meshes, const std::vector<HMatrix> &Hs, Mesh &mesh, HMatrix &H,
+                    std::vector<int64_t> &nseg, std::vector<int64_t> &gseg);
 
 }  // namespace hps

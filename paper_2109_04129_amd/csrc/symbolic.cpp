@@ -78,7 +78,7 @@ struct ND {
 
 }  // namespace
 
-void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, Plan &P) {
+void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, const std::vector<int64_t> &gseg, Plan &P) {
   const int64_t M = H.M;
   P.M = M;
   P.N = H.N;
@@ -97,16 +97,21 @@ void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, Plan &P) {
     }
     for (int d = 0; d < 3; ++d) cen[3 * g + d] /= (double)std::max<int64_t>(n, 1);
   }
+  if (gseg.size() < 2 || gseg.front() != 0 || gseg.back() != M)
+    throw Error{HPS_EINVAL, "internal: problem group ranges do not cover the groups"};
   P.order.clear();
   if (ordering == 1) {
     P.order.resize(M);
     std::iota(P.order.begin(), P.order.end(), 0);
   } else {
     ND nd(adj, cen, P.order);
-    std::vector<int32_t> all(M);
-    std::iota(all.begin(), all.end(), 0);
-    nd.run(all);
+    for (size_t q = 0; q + 1 < gseg.size(); ++q) {   // problems never couple: order each on its own
+      std::vector<int32_t> grp(gseg[q + 1] - gseg[q]);
+      std::iota(grp.begin(), grp.end(), (int32_t)gseg[q]);
+      nd.run(grp);
+    }
   }
+  if ((int64_t)P.order.size() != M) throw Error{HPS_EINVAL, "internal: ordering lost groups"};
   P.pos.assign(M, -1);
   for (int64_t e = 0; e < M; ++e) P.pos[P.order[e]] = (int32_t)e;
 

@@ -20,7 +20,8 @@ STATUS = {0: "HPS_OK", 1: "HPS_WRATIO", -1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: 
 EXPORTS = ["hps_params_default", "hps_create", "hps_destroy", "hps_last_error", "hps_set_mesh",
            "hps_num_unknowns", "hps_build_hmatrix", "hps_set_hmatrix", "hps_hmatrix_sizes",
            "hps_get_hmatrix", "hps_setup", "hps_solve_planewaves", "hps_solve_rhs",
-           "hps_excitation", "hps_hmatvec", "hps_profile", "hps_stats"]
+           "hps_excitation", "hps_hmatvec", "hps_profile", "hps_stats", "hps_batch_create",
+           "hps_batch_set_mesh", "hps_batch_set_hmatrix", "hps_num_problems", "hps_problem_unknowns"]
 
 
 class HpsError(RuntimeError):
@@ -76,6 +77,12 @@ def lib():
         L.hps_hmatvec.argtypes = [ctx, i64, vp, vp]
         L.hps_stats.argtypes = [ctx, ctypes.c_char_p, ctypes.c_size_t]
         L.hps_profile.argtypes = [ctx, ctypes.c_int]
+        L.hps_batch_create.argtypes = [P(ctx), ctypes.c_int, vp, i32]
+        L.hps_batch_set_mesh.argtypes = [ctx, i32, vp, i64, vp, i64]
+        L.hps_batch_set_hmatrix.argtypes = [ctx, i32, P(hps_params), i64, vp, i64, vp, i64, vp, vp, vp,
+                                            i64, vp, vp, vp, vp]
+        L.hps_num_problems.argtypes = [ctx, P(i32)]
+        L.hps_problem_unknowns.argtypes = [ctx, i32, P(i64)]
         for name in EXPORTS:
             if name not in ("hps_destroy", "hps_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -134,8 +141,7 @@ def hps_build_hmatrix(ctx, params):
     return _check(ctx, lib().hps_build_hmatrix(ctx, ctypes.byref(params)))
 
 
-def hps_set_hmatrix(ctx, params, N, perm, group_ptr, near_ts, near_off, near_vals,
-                    far_rng, far_rank, far_off, far_uv):
+def _hmatrix_args(N, perm, group_ptr, near_ts, near_off, near_vals, far_rng, far_rank, far_off, far_uv):
     perm = np.ascontiguousarray(perm, dtype=np.int64)
     group_ptr = np.ascontiguousarray(group_ptr, dtype=np.int64)
     near_ts = np.ascontiguousarray(near_ts, dtype=np.int32)
@@ -145,10 +151,51 @@ def hps_set_hmatrix(ctx, params, N, perm, group_ptr, near_ts, near_off, near_val
     far_rank = np.ascontiguousarray(far_rank, dtype=np.int32)
     far_off = np.ascontiguousarray(far_off, dtype=np.int64)
     far_uv = np.ascontiguousarray(far_uv, dtype=np.complex128)
-    return _check(ctx, lib().hps_set_hmatrix(
-        ctx, ctypes.byref(params), int(N), _ptr(perm), len(group_ptr) - 1, _ptr(group_ptr),
-        len(near_ts) // 2, _ptr(near_ts), _ptr(near_off), _ptr(near_vals),
-        len(far_rank), _ptr(far_rng), _ptr(far_rank), _ptr(far_off), _ptr(far_uv)))
+    keep = (perm, group_ptr, near_ts, near_off, near_vals, far_rng, far_rank, far_off, far_uv)
+    args = (int(N), _ptr(perm), len(group_ptr) - 1, _ptr(group_ptr), len(near_ts) // 2, _ptr(near_ts),
+            _ptr(near_off), _ptr(near_vals), len(far_rank), _ptr(far_rng), _ptr(far_rank), _ptr(far_off),
+            _ptr(far_uv))
+    return keep, args
+
+
+def hps_set_hmatrix(ctx, params, N, perm, group_ptr, near_ts, near_off, near_vals,
+                    far_rng, far_rank, far_off, far_uv):
+    keep, args = _hmatrix_args(N, perm, group_ptr, near_ts, near_off, near_vals, far_rng, far_rank, far_off,
+                               far_uv)
+    return _check(ctx, lib().hps_set_hmatrix(ctx, ctypes.byref(params), *args))
+
+
+def hps_batch_create(n_problems, device=0, stream=None):
+    c = ctypes.c_void_p()
+    st = lib().hps_batch_create(ctypes.byref(c), int(device), stream, int(n_problems))
+    if st < 0:
+        raise HpsError(st, "hps_batch_create failed: " + lib().hps_last_error(None).decode())
+    return c
+
+
+def hps_batch_set_mesh(ctx, p, xyz, tri):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    return _check(ctx, lib().hps_batch_set_mesh(ctx, int(p), _ptr(xyz), len(xyz), _ptr(tri), len(tri)))
+
+
+def hps_batch_set_hmatrix(ctx, p, params, N, perm, group_ptr, near_ts, near_off, near_vals,
+                          far_rng, far_rank, far_off, far_uv):
+    keep, args = _hmatrix_args(N, perm, group_ptr, near_ts, near_off, near_vals, far_rng, far_rank, far_off,
+                               far_uv)
+    return _check(ctx, lib().hps_batch_set_hmatrix(ctx, int(p), ctypes.byref(params), *args))
+
+
+def hps_num_problems(ctx):
+    n = ctypes.c_int32()
+    _check(ctx, lib().hps_num_problems(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def hps_problem_unknowns(ctx, p):
+    n = ctypes.c_int64()
+    _check(ctx, lib().hps_problem_unknowns(ctx, int(p), ctypes.byref(n)))
+    return n.value
 
 
 def hps_hmatrix_sizes(ctx):
@@ -178,18 +225,25 @@ def hps_solve_planewaves(ctx, khat, pol, X_ptr=None, want_rcs=True, want_ratio=T
     khat = np.ascontiguousarray(khat, dtype=np.float64).reshape(-1, 3)
     pol = np.ascontiguousarray(pol, dtype=np.float64).reshape(-1, 3)
     R = len(khat)
-    rcs = np.empty(R) if want_rcs else None
-    ratio = np.empty(R) if want_ratio else None
+    P = hps_num_problems(ctx)
+    rcs = np.empty(P * R) if want_rcs else None
+    ratio = np.empty(P * R) if want_ratio else None
     st = _check(ctx, lib().hps_solve_planewaves(ctx, R, _ptr(khat), _ptr(pol),
                                                 ctypes.c_void_p(X_ptr) if X_ptr else None,
                                                 _ptr(rcs), _ptr(ratio)))
+    if P > 1:       # batch: (P, R), problem-major
+        rcs = None if rcs is None else rcs.reshape(P, R)
+        ratio = None if ratio is None else ratio.reshape(P, R)
     return st, rcs, ratio
 
 
 def hps_solve_rhs(ctx, R, B_ptr, X_ptr, want_ratio=True):
-    ratio = np.empty(R) if want_ratio else None
+    P = hps_num_problems(ctx)
+    ratio = np.empty(P * R) if want_ratio else None
     st = _check(ctx, lib().hps_solve_rhs(ctx, int(R), ctypes.c_void_p(B_ptr), ctypes.c_void_p(X_ptr),
                                          _ptr(ratio)))
+    if P > 1 and ratio is not None:
+        ratio = ratio.reshape(P, R)
     return st, ratio
 
 

@@ -88,3 +88,87 @@ def test_host_hmatrix_matches_oracle(c0_workload, c0_hmatrix, c0_dense):
         Zh[tlo:thi, slo:shi] = B
         Zh[slo:shi, tlo:thi] = B.T
     assert rel(Zh, Zt) <= 2e-3
+
+
+def _batch_meshes():
+    from workloads import ellipsoid_mesh
+    xyz1, tri1 = icosphere(1, 1.0)
+    xyz2, tri2 = icosphere(2, 1.0)
+    xyz3, tri3 = ellipsoid_mesh(xyz2, tri2, (1.3, 0.9, 0.6))
+    return [(xyz1, tri1), (xyz3, tri3), (0.8 * xyz2, tri2)]
+
+
+def test_host_batch_merge_and_errors():
+    """A batch context merges its problems into one block-diagonal H-matrix
+    whose blocks are exactly those of single-problem contexts, shifted by the
+    offsets of the problems before them; misuse is rejected."""
+    meshes = _batch_meshes()
+    p = hps.hps_params_default(freq_hz=300e6, leaf_max=16)
+    with pytest.raises(hps.HpsError) as e:
+        hps.hps_batch_create(0, -1)
+    assert e.value.status == -1
+    ctx = hps.hps_batch_create(len(meshes), -1)
+    single = []
+    try:
+        assert hps.hps_num_problems(ctx) == 3
+        xyz, tri = meshes[0]
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_set_mesh(ctx, xyz, tri)                 # batch takes hps_batch_set_mesh
+        assert e.value.status == -1
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_batch_set_mesh(ctx, 3, xyz, tri)        # problem index out of range
+        assert e.value.status == -1
+        hps.hps_batch_set_mesh(ctx, 0, xyz, tri)
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_build_hmatrix(ctx, p)                   # meshes 1 and 2 missing
+        assert e.value.status == -5
+        for q in (1, 2):
+            hps.hps_batch_set_mesh(ctx, q, *meshes[q])
+        Ns = [hps.hps_problem_unknowns(ctx, q) for q in range(3)]
+        assert Ns == [120, 480, 480]
+        assert hps.hps_num_unknowns(ctx) == sum(Ns)
+        hps.hps_build_hmatrix(ctx, p)
+        B = hps.hps_get_hmatrix(ctx)
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_setup(ctx)                              # host-only context
+        assert e.value.status == -3
+        for q in range(3):
+            c = hps.hps_create(-1)
+            single.append(c)
+            hps.hps_set_mesh(c, *meshes[q])
+            hps.hps_build_hmatrix(c, p)
+            with pytest.raises(hps.HpsError) as e:
+                hps.hps_batch_set_mesh(c, 0, *meshes[q])    # not a batch context
+            assert e.value.status == -1
+        S = [hps.hps_get_hmatrix(c) for c in single]
+        noff = np.concatenate([[0], np.cumsum(Ns)])
+        goff = np.concatenate([[0], np.cumsum([len(s["group_ptr"]) - 1 for s in S])])
+        assert np.array_equal(B["perm"], np.concatenate([s["perm"] + o for s, o in zip(S, noff)]))
+        assert np.array_equal(B["group_ptr"], np.concatenate(
+            [[0]] + [s["group_ptr"][1:] + o for s, o in zip(S, noff)]))
+        assert np.array_equal(B["near_ts"], np.concatenate([s["near_ts"] + g for s, g in zip(S, goff)]))
+        assert np.array_equal(B["near_vals"], np.concatenate([s["near_vals"] for s in S]))
+        assert np.array_equal(B["far_rng"], np.concatenate([s["far_rng"] + o for s, o in zip(S, noff)]))
+        assert np.array_equal(B["far_rank"], np.concatenate([s["far_rank"] for s in S]))
+        assert np.array_equal(B["far_uv"], np.concatenate([s["far_uv"] for s in S]))
+        # no far block and no near block couples two problems
+        rng = B["far_rng"].reshape(-1, 4) - np.array([0, 1, 0, 1])     # inclusive ends
+        prob = np.searchsorted(noff, rng, side="right") - 1
+        assert np.all(prob == prob[:, :1])
+        ts = B["near_ts"].reshape(-1, 2)
+        gp = np.searchsorted(goff, ts, side="right") - 1
+        assert np.all(gp[:, 0] == gp[:, 1])
+        # per-problem installs must share one parameter set
+        p2 = hps.hps_params_default(freq_hz=310e6, leaf_max=16)
+        s0 = S[0]
+        hps.hps_batch_set_hmatrix(ctx, 0, p, Ns[0], s0["perm"], s0["group_ptr"], s0["near_ts"], s0["near_off"],
+                                  s0["near_vals"], s0["far_rng"], s0["far_rank"], s0["far_off"], s0["far_uv"])
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_batch_set_hmatrix(ctx, 0, p2, Ns[0], s0["perm"], s0["group_ptr"], s0["near_ts"],
+                                      s0["near_off"], s0["near_vals"], s0["far_rng"], s0["far_rank"],
+                                      s0["far_off"], s0["far_uv"])
+        assert e.value.status == -1
+    finally:
+        hps.hps_destroy(ctx)
+        for c in single:
+            hps.hps_destroy(c)
