@@ -196,7 +196,8 @@ def main():
                          "FP64 setup, one FP32 residual pass (= four-term series)", "variants": forms}
     R, K = g["R"], args.steps
     ms_per_step = 1e3 * g["total"] / K
-    dev = g["stats"].get("device", {})
+    dev = dict(g["stats"].get("device", {}))
+    dev.pop("launch_log", None)
     k = dev.get("kernels", {}).get(DOMINANT, {})
     achieved = k["flops"] / (k["ms"] * 1e-3) if k.get("ms") else None
     roofline = {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": "mfma",

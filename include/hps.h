@@ -71,10 +71,15 @@ typedef struct {
                               1 = natural (tree order of the groups).  The currents do
                               not depend on it; the eq. (45) ratio, which is measured in
                               the scaled unknowns, does. */
+  int32_t graphs;          /* 1 (default): the device part of a solve is captured once
+                              per RHS count into a HIP graph and replayed; 0: every
+                              kernel is launched from the host on each call.  Same
+                              results either way.  Solves run eagerly while
+                              hps_profile is on. */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
-   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0.
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 

@@ -71,6 +71,7 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (p->refine_passes < 0) return fail(c, HPS_EINVAL, "refine_passes must be >= 0");
   if (p->precision < 0 || p->precision > 2) return fail(c, HPS_EINVAL, "precision must be 0, 1 or 2");
   if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
+  if (p->graphs != 0 && p->graphs != 1) return fail(c, HPS_EINVAL, "graphs must be 0 or 1");
   return HPS_OK;
 }
 
@@ -167,6 +168,8 @@ hps_status hps_params_default(hps_params *p) {
   p->ratio_warn = 0.1;
   p->device_mem_cap = 0;
   p->host_threads = 0;
+  p->ordering = 0;
+  p->graphs = 1;
   return HPS_OK;
 }
 

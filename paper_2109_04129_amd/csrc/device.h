@@ -56,6 +56,7 @@ class DeviceState {
   void setup(const Plan &P, const HMatrix &H);         // throws Error
   int precision = 0;        // 0 FP64; 1 FP32 + BF16 far; 2 FP32 + FP16 far
   int refine = 0;           // residual-correction passes (precision form)
+  int graphs = 1;           // replay the solve's device work from captured HIP graphs
   // RHS in elimination order into buffer `dst` (N x R), from plane waves.
   void solve_planewaves(int64_t R, const double *khat, const double *pol, void *X, double *rcs,
                         double *ratio);

@@ -591,6 +591,19 @@ __global__ __launch_bounds__(256) void k_colreduce(const c2 *__restrict__ a, con
   if (threadIdx.x == 0) out[p * R + r] = (mode == 0) ? sx[0] : coef * (sx[0] * sx[0] + sy[0] * sy[0]);
 }
 
+template <class T>
+__global__ void k_copy(T *__restrict__ y, const T *__restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+// eq. (45) per problem and RHS: ||it_1|| / ||it_0|| from the squared norms
+__global__ void k_ratio(const double *__restrict__ n0, const double *__restrict__ n1, double *__restrict__ out,
+                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt(n1[i]) / sqrt(n0[i]);
+}
+
 // y += sgn * w
 __global__ void k_axpy(c2 *__restrict__ y, const c2 *__restrict__ w, double sgn, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -721,8 +734,30 @@ struct DeviceState::Impl {
   // vector buffers
   DevArray<c2> vB, vY, vW, vS, vI, vX;
   DevArray<c2> vT;
-  DevArray<double> red;
+  DevArray<double> red;            // squared norms (2 x nseg x R), then RCS (nseg x R)
+  DevArray<double> rat;            // eq. (45) ratios, nseg x R
+  DevArray<double> dkp;            // plane waves: khat, pol per RHS
   DevArray<int> status;
+  // Captured solve stages (device work only, fixed buffers) per RHS count.
+  bool use_graphs = true;
+  struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    int64_t R = -1;
+    void reset() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      x = nullptr;
+      g = nullptr;
+      R = -1;
+    }
+    ~Graph() { reset(); }
+  };
+  Graph g_pw, g_rhs;
+  void drop_graphs() {
+    g_pw.reset();
+    g_rhs.reset();
+  }
   // Flat tile / term arrays shared by many launches: one upload each.
   struct Pool {
     std::vector<Tile> tiles;
@@ -779,7 +814,9 @@ struct DeviceState::Impl {
   // ---- optional per-launch timing with HIP events on the library stream
   // kinds: 0..2 = k_gemm<mode>, 3 = k_inverse
   bool prof = false;
-  struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; };
+  struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; int64_t units; };
+  struct LaunchLog { int kind; int64_t units; double flops, ms; };
+  std::vector<LaunchLog> launch_log;   // every timed launch since profiling was switched on
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_free;
   struct KStat { int64_t launches = 0; double ms = 0.0, flops = 0.0, bytes = 0.0; };
@@ -794,9 +831,9 @@ struct DeviceState::Impl {
     ev_free.pop_back();
     return e;
   }
-  ProfRec *prof_begin(int kind, double flops, double bytes = 0.0) {
+  ProfRec *prof_begin(int kind, double flops, double bytes = 0.0, int64_t units = 0) {
     if (!prof) return nullptr;
-    prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes});
+    prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes, units});
     HIP_CHECK(hipEventRecord(prof_recs.back().a, s));
     return &prof_recs.back();
   }
@@ -811,6 +848,7 @@ struct DeviceState::Impl {
       kstat[r.kind].ms += ms;
       kstat[r.kind].flops += r.flops;
       kstat[r.kind].bytes += r.bytes;
+      if (launch_log.size() < 100000) launch_log.push_back(LaunchLog{r.kind, r.units, r.flops, (double)ms});
       ev_free.push_back(r.a);
       ev_free.push_back(r.b);
     }
@@ -821,7 +859,7 @@ struct DeviceState::Impl {
                     c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false) {
     if (n_tiles == 0) return;
     dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
-    ProfRec *pr = prof_begin(mode, flops, bytes);
+    ProfRec *pr = prof_begin(mode, flops, bytes, n_tiles);
     if (wide) {
       if (mode == 0)
         hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
@@ -846,6 +884,7 @@ struct DeviceState::Impl {
 
   void ensure_R(int64_t R) {
     if (R == built_R) return;
+    drop_graphs();
     b_fwd.clear();
     b_bwd.clear();
     b_fwd.resize(fwd.size());
@@ -870,7 +909,10 @@ struct DeviceState::Impl {
     spool.upload(s);
     vB.alloc(NR); vY.alloc(NR); vW.alloc(NR); vS.alloc(NR); vI.alloc(NR); vX.alloc(NR);
     vT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
-    red.alloc(2 * R * nseg + 8);
+    red.alloc(3 * R * nseg + 8);
+    rat.alloc(R * nseg + 8);
+    dkp.alloc(6 * R);
+    if (precision) ensure32(R);
     built_R = R;
   }
 
@@ -885,7 +927,7 @@ struct DeviceState::Impl {
   void g32(const Tile *tiles, const Term *terms, int64_t n, int at, const void *A, const float2 *B, float2 *C,
            double flops, double bytes) {
     if (n == 0) return;
-    ProfRec *pr = prof_begin(MODE, flops, bytes);
+    ProfRec *pr = prof_begin(MODE, flops, bytes, n);
     dim3 g((unsigned)n), blk(256);
     if (at == 0)
       hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
@@ -911,78 +953,121 @@ struct DeviceState::Impl {
     launch32(b_far1, 0, precision, far16.p, y, wT.p);
     launch32(b_far2, mode, precision, far16.p, wT.p, out);
   }
-  // out = two-term series applied to in (FP32); in is kept
-  void series32(int64_t R, const float2 *in, float2 *out, double *ratio_host) {
+  // out = power series applied to in (FP32); in is kept.  With want_ratio
+  // the eq. (45) ratios go to rat (device).  No host synchronisation.
+  void series32(int64_t R, const float2 *in, float2 *out, bool want_ratio) {
     const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    HIP_CHECK(hipMemcpyAsync(wS.p, in, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    const dim3 gn((unsigned)R, (unsigned)nseg);
+    copy(wS.p, in, NR);
     for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
     launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-    hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, wI.p, N, dsoff.p, red.p);
-    HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipMemcpyAsync(out, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    if (want_ratio && terms > 1) {
+      hipLaunchKernelGGL(k_colnorm32, gn, dim3(256), 0, s, wI.p, N, dsoff.p, red.p);
+      HIP_CHECK(hipGetLastError());
+    }
+    copy(out, (const float2 *)wI.p, NR);
     for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, out, out);
-    std::vector<double> n0(RP), n1(RP);
-    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, RP * sizeof(double), hipMemcpyDeviceToHost, s));
     const float2 *wprev = out;
     float2 *wa = wW.p, *wb = wX.p;
     for (int t = 1; t < terms; ++t) {
       far32(wprev, wS.p, 0);
       for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
       launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-      hipLaunchKernelGGL(k_colnorm32, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, wI.p, N, dsoff.p,
-                         red.p + RP);
-      HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync(wa, wI.p, NR * sizeof(float2), hipMemcpyDeviceToDevice, s));
+      if (want_ratio && t == 1) {
+        hipLaunchKernelGGL(k_colnorm32, gn, dim3(256), 0, s, wI.p, N, dsoff.p, red.p + RP);
+        HIP_CHECK(hipGetLastError());
+        ratio_kernel(RP);
+      }
+      copy(wa, (const float2 *)wI.p, NR);
       for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, wa, wa);
       hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, out, wa, (t & 1) ? -1.0f : 1.0f, NR);
       HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + RP, RP * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-      for (int64_t r = 0; r < RP; ++r) {
-        if (t == 1 && ratio_host) ratio_host[r] = std::sqrt(n1[r]) / std::sqrt(n0[r]);
-        n0[r] = n1[r];
-      }
       wprev = wa;
       std::swap(wa, wb);
     }
-    if (terms == 1 && ratio_host)
-      for (int64_t r = 0; r < RP; ++r) ratio_host[r] = 0.0;
   }
-  // out = H x with FP32 near blocks and 16-bit far factors
   void hmatvec32(const float2 *x, float2 *out) {
     launch32(b_near, 0, 0, near32.p, x, out);
     far32(x, out, 2);
   }
   // Precision form of the solve: x = P b, then refine passes
   // x <- x + P (b - H x); b in wB, x left in wY.
-  void solve32(int64_t R, double *ratio_host) {
+  void solve32(int64_t R) {
     const int64_t NR = N * R;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    series32(R, wB.p, wY.p, ratio_host);
+    series32(R, wB.p, wY.p, true);
     for (int it = 0; it < refine; ++it) {
       hmatvec32(wY.p, wZ.p);
       hipLaunchKernelGGL(k_sub32, dim3(gb), dim3(256), 0, s, wB.p, wZ.p, wR.p, NR);
       HIP_CHECK(hipGetLastError());
-      series32(R, wR.p, wZ.p, nullptr);
+      series32(R, wR.p, wZ.p, false);
       hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, wY.p, wZ.p, 1.0f, NR);
       HIP_CHECK(hipGetLastError());
     }
   }
 
-  // FP64 series (plain) or precision form; B in vB, x in vY (FP64)
-  void solve_any(int64_t R, double *ratio_host) {
+  // FP64 series (plain) or precision form; B in vB, x in vY (FP64), ratios
+  // in rat.  Device work only (capturable).
+  void solve_any(int64_t R) {
     if (precision == 0) {
-      series(R, ratio_host);
+      series(R);
       return;
     }
     const int64_t NR = N * R;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    ensure32(R);
     hipLaunchKernelGGL(k_to32, dim3(gb), dim3(256), 0, s, vB.p, wB.p, NR);
     HIP_CHECK(hipGetLastError());
-    solve32(R, ratio_host);
+    solve32(R);
     hipLaunchKernelGGL(k_to64, dim3(gb), dim3(256), 0, s, wY.p, vY.p, NR);
+    HIP_CHECK(hipGetLastError());
+  }
+
+  // Plane-wave solve on the device: RHS from dkp into vB, solve, monostatic
+  // RCS of every problem and RHS into red[2 RP, 3 RP).
+  void core_pw(int64_t R) {
+    const int64_t NR = N * R, RP = R * nseg;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, s, quad.p, dperm.p, N, R, dkp.p, k, vB.p);
+    HIP_CHECK(hipGetLastError());
+    solve_any(R);
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, vB.p, vY.p, N, dsoff.p,
+                       coef_rcs, 1, red.p + 2 * RP);
+    HIP_CHECK(hipGetLastError());
+  }
+  void core_rhs(int64_t R) { solve_any(R); }
+
+  // Run fn(R) on the stream: replayed from a graph captured on first use
+  // (per R), or launched directly when graphs are off or kernels are timed.
+  void run(Graph &g, int64_t R, void (Impl::*fn)(int64_t)) {
+    if (!use_graphs || prof) {
+      (this->*fn)(R);
+      return;
+    }
+    if (g.R != R || !g.x) {
+      g.reset();
+      HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        (this->*fn)(R);
+      } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(s, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+      }
+      HIP_CHECK(hipStreamEndCapture(s, &g.g));
+      HIP_CHECK(hipGraphInstantiate(&g.x, g.g, nullptr, nullptr, 0));
+      g.R = R;
+    }
+    HIP_CHECK(hipGraphLaunch(g.x, s));
+  }
+
+  template <class T>
+  void copy(T *y, const T *x, int64_t n) {
+    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, y, x, n);
+    HIP_CHECK(hipGetLastError());
+  }
+  void ratio_kernel(int64_t RP) {
+    hipLaunchKernelGGL(k_ratio, dim3((unsigned)cdiv(RP, 256)), dim3(256), 0, s, red.p, red.p + RP, rat.p, RP);
     HIP_CHECK(hipGetLastError());
   }
 
@@ -1002,42 +1087,35 @@ struct DeviceState::Impl {
     HIP_CHECK(hipGetLastError());
   }
 
-  // Power series (eqs. 25-36) on vB (elimination order, N x R): result in vY.
-  void series(int64_t R, double *ratio_host) {
+  // Power series (eqs. 25-36) on vB (elimination order, N x R): result in
+  // vY, eq. (45) ratios in rat.  Device work only (capturable).
+  void series(int64_t R) {
     const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    HIP_CHECK(hipMemcpyAsync(vS.p, vB.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+    copy(vS.p, (const c2 *)vB.p, NR);
     sweep_fwd(vS.p);                               // b~ = A^T b            (eq. 25)
     launch(b_dinv, 0, F.p, vS.p, vI.p);            // it_0 = b_o = D^-1 b~  (eq. 32)
-    colnorm2(vI.p, R, red.p);
-    HIP_CHECK(hipMemcpyAsync(vY.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+    if (terms > 1) colnorm2(vI.p, R, red.p);
+    copy(vY.p, (const c2 *)vI.p, NR);
     sweep_bwd(vY.p);                               // w_0 = A it_0          (eq. 26)
-    std::vector<double> n0(RP), n1(RP), worst(RP, 0.0);
-    if (terms > 1) HIP_CHECK(hipMemcpyAsync(n0.data(), red.p, RP * sizeof(double), hipMemcpyDeviceToHost, s));
     const c2 *wprev = vY.p;
     for (int t = 1; t < terms; ++t) {
       far_apply(wprev, vS.p, 0);                   // s = Z_F w_{t-1}
       sweep_fwd(vS.p);                             // A^T s
       launch(b_dinv, 0, F.p, vS.p, vI.p);          // it_t = D^-1 A^T Z_F A it_{t-1}  (eq. 31)
-      colnorm2(vI.p, R, red.p + RP);
-      HIP_CHECK(hipMemcpyAsync(vW.p, vI.p, NR * sizeof(c2), hipMemcpyDeviceToDevice, s));
+      if (t == 1) {
+        colnorm2(vI.p, R, red.p + RP);
+        ratio_kernel(RP);                          // ||it_1|| / ||it_0||   (eq. 45)
+      }
+      copy(vW.p, (const c2 *)vI.p, NR);
       sweep_bwd(vW.p);                             // w_t = A it_t
       hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, vY.p, vW.p, (t & 1) ? -1.0 : 1.0, NR);
       HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync(n1.data(), red.p + RP, RP * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-      for (int64_t r = 0; r < RP; ++r) {
-        const double q = std::sqrt(n1[r]) / std::sqrt(n0[r]);
-        if (t == 1) worst[r] = q;
-        n0[r] = n1[r];
-      }
       // keep w_t for the next term
       std::swap(vW.p, vX.p);
       std::swap(vW.n, vX.n);
       wprev = vX.p;
     }
-    if (ratio_host)
-      for (int64_t r = 0; r < RP; ++r) ratio_host[r] = (terms > 1) ? worst[r] : 0.0;
   }
 };
 
@@ -1087,6 +1165,9 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   refine = I.refine;
   I.ratio_warn = p.ratio_warn;
   I.mem_cap = p.device_mem_cap;
+  I.use_graphs = p.graphs != 0;
+  graphs = p.graphs;
+  I.drop_graphs();
   const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * 7 * 8;
   if (I.mem_cap && need > I.mem_cap) throw Error{HPS_ENOMEM, "H-matrix exceeds device_mem_cap"};
   {
@@ -1140,6 +1221,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   Impl &I = *impl;
   HIP_CHECK(hipSetDevice(device));
   hipStream_t s = I.s;
+  I.drop_graphs();
   I.P = P;
   I.ready = false;
   I.built_R = -1;
@@ -1421,7 +1503,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       const unsigned nb = (unsigned)li.count;
       const int64_t *po = d_inv_off.p + li.start;
       const int32_t *pn = d_inv_n.p + li.start, *pi = d_inv_id.p + li.start;
-      Impl::ProfRec *pr = I.prof_begin(3, li.flops);
+      Impl::ProfRec *pr = I.prof_begin(3, li.flops, 0.0, li.count);
       if (li.nc == 32)
         hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else if (li.nc == 64)
@@ -1632,8 +1714,26 @@ float elapsed(const Ev &a, const Ev &b) {
 }
 }  // namespace
 
+// With a library-owned (non-blocking) stream the caller's work on the legacy
+// default stream, which produced the inputs or allocated the outputs, must
+// finish first.
+static void order_after_caller(const DeviceState &d) {
+  if (d.own_stream) HIP_CHECK(hipStreamSynchronize(nullptr));
+}
+
 static void check_ready(const DeviceState::Impl *I) {
   if (!I->ready) throw Error{HPS_ESTATE, "setup has not been run"};
+}
+
+static void upload_planewaves(DeviceState::Impl &I, int64_t R, const double *khat, const double *pol) {
+  std::vector<double> kp(6 * R);
+  for (int64_t r = 0; r < R; ++r)
+    for (int d = 0; d < 3; ++d) {
+      kp[6 * r + d] = khat[3 * r + d];
+      kp[6 * r + 3 + d] = pol[3 * r + d];
+    }
+  HIP_CHECK(hipMemcpyAsync(I.dkp.p, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice, I.s));
+  HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
 void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *pol, void *X, double *rcs,
@@ -1641,41 +1741,29 @@ void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *
   Impl &I = *impl;
   check_ready(&I);
   HIP_CHECK(hipSetDevice(device));
+  order_after_caller(*this);
   I.ensure_R(R);
-  const int64_t N = I.N, NR = N * R;
-  std::vector<double> kp(6 * R);
-  for (int64_t r = 0; r < R; ++r)
-    for (int d = 0; d < 3; ++d) {
-      kp[6 * r + d] = khat[3 * r + d];
-      kp[6 * r + 3 + d] = pol[3 * r + d];
-    }
-  DevArray<double> dkp;
-  dkp.upload(kp, I.s);
-  Ev e0, e1, e2, e3;
+  const int64_t N = I.N, NR = N * R, RP = R * I.nseg;
+  upload_planewaves(I, R, khat, pol);
+  Ev e0, e1, e2;
   HIP_CHECK(hipEventRecord(e0.e, I.s));
-  hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, dkp.p, I.k,
-                     I.vB.p);
-  HIP_CHECK(hipGetLastError());
+  I.run(I.g_pw, R, &Impl::core_pw);
   HIP_CHECK(hipEventRecord(e1.e, I.s));
-  I.solve_any(R, ratio);
-  HIP_CHECK(hipEventRecord(e2.e, I.s));
-  if (rcs) {
-    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)I.nseg), dim3(256), 0, I.s, I.vB.p, I.vY.p, N,
-                       I.dsoff.p, I.coef_rcs, 1, I.red.p);
-    HIP_CHECK(hipGetLastError());
-  }
   if (X) {
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p,
+                       I.dsoff.p, I.nseg, N, R, 1);
     HIP_CHECK(hipGetLastError());
   }
-  HIP_CHECK(hipEventRecord(e3.e, I.s));
-  if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p, R * I.nseg * sizeof(double), hipMemcpyDeviceToHost, I.s));
+  HIP_CHECK(hipEventRecord(e2.e, I.s));
+  if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p + 2 * RP, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
+  if (ratio && terms > 1) HIP_CHECK(hipMemcpyAsync(ratio, I.rat.p, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
+  if (ratio && terms <= 1) std::fill(ratio, ratio + RP, 0.0);
   I.prof_collect();
-  times.rhs_ms = elapsed(e0, e1);
-  times.sweep_ms = elapsed(e1, e2);
-  times.rcs_ms = elapsed(e2, e3);
-  times.solve_ms = elapsed(e0, e3);
+  times.rhs_ms = 0.0;
+  times.sweep_ms = elapsed(e0, e1);
+  times.rcs_ms = elapsed(e1, e2);
+  times.solve_ms = elapsed(e0, e2);
   last_solve_flops = 0.0;
   for (double f : I.solve_flops_parts) last_solve_flops += f;
 }
@@ -1684,18 +1772,23 @@ void DeviceState::solve_rhs(int64_t R, const void *B, void *X, double *ratio) {
   Impl &I = *impl;
   check_ready(&I);
   HIP_CHECK(hipSetDevice(device));
+  order_after_caller(*this);
   I.ensure_R(R);
-  const int64_t N = I.N, NR = N * R;
+  const int64_t N = I.N, NR = N * R, RP = R * I.nseg;
   Ev e0, e1;
   HIP_CHECK(hipEventRecord(e0.e, I.s));
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p, I.dsoff.p,
-                     I.nseg, N, R, 0);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p,
+                     I.dsoff.p, I.nseg, N, R, 0);
   HIP_CHECK(hipGetLastError());
-  I.solve_any(R, ratio);
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
+  I.run(I.g_rhs, R, &Impl::core_rhs);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p,
+                     I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventRecord(e1.e, I.s));
+  if (ratio && terms > 1) HIP_CHECK(hipMemcpyAsync(ratio, I.rat.p, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
+  if (ratio && terms <= 1) std::fill(ratio, ratio + RP, 0.0);
+  I.prof_collect();
   times.solve_ms = elapsed(e0, e1);
 }
 
@@ -1703,20 +1796,15 @@ void DeviceState::excitation(int64_t R, const double *khat, const double *pol, v
   Impl &I = *impl;
   check_ready(&I);
   HIP_CHECK(hipSetDevice(device));
+  order_after_caller(*this);
   I.ensure_R(R);
   const int64_t N = I.N, NR = N * R;
-  std::vector<double> kp(6 * R);
-  for (int64_t r = 0; r < R; ++r)
-    for (int d = 0; d < 3; ++d) {
-      kp[6 * r + d] = khat[3 * r + d];
-      kp[6 * r + 3 + d] = pol[3 * r + d];
-    }
-  DevArray<double> dkp;
-  dkp.upload(kp, I.s);
-  hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, dkp.p, I.k,
+  upload_planewaves(I, R, khat, pol);
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, I.dkp.p, I.k,
                      I.vB.p);
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p,
+                     I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
@@ -1725,6 +1813,7 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   Impl &I = *impl;
   check_ready(&I);
   HIP_CHECK(hipSetDevice(device));
+  order_after_caller(*this);
   I.ensure_R(R);
   const int64_t N = I.N, NR = N * R;
   const unsigned g = (unsigned)cdiv(NR, 256);
@@ -1751,6 +1840,7 @@ void DeviceState::set_profiling(bool on) {
   I.prof_collect();
   I.prof = on;
   for (auto &k : I.kstat) k = Impl::KStat();
+  I.launch_log.clear();
 }
 
 std::string DeviceState::stats_json() const {
@@ -1779,6 +1869,14 @@ std::string DeviceState::stats_json() const {
         << ", \"ms\": " << I.kstat[k].ms << ", \"flops\": " << I.kstat[k].flops
         << ", \"bytes\": " << I.kstat[k].bytes << "}";
     o << ", \"profiling\": " << (I.prof ? 1 : 0) << "}";
+    if (I.prof) {   // kind (0..2 GEMM mode, 3 inverse), work units (tiles / blocks), flops, ms
+      o << ", \"launch_log\": [";
+      for (size_t i = 0; i < I.launch_log.size(); ++i) {
+        const auto &L = I.launch_log[i];
+        o << (i ? ", " : "") << "[" << L.kind << ", " << L.units << ", " << L.flops << ", " << L.ms << "]";
+      }
+      o << "]";
+    }
   }
   if (I.built_R > 0) {
     o << ", \"solve_flops\": {\"fwd\": " << I.solve_flops_parts[0] << ", \"bwd\": " << I.solve_flops_parts[1]

@@ -35,7 +35,8 @@ class hps_params(ctypes.Structure):
                 ("aca_tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("terms", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
                 ("ratio_warn", ctypes.c_double), ("device_mem_cap", ctypes.c_uint64),
-                ("host_threads", ctypes.c_int32), ("ordering", ctypes.c_int32)]
+                ("host_threads", ctypes.c_int32), ("ordering", ctypes.c_int32),
+                ("graphs", ctypes.c_int32)]
 
 
 _lib = None
@@ -263,6 +264,6 @@ def hps_profile(ctx, enable=True):
 
 def hps_stats(ctx):
     import json
-    buf = ctypes.create_string_buffer(1 << 16)
+    buf = ctypes.create_string_buffer(1 << 24)
     _check(ctx, lib().hps_stats(ctx, buf, len(buf)))
     return json.loads(buf.value.decode())
