@@ -70,25 +70,29 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 template <int MODE, int NB>
 __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
-                                              const Term *__restrict__ terms) {
+                                              const Term *__restrict__ terms, int ncols) {
   // workgroup tile: 32 rows x (32 NB) columns; wave w owns rows 16 (w / 2)
   // and NB column blocks of 16 starting at 16 NB (w % 2)
   constexpr int TN = 32 * NB;
   const Tile t = tiles[blockIdx.x];
   // r0 < 0: the tile stands for the whole m x n block and blockIdx.y picks
   // its sub-tile (surplus y indices exit); else one explicit tile.
-  int rb = t.r0, cb = t.c0;
+  int rb = t.r0, cb = t.c0, tn = t.n;
   if (t.r0 < 0) {
     const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
     if ((int)blockIdx.y >= nsr * nsc) return;
     rb = (blockIdx.y / nsc) * TM;
     cb = (blockIdx.y % nsc) * TN;
+  } else if (t.c0 < 0) {             // one row tile over ncols columns, blockIdx.y picks the column tile
+    tn = ncols;
+    cb = blockIdx.y * TN;
+    if (cb >= tn) return;
   } else if (blockIdx.y > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
-  if (row0 >= t.m || col0 >= t.n) return;            // wave-uniform
+  if (row0 >= t.m || col0 >= tn) return;             // wave-uniform
   const int li = lane & 15, lg = lane >> 4;
   const int arow = row0 + li;
   const bool arow_ok = arow < t.m;
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
         for (int j = 0; j < NB; ++j) {
           const int bcol = col0 + 16 * j + li;
           bv[j][s] = make_double2(0.0, 0.0);
-          if (bcol < t.n) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
         }
       }
 #pragma unroll
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
       for (int j = 0; j < NB; ++j) {
         const int bcol = col0 + 16 * j + li;
         c2 bv = make_double2(0.0, 0.0);
-        if (kok && bcol < t.n) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
         rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
         ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
         ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ri[j], 0, 0, 0);
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int ccol = col0 + 16 * j + li;
-    if (ccol >= t.n) continue;
+    if (ccol >= tn) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int crow = row0 + lg + 4 * r;
@@ -189,21 +193,25 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
 template <int MODE, int AT, int NB>
 __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
-                                                const Term *__restrict__ terms, const float *__restrict__ scales) {
+                                                const Term *__restrict__ terms, const float *__restrict__ scales, int ncols) {
   constexpr int TN = 32 * NB;
   const Tile t = tiles[blockIdx.x];
-  int rb = t.r0, cb = t.c0;
+  int rb = t.r0, cb = t.c0, tn = t.n;
   if (t.r0 < 0) {
     const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
     if ((int)blockIdx.y >= nsr * nsc) return;
     rb = (blockIdx.y / nsc) * TM;
     cb = (blockIdx.y % nsc) * TN;
+  } else if (t.c0 < 0) {             // one row tile over ncols columns, blockIdx.y picks the column tile
+    tn = ncols;
+    cb = blockIdx.y * TN;
+    if (cb >= tn) return;
   } else if (blockIdx.y > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
-  if (row0 >= t.m || col0 >= t.n) return;
+  if (row0 >= t.m || col0 >= tn) return;
   const int li = lane & 15, lg = lane >> 4;
   const int arow = row0 + li;
   const bool arow_ok = arow < t.m;
@@ -230,7 +238,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
         for (int j = 0; j < NB; ++j) {
           const int bcol = col0 + 16 * j + li;
           bv[j][s] = make_float2(0.f, 0.f);
-          if (bcol < t.n) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
         }
       }
 #pragma unroll
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       for (int j = 0; j < NB; ++j) {
         const int bcol = col0 + 16 * j + li;
         float2 bv = make_float2(0.f, 0.f);
-        if (kok && bcol < t.n) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+        if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
         rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, rr[j], 0, 0, 0);
         ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, ii[j], 0, 0, 0);
         ri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, ri[j], 0, 0, 0);
@@ -268,7 +276,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int ccol = col0 + 16 * j + li;
-    if (ccol >= t.n) continue;
+    if (ccol >= tn) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int crow = row0 + 4 * lg + r;
@@ -666,10 +674,22 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Host-side bounds check of a tile/term batch against the element counts of
 // the A, B and C buffers: every index a kernel can form must be in range.
+// Bounds of every tile and term against buffer sizes na, nb, nc (elements).
+// A tile with n < 0 covers a run-time number of columns: it is checked for
+// one column, with nb / nc the per-column buffer sizes, and its leading
+// dimensions must equal them, so that the check holds for any column count.
 void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, int64_t na, int64_t nb,
               int64_t nc, const char *what) {
   for (size_t it = 0; it < ntiles; ++it) {
-    const Tile &t = tiles[it];
+    const Tile &t0 = tiles[it];
+    Tile t = t0;
+    if (t0.n < 0) {
+      if (t0.ldc != nc) throw Error{HPS_EINVAL, std::string("internal: column stride of C in ") + what};
+      t.n = 1;
+      for (int32_t q = t0.t_begin; q < t0.t_end; ++q)
+        if (q >= 0 && q < (int64_t)terms.size() && terms[q].ldb != nb)
+          throw Error{HPS_EINVAL, std::string("internal: column stride of B in ") + what};
+    }
     if (t.m <= 0 || t.n <= 0) continue;
     if (t.c_off < 0 || t.ldc < t.m || t.c_off + (int64_t)(t.n - 1) * t.ldc + (t.m - 1) >= nc ||
         t.t_begin < 0 || t.t_end > (int64_t)terms.size() || t.t_begin > t.t_end)
@@ -744,12 +764,14 @@ struct DeviceState::Impl {
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
     int64_t R = -1;
+    int64_t pending = -1;          // R of the last eager run: captured if it comes again
     void reset() {
       if (x) (void)hipGraphExecDestroy(x);
       if (g) (void)hipGraphDestroy(g);
       x = nullptr;
       g = nullptr;
       R = -1;
+      pending = -1;
     }
     ~Graph() { reset(); }
   };
@@ -775,40 +797,57 @@ struct DeviceState::Impl {
   };
   struct Built {
     int64_t t0 = 0, n_tiles = 0;
-    double flops = 0.0, bytes = 0.0;   // algorithmic: each term's A and B blocks once, C read + written once
+    // per-RHS sums: sum m k over terms (m = rows of the target), sum m over
+    // targets, sum k over terms
+    double smk = 0.0, sm = 0.0, sk = 0.0;
+    double flops = 0.0, bytes = 0.0;   // for R RHS; algorithmic: each term's A and B once, C read + written once
+    void at(int64_t R) {
+      flops = 8.0 * (double)R * smk;
+      bytes = 32.0 * sm * (double)R + 16.0 * (smk + sk * (double)R);
+    }
   };
-  Pool spool;                      // solve schedules for the current R
+  Pool spool;                      // solve schedules (independent of R)
   int64_t built_R = -1;
   std::vector<Built> b_fwd, b_bwd;
   Built b_dinv, b_far1, b_far2, b_near;
   std::vector<double> solve_flops_parts;
 
-  // Append the tiles of schedule sc for R right-hand sides (32 x 32 tiles
-  // over target rows and RHS columns) and its terms to pool pl.
-  void build(const Sched &sc, int64_t R, Pool &pl, Built &out, int64_t na, int64_t nb, int64_t nc,
-             const char *what) {
+  // Append the tiles of schedule sc (one per 32 target rows; the RHS
+  // columns are split over blockIdx.y at launch) and its terms to pool pl.
+  // na: elements of A; nb, nc: per-column sizes of the B and C buffers.
+  void build(const Sched &sc, Pool &pl, Built &out, int64_t na, int64_t nb, int64_t nc, const char *what) {
     const int32_t base = (int32_t)pl.terms.size();
     pl.terms.insert(pl.terms.end(), sc.terms.begin(), sc.terms.end());
+    out = Built();
     out.t0 = (int64_t)pl.tiles.size();
-    out.bytes = 0.0;
-    double fl = 0.0;
     for (size_t t = 0; t < sc.targets.size(); ++t) {
       const int64_t coff = sc.targets[t].first;
       const int32_t m = sc.targets[t].second;
       const int32_t tb = sc.t_ptr[t], te = sc.t_ptr[t + 1];
       for (int64_t r0 = 0; r0 < m; r0 += TM)
-        for (int64_t c0 = 0; c0 < R; c0 += TN_SOLVE)
-          pl.tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, (int32_t)c0, m, (int32_t)R, base + tb, base + te});
-      double by = 32.0 * m * (double)R;
+        pl.tiles.push_back(Tile{coff, sc.ld[t], (int32_t)r0, -1, m, -1, base + tb, base + te});
+      out.sm += m;
       for (int32_t q = tb; q < te; ++q) {
-        fl += 8.0 * m * (double)R * sc.terms[q].k;
-        by += 16.0 * sc.terms[q].k * ((double)m + (double)R);
+        out.smk += (double)m * sc.terms[q].k;
+        out.sk += sc.terms[q].k;
       }
-      out.bytes += by;
     }
     out.n_tiles = (int64_t)pl.tiles.size() - out.t0;
-    out.flops = fl;
     validate(pl.tiles.data() + out.t0, (size_t)out.n_tiles, pl.terms, na, nb, nc, what);
+  }
+  void build_solve_pool() {
+    spool.clear();
+    b_fwd.assign(fwd.size(), Built());
+    b_bwd.assign(bwd.size(), Built());
+    const int64_t nF = (int64_t)F.n, nT = std::max<int64_t>(t_rows, 1);
+    for (size_t l = 0; l < fwd.size(); ++l) build(fwd[l], spool, b_fwd[l], nF, N, N, "forward sweep");
+    for (size_t l = 0; l < bwd.size(); ++l) build(bwd[l], spool, b_bwd[l], nF, N, N, "back sweep");
+    build(dinv, spool, b_dinv, nF, N, N, "D^-1");
+    build(far1, spool, b_far1, (int64_t)faruv.n, N, nT, "far stage 1");
+    build(far2, spool, b_far2, (int64_t)faruv.n, nT, N, "far stage 2");
+    build(nearmv, spool, b_near, (int64_t)near.n, N, N, "near matvec");
+    spool.upload(s);
+    built_R = -1;
   }
 
   // ---- optional per-launch timing with HIP events on the library stream
@@ -856,57 +895,51 @@ struct DeviceState::Impl {
   }
 
   void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
-                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false) {
+                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false, int ncols = 0) {
     if (n_tiles == 0) return;
     dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
     ProfRec *pr = prof_begin(mode, flops, bytes, n_tiles);
     if (wide) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
       else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
       else
-        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
     } else {
       if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
       else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
       else
-        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms);
+        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
     }
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
   void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
-    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, 1, b.flops, b.bytes, true);
+    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, (int)cdiv(cur_R, TN_SOLVE), b.flops,
+                 b.bytes, true, (int)cur_R);
   }
 
+  // Sizes the vectors for R RHS and the launches' work counts; the tile
+  // lists do not depend on R.
+  int64_t cur_R = 0;
   void ensure_R(int64_t R) {
     if (R == built_R) return;
+    if (R > (int64_t)INT32_MAX / 2 || cdiv(R, TN_SOLVE) > 65535) throw Error{HPS_EINVAL, "too many right-hand sides"};
     drop_graphs();
-    b_fwd.clear();
-    b_bwd.clear();
-    b_fwd.resize(fwd.size());
-    b_bwd.resize(bwd.size());
+    cur_R = R;
     solve_flops_parts.assign(4, 0.0);
-    spool.clear();
-    const int64_t NR = N * R, nF = (int64_t)F.n, nT = std::max<int64_t>(t_rows, 1) * R;
-    for (size_t l = 0; l < fwd.size(); ++l) {
-      build(fwd[l], R, spool, b_fwd[l], nF, NR, NR, "forward sweep");
-      solve_flops_parts[0] += b_fwd[l].flops;
-    }
-    for (size_t l = 0; l < bwd.size(); ++l) {
-      build(bwd[l], R, spool, b_bwd[l], nF, NR, NR, "back sweep");
-      solve_flops_parts[1] += b_bwd[l].flops;
-    }
-    build(dinv, R, spool, b_dinv, nF, NR, NR, "D^-1");
+    for (auto &b : b_fwd) { b.at(R); solve_flops_parts[0] += b.flops; }
+    for (auto &b : b_bwd) { b.at(R); solve_flops_parts[1] += b.flops; }
+    b_dinv.at(R);
     solve_flops_parts[2] = b_dinv.flops;
-    build(far1, R, spool, b_far1, (int64_t)faruv.n, NR, nT, "far stage 1");
-    build(far2, R, spool, b_far2, (int64_t)faruv.n, nT, NR, "far stage 2");
+    b_far1.at(R);
+    b_far2.at(R);
     solve_flops_parts[3] = b_far1.flops + b_far2.flops;
-    build(nearmv, R, spool, b_near, (int64_t)near.n, NR, NR, "near matvec");
-    spool.upload(s);
+    b_near.at(R);
+    const int64_t NR = N * R;
     vB.alloc(NR); vY.alloc(NR); vW.alloc(NR); vS.alloc(NR); vI.alloc(NR); vX.alloc(NR);
     vT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
     red.alloc(3 * R * nseg + 8);
@@ -928,13 +961,14 @@ struct DeviceState::Impl {
            double flops, double bytes) {
     if (n == 0) return;
     ProfRec *pr = prof_begin(MODE, flops, bytes, n);
-    dim3 g((unsigned)n), blk(256);
+    dim3 g((unsigned)n, (unsigned)cdiv(cur_R, TN_SOLVE)), blk(256);
+    const int nc = (int)cur_R;
     if (at == 0)
-      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
     else if (at == 1)
-      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
     else
-      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p);
+      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
@@ -1036,10 +1070,16 @@ struct DeviceState::Impl {
   }
   void core_rhs(int64_t R) { solve_any(R); }
 
-  // Run fn(R) on the stream: replayed from a graph captured on first use
-  // (per R), or launched directly when graphs are off or kernels are timed.
+  // Run fn(R) on the stream.  The first solve with a given R after a setup
+  // launches directly; a second one captures a graph, which later solves
+  // with that R replay.  Direct launches when graphs are off or kernels are
+  // timed.
   void run(Graph &g, int64_t R, void (Impl::*fn)(int64_t)) {
-    if (!use_graphs || prof) {
+    if (!use_graphs || prof || (!(g.x && g.R == R) && g.pending != R)) {
+      if (use_graphs && !prof && !(g.x && g.R == R)) {
+        g.reset();
+        g.pending = R;
+      }
       (this->*fn)(R);
       return;
     }
@@ -1697,6 +1737,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     I.nearmv.terms.insert(I.nearmv.terms.end(), nt[g].begin(), nt[g].end());
   }
   close(I.nearmv);
+  I.build_solve_pool();
   I.ready = true;
 }
 
