@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--cpu-rhs", type=int, default=8, help="RHS in the oracle's timed sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the batching form on the 32-ellipsoid workload (host H-matrix build "
+                         "of 735k unknowns takes a few minutes)")
+    ap.add_argument("--batch-workload", default="ellipsoids32_600MHz")
     return ap.parse_args()
 
 
@@ -142,6 +146,132 @@ def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
     hps.hps_destroy(ctx)
     return dict(N=N, R=R, total=total, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
                 ratio=ratio, stats=stats, build_s=build_s, err=err)
+
+
+def batch_leg(args):
+    """Batching form: all problems in one context (every setup level and solve
+    stage one launch for all of them) against the plain form, i.e. the same
+    problems one context at a time, on the same H-matrices."""
+    import torch
+    from paper_2109_04129_amd import hps
+    from workloads import batch_workload
+    bw = batch_workload(args.batch_workload)
+    P, R = len(bw["meshes"]), len(bw["khat"])
+    khat, pol = bw["khat"], bw["pol"]
+    stream = torch.cuda.current_stream().cuda_stream
+    prm = hps.hps_params_default(freq_hz=bw["freq_hz"], leaf_max=bw["leaf_max"], aca_tol=bw["aca_tol"], terms=2)
+    # H-matrices, one problem at a time on the host (not timed as setup)
+    parts, build_s = [], 0.0
+    for p, (xyz, tri) in enumerate(bw["meshes"]):
+        h = hps.hps_create(-1)
+        hps.hps_set_mesh(h, xyz, tri)
+        t0 = time.perf_counter()
+        hps.hps_build_hmatrix(h, prm)
+        build_s += time.perf_counter() - t0
+        g = hps.hps_get_hmatrix(h)
+        g["N"] = hps.hps_num_unknowns(h)
+        parts.append(g)
+        hps.hps_destroy(h)
+        print("[bench] H-matrix %d/%d (%d unknowns) built" % (p + 1, P, g["N"]), file=sys.stderr, flush=True)
+    Ns = [a["N"] for a in parts]
+    NT = sum(Ns)
+
+    def batch_ctx(precision):
+        c = hps.hps_batch_create(P, 0, stream)
+        for p, (xyz, tri) in enumerate(bw["meshes"]):
+            hps.hps_batch_set_mesh(c, p, xyz, tri)
+        prm.precision, prm.refine_passes = precision, (1 if precision else 0)
+        for p, a in enumerate(parts):
+            hps.hps_batch_set_hmatrix(c, p, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
+                                      a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        prm.precision, prm.refine_passes = 0, 0
+        return c
+
+    def timed(c, Xp, steps):
+        su, so = [], []
+        for _ in range(steps):
+            ta = time.perf_counter()
+            hps.hps_setup(c)
+            tb = time.perf_counter()
+            _, rcs, ratio = hps.hps_solve_planewaves(c, khat, pol, Xp.data_ptr())
+            so.append(time.perf_counter() - tb)
+            su.append(tb - ta)
+        return np.array(su), np.array(so), rcs, ratio
+
+    def run_batch(c, precision):
+        Xb = torch.zeros(R * NT, dtype=torch.complex128, device="cuda")
+        timed(c, Xb, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su, so, rcs, ratio = timed(c, Xb, args.steps)
+        torch.cuda.synchronize()
+        return dict(total=time.perf_counter() - t0, setup=su, solve=so, rcs=rcs, X=Xb.cpu().numpy())
+
+    ctx = batch_ctx(0)
+    res = {0: run_batch(ctx, 0)}
+    st = hps.hps_stats(ctx)
+    hps.hps_destroy(ctx)
+    print("[bench] batched FP64 done", file=sys.stderr, flush=True)
+    ctx = batch_ctx(2)                       # precision form of the batch, same H-matrices
+    res[2] = run_batch(ctx, 2)
+    dev = dict(hps.hps_stats(ctx).get("device", {}))
+    dev.pop("launch_log", None)
+    hps.hps_destroy(ctx)
+    print("[bench] batch legs done", file=sys.stderr, flush=True)
+    # plain form: the same problems, one context after the other
+    seq_total, seq_setup, seq_solve, worst, worst_db = 0.0, 0.0, 0.0, 0.0, 0.0
+    off = 0
+    for p, (xyz, tri) in enumerate(bw["meshes"]):
+        c = hps.hps_create(0, stream)
+        hps.hps_set_mesh(c, xyz, tri)
+        a = parts[p]
+        hps.hps_set_hmatrix(c, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
+                            a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        Xp = torch.zeros((R, Ns[p]), dtype=torch.complex128, device="cuda")
+        timed(c, Xp, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su, so, rcs_p, _ = timed(c, Xp, args.steps)
+        torch.cuda.synchronize()
+        seq_total += time.perf_counter() - t0
+        seq_setup += float(np.median(su))
+        seq_solve += float(np.median(so))
+        xp = Xp.cpu().numpy()
+        xb = res[0]["X"][off * R:(off + Ns[p]) * R].reshape(R, Ns[p])
+        worst = max(worst, float(np.max(np.linalg.norm(xb - xp, axis=1) / np.linalg.norm(xp, axis=1))))
+        # the precision form (two-term series plus one residual pass) equals
+        # the four-term series: its FP64 reference
+        prm.terms = 4
+        hps.hps_set_hmatrix(c, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
+                            a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(c)
+        _, rcs4, _ = hps.hps_solve_planewaves(c, khat, pol, Xp.data_ptr())
+        torch.cuda.synchronize()
+        prm.terms = 2
+        x4 = Xp.cpu().numpy()
+        xb = res[2]["X"][off * R:(off + Ns[p]) * R].reshape(R, Ns[p])
+        res[2]["err"] = max(res[2].get("err", 0.0),
+                            float(np.max(np.linalg.norm(xb - x4, axis=1) / np.linalg.norm(x4, axis=1))))
+        worst_db = max(worst_db, float(np.max(np.abs(10 * np.log10(res[2]["rcs"][p] / rcs4)))))
+        off += Ns[p]
+        hps.hps_destroy(c)
+        print("[bench] plain problem %d/%d done" % (p + 1, P), file=sys.stderr, flush=True)
+    K = args.steps
+    out = {"workload": bw["name"], "problems": P, "rhs_per_problem": R, "unknowns": NT,
+           "unknowns_min_max": [min(Ns), max(Ns)], "hmatrix_build_s": build_s,
+           "plain_sequential": {"rhs_per_s_step": P * R * K / seq_total, "setup_s": seq_setup,
+                                "solve_rhs_per_s": P * R / seq_solve}}
+    for form, name in ((0, "batched_fp64"), (2, "batched_mixed_fp16_far")):
+        r = res[form]
+        out[name] = {"rhs_per_s_step": P * R * K / r["total"], "setup_s": float(np.median(r["setup"])),
+                     "solve_rhs_per_s": P * R / float(np.median(r["solve"])),
+                     "speedup_step_vs_plain": (P * R * K / r["total"]) / (P * R * K / seq_total)}
+    out["batched_fp64"]["current_rel_err_vs_plain"] = worst
+    out["batched_mixed_fp16_far"]["current_rel_err_vs_fp64_terms4"] = res[2].get("err")
+    out["batched_mixed_fp16_far"]["rcs_db_err_vs_fp64_terms4"] = worst_db
+    out["device_stats_fp16_form"] = {k: dev.get(k) for k in ("levels", "upper_blocks", "factor_bytes", "times_ms")}
+    out["hmatrix"] = st.get("hmatrix")
+    return out
 
 
 def cpu_leg(args, w):
@@ -229,6 +359,7 @@ def main():
         "ratio_max": float(np.max(g["ratio"])),
         "roofline": roofline,
         "precision_form": mixed,
+        "batching_form": batch_leg(args) if args.batch else None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_leg(args, w),
         "device_stats": dev,
     }

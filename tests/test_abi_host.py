@@ -172,3 +172,4 @@ def test_host_batch_merge_and_errors():
         hps.hps_destroy(ctx)
         for c in single:
             hps.hps_destroy(c)
+

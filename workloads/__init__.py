@@ -7,4 +7,5 @@ HIP library receive its arrays as plain inputs.
 """
 
 from .meshes import icosphere, geodesic_sphere, ellipsoid_mesh, flat_plate  # noqa: F401
-from .configs import WORKLOADS, workload, monostatic_angles, plane_wave_dirs  # noqa: F401
+from .configs import (WORKLOADS, BATCH_WORKLOADS, workload, batch_workload,  # noqa: F401
+                      monostatic_angles, plane_wave_dirs)

@@ -113,6 +113,35 @@ def workload_mesh(spec):
     raise ValueError(kind)
 
 
+BATCH_WORKLOADS = {
+    "ellipsoids32_600MHz": dict(
+        desc="32 seed-drawn PEC ellipsoids (semi-axes log-uniform in [0.5, 2] m, aspect <= 4, "
+             "numpy default_rng(0)), geodesic meshes at lambda/10 for 600 MHz (8,670-38,880 RWG each, "
+             "735,090 in all), leaf<=128, ACA 1e-3, 64 RHS each: theta=90, phi=k*5.625 deg, theta-pol",
+        count=32, freq_hz=600e6, seed=0, leaf_max=128, aca_tol=1e-3,
+        rhs=("phi_list", {"phi": [k * 5.625 for k in range(64)]})),
+    "ellipsoids3_150MHz_small": dict(
+        desc="3 seed-drawn PEC ellipsoids as above at 150 MHz (a few thousand RWG in all), "
+             "leaf<=64, ACA 1e-3, 8 RHS: theta=90, phi=k*45 deg (small batching case)",
+        count=3, freq_hz=150e6, seed=0, leaf_max=64, aca_tol=1e-3, n_lo=100, n_hi=5000,
+        rhs=("phi_list", {"phi": [k * 45.0 for k in range(8)]})),
+}
+
+
+def batch_workload(name):
+    """Return dict(meshes=[(xyz, tri), ...], axes, freq_hz, leaf_max, aca_tol, khat, pol, ...)."""
+    w = dict(BATCH_WORKLOADS[name])
+    draws = batch_ellipsoids(w["count"], w["freq_hz"], w["seed"], w.get("n_lo", 2000), w.get("n_hi", 40000))
+    meshes = []
+    for axes, nu in draws:
+        xyz, tri = geodesic_sphere(nu, 1.0)
+        meshes.append(ellipsoid_mesh(xyz, tri, axes))
+    kind, kw = w["rhs"]
+    khat, pol = plane_wave_dirs(kind, **kw)
+    w.update(meshes=meshes, axes=[a for a, _ in draws], nu=[n for _, n in draws], khat=khat, pol=pol, name=name)
+    return w
+
+
 def workload(name):
     """Return dict(xyz, tri, freq_hz, leaf_max, aca_tol, khat, pol, ...)."""
     w = dict(WORKLOADS[name])
