@@ -65,6 +65,7 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // sum over k is unchanged.  Operands come straight from L2 (no LDS).
 constexpr int TM = 32;
 constexpr int NB_SOLVE = 1, TN_SOLVE = 32 * NB_SOLVE;   // solve tiles: 32 rows x 32 RHS
+constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops over its share of sub-tiles)
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int MODE, int NB>
@@ -75,99 +76,115 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
   // and NB column blocks of 16 starting at 16 NB (w % 2)
   constexpr int TN = 32 * NB;
   const Tile t = tiles[blockIdx.x];
-  // r0 < 0: the tile stands for the whole m x n block and blockIdx.y picks
-  // its sub-tile (surplus y indices exit); else one explicit tile.
-  int rb = t.r0, cb = t.c0, tn = t.n;
+  // r0 < 0: the tile stands for the whole m x n block; workgroup y takes its
+  // sub-tiles y, y + gridDim.y, ...  c0 < 0: one row tile over ncols
+  // columns, blockIdx.y picks the column tile.  Else one explicit tile.
+  int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
   if (t.r0 < 0) {
-    const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
-    if ((int)blockIdx.y >= nsr * nsc) return;
-    rb = (blockIdx.y / nsc) * TM;
-    cb = (blockIdx.y % nsc) * TN;
-  } else if (t.c0 < 0) {             // one row tile over ncols columns, blockIdx.y picks the column tile
+    nsc = (t.n + TN - 1) / TN;
+    nsub = ((t.m + TM - 1) / TM) * nsc;
+    st0 = blockIdx.y;
+    sstep = gridDim.y;
+  } else if (t.c0 < 0) {
     tn = ncols;
-    cb = blockIdx.y * TN;
-    if (cb >= tn) return;
+    cb0 = blockIdx.y * TN;
+    if (cb0 >= tn) return;
   } else if (blockIdx.y > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
-  if (row0 >= t.m || col0 >= tn) return;             // wave-uniform
   const int li = lane & 15, lg = lane >> 4;
-  const int arow = row0 + li;
-  const bool arow_ok = arow < t.m;
-  d4 rr[NB], ii[NB], ri[NB], ir[NB];
+  for (int st = st0; st < nsub; st += sstep) {
+    int rb = rb0, cb = cb0;
+    if (t.r0 < 0) {
+      rb = (st / nsc) * TM;
+      cb = (st % nsc) * TN;
+    }
+    const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
+    if (row0 >= t.m || col0 >= tn) continue;           // wave-uniform
+    const int arow = row0 + li;
+    const bool arow_ok = arow < t.m;
+    // read-modify-write modes: fetch C now, so its latency hides behind the products
+    c2 cold[NB][4];
+    if (MODE != 0) {
 #pragma unroll
-  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int q = t.t_begin; q < t.t_end; ++q) {
-    const Term tm = terms[q];
-    const c2 *Ab = A + tm.a_off;
-    // full chunks of 16: lane group g reads k = k0 + 4 g + s (four consecutive)
-    const int kfull = tm.k & ~15;
-    for (int k0 = 0; k0 < kfull; k0 += 16) {
-      c2 av[4], bv[NB][4];
+      for (int j = 0; j < NB; ++j) {
+        const int ccol = col0 + 16 * j + li;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * lg + s;
-        av[s] = make_double2(0.0, 0.0);
-        if (arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+        for (int r = 0; r < 4; ++r) {
+          const int crow = row0 + lg + 4 * r;
+          cold[j][r] = make_double2(0.0, 0.0);
+          if (ccol < tn && crow < t.m) cold[j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+        }
+      }
+    }
+    d4 rr[NB], ii[NB], ri[NB], ir[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = t.t_begin; q < t.t_end; ++q) {
+      const Term tm = terms[q];
+      const c2 *Ab = A + tm.a_off;
+      // full chunks of 16: lane group g reads k = k0 + 4 g + s (four consecutive)
+      const int kfull = tm.k & ~15;
+      for (int k0 = 0; k0 < kfull; k0 += 16) {
+        c2 av[4], bv[NB][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = k0 + 4 * lg + s;
+          av[s] = make_double2(0.0, 0.0);
+          if (arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int bcol = col0 + 16 * j + li;
+            bv[j][s] = make_double2(0.0, 0.0);
+            if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
+            ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
+            ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
+            ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+          }
+      }
+      // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
+      for (int kt = kfull; kt < tm.k; kt += 4) {
+        const int k = kt + lg;
+        const bool kok = k < tm.k;
+        c2 av = make_double2(0.0, 0.0);
+        if (kok && arow_ok) av = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           const int bcol = col0 + 16 * j + li;
-          bv[j][s] = make_double2(0.0, 0.0);
-          if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          c2 bv = make_double2(0.0, 0.0);
+          if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
+          ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
+          ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ri[j], 0, 0, 0);
+          ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, ir[j], 0, 0, 0);
         }
       }
+    }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+    for (int j = 0; j < NB; ++j) {
+      const int ccol = col0 + 16 * j + li;
+      if (ccol >= tn) continue;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
-          ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
-          ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
-          ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+      for (int r = 0; r < 4; ++r) {
+        const int crow = row0 + lg + 4 * r;
+        if (crow >= t.m) continue;
+        const c2 acc = make_double2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
+        c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+        if (MODE == 0) {
+          *p = acc;
+        } else if (MODE == 1) {
+          *p = make_double2(cold[j][r].x - acc.x, cold[j][r].y - acc.y);
+        } else {
+          *p = make_double2(cold[j][r].x + acc.x, cold[j][r].y + acc.y);
         }
-    }
-    // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
-    for (int kt = kfull; kt < tm.k; kt += 4) {
-      const int k = kt + lg;
-      const bool kok = k < tm.k;
-      c2 av = make_double2(0.0, 0.0);
-      if (kok && arow_ok) av = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int bcol = col0 + 16 * j + li;
-        c2 bv = make_double2(0.0, 0.0);
-        if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-        rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
-        ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
-        ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ri[j], 0, 0, 0);
-        ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, ir[j], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int ccol = col0 + 16 * j + li;
-    if (ccol >= tn) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int crow = row0 + lg + 4 * r;
-      if (crow >= t.m) continue;
-      const c2 acc = make_double2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
-      c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
-      if (MODE == 0) {
-        *p = acc;
-      } else if (MODE == 1) {
-        c2 v = *p;
-        v.x -= acc.x;
-        v.y -= acc.y;
-        *p = v;
-      } else {
-        c2 v = *p;
-        v.x += acc.x;
-        v.y += acc.y;
-        *p = v;
       }
     }
   }
@@ -215,6 +232,20 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
   const int li = lane & 15, lg = lane >> 4;
   const int arow = row0 + li;
   const bool arow_ok = arow < t.m;
+  // read-modify-write modes: fetch C now, so its latency hides behind the products
+  float2 cold[NB][4];
+  if (MODE != 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int ccol = col0 + 16 * j + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int crow = row0 + 4 * lg + r;
+        cold[j][r] = make_float2(0.f, 0.f);
+        if (ccol < tn && crow < t.m) cold[j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+      }
+    }
+  }
   f4 rr[NB], ii[NB], ri[NB], ir[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = f4{0.f, 0.f, 0.f, 0.f};
@@ -286,15 +317,9 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       if (MODE == 0) {
         *p = acc;
       } else if (MODE == 1) {
-        float2 v = *p;
-        v.x -= acc.x;
-        v.y -= acc.y;
-        *p = v;
+        *p = make_float2(cold[j][r].x - acc.x, cold[j][r].y - acc.y);
       } else {
-        float2 v = *p;
-        v.x += acc.x;
-        v.y += acc.y;
-        *p = v;
+        *p = make_float2(cold[j][r].x + acc.x, cold[j][r].y + acc.y);
       }
     }
   }
@@ -1555,7 +1580,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     }
     I.launch_tiles(pool.dtiles.p + coefl[l].t0, pool.dterms.p, coefl[l].n, 0, I.F.p, Wd, I.F.p, 1, coefl[l].flops,
                    coefl[l].bytes);
-    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd, schurl[l].sub,
+    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd,
+                   std::min(schurl[l].sub, SUB_Y),
                    schurl[l].flops, schurl[l].bytes);
   }
   HIP_CHECK(hipEventRecord(e1, s));
