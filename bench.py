@@ -75,7 +75,31 @@ def parse():
     return ap.parse_args()
 
 
-def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
+def build_hmatrix(w):
+    """The H-matrix of the workload, built once on the host (not timed as
+    setup) and installed in every leg."""
+    from paper_2109_04129_amd import hps
+    h = hps.hps_create(-1)
+    try:
+        hps.hps_set_mesh(h, w["xyz"], w["tri"])
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1)
+        t0 = time.perf_counter()
+        hps.hps_build_hmatrix(h, p)
+        build_s = time.perf_counter() - t0
+        g = hps.hps_get_hmatrix(h)
+        g["N"] = hps.hps_num_unknowns(h)
+    finally:
+        hps.hps_destroy(h)
+    print("[bench] H-matrix built in %.1f s" % build_s, file=sys.stderr, flush=True)
+    return g, build_s
+
+
+def install(hps, ctx, p, g):
+    hps.hps_set_hmatrix(ctx, p, g["N"], g["perm"], g["group_ptr"], g["near_ts"], g["near_off"], g["near_vals"],
+                        g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
+
+
+def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
     import torch
     from paper_2109_04129_amd import hps
 
@@ -91,10 +115,7 @@ def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
     hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
     p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
                                precision=precision, refine_passes=refine)
-    t0 = time.perf_counter()
-    hps.hps_build_hmatrix(ctx, p)
-    build_s = time.perf_counter() - t0
-    print("[bench] H-matrix built in %.1f s" % build_s, file=sys.stderr, flush=True)
+    install(hps, ctx, p, g)
     N = hps.hps_num_unknowns(ctx)
     khat, pol = w["khat"], w["pol"]
     R = len(khat)
@@ -119,23 +140,24 @@ def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
         a, b, rcs, ratio = step()
         setup_t.append(a)
         solve_t.append(b)
+        print("[bench] step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     stats = hps.hps_stats(ctx)
+    hps.hps_destroy(ctx)
     err = None
     if reference_terms:
-        # full-size accuracy of this form against the plain FP64 path (parity-
-        # tested against the oracle) on the same H-matrix, at the matching
-        # number of series terms
+        # accuracy of this form against the plain FP64 path (parity-tested
+        # against the oracle) on the same H-matrix, at the matching number of
+        # series terms
         Xm = X.cpu().numpy()
+        del X
         p.precision, p.refine_passes, p.terms = 0, 0, reference_terms
         ref = hps.hps_create(0, stream.cuda_stream)
         hps.hps_set_mesh(ref, w["xyz"], w["tri"])
-        g = hps.hps_get_hmatrix(ctx)
-        hps.hps_set_hmatrix(ref, p, N, g["perm"], g["group_ptr"], g["near_ts"], g["near_off"], g["near_vals"],
-                            g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
+        install(hps, ref, p, g)
         hps.hps_setup(ref)
-        Xr = torch.zeros_like(X)
+        Xr = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
         _, rcs_r, _ = hps.hps_solve_planewaves(ref, khat, pol, Xr.data_ptr())
         torch.cuda.synchronize()
         Xr = Xr.cpu().numpy()
@@ -143,9 +165,8 @@ def gpu_leg(args, w, precision=0, refine=0, reference_terms=None):
         err = {"terms_of_reference": reference_terms,
                "current_rel_err_max": float(np.max(np.linalg.norm(Xm - Xr, axis=1) / np.linalg.norm(Xr, axis=1))),
                "rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs / rcs_r))))}
-    hps.hps_destroy(ctx)
     return dict(N=N, R=R, total=total, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
-                ratio=ratio, stats=stats, build_s=build_s, err=err)
+                ratio=ratio, stats=stats, err=err)
 
 
 def batch_leg(args):
@@ -311,12 +332,15 @@ def main():
         sys.exit(2)
     from workloads import workload
     w = workload(args.workload)
-    g = gpu_leg(args, w)
+    hm, build_s = build_hmatrix(w)
+    print("[bench] workload %s: %d unknowns, %d RHS" % (args.workload, hm["N"], len(w["khat"])), file=sys.stderr,
+          flush=True)
+    g = gpu_leg(args, w, hm)
     mixed = None
     if not args.no_mixed:
         forms = {}
         for prec, name in ((1, "bf16_far"), (2, "fp16_far")):
-            gm = gpu_leg(args, w, precision=prec, refine=1, reference_terms=4)
+            gm = gpu_leg(args, w, hm, precision=prec, refine=1, reference_terms=4)
             forms[name] = {"rhs_per_s_step": gm["R"] * args.steps / gm["total"],
                            "setup_s": float(np.median(gm["setup"])),
                            "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
@@ -355,7 +379,7 @@ def main():
                    "aca_tol": w["aca_tol"], "freq_hz": w["freq_hz"], "form": "plain fp64", "terms": 2},
         "setup_s": float(np.median(g["setup"])),
         "solve_rhs_per_s": float(R / np.median(g["solve"])),
-        "hmatrix_build_s": g["build_s"],
+        "hmatrix_build_s": build_s,
         "ratio_max": float(np.max(g["ratio"])),
         "roofline": roofline,
         "precision_form": mixed,

@@ -55,7 +55,11 @@ typedef enum {
 
 typedef struct {
   double freq_hz;          /* > 0 */
-  int32_t leaf_max;        /* max unknowns per octree leaf (group), >= 1 */
+  int32_t leaf_max;        /* max unknowns per octree leaf (group), 1..1024.  Groups
+                              above 128 unknowns are eliminated as consecutive
+                              sub-groups of at most 128 (the pivot blocks of the
+                              setup); currents do not depend on it, the eq. (45)
+                              ratio does */
   double aca_tol;          /* eps of eq. (12), Frobenius, per far block, in (0, 1) */
   int32_t precision;       /* 0: FP64 throughout.  1: FP32 solve (D^-1, scaling
                               blocks, vectors) with BF16 far factors and a per-block
@@ -76,10 +80,12 @@ typedef struct {
                               kernel is launched from the host on each call.  Same
                               results either way.  Solves run eagerly while
                               hps_profile is on. */
+  int32_t verbose;         /* 1: the host H-matrix build reports its progress on
+                              stderr; 0 (default): silent */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
-   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1.
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 
@@ -129,7 +135,9 @@ hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
                       block b stores U (m x r, column-major) then V (n x r,
                       column-major), m = thi - tlo, n = shi - slo, with
                       Z[t, s] ~= U V^T and Z[s, t] ~= V U^T.
-   p supplies freq_hz (for excitation / RCS) and the solve options. */
+   p supplies freq_hz (for excitation / RCS) and the solve options.  Groups of
+   more than 128 unknowns are cut into consecutive sub-groups (near blocks cut
+   to match), as after hps_build_hmatrix. */
 hps_status hps_set_hmatrix(hps_ctx *ctx, const hps_params *p, int64_t N, const int64_t *perm,
                            int64_t M, const int64_t *group_ptr, int64_t n_near,
                            const int32_t *near_ts, const int64_t *near_off,
@@ -141,8 +149,9 @@ hps_status hps_set_hmatrix(hps_ctx *ctx, const hps_params *p, int64_t N, const i
    *M, *n_near, *n_far, *near_elems (total near c128 entries), *far_elems. */
 hps_status hps_hmatrix_sizes(const hps_ctx *ctx, int64_t *M, int64_t *n_near, int64_t *n_far,
                              int64_t *near_elems, int64_t *far_elems);
-/* Copy out the structure (host arrays sized by hps_hmatrix_sizes, same layout
-   as hps_set_hmatrix; any pointer may be NULL). */
+/* Copy out the structure (host arrays sized by hps_hmatrix_sizes, layout as
+   in hps_set_hmatrix, groups as held, i.e. after any cut of groups above 128
+   unknowns; any pointer may be NULL). */
 hps_status hps_get_hmatrix(const hps_ctx *ctx, int64_t *perm, int64_t *group_ptr, int32_t *near_ts,
                            int64_t *near_off, double *near_vals, int64_t *far_rng,
                            int32_t *far_rank, int64_t *far_off, double *far_uv);

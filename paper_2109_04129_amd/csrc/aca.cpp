@@ -9,6 +9,7 @@
 // the rank would reach m n / (m + n) the block is formed in full and truncated
 // by its SVD.  Recompression: QR of U and V, SVD of R_U R_V^T, truncation to
 // the smallest rank whose discarded singular values have norm <= eps ||s||.
+#include <cstdio>
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -300,13 +301,20 @@ void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *co
 }
 
 // ---------------------------------------------------------------- assembly
+// f(i) for i in [0, n) on `threads` host threads; with a label, every tenth
+// of the items started is reported on stderr.
 template <class F>
-static void parallel_for(int64_t n, int threads, F &&f) {
+static void parallel_for(int64_t n, int threads, F &&f, const char *label = nullptr) {
   std::atomic<int64_t> next{0};
+  const int64_t tenth = std::max<int64_t>(n / 10, 1);
   auto work = [&]() {
     while (true) {
       const int64_t i = next.fetch_add(1);
       if (i >= n) break;
+      if (label && i % tenth == 0) {
+        std::fprintf(stderr, "[hps] %s: %lld of %lld\n", label, (long long)i, (long long)n);
+        std::fflush(stderr);
+      }
       f(i);
     }
   };
@@ -347,7 +355,7 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
     const int64_t t = H.near_ts[2 * b], s = H.near_ts[2 * b + 1];
     op.block(&H.perm[H.gptr[t]], H.gptr[t + 1] - H.gptr[t], &H.perm[H.gptr[s]],
              H.gptr[s + 1] - H.gptr[s], &H.near_vals[H.near_off[b]]);
-  });
+  }, p.verbose ? "near blocks" : nullptr);
 
   const int64_t nf = (int64_t)far.size();
   H.far_rng.resize(4 * nf);
@@ -364,7 +372,7 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
     int r = 0;
     aca_block(op, &H.perm[tlo], thi - tlo, &H.perm[slo], shi - slo, p.aca_tol, Us[b], Vs[b], r);
     H.far_rank[b] = r;
-  });
+  }, p.verbose ? "far blocks (ACA)" : nullptr);
   H.far_off.assign(nf + 1, 0);
   for (int64_t b = 0; b < nf; ++b) H.far_off[b + 1] = H.far_off[b] + (int64_t)(Us[b].size() + Vs[b].size());
   H.far_uv.resize(H.far_off[nf]);

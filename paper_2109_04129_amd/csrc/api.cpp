@@ -65,7 +65,7 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (!p) return fail(c, HPS_EINVAL, "params is NULL");
   if (!(p->freq_hz > 0.0) || !std::isfinite(p->freq_hz)) return fail(c, HPS_EINVAL, "freq_hz must be > 0");
   if (p->leaf_max < 1) return fail(c, HPS_EINVAL, "leaf_max must be >= 1");
-  if (p->leaf_max > 128) return fail(c, HPS_EINVAL, "leaf_max above 128 is not supported by the setup kernels");
+  if (p->leaf_max > 1024) return fail(c, HPS_EINVAL, "leaf_max must be <= 1024");
   if (!(p->aca_tol > 0.0 && p->aca_tol < 1.0)) return fail(c, HPS_EINVAL, "aca_tol must be in (0, 1)");
   if (p->terms < 1) return fail(c, HPS_EINVAL, "terms must be >= 1");
   if (p->refine_passes < 0) return fail(c, HPS_EINVAL, "refine_passes must be >= 0");
@@ -111,7 +111,6 @@ hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64
   for (int64_t g = 0; g < M; ++g) {
     const int64_t sz = H.gptr[g + 1] - H.gptr[g];
     if (sz < 1) throw hps::Error{HPS_EINVAL, "empty group"};
-    if (sz > 128) throw hps::Error{HPS_EINVAL, "group larger than 128 unknowns"};
   }
   H.near_ts.assign(near_ts, near_ts + 2 * n_near);
   H.near_off.assign(near_off, near_off + n_near + 1);
@@ -145,6 +144,7 @@ hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64
   const int64_t fe = n_far > 0 ? far_off[n_far] : 0;
   H.far_uv.resize(fe);
   if (fe) std::memcpy((void *)H.far_uv.data(), far_uv, fe * sizeof(hps::cplx));
+  hps::split_groups(H, hps::kMaxPivot);
   return H;
 }
 
@@ -170,6 +170,7 @@ hps_status hps_params_default(hps_params *p) {
   p->host_threads = 0;
   p->ordering = 0;
   p->graphs = 1;
+  p->verbose = 0;
   return HPS_OK;
 }
 
@@ -351,6 +352,7 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
       for (int32_t q = 0; q < c->n_prob; ++q) {
         hps::HMatrix H;
         hps::build_hmatrix(c->pmesh[q], *p, H);
+        hps::split_groups(H, hps::kMaxPivot);
         c->pH[q] = std::move(H);
         c->pH_ok[q] = 1;
       }
@@ -358,6 +360,7 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
     } else {
       hps::HMatrix H;
       hps::build_hmatrix(c->mesh, *p, H);
+      hps::split_groups(H, hps::kMaxPivot);
       c->H = std::move(H);
       single_segments(c);
     }

@@ -80,3 +80,56 @@ void merge_problems(const std::vector<Mesh> &meshes, const std::vector<HMatrix> 
 }
 
 }  // namespace hps
+
+namespace hps {
+
+// Pivot blocks are at most max_size unknowns (the register-resident inverse):
+// a larger group is cut into consecutive sub-groups of near-equal size, which
+// the setup eliminates one after the other like any other groups.  The near
+// blocks are cut along the same lines (upper triangle of the group pattern
+// kept); far blocks refer to tree-position ranges and are unchanged.
+void split_groups(HMatrix &H, int64_t max_size) {
+  const int64_t M = H.M;
+  bool any = false;
+  for (int64_t g = 0; g < M; ++g) any = any || (H.gptr[g + 1] - H.gptr[g] > max_size);
+  if (!any) return;
+  std::vector<int64_t> ng0(M + 1, 0), gptr{0};
+  for (int64_t g = 0; g < M; ++g) {
+    const int64_t s = H.gptr[g + 1] - H.gptr[g];
+    const int64_t parts = (s + max_size - 1) / max_size, base = s / parts, extra = s % parts;
+    int64_t pos = H.gptr[g];
+    for (int64_t q = 0; q < parts; ++q) {
+      pos += base + (q < extra ? 1 : 0);
+      gptr.push_back(pos);
+    }
+    ng0[g + 1] = ng0[g] + parts;
+  }
+  std::vector<int32_t> ts;
+  std::vector<int64_t> off{0};
+  std::vector<cplx> vals;
+  ts.reserve(H.near_ts.size());
+  vals.reserve(H.near_vals.size());
+  for (int64_t b = 0; b < H.n_near(); ++b) {
+    const int32_t t = H.near_ts[2 * b], s = H.near_ts[2 * b + 1];
+    const int64_t ns = H.gptr[s + 1] - H.gptr[s];
+    const cplx *blk = H.near_vals.data() + H.near_off[b];
+    for (int64_t ta = ng0[t]; ta < ng0[t + 1]; ++ta)
+      for (int64_t sb = (t == s ? ta : ng0[s]); sb < ng0[s + 1]; ++sb) {
+        const int64_t r0 = gptr[ta] - H.gptr[t], r1 = gptr[ta + 1] - H.gptr[t];
+        const int64_t c0 = gptr[sb] - H.gptr[s], c1 = gptr[sb + 1] - H.gptr[s];
+        for (int64_t r = r0; r < r1; ++r)
+          vals.insert(vals.end(), blk + r * ns + c0, blk + r * ns + c1);
+        ts.push_back((int32_t)ta);
+        ts.push_back((int32_t)sb);
+        off.push_back((int64_t)vals.size());
+      }
+  }
+  if (ng0[M] > INT32_MAX) throw Error{HPS_EINVAL, "too many groups"};
+  H.M = ng0[M];
+  H.gptr = std::move(gptr);
+  H.near_ts = std::move(ts);
+  H.near_off = std::move(off);
+  H.near_vals = std::move(vals);
+}
+
+}  // namespace hps

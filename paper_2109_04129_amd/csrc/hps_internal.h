@@ -133,4 +133,9 @@ void make_plan(const HMatrix &H, const Mesh &mesh, int ordering, const std::vect
 void merge_problems(const std::vector<Mesh> &meshes, const std::vector<HMatrix> &Hs, Mesh &mesh, HMatrix &H,
                     std::vector<int64_t> &nseg, std::vector<int64_t> &gseg);
 
+// Cut groups larger than max_size unknowns into consecutive sub-groups
+// (near blocks cut to match, far blocks unchanged).
+void split_groups(HMatrix &H, int64_t max_size);
+constexpr int64_t kMaxPivot = 128;   // largest pivot block of the setup kernels
+
 }  // namespace hps

@@ -36,7 +36,7 @@ class hps_params(ctypes.Structure):
                 ("terms", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
                 ("ratio_warn", ctypes.c_double), ("device_mem_cap", ctypes.c_uint64),
                 ("host_threads", ctypes.c_int32), ("ordering", ctypes.c_int32),
-                ("graphs", ctypes.c_int32)]
+                ("graphs", ctypes.c_int32), ("verbose", ctypes.c_int32)]
 
 
 _lib = None

@@ -27,3 +27,17 @@ def hmatrix_arrays(H):
 
 def per_rhs_rel(x, ref):
     return np.linalg.norm(x - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+def dense_near_from_arrays(a):
+    """Dense near field (tree order) of an H-matrix given as hps_set_hmatrix
+    arrays; the (s, t) block is the transpose of the stored (t, s) one."""
+    gp = a["group_ptr"]
+    N = int(gp[-1])
+    Z = np.zeros((N, N), dtype=np.complex128)
+    for b, (t, s) in enumerate(np.asarray(a["near_ts"]).reshape(-1, 2)):
+        m, n = gp[t + 1] - gp[t], gp[s + 1] - gp[s]
+        B = a["near_vals"][a["near_off"][b]:a["near_off"][b + 1]].reshape(m, n)
+        Z[gp[t]:gp[t + 1], gp[s]:gp[s + 1]] = B
+        Z[gp[s]:gp[s + 1], gp[t]:gp[t + 1]] = B.T
+    return Z

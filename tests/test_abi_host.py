@@ -173,3 +173,37 @@ def test_host_batch_merge_and_errors():
         for c in single:
             hps.hps_destroy(c)
 
+
+
+def test_groups_above_128_are_cut(c0_workload):
+    """Leaves of up to 256 unknowns: the library holds groups of at most 128,
+    and its near field is the oracle's (groups of up to 256) entry for entry."""
+    from oracle.hmatrix import build_hmatrix
+    from hmat_io import dense_near_from_arrays
+    w = c0_workload
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], 256, w["aca_tol"], workers=min(8, os.cpu_count() or 1))
+    assert (H.groups[:, 1] - H.groups[:, 0]).max() > 128
+    ctx = hps.hps_create(-1)
+    try:
+        hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=256, aca_tol=w["aca_tol"]))
+        L = hps.hps_get_hmatrix(ctx)
+        L["N"] = hps.hps_num_unknowns(ctx)
+        # installing the oracle's H-matrix cuts its groups the same way
+        from hmat_io import hmatrix_arrays
+        a = hmatrix_arrays(H)
+        hps.hps_set_hmatrix(ctx, hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=256), a["N"], a["perm"],
+                            a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"], a["far_rng"],
+                            a["far_rank"], a["far_off"], a["far_uv"])
+        I = hps.hps_get_hmatrix(ctx)
+    finally:
+        hps.hps_destroy(ctx)
+    for X in (L, I):
+        sizes = np.diff(X["group_ptr"])
+        assert sizes.max() <= 128 and sizes.min() >= 1
+        assert np.array_equal(X["perm"], H.perm)
+    assert np.array_equal(I["group_ptr"], L["group_ptr"])
+    Zo = H.dense_near()
+    assert np.array_equal(dense_near_from_arrays(I), Zo)          # pure re-layout of the same values
+    assert np.abs(dense_near_from_arrays(L) - Zo).max() <= 1e-13 * np.abs(Zo).max()
+    assert np.array_equal(L["far_rng"], I["far_rng"])

@@ -93,6 +93,29 @@ def test_sphere_1920_two_terms(c0_workload, c0_hmatrix, ordering):
         hps.hps_destroy(ctx)
 
 
+def test_leaves_of_256(c0_workload):
+    """Oracle H-matrix with leaves of up to 256 unknowns (oracle pivots = those
+    groups); the library cuts them into pivots of at most 128.  Currents and
+    RCS do not depend on the blocking of the elimination."""
+    w = c0_workload
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], 256, w["aca_tol"], workers=8)
+    sizes = H.groups[:, 1] - H.groups[:, 0]
+    print("case: sphere 1,920 unknowns, leaves <= 256 (max %d), T=2" % sizes.max(), flush=True)
+    assert sizes.max() > 128
+    khat, pol = monostatic_angles([0.0, 60.0, 120.0], [0.0, 30.0, 90.0])
+    ctx = _ctx()
+    try:
+        _install(ctx, H, w["xyz"], w["tri"], w["freq_hz"], terms=2, leaf=256)
+        st, X, rcs, ratio = _solve(ctx, H.N, khat, pol)
+        x, ratios, sig = _oracle(H, w["freq_hz"], khat, pol, 2)
+        err = per_rhs_rel(X, x)
+        print("max rel current err", err.max(), flush=True)
+        assert err.max() < 1e-10
+        assert np.max(np.abs(10 * np.log10(rcs / sig))) < 1e-6
+    finally:
+        hps.hps_destroy(ctx)
+
+
 @pytest.mark.parametrize("terms", [1, 2, 3])
 def test_small_sphere_ragged_rhs(small, terms):
     """480 unknowns in 56 groups of 1..16, 37 RHS (ragged RHS tiles)."""
