@@ -419,20 +419,21 @@ __global__ __launch_bounds__(256) void k_far16(const c2 *__restrict__ in, uint32
 
 // ------------------------------------------------------------------ inverse
 // Gauss-Jordan inversion with partial pivoting (row interchanges recorded,
-// not performed) of n x n blocks, n <= NC, one block per workgroup of 4 NC
+// not performed) of n x n blocks, n <= NC, one block per workgroup of 8 NC
 // threads.  Equivalent to LU with partial pivoting followed by the inverse.
 // A zero pivot column flags the block as singular.
 //
-// Tile layout: thread (rg, cg) with tid = rg + RB*cg owns rows rg*4..rg*4+3 and
-// columns cg*CT..cg*CT+CT-1 (RB = NC/4 row groups, 16 column groups, CT = NC/16).
-// One barrier per elimination step.
+// Tile layout: thread (rg, cg) with tid = rg + RB*cg owns rows rg*2, rg*2+1 and
+// columns cg*CT..cg*CT+CT-1 (RB = NC/2 row groups, 16 column groups, CT = NC/16;
+// a column group lies inside one wave).  One barrier per elimination step.
 template <int NC>
-__global__ __launch_bounds__(4 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
+__global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
                                                     const int64_t *__restrict__ off,
                                                     const int32_t *__restrict__ nsz,
                                                     const int32_t *__restrict__ ids,
                                                     int *__restrict__ status) {
-  constexpr int RT = 4, RB = NC / RT, CT = NC / 16;
+  constexpr int RT = 2, RB = NC / RT, CT = NC / 16;
+  static_assert(64 % RB == 0, "a column group must lie inside one wave");
   const int blk = blockIdx.x;
   const int n = nsz[blk];
   const c2 *src = W + off[blk];
@@ -1570,11 +1571,11 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       const int32_t *pn = d_inv_n.p + li.start, *pi = d_inv_id.p + li.start;
       Impl::ProfRec *pr = I.prof_begin(3, li.flops, 0.0, li.count);
       if (li.nc == 32)
-        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(128), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else if (li.nc == 64)
-        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       else
-        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(1024), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
       HIP_CHECK(hipGetLastError());
       I.prof_end(pr);
     }
