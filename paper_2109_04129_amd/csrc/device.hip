@@ -60,9 +60,9 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // accumulators; re = rr - ii, im = ri + ir).  Operand layout of the
 // instruction: lane l supplies A[l % 16][k slot l / 16] and B[k slot
 // l / 16][l % 16]; result register r of lane l is D[l / 16 + 4 r][l % 16].
-// The contraction index is permuted so that each lane reads four
-// consecutive k (k = k0 + 4 (l / 16) + s in step s) for both operands; the
-// sum over k is unchanged.  Operands come straight from L2 (no LDS).
+// In step s of a chunk of 16 the lane groups take k = k0 + 4 s + l / 16, so
+// one load instruction reads four consecutive elements of each of 16 rows
+// (A) or columns (B).  Operands come straight from L2 (no LDS).
 constexpr int TM = 32;
 constexpr int NB_SOLVE = 1, TN_SOLVE = 32 * NB_SOLVE;   // solve tiles: 32 rows x 32 RHS
 constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops over its share of sub-tiles)
@@ -124,13 +124,13 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
     for (int q = t.t_begin; q < t.t_end; ++q) {
       const Term tm = terms[q];
       const c2 *Ab = A + tm.a_off;
-      // full chunks of 16: lane group g reads k = k0 + 4 g + s (four consecutive)
+      // full chunks of 16: in step s lane group g reads k = k0 + 4 s + g
       const int kfull = tm.k & ~15;
       for (int k0 = 0; k0 < kfull; k0 += 16) {
         c2 av[4], bv[NB][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int k = k0 + 4 * lg + s;
+          const int k = k0 + 4 * s + lg;
           av[s] = make_double2(0.0, 0.0);
           if (arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
 #pragma unroll
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       float2 av[4], bv[NB][4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * lg + s;
+        const int k = k0 + 4 * s + lg;
         av[s] = make_float2(0.f, 0.f);
         if (arow_ok) {
           const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
