@@ -82,10 +82,20 @@ typedef struct {
                               hps_profile is on. */
   int32_t verbose;         /* 1: the host H-matrix build reports its progress on
                               stderr; 0 (default): silent */
+  double leaf_box_min;     /* metres; > 0: octree cells narrower than this are never
+                              created, so leaves may hold more than leaf_max unknowns
+                              (electrically sized leaves, Sec. V.A: about half a
+                              wavelength for two-term convergence); 0 (default): off */
+  double series_tol;       /* > 0: adaptive series, `terms` is the maximum; the series
+                              stops after the first term t with ||it_t|| / ||it_0||
+                              < series_tol for every RHS (eqs. 35-36, 45); the
+                              precision form's residual pass uses as many terms.
+                              Solves are then launched without graphs.  0 (default):
+                              exactly `terms` terms */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
-   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0.
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 

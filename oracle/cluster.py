@@ -9,7 +9,10 @@ fix the leaf size by unknown count, so the tree is an octree:
   minimum and s = (largest extent) * (1 + 2^-20);
 * integer coordinates q = floor((p - lo) / s * 2^21) (clamped to 2^21 - 1);
   a cell at depth d holds the points with q >> (21 - d) equal to its coords;
-* a cell is split while it holds more than ``leaf_max`` points (depth <= 21);
+* a cell is split while it holds more than ``leaf_max`` points (depth <= 21)
+  and, when a minimum box side is given, while its children would still be at
+  least that wide (electrically sized leaves, Sec. V.A: leaves of at least
+  half a wavelength for two-term convergence);
   non-empty children are visited in the order c = 4 bx + 2 by + bz;
 * unknowns inside a leaf are ordered by RWG index; the tree order of the
   unknowns is the depth-first order of the leaves.
@@ -47,21 +50,35 @@ class Node:
         return [(c << sh, (c + 1) << sh) for c in self.ijk]
 
 
+def root_side(points):
+    ext = points.max(axis=0) - points.min(axis=0)
+    return ext.max() * (1.0 + 2.0 ** -20)
+
+
 def integer_coords(points):
     lo = points.min(axis=0)
-    ext = points.max(axis=0) - lo
-    s = ext.max() * (1.0 + 2.0 ** -20)
+    s = root_side(points)
     q = np.floor((points - lo) / s * float(1 << DEPTH_MAX)).astype(np.int64)
     return np.clip(q, 0, (1 << DEPTH_MAX) - 1)
 
 
-def build_tree(points, leaf_max):
-    q = integer_coords(np.asarray(points, dtype=np.float64))
+def depth_limit(side, box_min):
+    """Deepest level whose cells are still at least box_min wide."""
+    d = 0
+    while d < DEPTH_MAX and box_min > 0.0 and side / 2.0 ** (d + 1) >= box_min:
+        d += 1
+    return d if box_min > 0.0 else DEPTH_MAX
+
+
+def build_tree(points, leaf_max, box_min=0.0):
+    points = np.asarray(points, dtype=np.float64)
+    q = integer_coords(points)
+    dmax = depth_limit(root_side(points), box_min)
     root = Node(0, (0, 0, 0), np.arange(len(q)))
     stack = [root]
     while stack:
         nd = stack.pop()
-        if len(nd.pts) <= leaf_max or nd.depth >= DEPTH_MAX:
+        if len(nd.pts) <= leaf_max or nd.depth >= dmax:
             continue
         sh = DEPTH_MAX - nd.depth - 1
         bits = (q[nd.pts] >> sh) & 1

@@ -124,17 +124,18 @@ def _run(job, items, workers, chunk=64):
     return [r for c in res for r in c]
 
 
-def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1):
+def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0):
     """Mesh -> RWG -> octree -> near blocks (quadrature) + far blocks (ACA).
 
     With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
     near block (Z_F = 0), used to pin the series against a dense LU solve.
     ``workers`` > 1 evaluates independent blocks in forked processes (the
-    arithmetic of each block is unchanged).
+    arithmetic of each block is unchanged).  ``box_min`` > 0 stops the octree
+    at cells of at least that side (metres), whatever their unknown count.
     """
     rwg = build_rwg(xyz, tri)
     op = EFIEOperator(rwg, freq_hz)
-    tree = build_tree(edge_midpoints(rwg), leaf_max)
+    tree = build_tree(edge_midpoints(rwg), leaf_max, box_min)
     perm = tree["perm"]
     leaves = tree["leaves"]
     groups = np.array([(nd.lo, nd.hi) for nd in leaves], dtype=np.int64)

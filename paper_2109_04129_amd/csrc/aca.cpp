@@ -326,7 +326,7 @@ static void parallel_for(int64_t n, int threads, F &&f, const char *label = null
 
 void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
   Tree T;
-  build_tree(mesh, p.leaf_max, T);
+  build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
   block_partition(T, near, far);
   EFIE op(mesh, p.freq_hz);

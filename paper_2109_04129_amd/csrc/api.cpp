@@ -72,6 +72,10 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (p->precision < 0 || p->precision > 2) return fail(c, HPS_EINVAL, "precision must be 0, 1 or 2");
   if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
   if (p->graphs != 0 && p->graphs != 1) return fail(c, HPS_EINVAL, "graphs must be 0 or 1");
+  if (!(p->leaf_box_min >= 0.0) || !std::isfinite(p->leaf_box_min))
+    return fail(c, HPS_EINVAL, "leaf_box_min must be >= 0");
+  if (!(p->series_tol >= 0.0) || !std::isfinite(p->series_tol))
+    return fail(c, HPS_EINVAL, "series_tol must be >= 0");
   return HPS_OK;
 }
 
@@ -171,6 +175,8 @@ hps_status hps_params_default(hps_params *p) {
   p->ordering = 0;
   p->graphs = 1;
   p->verbose = 0;
+  p->leaf_box_min = 0.0;
+  p->series_tol = 0.0;
   return HPS_OK;
 }
 

@@ -752,6 +752,8 @@ struct DeviceState::Impl {
   DevArray<int64_t> dsoff;
   double k = 0.0, coef_rcs = 0.0, ratio_warn = 0.1;
   int terms = 2;
+  double series_tol = 0.0;         // > 0: stop the series once max ||it_t|| / ||it_0|| < series_tol
+  int terms_used = 0;              // terms of the last series
   uint64_t mem_cap = 0;
   // H-matrix on device
   DevArray<c2> near, faruv;
@@ -1015,14 +1017,15 @@ struct DeviceState::Impl {
   }
   // out = power series applied to in (FP32); in is kept.  With want_ratio
   // the eq. (45) ratios go to rat (device).  No host synchronisation.
-  void series32(int64_t R, const float2 *in, float2 *out, bool want_ratio) {
+  void series32(int64_t R, const float2 *in, float2 *out, bool want_ratio, int nterms) {
     const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
     const dim3 gn((unsigned)R, (unsigned)nseg);
     copy(wS.p, in, NR);
     for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
     launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-    if (want_ratio && terms > 1) {
+    const bool adapt = want_ratio && series_tol > 0.0;
+    if (want_ratio && nterms > 1) {
       hipLaunchKernelGGL(k_colnorm32, gn, dim3(256), 0, s, wI.p, N, dsoff.p, red.p);
       HIP_CHECK(hipGetLastError());
     }
@@ -1030,14 +1033,15 @@ struct DeviceState::Impl {
     for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, out, out);
     const float2 *wprev = out;
     float2 *wa = wW.p, *wb = wX.p;
-    for (int t = 1; t < terms; ++t) {
+    if (want_ratio) terms_used = 1;
+    for (int t = 1; t < nterms; ++t) {
       far32(wprev, wS.p, 0);
       for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
       launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
-      if (want_ratio && t == 1) {
+      if (want_ratio && (t == 1 || adapt)) {
         hipLaunchKernelGGL(k_colnorm32, gn, dim3(256), 0, s, wI.p, N, dsoff.p, red.p + RP);
         HIP_CHECK(hipGetLastError());
-        ratio_kernel(RP);
+        if (t == 1) ratio_kernel(RP);
       }
       copy(wa, (const float2 *)wI.p, NR);
       for (int64_t l = (int64_t)b_bwd.size() - 1; l >= 0; --l) launch32(b_bwd[l], 1, 0, F32.p, wa, wa);
@@ -1045,6 +1049,8 @@ struct DeviceState::Impl {
       HIP_CHECK(hipGetLastError());
       wprev = wa;
       std::swap(wa, wb);
+      if (want_ratio) terms_used = t + 1;
+      if (adapt && converged(RP)) break;
     }
   }
   void hmatvec32(const float2 *x, float2 *out) {
@@ -1056,12 +1062,12 @@ struct DeviceState::Impl {
   void solve32(int64_t R) {
     const int64_t NR = N * R;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    series32(R, wB.p, wY.p, true);
+    series32(R, wB.p, wY.p, true, terms);
     for (int it = 0; it < refine; ++it) {
       hmatvec32(wY.p, wZ.p);
       hipLaunchKernelGGL(k_sub32, dim3(gb), dim3(256), 0, s, wB.p, wZ.p, wR.p, NR);
       HIP_CHECK(hipGetLastError());
-      series32(R, wR.p, wZ.p, false);
+      series32(R, wR.p, wZ.p, false, terms_used);   // the residual pass uses as many terms
       hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, wY.p, wZ.p, 1.0f, NR);
       HIP_CHECK(hipGetLastError());
     }
@@ -1101,8 +1107,9 @@ struct DeviceState::Impl {
   // with that R replay.  Direct launches when graphs are off or kernels are
   // timed.
   void run(Graph &g, int64_t R, void (Impl::*fn)(int64_t)) {
-    if (!use_graphs || prof || (!(g.x && g.R == R) && g.pending != R)) {
-      if (use_graphs && !prof && !(g.x && g.R == R)) {
+    const bool capturable = use_graphs && !prof && series_tol <= 0.0;
+    if (!capturable || (!(g.x && g.R == R) && g.pending != R)) {
+      if (capturable && !(g.x && g.R == R)) {
         g.reset();
         g.pending = R;
       }
@@ -1153,8 +1160,21 @@ struct DeviceState::Impl {
     HIP_CHECK(hipGetLastError());
   }
 
+  // Adaptive series: squared norms of it_0 (red[0, RP)) and it_t (red[RP,
+  // 2 RP)) to the host; true when every problem and RHS has
+  // ||it_t|| / ||it_0|| < series_tol.  Synchronises the stream.
+  bool converged(int64_t RP) {
+    std::vector<double> n(2 * RP);
+    HIP_CHECK(hipMemcpyAsync(n.data(), red.p, 2 * RP * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    double q = 0.0;
+    for (int64_t i = 0; i < RP; ++i) q = std::max(q, n[RP + i] > 0.0 ? std::sqrt(n[RP + i] / n[i]) : 0.0);
+    return q < series_tol;
+  }
+
   // Power series (eqs. 25-36) on vB (elimination order, N x R): result in
-  // vY, eq. (45) ratios in rat.  Device work only (capturable).
+  // vY, eq. (45) ratios in rat.  Device work only (capturable) unless the
+  // term count is adaptive.
   void series(int64_t R) {
     const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
@@ -1165,14 +1185,13 @@ struct DeviceState::Impl {
     copy(vY.p, (const c2 *)vI.p, NR);
     sweep_bwd(vY.p);                               // w_0 = A it_0          (eq. 26)
     const c2 *wprev = vY.p;
+    terms_used = 1;
     for (int t = 1; t < terms; ++t) {
       far_apply(wprev, vS.p, 0);                   // s = Z_F w_{t-1}
       sweep_fwd(vS.p);                             // A^T s
       launch(b_dinv, 0, F.p, vS.p, vI.p);          // it_t = D^-1 A^T Z_F A it_{t-1}  (eq. 31)
-      if (t == 1) {
-        colnorm2(vI.p, R, red.p + RP);
-        ratio_kernel(RP);                          // ||it_1|| / ||it_0||   (eq. 45)
-      }
+      if (t == 1 || series_tol > 0.0) colnorm2(vI.p, R, red.p + RP);
+      if (t == 1) ratio_kernel(RP);                // ||it_1|| / ||it_0||   (eq. 45)
       copy(vW.p, (const c2 *)vI.p, NR);
       sweep_bwd(vW.p);                             // w_t = A it_t
       hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, vY.p, vW.p, (t & 1) ? -1.0 : 1.0, NR);
@@ -1181,6 +1200,8 @@ struct DeviceState::Impl {
       std::swap(vW.p, vX.p);
       std::swap(vW.n, vX.n);
       wprev = vX.p;
+      terms_used = t + 1;
+      if (series_tol > 0.0 && converged(RP)) break;
     }
   }
 };
@@ -1224,6 +1245,7 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   const double eta = mu0 * c0;
   I.coef_rcs = I.k * I.k * eta * eta / (4.0 * pi);
   I.terms = std::max(1, p.terms);
+  I.series_tol = p.series_tol;
   terms = I.terms;
   I.precision = p.precision;
   I.refine = std::max(0, p.refine_passes);
@@ -1923,6 +1945,7 @@ std::string DeviceState::stats_json() const {
       << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
+  o << ", \"terms\": " << I.terms << ", \"series_tol\": " << I.series_tol << ", \"terms_used\": " << I.terms_used;
   o << ", \"schedule_split\": {\"build_ms\": " << sched_split[0] << ", \"validate_ms\": " << sched_split[1]
     << ", \"upload_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
   o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms

@@ -53,7 +53,8 @@ struct Tree {
   std::vector<int32_t> leaf_node;
 };
 
-void build_tree(const Mesh &m, int leaf_max, Tree &t);
+// box_min > 0: cells narrower than box_min (metres) are never created.
+void build_tree(const Mesh &m, int leaf_max, double box_min, Tree &t);
 bool cells_touch(const TreeNode &a, const TreeNode &b);
 void block_partition(const Tree &t, std::vector<std::pair<int32_t, int32_t>> &near_leaves,
                      std::vector<std::pair<int32_t, int32_t>> &far_nodes);

@@ -6,7 +6,9 @@
 //
 // Cell coordinates: q = floor((p - lo) / s * 2^21), lo = per-axis minimum of
 // the edge midpoints, s = largest extent * (1 + 2^-20).  A cell splits while it
-// holds more than leaf_max points; children in the order 4 bx + 2 by + bz;
+// holds more than leaf_max points and its children would be at least box_min
+// wide (electrically sized leaves, Sec. V.A); children in the order
+// 4 bx + 2 by + bz;
 // unknowns inside a leaf sorted by RWG index; tree order = depth-first.
 #include <algorithm>
 #include <cmath>
@@ -17,7 +19,7 @@ namespace hps {
 
 static const int kDepth = 21;
 
-void build_tree(const Mesh &m, int leaf_max, Tree &T) {
+void build_tree(const Mesh &m, int leaf_max, double box_min, Tree &T) {
   const int64_t N = m.N;
   std::vector<double> pt(3 * N);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -32,6 +34,12 @@ void build_tree(const Mesh &m, int leaf_max, Tree &T) {
   for (int d = 0; d < 3; ++d) ext = std::max(ext, hi[d] - lo[d]);
   const double s = ext * (1.0 + std::ldexp(1.0, -20));
   const double scale = (double)(1 << kDepth);
+  // deepest level whose cells are at least box_min wide
+  int depth_cap = kDepth;
+  if (box_min > 0.0) {
+    depth_cap = 0;
+    while (depth_cap < kDepth && s / std::ldexp(1.0, depth_cap + 1) >= box_min) ++depth_cap;
+  }
   std::vector<int64_t> q(3 * N);
   for (int64_t n = 0; n < N; ++n)
     for (int d = 0; d < 3; ++d) {
@@ -61,7 +69,7 @@ void build_tree(const Mesh &m, int leaf_max, Tree &T) {
     T.nodes.push_back(nd);
     kids.emplace_back();
     if (it.parent >= 0) kids[it.parent].push_back(id);
-    if ((int64_t)it.pts.size() <= leaf_max || it.depth >= kDepth) {
+    if ((int64_t)it.pts.size() <= leaf_max || it.depth >= depth_cap) {
       std::sort(it.pts.begin(), it.pts.end());
       T.nodes[id].leaf = (int32_t)T.leaf_node.size();
       T.leaf_node.push_back(id);

@@ -36,7 +36,8 @@ class hps_params(ctypes.Structure):
                 ("terms", ctypes.c_int32), ("refine_passes", ctypes.c_int32),
                 ("ratio_warn", ctypes.c_double), ("device_mem_cap", ctypes.c_uint64),
                 ("host_threads", ctypes.c_int32), ("ordering", ctypes.c_int32),
-                ("graphs", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("graphs", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("leaf_box_min", ctypes.c_double), ("series_tol", ctypes.c_double)]
 
 
 _lib = None

@@ -207,3 +207,30 @@ def test_groups_above_128_are_cut(c0_workload):
     assert np.array_equal(dense_near_from_arrays(I), Zo)          # pure re-layout of the same values
     assert np.abs(dense_near_from_arrays(L) - Zo).max() <= 1e-13 * np.abs(Zo).max()
     assert np.array_equal(L["far_rng"], I["far_rng"])
+
+
+def test_minimum_box_side_matches_oracle(c0_workload):
+    """Leaves of at least half a wavelength (0.75 m at 200 MHz): the library's
+    tree and near/far split equal the oracle's (groups above 128 unknowns cut
+    into consecutive pivots), and its near field equals the oracle's."""
+    from oracle.hmatrix import build_hmatrix
+    from hmat_io import dense_near_from_arrays
+    w = c0_workload
+    box = 0.5 * 299792458.0 / w["freq_hz"]
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], 64, w["aca_tol"], workers=min(8, os.cpu_count() or 1),
+                      box_min=box)
+    assert (H.groups[:, 1] - H.groups[:, 0]).max() > 64
+    ctx = hps.hps_create(-1)
+    try:
+        hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=64, aca_tol=w["aca_tol"],
+                                                          leaf_box_min=box))
+        L = hps.hps_get_hmatrix(ctx)
+    finally:
+        hps.hps_destroy(ctx)
+    assert np.array_equal(L["perm"], H.perm)
+    assert set(H.groups[:, 0]) <= set(L["group_ptr"][:-1])          # library groups refine the oracle's
+    assert np.diff(L["group_ptr"]).max() <= 128
+    assert np.array_equal(L["far_rng"].reshape(-1, 4), np.array([f[:4] for f in H.far]).reshape(-1, 4))
+    Zo = H.dense_near()
+    assert np.abs(dense_near_from_arrays(L) - Zo).max() <= 1e-13 * np.abs(Zo).max()

@@ -214,3 +214,67 @@ def test_precision_form(c0_workload, c0_hmatrix, precision, refine, bar):
     assert err < bar
     assert db < 0.1
     assert np.allclose(ratio, ratios[0], rtol=1e-2)
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-9), (2, 1e-4)])
+def test_adaptive_series_reaches_the_direct_solution(small, precision, bar):
+    """With the far field scaled by 0.1 the series contracts; the adaptive
+    term count (series_tol) runs it until ||it_t|| / ||it_0|| < 1e-11 and the
+    currents equal the direct solution of (Z_N + 0.1 Z_F) x = b (dense LU of
+    the oracle's blocks), which the series converges to (eqs. 27-36)."""
+    xyz, tri, H = small
+    a = hmatrix_arrays(H)
+    c = 0.1
+    a["far_uv"] = a["far_uv"] * np.sqrt(c)           # U and V scaled: every far block times c
+    khat, pol = monostatic_angles([0.0, 75.0, 160.0], [0.0, 40.0, 250.0])
+    b = excitation(H.rwg, 300e6, khat, pol)
+    Z = H.dense_near() + c * H.dense_far()           # tree order
+    P = H.perm
+    xt = np.linalg.solve(Z, b[P])
+    x = np.empty_like(xt)
+    x[P] = xt
+    print("case: small sphere, far field x 0.1, adaptive series, precision", precision, flush=True)
+    ctx = _ctx()
+    try:
+        hps.hps_set_mesh(ctx, xyz, tri)
+        p = hps.hps_params_default(freq_hz=300e6, leaf_max=16, aca_tol=1e-3, terms=80, series_tol=1e-11,
+                                   precision=precision, refine_passes=1 if precision else 0)
+        hps.hps_set_hmatrix(ctx, p, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
+                            a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(ctx)
+        st, X, rcs, ratio = _solve(ctx, H.N, khat, pol)
+        used = hps.hps_stats(ctx)["device"]["terms_used"]
+    finally:
+        hps.hps_destroy(ctx)
+    err = per_rhs_rel(X, x)
+    print("terms used", used, "max rel err vs direct", err.max(), "ratio", ratio, flush=True)
+    assert 2 < used < 80
+    assert err.max() < bar
+
+
+def test_half_wavelength_leaves():
+    """Electrically sized leaves (cells of at least half a wavelength, Sec.
+    V.A) on the 1,920-unknown sphere at 600 MHz (leaf_max 64 would split
+    further): library vs oracle on the oracle's H-matrix, currents and RCS
+    to the parity bar (the library's own build with the same rule matches
+    the oracle's, checked on the CPU)."""
+    xyz, tri = icosphere(3, 1.0)
+    f = 600e6
+    lam = 299792458.0 / f
+    H = build_hmatrix(xyz, tri, f, 16, 1e-3, workers=8, box_min=0.5 * lam)
+    sizes = H.groups[:, 1] - H.groups[:, 0]
+    print("case: sphere 1,920 unknowns at 600 MHz, leaves >= lambda/2 (%d groups, max %d, %d far blocks)"
+          % (H.M, sizes.max(), len(H.far)), flush=True)
+    assert len(H.far) > 0 and sizes.max() > 16
+    khat, pol = monostatic_angles([0.0, 90.0], [0.0, 0.0])
+    ctx = _ctx()
+    try:
+        _install(ctx, H, xyz, tri, f, terms=2, leaf=16)
+        st, X, rcs, ratio = _solve(ctx, H.N, khat, pol)
+    finally:
+        hps.hps_destroy(ctx)
+    x, _, sig = _oracle(H, f, khat, pol, 2)
+    err = per_rhs_rel(X, x)
+    print("max rel current err", err.max(), "ratio", ratio, flush=True)
+    assert err.max() < 1e-10
+    assert np.max(np.abs(10 * np.log10(rcs / sig))) < 1e-6

@@ -92,3 +92,27 @@ def test_hmatrix_vs_dense(c0_hmatrix, c0_dense):
     # holds only approximately block by block (observed max ~2.1 eps)
     errs = [rel(U @ V.T, Zt[tlo:thi, slo:shi]) for tlo, thi, slo, shi, U, V in H.far[::3]]
     assert max(errs) <= 5e-3 and np.median(errs) <= 1e-3
+
+
+def test_minimum_box_side_stops_the_tree():
+    """Electrically sized leaves: no cell narrower than box_min is created; a
+    leaf holds more than leaf_max points only at that depth limit."""
+    from oracle.cluster import root_side, depth_limit
+    xyz, tri = icosphere(3)
+    rwg = build_rwg(xyz, tri)
+    pts = edge_midpoints(rwg)
+    side = root_side(pts)
+    for box_min in (0.3, 0.75, 1.2, 5.0):
+        d = depth_limit(side, box_min)
+        assert side / 2.0 ** d >= box_min or d == 0
+        assert side / 2.0 ** (d + 1) < box_min
+        tree = build_tree(pts, 16, box_min)
+        assert np.array_equal(np.sort(tree["perm"]), np.arange(rwg["N"]))
+        for nd in tree["leaves"]:
+            assert nd.depth <= d
+            assert nd.hi - nd.lo <= 16 or nd.depth == d
+        if box_min >= side:
+            assert len(tree["leaves"]) == 1
+    # box_min = 0 is the plain count rule
+    a, b = build_tree(pts, 16), build_tree(pts, 16, 0.0)
+    assert np.array_equal(a["perm"], b["perm"]) and len(a["leaves"]) == len(b["leaves"])
