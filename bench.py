@@ -81,7 +81,7 @@ def build_hmatrix(w):
     from paper_2109_04129_amd import hps
     h = hps.hps_create(-1)
     try:
-        hps.hps_set_mesh(h, w["xyz"], w["tri"])
+        set_mesh(hps, h, w)
         p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1)
         t0 = time.perf_counter()
         hps.hps_build_hmatrix(h, p)
@@ -92,6 +92,10 @@ def build_hmatrix(w):
         hps.hps_destroy(h)
     print("[bench] H-matrix built in %.1f s" % build_s, file=sys.stderr, flush=True)
     return g, build_s
+
+
+def set_mesh(hps, ctx, w):
+    (hps.hps_set_open_mesh if w.get("open") else hps.hps_set_mesh)(ctx, w["xyz"], w["tri"])
 
 
 def install(hps, ctx, p, g):
@@ -112,7 +116,7 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
         del src, dst
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
-    hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+    set_mesh(hps, ctx, w)
     p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
                                precision=precision, refine_passes=refine)
     install(hps, ctx, p, g)
@@ -154,7 +158,7 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
         del X
         p.precision, p.refine_passes, p.terms = 0, 0, reference_terms
         ref = hps.hps_create(0, stream.cuda_stream)
-        hps.hps_set_mesh(ref, w["xyz"], w["tri"])
+        set_mesh(hps, ref, w)
         install(hps, ref, p, g)
         hps.hps_setup(ref)
         Xr = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
@@ -305,7 +309,8 @@ def cpu_leg(args, w):
     from oracle.series import PowerSeries
     workers = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
-    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"], workers=workers)
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"], workers=workers,
+                      open_surface=w.get("open", False))
     print("[bench] oracle H-matrix built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     S = schur_scaling(H, min_degree_order(group_graph(H)))

@@ -119,6 +119,12 @@ const char *hps_last_error(const hps_ctx *ctx);
 hps_status hps_set_mesh(hps_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri,
                         int64_t nt);
 
+/* Same for an open sheet (e.g. the square plate of Sec. V.C.2): edges that
+   belong to one triangle only (the rim) are accepted and carry no unknown;
+   the EFIE holds on open PEC surfaces.  Interior edges as in hps_set_mesh. */
+hps_status hps_set_open_mesh(hps_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri,
+                             int64_t nt);
+
 /* Number of RWG unknowns of the current mesh. */
 hps_status hps_num_unknowns(const hps_ctx *ctx, int64_t *N);
 

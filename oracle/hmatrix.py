@@ -124,7 +124,7 @@ def _run(job, items, workers, chunk=64):
     return [r for c in res for r in c]
 
 
-def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0):
+def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0, open_surface=False):
     """Mesh -> RWG -> octree -> near blocks (quadrature) + far blocks (ACA).
 
     With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
@@ -132,8 +132,10 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     ``workers`` > 1 evaluates independent blocks in forked processes (the
     arithmetic of each block is unchanged).  ``box_min`` > 0 stops the octree
     at cells of at least that side (metres), whatever their unknown count.
+    ``open_surface`` accepts boundary edges (an open PEC sheet such as the
+    square plate of Sec. V.C.2), which carry no unknown.
     """
-    rwg = build_rwg(xyz, tri)
+    rwg = build_rwg(xyz, tri, allow_open=open_surface)
     op = EFIEOperator(rwg, freq_hz)
     tree = build_tree(edge_midpoints(rwg), leaf_max, box_min)
     perm = tree["perm"]

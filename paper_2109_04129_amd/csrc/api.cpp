@@ -213,7 +213,7 @@ void hps_destroy(hps_ctx *c) {
 
 const char *hps_last_error(const hps_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
+static hps_status set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bool open) {
   if (!c) return HPS_EINVAL;
   if (c->n_prob) return fail(c, HPS_EINVAL, "batch context: use hps_batch_set_mesh");
   if (!xyz || !tri || nv <= 0 || nt <= 0) return fail(c, HPS_EINVAL, "empty mesh");
@@ -223,13 +223,21 @@ hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t
     m.nt = nt;
     m.xyz.assign(xyz, xyz + 3 * nv);
     m.tri.assign(tri, tri + 3 * nt);
-    hps::build_rwg(m);
+    hps::build_rwg(m, open);
     c->mesh = std::move(m);
     c->have_mesh = true;
     c->have_h = false;
     c->have_setup = false;
     return HPS_OK;
   });
+}
+
+hps_status hps_set_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
+  return set_mesh(c, xyz, nv, tri, nt, false);
+}
+
+hps_status hps_set_open_mesh(hps_ctx *c, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt) {
+  return set_mesh(c, xyz, nv, tri, nt, true);
 }
 
 hps_status hps_num_unknowns(const hps_ctx *c, int64_t *N) {

@@ -34,8 +34,10 @@ struct Mesh {
   std::vector<double> len;     // edge length
 };
 
-// Validates and builds the RWG functions; throws Error on bad meshes.
-void build_rwg(Mesh &m);
+// Validates and builds the RWG functions; throws Error on bad meshes.  With
+// allow_open, edges of one triangle (the rim of an open sheet) are accepted
+// and carry no unknown.
+void build_rwg(Mesh &m, bool allow_open = false);
 
 // ---------------------------------------------------------------- octree
 struct TreeNode {

@@ -20,7 +20,7 @@ struct EdgeRec {
 };
 }  // namespace
 
-void build_rwg(Mesh &m) {
+void build_rwg(Mesh &m, bool allow_open) {
   const int64_t nt = m.nt, nv = m.nv;
   if (nt <= 0 || nv <= 0) throw Error{HPS_EINVAL, "empty mesh"};
   for (int64_t i = 0; i < 3 * nt; ++i)
@@ -70,8 +70,13 @@ void build_rwg(Mesh &m) {
     size_t j = i;
     while (j < recs.size() && recs[j].a == recs[i].a && recs[j].b == recs[i].b) ++j;
     const size_t cnt = j - i;
-    if (cnt == 1) throw Error{HPS_EINVAL, "open boundary edge (" + std::to_string(recs[i].a) + "," +
-                                              std::to_string(recs[i].b) + ")"};
+    if (cnt == 1) {
+      if (!allow_open)
+        throw Error{HPS_EINVAL, "open boundary edge (" + std::to_string(recs[i].a) + "," + std::to_string(recs[i].b) +
+                                    ")"};
+      i = j;               // rim of an open sheet: no unknown
+      continue;
+    }
     if (cnt > 2) throw Error{HPS_EINVAL, "non-manifold edge"};
     const EdgeRec &r0 = recs[i], &r1 = recs[i + 1];
     if (r0.fwd == r1.fwd) throw Error{HPS_EINVAL, "inconsistent triangle orientation"};

@@ -21,7 +21,8 @@ EXPORTS = ["hps_params_default", "hps_create", "hps_destroy", "hps_last_error", 
            "hps_num_unknowns", "hps_build_hmatrix", "hps_set_hmatrix", "hps_hmatrix_sizes",
            "hps_get_hmatrix", "hps_setup", "hps_solve_planewaves", "hps_solve_rhs",
            "hps_excitation", "hps_hmatvec", "hps_profile", "hps_stats", "hps_batch_create",
-           "hps_batch_set_mesh", "hps_batch_set_hmatrix", "hps_num_problems", "hps_problem_unknowns"]
+           "hps_batch_set_mesh", "hps_batch_set_hmatrix", "hps_num_problems", "hps_problem_unknowns",
+           "hps_set_open_mesh"]
 
 
 class HpsError(RuntimeError):
@@ -66,6 +67,7 @@ def lib():
         L.hps_last_error.argtypes = [ctx]
         L.hps_last_error.restype = ctypes.c_char_p
         L.hps_set_mesh.argtypes = [ctx, vp, i64, vp, i64]
+        L.hps_set_open_mesh.argtypes = [ctx, vp, i64, vp, i64]
         L.hps_num_unknowns.argtypes = [ctx, P(i64)]
         L.hps_build_hmatrix.argtypes = [ctx, P(hps_params)]
         L.hps_set_hmatrix.argtypes = [ctx, P(hps_params), i64, vp, i64, vp, i64, vp, vp, vp,
@@ -131,6 +133,12 @@ def hps_set_mesh(ctx, xyz, tri):
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     return _check(ctx, lib().hps_set_mesh(ctx, _ptr(xyz), len(xyz), _ptr(tri), len(tri)))
+
+
+def hps_set_open_mesh(ctx, xyz, tri):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    return _check(ctx, lib().hps_set_open_mesh(ctx, _ptr(xyz), len(xyz), _ptr(tri), len(tri)))
 
 
 def hps_num_unknowns(ctx):

@@ -234,3 +234,34 @@ def test_minimum_box_side_matches_oracle(c0_workload):
     assert np.array_equal(L["far_rng"].reshape(-1, 4), np.array([f[:4] for f in H.far]).reshape(-1, 4))
     Zo = H.dense_near()
     assert np.abs(dense_near_from_arrays(L) - Zo).max() <= 1e-13 * np.abs(Zo).max()
+
+
+def test_open_plate_matches_oracle():
+    """Open sheet: hps_set_mesh rejects the rim, hps_set_open_mesh takes it;
+    the library's RWG numbering, tree, near/far split and near entries equal
+    the oracle's (open_surface=True)."""
+    from oracle.hmatrix import build_hmatrix
+    from workloads import workload
+    w = workload("plate_2lambda_300MHz")
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"],
+                      workers=min(8, os.cpu_count() or 1), open_surface=True)
+    ctx = hps.hps_create(-1)
+    try:
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        assert e.value.status == -1
+        hps.hps_set_open_mesh(ctx, w["xyz"], w["tri"])
+        assert hps.hps_num_unknowns(ctx) == H.N == 1160
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"],
+                                                          aca_tol=w["aca_tol"]))
+        L = hps.hps_get_hmatrix(ctx)
+    finally:
+        hps.hps_destroy(ctx)
+    assert np.array_equal(L["perm"], H.perm)
+    assert np.array_equal(L["group_ptr"], np.r_[H.groups[:, 0], H.N])
+    assert np.array_equal(L["far_rng"].reshape(-1, 4), np.array([f[:4] for f in H.far]))
+    keys = [tuple(x) for x in L["near_ts"].reshape(-1, 2)]
+    assert keys == sorted(H.near)
+    for b, k in enumerate(keys):
+        blk = L["near_vals"][L["near_off"][b]:L["near_off"][b + 1]].reshape(H.near[k].shape)
+        assert np.abs(blk - H.near[k]).max() <= 1e-13 * np.abs(H.near[k]).max()

@@ -35,8 +35,8 @@ def _ctx():
     return hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
 
 
-def _install(ctx, H, xyz, tri, freq, terms=2, leaf=128, ordering=0):
-    hps.hps_set_mesh(ctx, xyz, tri)
+def _install(ctx, H, xyz, tri, freq, terms=2, leaf=128, ordering=0, open_surface=False):
+    (hps.hps_set_open_mesh if open_surface else hps.hps_set_mesh)(ctx, xyz, tri)
     p = hps.hps_params_default(freq_hz=freq, leaf_max=leaf, aca_tol=1e-3, terms=terms, ordering=ordering)
     a = hmatrix_arrays(H)
     hps.hps_set_hmatrix(ctx, p, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
@@ -274,6 +274,26 @@ def test_half_wavelength_leaves():
     finally:
         hps.hps_destroy(ctx)
     x, _, sig = _oracle(H, f, khat, pol, 2)
+    err = per_rhs_rel(X, x)
+    print("max rel current err", err.max(), "ratio", ratio, flush=True)
+    assert err.max() < 1e-10
+    assert np.max(np.abs(10 * np.log10(rcs / sig))) < 1e-6
+
+
+def test_open_plate():
+    """The square plate of Sec. V.C.2 at 2 wavelengths (1,160 unknowns, open
+    surface, EFIE): GPU vs oracle on the oracle's H-matrix, theta = 0..180."""
+    from workloads import workload
+    w = workload("plate_2lambda_300MHz")
+    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"], workers=8, open_surface=True)
+    print("case: plate 2 lambda, 1,160 unknowns, %d RHS" % len(w["khat"]), flush=True)
+    ctx = _ctx()
+    try:
+        _install(ctx, H, w["xyz"], w["tri"], w["freq_hz"], terms=2, leaf=w["leaf_max"], open_surface=True)
+        st, X, rcs, ratio = _solve(ctx, H.N, w["khat"], w["pol"])
+    finally:
+        hps.hps_destroy(ctx)
+    x, _, sig = _oracle(H, w["freq_hz"], w["khat"], w["pol"], 2)
     err = per_rhs_rel(X, x)
     print("max rel current err", err.max(), "ratio", ratio, flush=True)
     assert err.max() < 1e-10

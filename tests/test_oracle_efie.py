@@ -183,3 +183,21 @@ def test_dense_efie_sphere_vs_mie(c0_workload, c0_hmatrix, c0_dense):
     sm = 10 * np.log10(mie.bistatic_rcs(1.0, k, math.pi - th, "E"))
     keep = sm > sm.max() - 20
     assert np.sqrt(np.mean((sb - sm)[keep] ** 2)) < 1.0
+
+
+def test_open_plate_broadside_matches_physical_optics():
+    """Open PEC sheet (the square plate of Sec. V.C.2, here 2 wavelengths at
+    lambda/10): the dense EFIE solution's broadside backscatter is close to the
+    physical-optics value 4 pi A^2 / lambda^2, the large-plate limit (edge
+    diffraction of a 2-lambda plate moves it by a few tenths of a dB)."""
+    from workloads import workload
+    w = workload("plate_2lambda_300MHz")
+    rwg = build_rwg(w["xyz"], w["tri"], allow_open=True)
+    assert rwg["N"] == 3 * 20 * 20 - 2 * 20          # interior edges of the 20 x 20 grid
+    op = EFIEOperator(rwg, w["freq_hz"])
+    khat, pol = w["khat"][:1], w["pol"][:1]           # theta = 0: normal incidence
+    x = np.linalg.solve(op.dense(), excitation(rwg, w["freq_hz"], khat, pol))
+    sig = monostatic_rcs(rwg, w["freq_hz"], khat, pol, x)[0]
+    lam = 299792458.0 / w["freq_hz"]
+    po = 4.0 * np.pi * (2.0 * lam) ** 4 / lam ** 2
+    assert abs(10.0 * np.log10(sig / po)) < 1.0

@@ -11,7 +11,7 @@ import math
 
 import numpy as np
 
-from .meshes import icosphere, geodesic_sphere, ellipsoid_mesh
+from .meshes import icosphere, geodesic_sphere, ellipsoid_mesh, flat_plate
 
 C0_LIGHT = 299792458.0
 
@@ -90,6 +90,17 @@ WORKLOADS = {
              "FP32 scale, FP32 D^-1 and scaling blocks, FP64 setup, one FP32 residual pass",
         mesh=("icosphere", 5, 1.0), freq_hz=790e6, leaf_max=128, aca_tol=1e-3,
         rhs=("theta_sweep", {"start": 0.0, "stop": 180.0, "step": 1.0}), precision=1),
+    "plate_20lambda_300MHz": dict(
+        desc="PEC square plate of 20 wavelengths at 300 MHz in the z=0 plane, 200 x 200 squares of "
+             "two triangles (lambda/10, 119,600 RWG), open surface, leaf<=128, ACA 1e-3, 181 RHS "
+             "theta=0..180 step 1, phi=0, theta-pol (VV)",
+        mesh=("plate", 20.0 * C0_LIGHT / 300e6, 200), open=True, freq_hz=300e6, leaf_max=128, aca_tol=1e-3,
+        rhs=("theta_sweep", {"start": 0.0, "stop": 180.0, "step": 1.0}), precision=0),
+    "plate_2lambda_300MHz": dict(
+        desc="PEC square plate of 2 wavelengths at 300 MHz, 20 x 20 squares (lambda/10, 1,160 RWG), "
+             "open surface, leaf<=64, ACA 1e-3, 7 RHS theta=0..180 step 30, phi=0, theta-pol",
+        mesh=("plate", 2.0 * C0_LIGHT / 300e6, 20), open=True, freq_hz=300e6, leaf_max=64, aca_tol=1e-3,
+        rhs=("theta_sweep", {"start": 0.0, "stop": 180.0, "step": 30.0}), precision=0),
     "ellipsoid_4x2x1_300MHz": dict(
         desc="PEC ellipsoid 4x2x1 m, icosphere subdiv 7 mapped affinely (327,680 tris, "
              "491,520 RWG), 300 MHz, leaf<=256, ACA 1e-3, 721 RHS theta=90, phi=0..360 step 0.5",
@@ -107,6 +118,8 @@ def workload_mesh(spec):
     if kind == "ellipsoid":
         xyz, tri = icosphere(spec[1], 1.0)
         return ellipsoid_mesh(xyz, tri, spec[2])
+    if kind == "plate":
+        return flat_plate(spec[1], spec[2])
     if kind == "geodesic_ellipsoid":
         xyz, tri = geodesic_sphere(spec[1], 1.0)
         return ellipsoid_mesh(xyz, tri, spec[2])
@@ -149,4 +162,5 @@ def workload(name):
     kind, kw = w["rhs"]
     khat, pol = plane_wave_dirs(kind, **kw)
     w.update(xyz=xyz, tri=tri, khat=khat, pol=pol, name=name)
+    w.setdefault("open", False)
     return w
