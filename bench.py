@@ -76,10 +76,12 @@ def parse():
 
 
 def build_hmatrix(w):
-    """The H-matrix of the workload, built once on the host (not timed as
-    setup) and installed in every leg."""
+    """The H-matrix of the workload, built once (near blocks on the device,
+    far blocks on host threads; not timed as setup) and installed in every
+    leg."""
+    import torch
     from paper_2109_04129_amd import hps
-    h = hps.hps_create(-1)
+    h = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
     try:
         set_mesh(hps, h, w)
         p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1)
@@ -185,10 +187,11 @@ def batch_leg(args):
     khat, pol = bw["khat"], bw["pol"]
     stream = torch.cuda.current_stream().cuda_stream
     prm = hps.hps_params_default(freq_hz=bw["freq_hz"], leaf_max=bw["leaf_max"], aca_tol=bw["aca_tol"], terms=2)
-    # H-matrices, one problem at a time on the host (not timed as setup)
+    # H-matrices, one problem at a time (near blocks on the device, far blocks
+    # on host threads; not timed as setup)
     parts, build_s = [], 0.0
     for p, (xyz, tri) in enumerate(bw["meshes"]):
-        h = hps.hps_create(-1)
+        h = hps.hps_create(0, stream)
         hps.hps_set_mesh(h, xyz, tri)
         t0 = time.perf_counter()
         hps.hps_build_hmatrix(h, prm)

@@ -92,10 +92,13 @@ typedef struct {
                               precision form's residual pass uses as many terms.
                               Solves are then launched without graphs.  0 (default):
                               exactly `terms` terms */
+  int32_t host_near;       /* 0 (default): with a device, hps_build_hmatrix computes the
+                              near blocks on it while the host compresses the far
+                              blocks; 1: near blocks on host threads too */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
-   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0.
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0, host_near 0.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 
@@ -131,8 +134,10 @@ hps_status hps_num_unknowns(const hps_ctx *ctx, int64_t *N);
 /* Build the H-matrix of the mesh (Sec. II): octree over edge midpoints with at
    most leaf_max unknowns per leaf; near blocks = touching leaf pairs (EFIE
    Galerkin quadrature, Z = Z^T exactly); far blocks = non-touching cluster
-   pairs, re-compressed ACA to aca_tol (eqs. 10-12).  Host threads; the blocks
-   are then copied to the device (if any).  Not part of "setup". */
+   pairs, re-compressed ACA to aca_tol (eqs. 10-12).  The near blocks are
+   computed on the device when the context has one (see host_near), the far
+   blocks on host threads at the same time; the blocks are then held on both
+   sides.  Not part of "setup". */
 hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
 
 /* Install an H-matrix built elsewhere instead (same meaning as above), all

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <exception>
 #include <thread>
 
 #include "hps_internal.h"
@@ -324,7 +325,7 @@ static void parallel_for(int64_t n, int threads, F &&f, const char *label = null
   for (auto &th : pool) th.join();
 }
 
-void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
+void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill) {
   Tree T;
   build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
@@ -351,11 +352,27 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
     H.near_off[b + 1] = H.near_off[b] + mt * ms;
   }
   H.near_vals.assign(H.near_off[nn], 0.0);
-  parallel_for(nn, threads, [&](int64_t b) {
-    const int64_t t = H.near_ts[2 * b], s = H.near_ts[2 * b + 1];
-    op.block(&H.perm[H.gptr[t]], H.gptr[t + 1] - H.gptr[t], &H.perm[H.gptr[s]],
-             H.gptr[s + 1] - H.gptr[s], &H.near_vals[H.near_off[b]]);
-  }, p.verbose ? "near blocks" : nullptr);
+  std::thread near_thread;
+  std::exception_ptr near_error;
+  if (near_fill) {
+    near_thread = std::thread([&]() {
+      try {
+        (*near_fill)(H);
+      } catch (...) {
+        near_error = std::current_exception();
+      }
+    });
+  } else {
+    parallel_for(nn, threads, [&](int64_t b) {
+      const int64_t t = H.near_ts[2 * b], s = H.near_ts[2 * b + 1];
+      op.block(&H.perm[H.gptr[t]], H.gptr[t + 1] - H.gptr[t], &H.perm[H.gptr[s]],
+               H.gptr[s + 1] - H.gptr[s], &H.near_vals[H.near_off[b]]);
+    }, p.verbose ? "near blocks" : nullptr);
+  }
+  struct Joiner {            // the near thread is joined on every path out
+    std::thread &t;
+    ~Joiner() { if (t.joinable()) t.join(); }
+  } joiner{near_thread};
 
   const int64_t nf = (int64_t)far.size();
   H.far_rng.resize(4 * nf);
@@ -380,6 +397,8 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H) {
     std::copy(Us[b].begin(), Us[b].end(), H.far_uv.begin() + H.far_off[b]);
     std::copy(Vs[b].begin(), Vs[b].end(), H.far_uv.begin() + H.far_off[b] + (int64_t)Us[b].size());
   }
+  if (near_thread.joinable()) near_thread.join();
+  if (near_error) std::rethrow_exception(near_error);
 }
 
 }  // namespace hps

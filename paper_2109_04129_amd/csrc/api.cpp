@@ -177,6 +177,7 @@ hps_status hps_params_default(hps_params *p) {
   p->verbose = 0;
   p->leaf_box_min = 0.0;
   p->series_tol = 0.0;
+  p->host_near = 0;
   return HPS_OK;
 }
 
@@ -365,7 +366,9 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
     if (c->n_prob) {
       for (int32_t q = 0; q < c->n_prob; ++q) {
         hps::HMatrix H;
-        hps::build_hmatrix(c->pmesh[q], *p, H);
+        const hps::Mesh &mq = c->pmesh[q];
+        const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(mq, p->freq_hz, h); };
+        hps::build_hmatrix(mq, *p, H, (c->dev && !p->host_near) ? &fill : nullptr);
         hps::split_groups(H, hps::kMaxPivot);
         c->pH[q] = std::move(H);
         c->pH_ok[q] = 1;
@@ -373,7 +376,8 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
       merge_batch(c);
     } else {
       hps::HMatrix H;
-      hps::build_hmatrix(c->mesh, *p, H);
+      const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(c->mesh, p->freq_hz, h); };
+      hps::build_hmatrix(c->mesh, *p, H, (c->dev && !p->host_near) ? &fill : nullptr);
       hps::split_groups(H, hps::kMaxPivot);
       c->H = std::move(H);
       single_segments(c);

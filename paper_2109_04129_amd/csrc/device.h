@@ -64,6 +64,9 @@ class DeviceState {
   void excitation(int64_t R, const double *khat, const double *pol, void *B);
   void hmatvec(int64_t R, const void *X, void *Y);
   std::string stats_json() const;
+  // EFIE entries of the near blocks of H (structure set, values sized) on the
+  // device, copied into H.near_vals; synchronous.
+  void near_fill(const Mesh &m, double freq_hz, HMatrix &H);
   void set_profiling(bool on);
 
   int device;

@@ -670,6 +670,213 @@ __global__ void k_permute(const c2 *__restrict__ in, c2 *__restrict__ out, const
     out[o] = in[idx];
 }
 
+// ------------------------------------------------------------------ near-field fill
+// EFIE Galerkin entries of the near blocks on the device (the host build's
+// definition, eqs. 2-3 and 9 with e^{jwt}): each entry sums the four triangle
+// pairs of its two RWG functions; the outer triangle is the one with the
+// smaller id; shared vertex or centroid distance < 2h: 7-point outer rule,
+// inner = closed-form 1/R and (r' - rho)/R integrals + 7 points on the
+// bounded remainder (exp(-jkR) - 1)/R; < 4h: 7 x 7 points; else 3 x 3.
+struct NearMesh {
+  const double *xyz, *cen, *area, *len;
+  const int32_t *tri, *tp, *tm, *vp, *vm;
+  double k, h, cA, cPhi;          // cA = w mu / 4 and cPhi = -1 / (w eps) times j
+};
+
+__device__ __forceinline__ double ddot3(const double *a, const double *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+template <int NQ>
+__device__ void quad_points(const NearMesh &M, int32_t t, double (*p)[3]) {
+  const double *v0 = M.xyz + 3 * M.tri[3 * t], *v1 = M.xyz + 3 * M.tri[3 * t + 1], *v2 = M.xyz + 3 * M.tri[3 * t + 2];
+  if (NQ == 7) {
+    const double s15 = sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
+    const double B[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {b1, a1, a1}, {a1, b1, a1}, {a1, a1, b1},
+                            {b2, a2, a2}, {a2, b2, a2}, {a2, a2, b2}};
+    for (int q = 0; q < 7; ++q)
+      for (int d = 0; d < 3; ++d) p[q][d] = B[q][0] * v0[d] + B[q][1] * v1[d] + B[q][2] * v2[d];
+  } else {
+    for (int q = 0; q < 3; ++q)
+      for (int d = 0; d < 3; ++d) {
+        const double c0 = (q == 0) ? 2.0 / 3.0 : 1.0 / 6.0, c1 = (q == 1) ? 2.0 / 3.0 : 1.0 / 6.0,
+                     c2_ = (q == 2) ? 2.0 / 3.0 : 1.0 / 6.0;
+        p[q][d] = c0 * v0[d] + c1 * v1[d] + c2_ * v2[d];
+      }
+  }
+}
+
+__device__ __forceinline__ double quad_w(int nq, int q) {
+  if (nq == 3) return 1.0 / 3.0;
+  const double s15 = sqrt(15.0);
+  return q == 0 ? 9.0 / 40.0 : (q < 4 ? (155.0 - s15) / 1200.0 : (155.0 + s15) / 1200.0);
+}
+
+// closed-form int_T 1/R dS' and int_T (r' - rho)/R dS' for observation point r
+__device__ void tri_potentials(const NearMesh &M, int32_t t, const double *r, double &I1, double Ir[3],
+                               double rho[3]) {
+  const double *V[3] = {M.xyz + 3 * M.tri[3 * t], M.xyz + 3 * M.tri[3 * t + 1], M.xyz + 3 * M.tri[3 * t + 2]};
+  double e1[3], e2[3], n[3];
+  for (int d = 0; d < 3; ++d) { e1[d] = V[1][d] - V[0][d]; e2[d] = V[2][d] - V[0][d]; }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nn = sqrt(ddot3(n, n));
+  for (int d = 0; d < 3; ++d) n[d] /= nn;
+  double rv[3];
+  for (int d = 0; d < 3; ++d) rv[d] = r[d] - V[0][d];
+  const double h = ddot3(rv, n), ah = fabs(h);
+  for (int d = 0; d < 3; ++d) rho[d] = r[d] - h * n[d];
+  I1 = 0.0;
+  Ir[0] = Ir[1] = Ir[2] = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double *pa = V[e], *pb = V[(e + 1) % 3];
+    double s[3], u[3], da[3], db[3];
+    for (int d = 0; d < 3; ++d) s[d] = pb[d] - pa[d];
+    const double ls = sqrt(ddot3(s, s));
+    for (int d = 0; d < 3; ++d) s[d] /= ls;
+    u[0] = s[1] * n[2] - s[2] * n[1];
+    u[1] = s[2] * n[0] - s[0] * n[2];
+    u[2] = s[0] * n[1] - s[1] * n[0];
+    for (int d = 0; d < 3; ++d) { da[d] = pa[d] - rho[d]; db[d] = pb[d] - rho[d]; }
+    const double lp = ddot3(db, s), lm = ddot3(da, s), t0 = ddot3(da, u);
+    const double R0sq = t0 * t0 + h * h;
+    const double Rp = sqrt(lp * lp + R0sq), Rm = sqrt(lm * lm + R0sq);
+    double F = 0.0;
+    if (R0sq > 0.0) F = (lp + lm >= 0.0) ? log((Rp + lp) / (Rm + lm)) : log((Rm - lm) / (Rp - lp));
+    double beta = 0.0;
+    const double dp = R0sq + ah * Rp, dm = R0sq + ah * Rm;
+    if (dp > 0.0) beta += atan(t0 * lp / dp);
+    if (dm > 0.0) beta -= atan(t0 * lm / dm);
+    I1 += t0 * F - ah * beta;
+    const double c = 0.5 * (R0sq * F + lp * Rp - lm * Rm);
+    for (int d = 0; d < 3; ++d) Ir[d] += c * u[d];
+  }
+}
+
+// (jw mu / 4) II (r - vO).(r' - vI) G - (j / (w eps)) II G over O x I, outer O
+__device__ c2 pair_integral_dev(const NearMesh &M, int32_t O, const double *vO, int32_t I, const double *vI) {
+  const int32_t *to = M.tri + 3 * O, *ti = M.tri + 3 * I;
+  bool share = false;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) share |= (to[a] == ti[b]);
+  double dc[3];
+  for (int d = 0; d < 3; ++d) dc[d] = M.cen[3 * O + d] - M.cen[3 * I + d];
+  const double d2 = ddot3(dc, dc);
+  const double k = M.k, AO = M.area[O], AI = M.area[I];
+  const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+  double re = 0.0, im = 0.0;     // accumulated complex integral
+  if (share || d2 < (2.0 * M.h) * (2.0 * M.h)) {
+    double po[7][3], pi[7][3];
+    quad_points<7>(M, O, po);
+    quad_points<7>(M, I, pi);
+    for (int a = 0; a < 7; ++a) {
+      double I1, Ir[3], rho[3];
+      tri_potentials(M, I, po[a], I1, Ir, rho);
+      // s = I1 / 4pi + AI sum_b w_b g_b ; v = (Ir + (rho - vI) I1) / 4pi + AI sum_b w_b (pi_b - vI) g_b
+      double s_re = I1 * inv4pi, s_im = 0.0;
+      double v_re[3], v_im[3];
+      for (int d = 0; d < 3; ++d) { v_re[d] = (Ir[d] + (rho[d] - vI[d]) * I1) * inv4pi; v_im[d] = 0.0; }
+      double gs_re = 0.0, gs_im = 0.0, gv_re[3] = {0.0, 0.0, 0.0}, gv_im[3] = {0.0, 0.0, 0.0};
+      for (int b = 0; b < 7; ++b) {
+        double dd[3];
+        for (int d = 0; d < 3; ++d) dd[d] = po[a][d] - pi[b][d];
+        const double R = sqrt(ddot3(dd, dd));
+        const double x = 0.5 * k * R;
+        const double sinc = (x == 0.0) ? 1.0 : sin(x) / x;
+        // (exp(-jkR) - 1) / (4 pi R) = -jk/(4 pi) sinc(kR/2) exp(-jkR/2)
+        double sx, cx;
+        sincos(x, &sx, &cx);
+        const double amp = k * inv4pi * sinc;
+        const double g_re = -amp * sx, g_im = -amp * cx;      // (-j amp)(cx - j sx)
+        const double w = quad_w(7, b);
+        gs_re += w * g_re;
+        gs_im += w * g_im;
+        for (int d = 0; d < 3; ++d) {
+          const double f = w * (pi[b][d] - vI[d]);
+          gv_re[d] += f * g_re;
+          gv_im[d] += f * g_im;
+        }
+      }
+      s_re += AI * gs_re;
+      s_im += AI * gs_im;
+      double dv_re = 0.0, dv_im = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        v_re[d] += AI * gv_re[d];
+        v_im[d] += AI * gv_im[d];
+        dv_re += (po[a][d] - vO[d]) * v_re[d];
+        dv_im += (po[a][d] - vO[d]) * v_im[d];
+      }
+      // cA j dotv + cPhi j s  (cA, cPhi real: the j factor is applied here)
+      const double w = quad_w(7, a);
+      re += w * (-M.cA * dv_im - M.cPhi * s_im);
+      im += w * (M.cA * dv_re + M.cPhi * s_re);
+    }
+    return make_double2(AO * re, AO * im);
+  }
+  const int nq = (d2 < (4.0 * M.h) * (4.0 * M.h)) ? 7 : 3;
+  double po[7][3], pi[7][3];
+  if (nq == 7) {
+    quad_points<7>(M, O, po);
+    quad_points<7>(M, I, pi);
+  } else {
+    quad_points<3>(M, O, po);
+    quad_points<3>(M, I, pi);
+  }
+  for (int a = 0; a < nq; ++a) {
+    double ro[3];
+    for (int d = 0; d < 3; ++d) ro[d] = po[a][d] - vO[d];
+    double in_re = 0.0, in_im = 0.0;
+    for (int b = 0; b < nq; ++b) {
+      double dd[3], ri[3];
+      for (int d = 0; d < 3; ++d) { dd[d] = po[a][d] - pi[b][d]; ri[d] = pi[b][d] - vI[d]; }
+      const double R = sqrt(ddot3(dd, dd));
+      double skr, ckr;
+      sincos(k * R, &skr, &ckr);
+      const double gr = ckr * (inv4pi / R), gi = -skr * (inv4pi / R);
+      // G (j (cA ro.ri + cPhi)) = (gr + j gi) j c = -gi c + j gr c
+      const double c = M.cA * ddot3(ro, ri) + M.cPhi;
+      const double w = quad_w(nq, b);
+      in_re += w * (-gi * c);
+      in_im += w * (gr * c);
+    }
+    const double w = quad_w(nq, a);
+    re += w * in_re;
+    im += w * in_im;
+  }
+  return make_double2(AO * AI * re, AO * AI * im);
+}
+
+__device__ c2 efie_entry(const NearMesh &M, int64_t m_, int64_t n_) {
+  const int64_t a = m_ < n_ ? m_ : n_, b = m_ < n_ ? n_ : m_;
+  const int32_t ta[2] = {M.tp[a], M.tm[a]}, tb[2] = {M.tp[b], M.tm[b]};
+  const int32_t va[2] = {M.vp[a], M.vm[a]}, vb[2] = {M.vp[b], M.vm[b]};
+  double zr = 0.0, zi = 0.0;
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) {
+      const int32_t P = ta[p], Q = tb[q];
+      const double *vP = M.xyz + 3 * va[p], *vQ = M.xyz + 3 * vb[q];
+      const c2 I = (P <= Q) ? pair_integral_dev(M, P, vP, Q, vQ) : pair_integral_dev(M, Q, vQ, P, vP);
+      const double f = ((p == q) ? 1.0 : -1.0) * M.len[a] * M.len[b] / (M.area[P] * M.area[Q]);
+      zr += f * I.x;
+      zi += f * I.y;
+    }
+  return make_double2(zr, zi);
+}
+
+// One workgroup per near block (row-major m x n, rows of group t, columns of s).
+__global__ __launch_bounds__(256) void k_near(NearMesh M, const int64_t *__restrict__ perm,
+                                              const int64_t *__restrict__ gptr, const int32_t *__restrict__ ts,
+                                              const int64_t *__restrict__ off, c2 *__restrict__ out) {
+  const int64_t b = blockIdx.x;
+  const int32_t t = ts[2 * b], s = ts[2 * b + 1];
+  const int64_t m = gptr[t + 1] - gptr[t], n = gptr[s + 1] - gptr[s];
+  for (int64_t i = threadIdx.x; i < m * n; i += blockDim.x) {
+    const int64_t r = i / n, c = i % n;
+    out[off[b] + i] = efie_entry(M, perm[gptr[t] + r], perm[gptr[s] + c]);
+  }
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -1921,6 +2128,29 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   }
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
   HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+void DeviceState::near_fill(const Mesh &m, double freq_hz, HMatrix &H) {
+  HIP_CHECK(hipSetDevice(device));
+  Impl &I = *impl;
+  const int64_t nn = H.n_near();
+  if (nn == 0) return;
+  const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi, eps0 = 1.0 / (mu0 * c0 * c0);
+  const double w = 2.0 * pi * freq_hz;
+  DevArray<double> xyz, cen, area, len;
+  DevArray<int32_t> tri, tp, tm, vp, vm, ts;
+  DevArray<int64_t> perm, gptr, off;
+  DevArray<c2> out;
+  xyz.upload(m.xyz, I.s); cen.upload(m.cen, I.s); area.upload(m.area, I.s); len.upload(m.len, I.s);
+  tri.upload(m.tri, I.s); tp.upload(m.tp, I.s); tm.upload(m.tm, I.s); vp.upload(m.vp, I.s); vm.upload(m.vm, I.s);
+  perm.upload(H.perm, I.s); gptr.upload(H.gptr, I.s); ts.upload(H.near_ts, I.s); off.upload(H.near_off, I.s);
+  const int64_t total = H.near_off[nn];
+  out.alloc((size_t)total);
+  NearMesh M{xyz.p, cen.p, area.p, len.p, tri.p, tp.p, tm.p, vp.p, vm.p, w / c0, m.hmax, w * mu0 / 4.0, -1.0 / (w * eps0)};
+  hipLaunchKernelGGL(k_near, dim3((unsigned)nn), dim3(256), 0, I.s, M, perm.p, gptr.p, ts.p, off.p, out.p);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemcpyAsync((void *)H.near_vals.data(), out.p, (size_t)total * sizeof(c2), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <functional>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -93,7 +94,13 @@ struct EFIE {
 void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
                double eps, std::vector<cplx> &U, std::vector<cplx> &V, int &rank);
 
-void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H);
+// Fills H.near_vals (sized from H.near_off) from the near block list of H;
+// called on its own host thread while the far blocks are compressed.
+using NearFill = std::function<void(HMatrix &H)>;
+
+// With near_fill the near blocks are computed by it (the device), else on
+// host threads; far blocks are always compressed on the host.
+void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill = nullptr);
 
 // Small dense complex linear algebra used by the ACA recompression.
 void householder_qr(int64_t m, int64_t n, cplx *A /* m x n col-major, in/out */,

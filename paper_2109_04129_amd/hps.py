@@ -38,7 +38,8 @@ class hps_params(ctypes.Structure):
                 ("ratio_warn", ctypes.c_double), ("device_mem_cap", ctypes.c_uint64),
                 ("host_threads", ctypes.c_int32), ("ordering", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("leaf_box_min", ctypes.c_double), ("series_tol", ctypes.c_double)]
+                ("leaf_box_min", ctypes.c_double), ("series_tol", ctypes.c_double),
+                ("host_near", ctypes.c_int32)]
 
 
 _lib = None

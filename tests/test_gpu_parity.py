@@ -298,3 +298,35 @@ def test_open_plate():
     print("max rel current err", err.max(), "ratio", ratio, flush=True)
     assert err.max() < 1e-10
     assert np.max(np.abs(10 * np.log10(rcs / sig))) < 1e-6
+
+
+def test_device_near_field_fill(c0_workload, c0_hmatrix):
+    """hps_build_hmatrix on a device context computes the near blocks on the
+    GPU: every entry equals the oracle's (same quadrature definition) to
+    rounding, and the host build (host_near = 1) to rounding as well; the far
+    blocks (host ACA either way) are identical."""
+    w, H = c0_workload, c0_hmatrix
+    print("case: sphere 1,920 unknowns, near-field fill on the device", flush=True)
+    out = {}
+    for host_near in (0, 1):
+        ctx = _ctx()
+        try:
+            hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+            hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"],
+                                                              aca_tol=w["aca_tol"], host_near=host_near))
+            out[host_near] = hps.hps_get_hmatrix(ctx)
+        finally:
+            hps.hps_destroy(ctx)
+    G, C = out[0], out[1]
+    assert np.array_equal(G["near_ts"], C["near_ts"]) and np.array_equal(G["far_uv"], C["far_uv"])
+    keys = [tuple(x) for x in G["near_ts"].reshape(-1, 2)]
+    assert keys == sorted(H.near)
+    worst_o, worst_h = 0.0, 0.0
+    for b, k in enumerate(keys):
+        blk = G["near_vals"][G["near_off"][b]:G["near_off"][b + 1]].reshape(H.near[k].shape)
+        hst = C["near_vals"][C["near_off"][b]:C["near_off"][b + 1]].reshape(H.near[k].shape)
+        scale = np.abs(H.near[k]).max()
+        worst_o = max(worst_o, np.abs(blk - H.near[k]).max() / scale)
+        worst_h = max(worst_h, np.abs(blk - hst).max() / scale)
+    print("device near vs oracle %.2e, vs host %.2e" % (worst_o, worst_h), flush=True)
+    assert worst_o <= 1e-12 and worst_h <= 1e-12
