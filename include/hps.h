@@ -93,8 +93,9 @@ typedef struct {
                               Solves are then launched without graphs.  0 (default):
                               exactly `terms` terms */
   int32_t host_near;       /* 0 (default): with a device, hps_build_hmatrix computes the
-                              near blocks on it while the host compresses the far
-                              blocks; 1: near blocks on host threads too */
+                              near blocks and the ACA samples of the far blocks on it
+                              (the host recompresses them); 1: the whole build on
+                              host threads */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
@@ -134,10 +135,10 @@ hps_status hps_num_unknowns(const hps_ctx *ctx, int64_t *N);
 /* Build the H-matrix of the mesh (Sec. II): octree over edge midpoints with at
    most leaf_max unknowns per leaf; near blocks = touching leaf pairs (EFIE
    Galerkin quadrature, Z = Z^T exactly); far blocks = non-touching cluster
-   pairs, re-compressed ACA to aca_tol (eqs. 10-12).  The near blocks are
-   computed on the device when the context has one (see host_near), the far
-   blocks on host threads at the same time; the blocks are then held on both
-   sides.  Not part of "setup". */
+   pairs, re-compressed ACA to aca_tol (eqs. 10-12).  With a device (see
+   host_near) the near blocks and the ACA sampling run on it and the host
+   recompresses the far factors; the blocks are then held on both sides.  Not
+   part of "setup". */
 hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
 
 /* Install an H-matrix built elsewhere instead (same meaning as above), all

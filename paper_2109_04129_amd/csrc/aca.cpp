@@ -325,7 +325,8 @@ static void parallel_for(int64_t n, int threads, F &&f, const char *label = null
   for (auto &th : pool) th.join();
 }
 
-void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill) {
+void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill,
+                   const FarSample *far_sample) {
   Tree T;
   build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
@@ -352,44 +353,70 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
     H.near_off[b + 1] = H.near_off[b] + mt * ms;
   }
   H.near_vals.assign(H.near_off[nn], 0.0);
-  std::thread near_thread;
-  std::exception_ptr near_error;
-  if (near_fill) {
-    near_thread = std::thread([&]() {
+  const int64_t nf = (int64_t)far.size();
+  H.far_rng.resize(4 * nf);
+  H.far_rank.assign(nf, 0);
+  for (int64_t b = 0; b < nf; ++b) {
+    const TreeNode &a = T.nodes[far[b].first], &c = T.nodes[far[b].second];
+    H.far_rng[4 * b] = a.lo; H.far_rng[4 * b + 1] = a.hi;
+    H.far_rng[4 * b + 2] = c.lo; H.far_rng[4 * b + 3] = c.hi;
+  }
+
+  // device work (near blocks, then the ACA sampling) on its own thread
+  FarRaw raw;
+  std::thread dev_thread;
+  std::exception_ptr dev_error;
+  if (near_fill || far_sample) {
+    dev_thread = std::thread([&]() {
       try {
-        (*near_fill)(H);
+        if (near_fill) (*near_fill)(H);
+        if (far_sample) (*far_sample)(H, raw);
       } catch (...) {
-        near_error = std::current_exception();
+        dev_error = std::current_exception();
       }
     });
-  } else {
+  }
+  struct Joiner {            // the device thread is joined on every path out
+    std::thread &t;
+    ~Joiner() { if (t.joinable()) t.join(); }
+  } joiner{dev_thread};
+  if (!near_fill) {
     parallel_for(nn, threads, [&](int64_t b) {
       const int64_t t = H.near_ts[2 * b], s = H.near_ts[2 * b + 1];
       op.block(&H.perm[H.gptr[t]], H.gptr[t + 1] - H.gptr[t], &H.perm[H.gptr[s]],
                H.gptr[s + 1] - H.gptr[s], &H.near_vals[H.near_off[b]]);
     }, p.verbose ? "near blocks" : nullptr);
   }
-  struct Joiner {            // the near thread is joined on every path out
-    std::thread &t;
-    ~Joiner() { if (t.joinable()) t.join(); }
-  } joiner{near_thread};
-
-  const int64_t nf = (int64_t)far.size();
-  H.far_rng.resize(4 * nf);
-  H.far_rank.assign(nf, 0);
   std::vector<std::vector<cplx>> Us(nf), Vs(nf);
-  for (int64_t b = 0; b < nf; ++b) {
-    const TreeNode &a = T.nodes[far[b].first], &c = T.nodes[far[b].second];
-    H.far_rng[4 * b] = a.lo; H.far_rng[4 * b + 1] = a.hi;
-    H.far_rng[4 * b + 2] = c.lo; H.far_rng[4 * b + 3] = c.hi;
+  if (far_sample) {
+    dev_thread.join();
+    if (dev_error) std::rethrow_exception(dev_error);
+    if ((int64_t)raw.rank.size() != nf) throw Error{HPS_EINVAL, "internal: device ACA result size"};
+    // recompress the device's factors; blocks it left over get the host ACA
+    parallel_for(nf, threads, [&](int64_t b) {
+      const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
+      const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
+      const int64_t m = thi - tlo, n = shi - slo, k = raw.rank[b];
+      int r = 0;
+      if (k < 0) {
+        aca_block(op, &H.perm[tlo], m, &H.perm[slo], n, p.aca_tol, Us[b], Vs[b], r);
+      } else if (k > 0) {
+        const cplx *u = raw.uv.data() + raw.off[b];
+        Us[b].assign(u, u + m * k);
+        Vs[b].assign(u + m * k, u + (m + n) * k);
+        recompress(m, n, k, Us[b], Vs[b], p.aca_tol, r);
+      }
+      H.far_rank[b] = r;
+    }, p.verbose ? "far blocks (recompression)" : nullptr);
+  } else {
+    parallel_for(nf, threads, [&](int64_t b) {
+      const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
+      const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
+      int r = 0;
+      aca_block(op, &H.perm[tlo], thi - tlo, &H.perm[slo], shi - slo, p.aca_tol, Us[b], Vs[b], r);
+      H.far_rank[b] = r;
+    }, p.verbose ? "far blocks (ACA)" : nullptr);
   }
-  parallel_for(nf, threads, [&](int64_t b) {
-    const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
-    const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
-    int r = 0;
-    aca_block(op, &H.perm[tlo], thi - tlo, &H.perm[slo], shi - slo, p.aca_tol, Us[b], Vs[b], r);
-    H.far_rank[b] = r;
-  }, p.verbose ? "far blocks (ACA)" : nullptr);
   H.far_off.assign(nf + 1, 0);
   for (int64_t b = 0; b < nf; ++b) H.far_off[b + 1] = H.far_off[b] + (int64_t)(Us[b].size() + Vs[b].size());
   H.far_uv.resize(H.far_off[nf]);
@@ -397,8 +424,8 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
     std::copy(Us[b].begin(), Us[b].end(), H.far_uv.begin() + H.far_off[b]);
     std::copy(Vs[b].begin(), Vs[b].end(), H.far_uv.begin() + H.far_off[b] + (int64_t)Us[b].size());
   }
-  if (near_thread.joinable()) near_thread.join();
-  if (near_error) std::rethrow_exception(near_error);
+  if (dev_thread.joinable()) dev_thread.join();
+  if (dev_error) std::rethrow_exception(dev_error);
 }
 
 }  // namespace hps

@@ -877,6 +877,180 @@ __global__ __launch_bounds__(256) void k_near(NearMesh M, const int64_t *__restr
   }
 }
 
+// ------------------------------------------------------------------ ACA on the device
+// Partial-pivoting ACA of one far block per workgroup, the host build's
+// rule: first pivot row 0; pivot column = largest residual modulus in the
+// row (lowest index on ties); v = row / row[j]; u = residual column j; the
+// squared Frobenius norm of the running approximation is updated with the
+// cross terms; stop when |u| |v| <= eps ||S||_F; next row = largest |u| over
+// unused rows; zero residual rows are skipped.  The raw factors (rank k)
+// stay in the workgroup's scratch; rank -1 hands the block back to the host
+// (rank limit m n / (m + n) reached, more than kAcaCap terms, or m too
+// large for the row bitmap).  Recompression happens on the host.
+constexpr int kAcaCap = 48;
+constexpr int kAcaMaxRows = 65536;
+
+struct AcaBlock {
+  int64_t tlo, m, slo, n, scratch;    // scratch: U (m x cap) then V (n x cap), column-major
+};
+
+__device__ __forceinline__ double cabs2(c2 a) { return a.x * a.x + a.y * a.y; }
+
+// block-wide argmax of (value, index): largest value, lowest index on ties
+__device__ void block_argmax(double &v, int &i, double *sv, int *si) {
+  const int t = threadIdx.x;
+  sv[t] = v;
+  si[t] = i;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (t < s) {
+      const double ov = sv[t + s];
+      const int oi = si[t + s];
+      if (ov > sv[t] || (ov == sv[t] && oi < si[t])) { sv[t] = ov; si[t] = oi; }
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  i = si[0];
+  __syncthreads();
+}
+
+// block-wide sum of a complex value
+__device__ c2 block_csum(c2 a, double *sx, double *sy) {
+  const int t = threadIdx.x;
+  sx[t] = a.x;
+  sy[t] = a.y;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (t < s) { sx[t] += sx[t + s]; sy[t] += sy[t + s]; }
+    __syncthreads();
+  }
+  const c2 r = make_double2(sx[0], sy[0]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restrict__ perm,
+                                             const AcaBlock *__restrict__ blocks, double eps, c2 *__restrict__ scratch,
+                                             int32_t *__restrict__ rank_out) {
+  const AcaBlock B = blocks[blockIdx.x];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ uint32_t used[kAcaMaxRows / 32];
+  __shared__ double sv[256], sw[256];
+  __shared__ int si[256];
+  const int64_t m = B.m, n = B.n;
+  if (m > kAcaMaxRows) {
+    if (tid == 0) rank_out[blockIdx.x] = -1;
+    return;
+  }
+  c2 *U = scratch + B.scratch, *V = U + m * kAcaCap;
+  const int64_t *rows = perm + B.tlo, *cols = perm + B.slo;
+  for (int64_t w = tid; w < (m + 31) / 32; w += nt) used[w] = 0u;
+  __syncthreads();
+  const double limit = (double)(m * n) / (double)(m + n);
+  int k = 0, result = -2;      // -2: running
+  int64_t i = 0;
+  double norm2 = 0.0;
+  while (result == -2) {
+    if ((double)(k + 1) >= limit || k >= kAcaCap) { result = -1; break; }
+    // residual row i into V[:, k]
+    for (int64_t j = tid; j < n; j += nt) {
+      c2 z = efie_entry(M, rows[i], cols[j]);
+      for (int l = 0; l < k; ++l) {
+        const c2 u = U[l * m + i], v = V[l * n + j];
+        z.x -= u.x * v.x - u.y * v.y;
+        z.y -= u.x * v.y + u.y * v.x;
+      }
+      V[k * n + j] = z;
+    }
+    if (tid == 0) used[i >> 5] |= 1u << (i & 31);
+    double best = -1.0;
+    int jp = 0x7fffffff;
+    for (int64_t j = tid; j < n; j += nt) {
+      const double a = sqrt(cabs2(V[k * n + j]));
+      if (a > best) { best = a; jp = (int)j; }
+    }
+    block_argmax(best, jp, sv, si);       // also orders the row writes and the bitmap update
+    if (best == 0.0) {                    // zero residual row: next unused row, if any
+      int nx = 0x7fffffff;
+      double one = -1.0;
+      for (int64_t a = tid; a < m; a += nt)
+        if (!((used[a >> 5] >> (a & 31)) & 1u) && (int)a < nx) { nx = (int)a; one = 1.0; }
+      block_argmax(one, nx, sv, si);
+      if (one < 0.0) { result = k; break; }
+      i = nx;
+      continue;
+    }
+    const c2 piv = V[k * n + jp];
+    const double pd = cabs2(piv);
+    const c2 pinv = make_double2(piv.x / pd, -piv.y / pd);
+    // residual column jp into U[:, k]
+    for (int64_t a = tid; a < m; a += nt) {
+      c2 z = efie_entry(M, rows[a], cols[jp]);
+      for (int l = 0; l < k; ++l) {
+        const c2 v = V[l * n + jp], u = U[l * m + a];
+        z.x -= v.x * u.x - v.y * u.y;
+        z.y -= v.x * u.y + v.y * u.x;
+      }
+      U[k * m + a] = z;
+    }
+    for (int64_t j = tid; j < n; j += nt) {
+      const c2 r = V[k * n + j];
+      V[k * n + j] = make_double2(r.x * pinv.x - r.y * pinv.y, r.x * pinv.y + r.y * pinv.x);
+    }
+    __syncthreads();
+    double pu = 0.0, pv = 0.0;
+    for (int64_t a = tid; a < m; a += nt) pu += cabs2(U[k * m + a]);
+    for (int64_t j = tid; j < n; j += nt) pv += cabs2(V[k * n + j]);
+    const c2 s2 = block_csum(make_double2(pu, pv), sv, sw);
+    const double nu2 = s2.x, nv2 = s2.y;
+    double cross = 0.0;
+    for (int l = 0; l < k; ++l) {
+      c2 uu = make_double2(0.0, 0.0), vv = make_double2(0.0, 0.0);
+      for (int64_t a = tid; a < m; a += nt) {      // conj(U_l) . u
+        const c2 x = U[l * m + a], y = U[k * m + a];
+        uu.x += x.x * y.x + x.y * y.y;
+        uu.y += x.x * y.y - x.y * y.x;
+      }
+      for (int64_t j = tid; j < n; j += nt) {
+        const c2 x = V[l * n + j], y = V[k * n + j];
+        vv.x += x.x * y.x + x.y * y.y;
+        vv.y += x.x * y.y - x.y * y.x;
+      }
+      const c2 su = block_csum(uu, sv, sw), sv2 = block_csum(vv, sv, sw);
+      cross += su.x * sv2.x - su.y * sv2.y;
+    }
+    norm2 += 2.0 * cross + nu2 * nv2;
+    ++k;
+    if (sqrt(nu2 * nv2) <= eps * sqrt(norm2)) { result = k; break; }
+    // next row: largest |u| over unused rows
+    double bu = -1.0;
+    int nx = 0x7fffffff;
+    for (int64_t a = tid; a < m; a += nt)
+      if (!((used[a >> 5] >> (a & 31)) & 1u)) {
+        const double av = sqrt(cabs2(U[(k - 1) * m + a]));
+        if (av > bu || (av == bu && (int)a < nx)) { bu = av; nx = (int)a; }
+      }
+    block_argmax(bu, nx, sv, si);
+    if (bu < 0.0) { result = k; break; }   // every row used
+    i = nx;
+  }
+  if (tid == 0) rank_out[blockIdx.x] = result;
+}
+
+// Raw factors of the finished blocks into one packed array: U (m x k) then
+// V (n x k) per block at pack[b].
+__global__ void k_aca_pack(const AcaBlock *__restrict__ blocks, const int32_t *__restrict__ rank,
+                           const int64_t *__restrict__ pack, const c2 *__restrict__ scratch, c2 *__restrict__ out) {
+  const AcaBlock B = blocks[blockIdx.x];
+  const int k = rank[blockIdx.x];
+  if (k <= 0) return;
+  const c2 *U = scratch + B.scratch, *V = U + B.m * kAcaCap;
+  c2 *o = out + pack[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < B.m * k; e += blockDim.x) o[e] = U[e];
+  for (int64_t e = threadIdx.x; e < B.n * k; e += blockDim.x) o[B.m * k + e] = V[e];
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -2131,27 +2305,103 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
+namespace {
+// Mesh arrays on the device for the entry kernels (freed with the object).
+struct DevMesh {
+  DevArray<double> xyz, cen, area, len;
+  DevArray<int32_t> tri, tp, tm, vp, vm;
+  NearMesh M;
+  DevMesh(const Mesh &m, double freq_hz, hipStream_t st) {
+    const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi, eps0 = 1.0 / (mu0 * c0 * c0);
+    const double w = 2.0 * pi * freq_hz;
+    xyz.upload(m.xyz, st); cen.upload(m.cen, st); area.upload(m.area, st); len.upload(m.len, st);
+    tri.upload(m.tri, st); tp.upload(m.tp, st); tm.upload(m.tm, st); vp.upload(m.vp, st); vm.upload(m.vm, st);
+    M = NearMesh{xyz.p, cen.p, area.p, len.p, tri.p, tp.p, tm.p, vp.p, vm.p, w / c0, m.hmax, w * mu0 / 4.0,
+                 -1.0 / (w * eps0)};
+  }
+};
+}  // namespace
+
 void DeviceState::near_fill(const Mesh &m, double freq_hz, HMatrix &H) {
   HIP_CHECK(hipSetDevice(device));
   Impl &I = *impl;
   const int64_t nn = H.n_near();
   if (nn == 0) return;
-  const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi, eps0 = 1.0 / (mu0 * c0 * c0);
-  const double w = 2.0 * pi * freq_hz;
-  DevArray<double> xyz, cen, area, len;
-  DevArray<int32_t> tri, tp, tm, vp, vm, ts;
+  DevMesh dm(m, freq_hz, I.s);
+  DevArray<int32_t> ts;
   DevArray<int64_t> perm, gptr, off;
   DevArray<c2> out;
-  xyz.upload(m.xyz, I.s); cen.upload(m.cen, I.s); area.upload(m.area, I.s); len.upload(m.len, I.s);
-  tri.upload(m.tri, I.s); tp.upload(m.tp, I.s); tm.upload(m.tm, I.s); vp.upload(m.vp, I.s); vm.upload(m.vm, I.s);
   perm.upload(H.perm, I.s); gptr.upload(H.gptr, I.s); ts.upload(H.near_ts, I.s); off.upload(H.near_off, I.s);
   const int64_t total = H.near_off[nn];
   out.alloc((size_t)total);
-  NearMesh M{xyz.p, cen.p, area.p, len.p, tri.p, tp.p, tm.p, vp.p, vm.p, w / c0, m.hmax, w * mu0 / 4.0, -1.0 / (w * eps0)};
-  hipLaunchKernelGGL(k_near, dim3((unsigned)nn), dim3(256), 0, I.s, M, perm.p, gptr.p, ts.p, off.p, out.p);
+  hipLaunchKernelGGL(k_near, dim3((unsigned)nn), dim3(256), 0, I.s, dm.M, perm.p, gptr.p, ts.p, off.p, out.p);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipMemcpyAsync((void *)H.near_vals.data(), out.p, (size_t)total * sizeof(c2), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, FarRaw &raw) {
+  HIP_CHECK(hipSetDevice(device));
+  Impl &I = *impl;
+  const int64_t nf = H.n_far();
+  raw.rank.assign(nf, -1);
+  raw.off.assign(nf, 0);
+  raw.uv.clear();
+  if (nf == 0) return;
+  DevMesh dm(m, freq_hz, I.s);
+  DevArray<int64_t> perm;
+  perm.upload(H.perm, I.s);
+  const int64_t cap_elems = (int64_t)1 << 28;         // 4 GiB of scratch per chunk
+  DevArray<c2> scratch, packed;
+  DevArray<AcaBlock> dblk;
+  DevArray<int32_t> drank;
+  DevArray<int64_t> dpack;
+  int64_t b0 = 0;
+  while (b0 < nf) {
+    std::vector<AcaBlock> blk;
+    int64_t need = 0;
+    int64_t b = b0;
+    for (; b < nf; ++b) {
+      const int64_t mm = H.far_rng[4 * b + 1] - H.far_rng[4 * b], nn = H.far_rng[4 * b + 3] - H.far_rng[4 * b + 2];
+      const int64_t e = (mm + nn) * kAcaCap;
+      if (!blk.empty() && need + e > cap_elems) break;
+      blk.push_back(AcaBlock{H.far_rng[4 * b], mm, H.far_rng[4 * b + 2], nn, need});
+      need += e;
+    }
+    const int64_t nb = (int64_t)blk.size();
+    scratch.alloc((size_t)need);
+    dblk.upload(blk, I.s);
+    drank.alloc((size_t)nb);
+    hipLaunchKernelGGL(k_aca, dim3((unsigned)nb), dim3(256), 0, I.s, dm.M, perm.p, dblk.p, eps, scratch.p, drank.p);
+    HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> rk(nb);
+    HIP_CHECK(hipMemcpyAsync(rk.data(), drank.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, I.s));
+    HIP_CHECK(hipStreamSynchronize(I.s));
+    std::vector<int64_t> pk(nb, 0);
+    int64_t tot = 0;
+    for (int64_t q = 0; q < nb; ++q) {
+      pk[q] = tot;
+      if (rk[q] > 0) tot += (blk[q].m + blk[q].n) * rk[q];
+    }
+    if (tot > 0) {
+      dpack.upload(pk, I.s);
+      packed.alloc((size_t)tot);
+      hipLaunchKernelGGL(k_aca_pack, dim3((unsigned)nb), dim3(256), 0, I.s, dblk.p, drank.p, dpack.p, scratch.p,
+                         packed.p);
+      HIP_CHECK(hipGetLastError());
+    }
+    const int64_t base = (int64_t)raw.uv.size();
+    raw.uv.resize(base + tot);
+    if (tot > 0)
+      HIP_CHECK(hipMemcpyAsync((void *)(raw.uv.data() + base), packed.p, (size_t)tot * sizeof(c2),
+                               hipMemcpyDeviceToHost, I.s));
+    HIP_CHECK(hipStreamSynchronize(I.s));
+    for (int64_t q = 0; q < nb; ++q) {
+      raw.rank[b0 + q] = rk[q];
+      raw.off[b0 + q] = base + pk[q];
+    }
+    b0 = b;
+  }
 }
 
 void DeviceState::set_profiling(bool on) {

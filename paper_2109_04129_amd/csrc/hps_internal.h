@@ -98,9 +98,22 @@ void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *co
 // called on its own host thread while the far blocks are compressed.
 using NearFill = std::function<void(HMatrix &H)>;
 
-// With near_fill the near blocks are computed by it (the device), else on
-// host threads; far blocks are always compressed on the host.
-void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill = nullptr);
+// Unrecompressed ACA factors of the far blocks: block b has rank[b] terms
+// (U m x k then V n x k, column-major, at uv[off[b]]), or rank[b] = -1 when
+// it is left to the host ACA (rank limit, term cap).
+struct FarRaw {
+  std::vector<int32_t> rank;
+  std::vector<int64_t> off;
+  std::vector<cplx> uv;
+};
+using FarSample = std::function<void(const HMatrix &H, FarRaw &raw)>;
+
+// With near_fill / far_sample the near blocks and the ACA sampling of the far
+// blocks run there (the device, on one host thread, in that order); the far
+// blocks are then recompressed on host threads.  Without them everything
+// runs on host threads.
+void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill = nullptr,
+                   const FarSample *far_sample = nullptr);
 
 // Small dense complex linear algebra used by the ACA recompression.
 void householder_qr(int64_t m, int64_t n, cplx *A /* m x n col-major, in/out */,

@@ -23,6 +23,7 @@ from oracle.scaling import group_graph, min_degree_order, natural_order, schur_s
 from oracle.series import PowerSeries
 from workloads import icosphere, monostatic_angles
 from hmat_io import hmatrix_arrays, per_rhs_rel
+from conftest import rel
 
 torch = pytest.importorskip("torch")
 from paper_2109_04129_amd import hps  # noqa: E402
@@ -300,13 +301,14 @@ def test_open_plate():
     assert np.max(np.abs(10 * np.log10(rcs / sig))) < 1e-6
 
 
-def test_device_near_field_fill(c0_workload, c0_hmatrix):
-    """hps_build_hmatrix on a device context computes the near blocks on the
-    GPU: every entry equals the oracle's (same quadrature definition) to
-    rounding, and the host build (host_near = 1) to rounding as well; the far
-    blocks (host ACA either way) are identical."""
+def test_device_hmatrix_build(c0_workload, c0_hmatrix, c0_dense):
+    """hps_build_hmatrix on a device context computes the near blocks and the
+    ACA samples of the far blocks on the GPU (the host recompresses): near
+    entries equal the oracle's and the host build's (host_near = 1) to
+    rounding; the far field approximates the dense matrix to the ACA bound,
+    like the host build, with the same structure."""
     w, H = c0_workload, c0_hmatrix
-    print("case: sphere 1,920 unknowns, near-field fill on the device", flush=True)
+    print("case: sphere 1,920 unknowns, H-matrix build on the device", flush=True)
     out = {}
     for host_near in (0, 1):
         ctx = _ctx()
@@ -318,7 +320,7 @@ def test_device_near_field_fill(c0_workload, c0_hmatrix):
         finally:
             hps.hps_destroy(ctx)
     G, C = out[0], out[1]
-    assert np.array_equal(G["near_ts"], C["near_ts"]) and np.array_equal(G["far_uv"], C["far_uv"])
+    assert np.array_equal(G["near_ts"], C["near_ts"]) and np.array_equal(G["far_rng"], C["far_rng"])
     keys = [tuple(x) for x in G["near_ts"].reshape(-1, 2)]
     assert keys == sorted(H.near)
     worst_o, worst_h = 0.0, 0.0
@@ -328,5 +330,20 @@ def test_device_near_field_fill(c0_workload, c0_hmatrix):
         scale = np.abs(H.near[k]).max()
         worst_o = max(worst_o, np.abs(blk - H.near[k]).max() / scale)
         worst_h = max(worst_h, np.abs(blk - hst).max() / scale)
-    print("device near vs oracle %.2e, vs host %.2e" % (worst_o, worst_h), flush=True)
+    P = H.perm
+    Zt = c0_dense[np.ix_(P, P)]
+    errs = {}
+    for name, L in (("device", G), ("host", C)):
+        Zh = H.dense_near()
+        for b, (tlo, thi, slo, shi) in enumerate(L["far_rng"].reshape(-1, 4)):
+            r, m, n = L["far_rank"][b], thi - tlo, shi - slo
+            uv = L["far_uv"][L["far_off"][b]:L["far_off"][b + 1]]
+            B = uv[:m * r].reshape(r, m).T @ uv[m * r:].reshape(r, n)
+            Zh[tlo:thi, slo:shi] = B
+            Zh[slo:shi, tlo:thi] = B.T
+        errs[name] = rel(Zh, Zt)
+    print("device near vs oracle %.2e, vs host %.2e; far-field error device %.2e host %.2e; mean rank %.2f / %.2f"
+          % (worst_o, worst_h, errs["device"], errs["host"], G["far_rank"].mean(), C["far_rank"].mean()), flush=True)
     assert worst_o <= 1e-12 and worst_h <= 1e-12
+    assert errs["device"] <= 2e-3 and errs["host"] <= 2e-3
+    assert abs(G["far_rank"].mean() - C["far_rank"].mean()) <= 0.1 * C["far_rank"].mean()
