@@ -12,8 +12,12 @@
 #include <cstdio>
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <exception>
+#include <mutex>
 #include <thread>
 
 #include "hps_internal.h"
@@ -327,6 +331,13 @@ static void parallel_for(int64_t n, int threads, F &&f, const char *label = null
 
 void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill,
                    const FarSample *far_sample) {
+  const auto t_start = std::chrono::steady_clock::now();
+  auto stage = [&](const char *what) {
+    if (!p.verbose) return;
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "[hps] %s at %.2f s\n", what, sec);
+    std::fflush(stderr);
+  };
   Tree T;
   build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
@@ -362,18 +373,45 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
     H.far_rng[4 * b + 2] = c.lo; H.far_rng[4 * b + 3] = c.hi;
   }
 
-  // device work (near blocks, then the ACA sampling) on its own thread
-  FarRaw raw;
+  stage("tree and block partition done");
+  // Device work on its own thread: the ACA sampling of the far blocks, chunk
+  // by chunk, then the near blocks.  Host threads recompress each chunk as it
+  // arrives (blocks the device left over get the host ACA).
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<FarChunk> chunks;              // stable element addresses
+  std::vector<const cplx *> src(far_sample ? nf : 0);
+  std::vector<int32_t> raw_rank(far_sample ? nf : 0);
+  int64_t ready = 0;                        // far blocks [0, ready) have arrived
+  bool dev_done = false;
   std::thread dev_thread;
   std::exception_ptr dev_error;
   if (near_fill || far_sample) {
     dev_thread = std::thread([&]() {
       try {
+        if (far_sample) {
+          (*far_sample)(H, [&](FarChunk &&ch) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (ch.b0 != ready || ch.b1 < ch.b0 || ch.b1 > nf) throw Error{HPS_EINVAL, "internal: device ACA chunk order"};
+            chunks.push_back(std::move(ch));
+            const FarChunk &c = chunks.back();
+            for (int64_t b = c.b0; b < c.b1; ++b) {
+              raw_rank[b] = c.rank[b - c.b0];
+              src[b] = c.uv.data() + c.off[b - c.b0];
+            }
+            ready = c.b1;
+            cv.notify_all();
+          });
+          stage("device ACA sampling done");
+        }
         if (near_fill) (*near_fill)(H);
-        if (far_sample) (*far_sample)(H, raw);
+        stage("device near blocks done");
       } catch (...) {
         dev_error = std::current_exception();
       }
+      std::lock_guard<std::mutex> lk(mu);
+      dev_done = true;
+      cv.notify_all();
     });
   }
   struct Joiner {            // the device thread is joined on every path out
@@ -389,25 +427,44 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
   }
   std::vector<std::vector<cplx>> Us(nf), Vs(nf);
   if (far_sample) {
+    int64_t next = 0;
+    const int64_t tenth = std::max<int64_t>(nf / 10, 1);
+    auto work = [&]() {
+      while (true) {
+        int64_t b;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&]() { return next < ready || dev_done; });
+          if (next >= ready) break;           // device finished (or failed) and nothing is left
+          b = next++;
+        }
+        if (p.verbose && b % tenth == 0) {
+          std::fprintf(stderr, "[hps] far blocks (recompression): %lld of %lld\n", (long long)b, (long long)nf);
+          std::fflush(stderr);
+        }
+        const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
+        const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
+        const int64_t m = thi - tlo, n = shi - slo, k = raw_rank[b];
+        int r = 0;
+        if (k < 0) {
+          aca_block(op, &H.perm[tlo], m, &H.perm[slo], n, p.aca_tol, Us[b], Vs[b], r);
+        } else if (k > 0) {
+          const cplx *u = src[b];
+          Us[b].assign(u, u + m * k);
+          Vs[b].assign(u + m * k, u + (m + n) * k);
+          recompress(m, n, k, Us[b], Vs[b], p.aca_tol, r);
+        }
+        H.far_rank[b] = r;
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
     dev_thread.join();
     if (dev_error) std::rethrow_exception(dev_error);
-    if ((int64_t)raw.rank.size() != nf) throw Error{HPS_EINVAL, "internal: device ACA result size"};
-    // recompress the device's factors; blocks it left over get the host ACA
-    parallel_for(nf, threads, [&](int64_t b) {
-      const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
-      const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
-      const int64_t m = thi - tlo, n = shi - slo, k = raw.rank[b];
-      int r = 0;
-      if (k < 0) {
-        aca_block(op, &H.perm[tlo], m, &H.perm[slo], n, p.aca_tol, Us[b], Vs[b], r);
-      } else if (k > 0) {
-        const cplx *u = raw.uv.data() + raw.off[b];
-        Us[b].assign(u, u + m * k);
-        Vs[b].assign(u + m * k, u + (m + n) * k);
-        recompress(m, n, k, Us[b], Vs[b], p.aca_tol, r);
-      }
-      H.far_rank[b] = r;
-    }, p.verbose ? "far blocks (recompression)" : nullptr);
+    if (ready != nf) throw Error{HPS_EINVAL, "internal: device ACA left far blocks out"};
+    chunks.clear();
   } else {
     parallel_for(nf, threads, [&](int64_t b) {
       const int64_t tlo = H.far_rng[4 * b], thi = H.far_rng[4 * b + 1];
@@ -417,15 +474,19 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
       H.far_rank[b] = r;
     }, p.verbose ? "far blocks (ACA)" : nullptr);
   }
+  stage("far blocks done");
   H.far_off.assign(nf + 1, 0);
   for (int64_t b = 0; b < nf; ++b) H.far_off[b + 1] = H.far_off[b] + (int64_t)(Us[b].size() + Vs[b].size());
   H.far_uv.resize(H.far_off[nf]);
-  for (int64_t b = 0; b < nf; ++b) {
+  parallel_for(nf, threads, [&](int64_t b) {
     std::copy(Us[b].begin(), Us[b].end(), H.far_uv.begin() + H.far_off[b]);
     std::copy(Vs[b].begin(), Vs[b].end(), H.far_uv.begin() + H.far_off[b] + (int64_t)Us[b].size());
-  }
+    std::vector<cplx>().swap(Us[b]);
+    std::vector<cplx>().swap(Vs[b]);
+  });
   if (dev_thread.joinable()) dev_thread.join();
   if (dev_error) std::rethrow_exception(dev_error);
+  stage("far factors assembled");
 }
 
 }  // namespace hps

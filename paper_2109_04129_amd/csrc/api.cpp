@@ -368,8 +368,8 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
         hps::HMatrix H;
         const hps::Mesh &mq = c->pmesh[q];
         const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(mq, p->freq_hz, h); };
-        const hps::FarSample sample = [&](const hps::HMatrix &h, hps::FarRaw &raw) {
-          c->dev->far_sample(mq, p->freq_hz, h, p->aca_tol, raw);
+        const hps::FarSample sample = [&](const hps::HMatrix &h, const hps::FarEmit &emit) {
+          c->dev->far_sample(mq, p->freq_hz, h, p->aca_tol, emit);
         };
         const bool dev = c->dev && !p->host_near;
         hps::build_hmatrix(mq, *p, H, dev ? &fill : nullptr, dev ? &sample : nullptr);
@@ -381,8 +381,8 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
     } else {
       hps::HMatrix H;
       const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(c->mesh, p->freq_hz, h); };
-      const hps::FarSample sample = [&](const hps::HMatrix &h, hps::FarRaw &raw) {
-        c->dev->far_sample(c->mesh, p->freq_hz, h, p->aca_tol, raw);
+      const hps::FarSample sample = [&](const hps::HMatrix &h, const hps::FarEmit &emit) {
+        c->dev->far_sample(c->mesh, p->freq_hz, h, p->aca_tol, emit);
       };
       const bool dev = c->dev && !p->host_near;
       hps::build_hmatrix(c->mesh, *p, H, dev ? &fill : nullptr, dev ? &sample : nullptr);

@@ -67,8 +67,9 @@ class DeviceState {
   // EFIE entries of the near blocks of H (structure set, values sized) on the
   // device, copied into H.near_vals; synchronous.
   void near_fill(const Mesh &m, double freq_hz, HMatrix &H);
-  // Raw ACA factors of every far block of H (far_rng set), see FarRaw.
-  void far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, FarRaw &raw);
+  // Raw ACA factors of every far block of H (far_rng set), chunk by chunk
+  // to emit, see FarChunk.
+  void far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, const FarEmit &emit);
   void set_profiling(bool on);
 
   int device;

@@ -938,6 +938,7 @@ __global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restri
   __shared__ uint32_t used[kAcaMaxRows / 32];
   __shared__ double sv[256], sw[256];
   __shared__ int si[256];
+  __shared__ double xpart[4][kAcaCap][4];     // per-wave cross-term sums
   const int64_t m = B.m, n = B.n;
   if (m > kAcaMaxRows) {
     if (tid == 0) rank_out[blockIdx.x] = -1;
@@ -1004,21 +1005,35 @@ __global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restri
     for (int64_t j = tid; j < n; j += nt) pv += cabs2(V[k * n + j]);
     const c2 s2 = block_csum(make_double2(pu, pv), sv, sw);
     const double nu2 = s2.x, nv2 = s2.y;
+    // cross terms sum_l (U_l^H u)(V_l^H v): wave sums into LDS, one barrier
+    {
+      const int wv = tid >> 6, ln = tid & 63;
+      for (int l = 0; l < k; ++l) {
+        double q[4] = {0.0, 0.0, 0.0, 0.0};      // U_l^H u (re, im), V_l^H v (re, im)
+        for (int64_t a = tid; a < m; a += nt) {
+          const c2 x = U[l * m + a], y = U[k * m + a];
+          q[0] += x.x * y.x + x.y * y.y;
+          q[1] += x.x * y.y - x.y * y.x;
+        }
+        for (int64_t j = tid; j < n; j += nt) {
+          const c2 x = V[l * n + j], y = V[k * n + j];
+          q[2] += x.x * y.x + x.y * y.y;
+          q[3] += x.x * y.y - x.y * y.x;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          for (int w = 32; w > 0; w >>= 1) q[c] += __shfl_xor(q[c], w, 64);
+        if (ln == 0)
+          for (int c = 0; c < 4; ++c) xpart[wv][l][c] = q[c];
+      }
+    }
+    __syncthreads();
     double cross = 0.0;
     for (int l = 0; l < k; ++l) {
-      c2 uu = make_double2(0.0, 0.0), vv = make_double2(0.0, 0.0);
-      for (int64_t a = tid; a < m; a += nt) {      // conj(U_l) . u
-        const c2 x = U[l * m + a], y = U[k * m + a];
-        uu.x += x.x * y.x + x.y * y.y;
-        uu.y += x.x * y.y - x.y * y.x;
-      }
-      for (int64_t j = tid; j < n; j += nt) {
-        const c2 x = V[l * n + j], y = V[k * n + j];
-        vv.x += x.x * y.x + x.y * y.y;
-        vv.y += x.x * y.y - x.y * y.x;
-      }
-      const c2 su = block_csum(uu, sv, sw), sv2 = block_csum(vv, sv, sw);
-      cross += su.x * sv2.x - su.y * sv2.y;
+      double q[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < 4; ++w)
+        for (int c = 0; c < 4; ++c) q[c] += xpart[w][l][c];
+      cross += q[0] * q[2] - q[1] * q[3];
     }
     norm2 += 2.0 * cross + nu2 * nv2;
     ++k;
@@ -1639,16 +1654,14 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   I.drop_graphs();
   const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * 7 * 8;
   if (I.mem_cap && need > I.mem_cap) throw Error{HPS_ENOMEM, "H-matrix exceeds device_mem_cap"};
-  {
-    std::vector<c2> tmp(H.near_vals.size());
-    std::memcpy(tmp.data(), H.near_vals.data(), tmp.size() * sizeof(c2));
-    I.near.upload(tmp, I.s);
-    HIP_CHECK(hipStreamSynchronize(I.s));
-    tmp.resize(H.far_uv.size());
-    std::memcpy(tmp.data(), H.far_uv.data(), tmp.size() * sizeof(c2));
-    I.faruv.upload(tmp, I.s);
-    HIP_CHECK(hipStreamSynchronize(I.s));
-  }
+  // complex<double> and double2 share their layout: copy straight from the host arrays
+  I.near.alloc(H.near_vals.size());
+  if (!H.near_vals.empty())
+    HIP_CHECK(hipMemcpyAsync(I.near.p, H.near_vals.data(), H.near_vals.size() * sizeof(c2), hipMemcpyHostToDevice, I.s));
+  I.faruv.alloc(H.far_uv.size());
+  if (!H.far_uv.empty())
+    HIP_CHECK(hipMemcpyAsync(I.faruv.p, H.far_uv.data(), H.far_uv.size() * sizeof(c2), hipMemcpyHostToDevice, I.s));
+  HIP_CHECK(hipStreamSynchronize(I.s));
   // structure copy without values
   I.hcopy = HMatrix();
   I.hcopy.N = H.N; I.hcopy.M = H.M; I.hcopy.perm = H.perm; I.hcopy.gptr = H.gptr;
@@ -2340,18 +2353,18 @@ void DeviceState::near_fill(const Mesh &m, double freq_hz, HMatrix &H) {
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
-void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, FarRaw &raw) {
+void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, const FarEmit &emit) {
   HIP_CHECK(hipSetDevice(device));
   Impl &I = *impl;
   const int64_t nf = H.n_far();
-  raw.rank.assign(nf, -1);
-  raw.off.assign(nf, 0);
-  raw.uv.clear();
   if (nf == 0) return;
   DevMesh dm(m, freq_hz, I.s);
   DevArray<int64_t> perm;
   perm.upload(H.perm, I.s);
-  const int64_t cap_elems = (int64_t)1 << 28;         // 4 GiB of scratch per chunk
+  // chunks: at most 4 GiB of scratch, and about a sixteenth of the blocks
+  // (no fewer than 4096) so that the host recompression starts early
+  const int64_t cap_elems = (int64_t)1 << 28;
+  const int64_t cap_blocks = std::max<int64_t>(4096, (nf + 15) / 16);
   DevArray<c2> scratch, packed;
   DevArray<AcaBlock> dblk;
   DevArray<int32_t> drank;
@@ -2361,7 +2374,7 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, do
     std::vector<AcaBlock> blk;
     int64_t need = 0;
     int64_t b = b0;
-    for (; b < nf; ++b) {
+    for (; b < nf && b - b0 < cap_blocks; ++b) {
       const int64_t mm = H.far_rng[4 * b + 1] - H.far_rng[4 * b], nn = H.far_rng[4 * b + 3] - H.far_rng[4 * b + 2];
       const int64_t e = (mm + nn) * kAcaCap;
       if (!blk.empty() && need + e > cap_elems) break;
@@ -2374,32 +2387,29 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, do
     drank.alloc((size_t)nb);
     hipLaunchKernelGGL(k_aca, dim3((unsigned)nb), dim3(256), 0, I.s, dm.M, perm.p, dblk.p, eps, scratch.p, drank.p);
     HIP_CHECK(hipGetLastError());
-    std::vector<int32_t> rk(nb);
-    HIP_CHECK(hipMemcpyAsync(rk.data(), drank.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, I.s));
+    FarChunk ch;
+    ch.b0 = b0;
+    ch.b1 = b;
+    ch.rank.resize(nb);
+    HIP_CHECK(hipMemcpyAsync(ch.rank.data(), drank.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, I.s));
     HIP_CHECK(hipStreamSynchronize(I.s));
-    std::vector<int64_t> pk(nb, 0);
+    ch.off.assign(nb, 0);
     int64_t tot = 0;
     for (int64_t q = 0; q < nb; ++q) {
-      pk[q] = tot;
-      if (rk[q] > 0) tot += (blk[q].m + blk[q].n) * rk[q];
+      ch.off[q] = tot;
+      if (ch.rank[q] > 0) tot += (blk[q].m + blk[q].n) * ch.rank[q];
     }
+    ch.uv.resize(tot);
     if (tot > 0) {
-      dpack.upload(pk, I.s);
+      dpack.upload(ch.off, I.s);
       packed.alloc((size_t)tot);
       hipLaunchKernelGGL(k_aca_pack, dim3((unsigned)nb), dim3(256), 0, I.s, dblk.p, drank.p, dpack.p, scratch.p,
                          packed.p);
       HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync((void *)ch.uv.data(), packed.p, (size_t)tot * sizeof(c2), hipMemcpyDeviceToHost, I.s));
     }
-    const int64_t base = (int64_t)raw.uv.size();
-    raw.uv.resize(base + tot);
-    if (tot > 0)
-      HIP_CHECK(hipMemcpyAsync((void *)(raw.uv.data() + base), packed.p, (size_t)tot * sizeof(c2),
-                               hipMemcpyDeviceToHost, I.s));
     HIP_CHECK(hipStreamSynchronize(I.s));
-    for (int64_t q = 0; q < nb; ++q) {
-      raw.rank[b0 + q] = rk[q];
-      raw.off[b0 + q] = base + pk[q];
-    }
+    emit(std::move(ch));
     b0 = b;
   }
 }

@@ -98,20 +98,25 @@ void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *co
 // called on its own host thread while the far blocks are compressed.
 using NearFill = std::function<void(HMatrix &H)>;
 
-// Unrecompressed ACA factors of the far blocks: block b has rank[b] terms
-// (U m x k then V n x k, column-major, at uv[off[b]]), or rank[b] = -1 when
-// it is left to the host ACA (rank limit, term cap).
-struct FarRaw {
+// Unrecompressed ACA factors of the far blocks [b0, b1): block b has
+// rank[b - b0] terms (U m x k then V n x k, column-major, at
+// uv[off[b - b0]]), or rank -1 when it is left to the host ACA (rank limit,
+// term cap).
+struct FarChunk {
+  int64_t b0 = 0, b1 = 0;
   std::vector<int32_t> rank;
   std::vector<int64_t> off;
   std::vector<cplx> uv;
 };
-using FarSample = std::function<void(const HMatrix &H, FarRaw &raw)>;
+using FarEmit = std::function<void(FarChunk &&chunk)>;
+// Hands every far block of H (far_rng set) to emit, in chunks of increasing
+// block index.
+using FarSample = std::function<void(const HMatrix &H, const FarEmit &emit)>;
 
-// With near_fill / far_sample the near blocks and the ACA sampling of the far
-// blocks run there (the device, on one host thread, in that order); the far
-// blocks are then recompressed on host threads.  Without them everything
-// runs on host threads.
+// With near_fill / far_sample the ACA sampling of the far blocks and then the
+// near blocks run there (the device, on one host thread, in that order); host
+// threads recompress each chunk of far blocks as it arrives.  Without them
+// everything runs on host threads.
 void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const NearFill *near_fill = nullptr,
                    const FarSample *far_sample = nullptr);
 
