@@ -425,25 +425,71 @@ __global__ __launch_bounds__(256) void k_far16(const c2 *__restrict__ in, uint32
 //
 // Tile layout: thread (rg, cg) with tid = rg + RB*cg owns rows rg*2, rg*2+1 and
 // columns cg*CT..cg*CT+CT-1 (RB = NC/2 row groups, 16 column groups, CT = NC/16;
-// a column group lies inside one wave).  One barrier per elimination step.
+// a column group fills whole 16-lane rows of one wave).  One barrier per
+// elimination step.
+//
+// The pivot row is not scaled at its step: every row r is kept multiplied by
+// its own pivot piv_r from then on (row operations commute with that scaling),
+// its pivot-column entry is stored as 1, and the store multiplies row r by
+// 1 / piv_r.  So the step is one rank-1 update of all rows with the pivot
+// row's multiplier set to zero.
+
+// 64-bit DPP move inside a wave; lanes outside the 16-lane row or the row
+// mask read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWMASK, 0xF, true);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// Maximum over each group of RB consecutive lanes (RB = 16, 32 or 64), left
+// in the group's last lane.  Every lane of the wave must be active.
+template <int RB>
+__device__ __forceinline__ uint64_t group_max(uint64_t k) {
+  k = umax64(k, dpp64<0x111, 0xF>(k));                 // row_shr:1
+  k = umax64(k, dpp64<0x112, 0xF>(k));                 // row_shr:2
+  k = umax64(k, dpp64<0x114, 0xF>(k));                 // row_shr:4
+  k = umax64(k, dpp64<0x118, 0xF>(k));                 // row_shr:8: lane 15 holds the row maximum
+  if (RB >= 32) k = umax64(k, dpp64<0x142, 0xA>(k));   // row_bcast:15 into rows 1 and 3
+  if (RB >= 64) k = umax64(k, dpp64<0x143, 0xC>(k));   // row_bcast:31 into rows 2 and 3
+  return k;
+}
+
+// Value of lane src_lane (the same for the whole group) to every lane.
+template <int RB>
+__device__ __forceinline__ double group_bcast(double v, int src_lane) {
+  if (RB == 64) {                     // one group per wave: the source lane is wave-uniform
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, src_lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src_lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  }
+  return __shfl(v, src_lane, 64);
+}
+
 template <int NC>
 __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
                                                     const int64_t *__restrict__ off,
                                                     const int32_t *__restrict__ nsz,
                                                     const int32_t *__restrict__ ids,
                                                     int *__restrict__ status) {
-  constexpr int RT = 2, RB = NC / RT, CT = NC / 16;
-  static_assert(64 % RB == 0, "a column group must lie inside one wave");
+  constexpr int RT = 2, RB = NC / RT, CT = NC / 16, GW = 64 / RB;
+  static_assert(64 % RB == 0 && RB >= 16, "a column group must fill whole rows of one wave");
+  static_assert(NC <= 128, "the row index is packed in 7 bits of the pivot key");
   const int blk = blockIdx.x;
   const int n = nsz[blk];
   const c2 *src = W + off[blk];
   c2 *dst = F + off[blk];
   const int tid = threadIdx.x, rg = tid % RB, cg = tid / RB;
-  const int lane = tid & 63;
-  const int gbase = lane - rg;          // first lane of my column group (RB divides 64)
-  __shared__ c2 colbuf[2][NC];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int gbase = lane - rg;          // first lane of my column group
+  __shared__ c2 colbuf[2][NC];          // pivot column of the step (pivot row entry zeroed)
+  __shared__ c2 pinv[2];
   __shared__ int pbuf[2];
   __shared__ int pivrow[NC], stepof[NC];
+  __shared__ c2 rowinv[NC];             // 1 / pivot of each row
   c2 a[RT][CT];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
@@ -459,76 +505,80 @@ __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2
   bool singular = false;
   for (int k = 0; k < n; ++k) {
     const int s = k & 1;
-    if (cg == k / CT) {
-      const int kc = k % CT;
-      double best = -1.0;
-      int bi = 0x7fffffff;
+    const int cgk = k / CT, kc = k % CT;
+    if (wave == cgk / GW) {
+      // Pivot search on column k, at raised wave priority: the other waves of
+      // this SIMD are still in the previous update.  Key = |z|^2 with its last
+      // 7 mantissa bits replaced by (127 - row): largest modulus, lowest row
+      // on ties.
+      __builtin_amdgcn_s_setprio(3);
+      const bool mine = (cg == cgk);
+      uint64_t key = 0;
+      c2 v[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        c2 v = make_double2(0.0, 0.0);
+        v[r] = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int j = 0; j < CT; ++j) {
-          const double w = (j == kc) ? 1.0 : 0.0;
-          v.x = fma(w, a[r][j].x, v.x);
-          v.y = fma(w, a[r][j].y, v.y);
+        for (int j = 0; j < CT; ++j)
+          if (j == kc) v[r] = a[r][j];
+        const int row = rg * RT + r;
+        if (mine) colbuf[s][row] = v[r];
+        const double m = v[r].x * v[r].x + v[r].y * v[r].y;
+        const uint64_t kr = ((uint64_t)__double_as_longlong(m) & ~(uint64_t)0x7F) | (uint64_t)(0x7F - row);
+        key = (mine && !((used >> r) & 1u)) ? umax64(key, kr) : key;
+      }
+      key = group_max<RB>(key);
+      const uint32_t klo = __shfl((uint32_t)key, gbase + RB - 1, 64);
+      const uint32_t khi = __shfl((uint32_t)(key >> 32), gbase + RB - 1, 64);
+      const uint64_t K = ((uint64_t)khi << 32) | klo;
+      const int p = (K >> 7) ? 0x7F - (int)(K & 0x7F) : -1;
+      if (mine) {
+        // column k becomes 1 on the pivot row, 0 elsewhere; the update then
+        // leaves -multiplier in the other rows
+        const bool isp = (p >= 0) && (rg == p / RT);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const c2 nv = (isp && r == p % RT) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+            if (j == kc) a[r][j] = nv;
         }
-        colbuf[s][rg * RT + r] = v;
-        const double m = v.x * v.x + v.y * v.y;
-        const bool ok = !((used >> r) & 1u) && m > best;
-        best = ok ? m : best;
-        bi = ok ? rg * RT + r : bi;
+        if (isp) {
+          const c2 iv = cinv((p % RT) ? v[1] : v[0]);
+          pinv[s] = iv;
+          rowinv[p] = iv;
+          colbuf[s][p] = make_double2(0.0, 0.0);    // the pivot row is not updated
+          pbuf[s] = p;
+          pivrow[k] = p;
+          stepof[p] = k;
+        }
+        if (p < 0 && rg == 0) pbuf[s] = -1;
       }
-      // reduce (max value, lowest row on ties) over the RB lanes of the group
-#pragma unroll
-      for (int w = 1; w < RB; w <<= 1) {
-        const double ob = __shfl_xor(best, w, 64);
-        const int oi = __shfl_xor(bi, w, 64);
-        const bool take = (ob > best) || (ob == best && oi < bi);
-        best = take ? ob : best;
-        bi = take ? oi : bi;
-      }
-      if (rg == 0) {
-        const int p = (best > 0.0 && bi < n) ? bi : -1;
-        pbuf[s] = p;
-        if (p >= 0) { pivrow[k] = p; stepof[p] = k; }
-      }
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     const int p = pbuf[s];
     if (p < 0) { singular = true; break; }
-    const c2 inv = cinv(colbuf[s][p]);
-    c2 m[RT];
+    const c2 inv = pinv[s];
+    c2 mi[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) m[r] = colbuf[s][rg * RT + r];
+    for (int r = 0; r < RT; ++r) mi[r] = cmul(colbuf[s][rg * RT + r], inv);
     const int pr = p % RT, src_lane = gbase + p / RT;
-    const bool ownp = (rg == p / RT);
+    c2 rp[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
-      c2 v = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        const double w = (r == pr) ? 1.0 : 0.0;
-        v.x = fma(w, a[r][j].x, v.x);
-        v.y = fma(w, a[r][j].y, v.y);
-      }
-      c2 rowp;
-      rowp.x = __shfl(v.x, src_lane, 64);
-      rowp.y = __shfl(v.y, src_lane, 64);
-      const c2 rp = cmul(rowp, inv);
-      const bool isk = (cg * CT + j == k);
-      const double delta = isk ? 0.0 : 1.0;
-      const c2 beta = isk ? inv : rp;
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        c2 t;
-        t.x = fma(-m[r].x, beta.x, fma(m[r].y, beta.y, a[r][j].x * delta));
-        t.y = fma(-m[r].x, beta.y, fma(-m[r].y, beta.x, a[r][j].y * delta));
-        const bool isp = ownp && (r == pr);
-        a[r][j].x = isp ? beta.x : t.x;
-        a[r][j].y = isp ? beta.y : t.y;
-      }
+      const c2 v = pr ? a[1][j] : a[0][j];
+      rp[j].x = group_bcast<RB>(v.x, src_lane);
+      rp[j].y = group_bcast<RB>(v.y, src_lane);
     }
-    if (ownp) used |= 1u << pr;
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        a[r][j].x = fma(-mi[r].x, rp[j].x, fma(mi[r].y, rp[j].y, a[r][j].x));
+        a[r][j].y = fma(-mi[r].x, rp[j].y, fma(-mi[r].y, rp[j].x, a[r][j].y));
+      }
+    if (rg == p / RT) used |= 1u << pr;
   }
   if (singular) {
     if (tid == 0) atomicMax(status, ids[blk] + 1);
@@ -536,12 +586,15 @@ __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RT; ++r)
+  for (int r = 0; r < RT; ++r) {
+    const int row = rg * RT + r;
+    const c2 ri = row < n ? rowinv[row] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
-      const int row = rg * RT + r, col = cg * CT + j;
-      if (row < n && col < n) dst[(int64_t)pivrow[col] * n + stepof[row]] = a[r][j];
+      const int col = cg * CT + j;
+      if (row < n && col < n) dst[(int64_t)pivrow[col] * n + stepof[row]] = cmul(a[r][j], ri);
     }
+  }
 }
 
 // ------------------------------------------------------------------ small kernels
