@@ -1312,6 +1312,7 @@ struct DeviceState::Impl {
     out.n_tiles = (int64_t)pl.tiles.size() - out.t0;
     validate(pl.tiles.data() + out.t0, (size_t)out.n_tiles, pl.terms, na, nb, nc, what);
   }
+  // host side of the solve schedules; upload_solve_pool() copies them
   void build_solve_pool() {
     spool.clear();
     b_fwd.assign(fwd.size(), Built());
@@ -1323,9 +1324,9 @@ struct DeviceState::Impl {
     build(far1, spool, b_far1, (int64_t)faruv.n, N, nT, "far stage 1");
     build(far2, spool, b_far2, (int64_t)faruv.n, nT, N, "far stage 2");
     build(nearmv, spool, b_near, (int64_t)near.n, N, N, "near matvec");
-    spool.upload(s);
     built_R = -1;
   }
+  void upload_solve_pool() { spool.upload(s); }
 
   // ---- optional per-launch timing with HIP events on the library stream
   // kinds: 0..2 = k_gemm<mode>, 3 = k_inverse
@@ -2055,51 +2056,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
                    schurl[l].flops, schurl[l].bytes);
   }
   HIP_CHECK(hipEventRecord(e1, s));
-  HIP_CHECK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-  times.schur_ms = ms;
-  I.prof_collect();
-  HIP_CHECK(hipEventDestroy(e0));
-  HIP_CHECK(hipEventDestroy(e1));
-  int st = 0;
-  HIP_CHECK(hipMemcpy(&st, I.status.p, sizeof(int), hipMemcpyDeviceToHost));
-  if (st > 0) throw Error{HPS_ESINGULAR, "singular scaled diagonal block of group " + std::to_string(P.order[st - 1])};
-  I.P.setup_flops = flops;
 
-  // ---- precision form: FP32 copies of the factor panels and near blocks,
-  // far factors to 16-bit pairs with one FP32 scale per factor per block
-  if (I.precision > 0) {
-    I.F32.alloc(PE);
-    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PE);
-    HIP_CHECK(hipGetLastError());
-    const int64_t nn = std::max<int64_t>((int64_t)I.near.n, 1);
-    I.near32.alloc(nn);
-    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, s, I.near.p, I.near32.p, (int64_t)I.near.n);
-    HIP_CHECK(hipGetLastError());
-    const HMatrix &Hf = I.hcopy;
-    std::vector<FarPart> parts(2 * Hf.n_far());
-    for (int64_t b = 0; b < Hf.n_far(); ++b) {
-      const int64_t m = Hf.far_rng[4 * b + 1] - Hf.far_rng[4 * b], n = Hf.far_rng[4 * b + 3] - Hf.far_rng[4 * b + 2];
-      const int64_t r = Hf.far_rank[b];
-      parts[2 * b] = FarPart{Hf.far_off[b], m * r};
-      parts[2 * b + 1] = FarPart{Hf.far_off[b] + m * r, n * r};
-      if (Hf.far_off[b] + (m + n) * r > (int64_t)I.faruv.n) throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
-    }
-    I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
-    I.fscale.alloc(std::max<size_t>(parts.size(), 1));
-    if (!parts.empty()) {
-      DevArray<FarPart> dparts;
-      dparts.upload(parts, s);
-      if (I.precision == 1)
-        hipLaunchKernelGGL(k_far16<1>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
-      else
-        hipLaunchKernelGGL(k_far16<2>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
-      HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipStreamSynchronize(s));
-    }
-  }
-
+  // the solve schedules are built on the host while the device runs the levels
   // ---- solve schedules (terms independent of R)
   auto add_target = [](Impl::Sched &sc, int64_t coff, int32_t m, int32_t ld) {
     sc.targets.push_back({coff, m});
@@ -2234,6 +2192,52 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   }
   close(I.nearmv);
   I.build_solve_pool();
+  HIP_CHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  times.schur_ms = ms;
+  I.prof_collect();
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+  int st = 0;
+  HIP_CHECK(hipMemcpy(&st, I.status.p, sizeof(int), hipMemcpyDeviceToHost));
+  if (st > 0) throw Error{HPS_ESINGULAR, "singular scaled diagonal block of group " + std::to_string(P.order[st - 1])};
+  I.P.setup_flops = flops;
+
+  // ---- precision form: FP32 copies of the factor panels and near blocks,
+  // far factors to 16-bit pairs with one FP32 scale per factor per block
+  if (I.precision > 0) {
+    I.F32.alloc(PE);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PE);
+    HIP_CHECK(hipGetLastError());
+    const int64_t nn = std::max<int64_t>((int64_t)I.near.n, 1);
+    I.near32.alloc(nn);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, s, I.near.p, I.near32.p, (int64_t)I.near.n);
+    HIP_CHECK(hipGetLastError());
+    const HMatrix &Hf = I.hcopy;
+    std::vector<FarPart> parts(2 * Hf.n_far());
+    for (int64_t b = 0; b < Hf.n_far(); ++b) {
+      const int64_t m = Hf.far_rng[4 * b + 1] - Hf.far_rng[4 * b], n = Hf.far_rng[4 * b + 3] - Hf.far_rng[4 * b + 2];
+      const int64_t r = Hf.far_rank[b];
+      parts[2 * b] = FarPart{Hf.far_off[b], m * r};
+      parts[2 * b + 1] = FarPart{Hf.far_off[b] + m * r, n * r};
+      if (Hf.far_off[b] + (m + n) * r > (int64_t)I.faruv.n) throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
+    }
+    I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
+    I.fscale.alloc(std::max<size_t>(parts.size(), 1));
+    if (!parts.empty()) {
+      DevArray<FarPart> dparts;
+      dparts.upload(parts, s);
+      if (I.precision == 1)
+        hipLaunchKernelGGL(k_far16<1>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
+      else
+        hipLaunchKernelGGL(k_far16<2>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+  }
+
+  I.upload_solve_pool();
   I.ready = true;
 }
 
