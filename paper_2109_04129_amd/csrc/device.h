@@ -78,6 +78,8 @@ class DeviceState {
   StageTimes times;
   int terms = 2;
   double last_solve_flops = 0.0;
+  // setup schedule: ms until every level was built, ms the launching thread
+  // waited for builds, ms it spent staging and enqueueing, tiles, terms
   double sched_split[5] = {0, 0, 0, 0, 0};
 
   struct Impl;

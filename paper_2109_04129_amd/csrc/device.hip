@@ -23,6 +23,9 @@
 #include <map>
 #include <sstream>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <thread>
 
 #include "device.h"
@@ -1145,6 +1148,37 @@ struct DevArray {
   ~DevArray() { release(); }
 };
 
+// Pinned host array (hipHostMalloc), grow-only; the source of asynchronous
+// uploads that must not wait for earlier work on the stream.  Growing frees
+// the old block, so callers synchronise with the device before reusing a
+// chunk across calls (every setup ends with a synchronisation).
+template <class T>
+struct PinnedArray {
+  T *p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    HIP_CHECK(hipHostMalloc((void **)&p, count * sizeof(T), hipHostMallocDefault));
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  PinnedArray() = default;
+  PinnedArray(const PinnedArray &) = delete;
+  PinnedArray &operator=(const PinnedArray &) = delete;
+  PinnedArray(PinnedArray &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  PinnedArray &operator=(PinnedArray &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~PinnedArray() { release(); }
+};
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Host-side bounds check of a tile/term batch against the element counts of
@@ -1183,14 +1217,6 @@ void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, 
 }
 
 }  // namespace
-
-struct LevelInv {
-  int nc;                       // 32, 64 or 128
-  std::vector<int64_t> off;
-  std::vector<int32_t> n, id;
-  DevArray<int64_t> d_off;
-  DevArray<int32_t> d_n, d_id;
-};
 
 struct DeviceState::Impl {
   hipStream_t s;
@@ -1283,6 +1309,40 @@ struct DeviceState::Impl {
       bytes = 32.0 * sm * (double)R + 16.0 * (smk + sk * (double)R);
     }
   };
+  // staging and device copies of one chunk of setup levels (grow-only, kept
+  // across setups)
+  struct Chunk {
+    PinnedArray<Tile> h_tiles;
+    PinnedArray<Term> h_terms;
+    PinnedArray<int64_t> h_inv_off;
+    PinnedArray<int32_t> h_inv_n, h_inv_id;
+    DevArray<Tile> d_tiles;
+    DevArray<Term> d_terms;
+    DevArray<int64_t> d_inv_off;
+    DevArray<int32_t> d_inv_n, d_inv_id;
+    void reserve(int64_t nt, int64_t nm, int64_t ni) {
+      h_tiles.alloc((size_t)nt);
+      h_terms.alloc((size_t)nm);
+      h_inv_off.alloc((size_t)ni);
+      h_inv_n.alloc((size_t)ni);
+      h_inv_id.alloc((size_t)ni);
+      d_tiles.alloc((size_t)nt);
+      d_terms.alloc((size_t)nm);
+      d_inv_off.alloc((size_t)ni);
+      d_inv_n.alloc((size_t)ni);
+      d_inv_id.alloc((size_t)ni);
+    }
+    void upload(int64_t nt, int64_t nm, int64_t ni, hipStream_t st) {
+      if (nt) HIP_CHECK(hipMemcpyAsync(d_tiles.p, h_tiles.p, nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+      if (nm) HIP_CHECK(hipMemcpyAsync(d_terms.p, h_terms.p, nm * sizeof(Term), hipMemcpyHostToDevice, st));
+      if (ni) {
+        HIP_CHECK(hipMemcpyAsync(d_inv_off.p, h_inv_off.p, ni * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_inv_n.p, h_inv_n.p, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(d_inv_id.p, h_inv_id.p, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      }
+    }
+  };
+  std::deque<Chunk> chunks;       // a deque: growing never relocates the arrays
   Pool spool;                      // solve schedules (independent of R)
   int64_t built_R = -1;
   std::vector<Built> b_fwd, b_bwd;
@@ -1942,119 +2002,150 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     tcount.clear();
     tjrow.clear();
   };
-  {
-    const int nthreads = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16));
-    std::atomic<int> next{0};
-    auto worker = [&]() {
-      std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
-      std::vector<Term> pair_term;
-      while (true) {
-        const int l = next.fetch_add(1);
-        if (l >= L) break;
-        try {
-          build_level(l, slot, tgt, tcount, tjrow, pair_id, pair_term);
-        } catch (const Error &e) {
-          lv_out[l].err = e.msg;
-        }
+  // Levels are built on worker threads in level order while this thread
+  // uploads and launches them in chunks of growing size (2, 4, 8, ... levels),
+  // so the device starts on the first levels while later ones are built.
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<char> built(L, 0);
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
+    std::vector<Term> pair_term;
+    while (true) {
+      const int l = next.fetch_add(1);
+      if (l >= L) break;
+      try {
+        build_level(l, slot, tgt, tcount, tjrow, pair_id, pair_term);
+        LevelOut &o = lv_out[l];
+        validate(o.ctiles.data(), o.ctiles.size(), o.cterms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
+        validate(o.stiles.data(), o.stiles.size(), o.sterms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
+      } catch (const Error &e) {
+        lv_out[l].err = e.msg;
       }
-    };
-    std::vector<std::thread> pool_threads;
-    for (int t = 1; t < nthreads; ++t) pool_threads.emplace_back(worker);
-    worker();
-    for (auto &th : pool_threads) th.join();
-    for (int l = 0; l < L; ++l)
-      if (!lv_out[l].err.empty()) throw Error{HPS_EINVAL, lv_out[l].err};
-  }
-  // concatenate in level order
-  std::vector<InvLaunch> invl;
-  std::vector<int64_t> inv_off;
-  std::vector<int32_t> inv_n, inv_id;
-  std::vector<GemmLaunch> coefl(L), schurl(L);
-  Impl::Pool pool;
-  double flops = 0.0;
-  {
-    size_t nt = 0, nm = 0;
-    for (auto &o : lv_out) {
-      nt += o.ctiles.size() + o.stiles.size();
-      nm += o.cterms.size() + o.sterms.size();
+      std::lock_guard<std::mutex> lk(mu);
+      built[l] = 1;
+      cv.notify_all();
     }
-    pool.tiles.reserve(nt);
-    pool.terms.reserve(nm);
-  }
-  const int ncls[3] = {32, 64, 128};
-  for (int l = 0; l < L; ++l) {
-    LevelOut &o = lv_out[l];
-    for (int c = 0; c < 3; ++c) {
-      if (o.inv_off[c].empty()) continue;
-      invl.push_back(InvLaunch{ncls[c], (int64_t)inv_off.size(), (int64_t)o.inv_off[c].size(), l, o.inv_flops[c]});
-      inv_off.insert(inv_off.end(), o.inv_off[c].begin(), o.inv_off[c].end());
-      inv_n.insert(inv_n.end(), o.inv_n[c].begin(), o.inv_n[c].end());
-      inv_id.insert(inv_id.end(), o.inv_id[c].begin(), o.inv_id[c].end());
+  };
+  const int nthreads = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), 16));
+  std::vector<std::thread> pool_threads;
+  struct Joiner {
+    std::vector<std::thread> &t;
+    std::atomic<int> &next;
+    int L;
+    ~Joiner() {
+      next.store(L);                    // on an early exit the workers stop after their level
+      for (auto &th : t)
+        if (th.joinable()) th.join();
     }
-    auto append = [&](std::vector<Tile> &tl, std::vector<Term> &tm, GemmLaunch &dst, const GemmLaunch &src) {
-      const int32_t base = (int32_t)pool.terms.size();
-      pool.terms.insert(pool.terms.end(), tm.begin(), tm.end());
-      dst = src;
-      dst.t0 = (int64_t)pool.tiles.size();
-      for (Tile t : tl) {
-        t.t_begin += base;
-        t.t_end += base;
-        pool.tiles.push_back(t);
-      }
-      dst.n = (int64_t)tl.size();
-      std::vector<Tile>().swap(tl);
-      std::vector<Term>().swap(tm);
-    };
-    append(o.ctiles, o.cterms, coefl[l], o.coef);
-    append(o.stiles, o.sterms, schurl[l], o.schur);
-    flops += o.flops;
-  }
-  const auto th1 = std::chrono::steady_clock::now();
-  validate(pool.tiles.data(), pool.tiles.size(), pool.terms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
-  const auto th2 = std::chrono::steady_clock::now();
-  pool.upload(s);
-  HIP_CHECK(hipStreamSynchronize(s));
-  const auto th3 = std::chrono::steady_clock::now();
-  sched_split[0] = std::chrono::duration<double, std::milli>(th1 - th0).count();
-  sched_split[1] = std::chrono::duration<double, std::milli>(th2 - th1).count();
-  sched_split[2] = std::chrono::duration<double, std::milli>(th3 - th2).count();
-  sched_split[3] = (double)pool.tiles.size();
-  sched_split[4] = (double)pool.terms.size();
-  DevArray<int64_t> d_inv_off;
-  DevArray<int32_t> d_inv_n, d_inv_id;
-  d_inv_off.upload(inv_off, s);
-  d_inv_n.upload(inv_n, s);
-  d_inv_id.upload(inv_id, s);
-  HIP_CHECK(hipMemsetAsync(I.status.p, 0, sizeof(int), s));
-  times.inverse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+  } joiner{pool_threads, next, L};
+  for (int t = 0; t < nthreads; ++t) pool_threads.emplace_back(worker);
 
+  std::vector<int> cut{0};
+  for (int w = 2; cut.back() < L; w *= 2) cut.push_back(std::min(L, cut.back() + w));
+  const int n_chunks = (int)cut.size() - 1;
+  if ((int)I.chunks.size() < n_chunks) I.chunks.resize(n_chunks);
+  double flops = 0.0, wait_ms = 0.0, stage_ms = 0.0;
+  int64_t n_tiles_all = 0, n_terms_all = 0;
+  const int ncls[3] = {32, 64, 128};
+  HIP_CHECK(hipMemsetAsync(I.status.p, 0, sizeof(int), s));
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
-  HIP_CHECK(hipEventRecord(e0, s));
-  size_t ii = 0;
-  for (int l = 0; l < L; ++l) {
-    for (; ii < invl.size() && invl[ii].level == l; ++ii) {
-      const InvLaunch &li = invl[ii];
-      const unsigned nb = (unsigned)li.count;
-      const int64_t *po = d_inv_off.p + li.start;
-      const int32_t *pn = d_inv_n.p + li.start, *pi = d_inv_id.p + li.start;
-      Impl::ProfRec *pr = I.prof_begin(3, li.flops, 0.0, li.count);
-      if (li.nc == 32)
-        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-      else if (li.nc == 64)
-        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-      else
-        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(1024), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-      HIP_CHECK(hipGetLastError());
-      I.prof_end(pr);
+  for (int c = 0; c < n_chunks; ++c) {
+    const int lo = cut[c], hi = cut[c + 1];
+    {
+      const auto tw = std::chrono::steady_clock::now();
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&]() {
+        for (int l = lo; l < hi; ++l)
+          if (!built[l]) return false;
+        return true;
+      });
+      wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw).count();
     }
-    I.launch_tiles(pool.dtiles.p + coefl[l].t0, pool.dterms.p, coefl[l].n, 0, I.F.p, Wd, I.F.p, 1, coefl[l].flops,
-                   coefl[l].bytes);
-    I.launch_tiles(pool.dtiles.p + schurl[l].t0, pool.dterms.p, schurl[l].n, 1, Wd, I.F.p, Wd,
-                   std::min(schurl[l].sub, SUB_Y),
-                   schurl[l].flops, schurl[l].bytes);
+    for (int l = lo; l < hi; ++l)
+      if (!lv_out[l].err.empty()) throw Error{HPS_EINVAL, lv_out[l].err};
+    const auto tst = std::chrono::steady_clock::now();
+    Impl::Chunk &ch = I.chunks[c];
+    int64_t nt = 0, nm = 0, ni = 0;
+    for (int l = lo; l < hi; ++l) {
+      const LevelOut &o = lv_out[l];
+      nt += (int64_t)(o.ctiles.size() + o.stiles.size());
+      nm += (int64_t)(o.cterms.size() + o.sterms.size());
+      for (int k = 0; k < 3; ++k) ni += (int64_t)o.inv_off[k].size();
+    }
+    ch.reserve(nt, nm, ni);
+    // concatenate into the chunk's pinned staging arrays (term indices rebased)
+    std::vector<InvLaunch> invl;
+    std::vector<GemmLaunch> coefl(hi - lo), schurl(hi - lo);
+    int64_t ti = 0, mi_ = 0, ii = 0;
+    for (int l = lo; l < hi; ++l) {
+      LevelOut &o = lv_out[l];
+      for (int k = 0; k < 3; ++k) {
+        const int64_t cnt = (int64_t)o.inv_off[k].size();
+        if (cnt == 0) continue;
+        invl.push_back(InvLaunch{ncls[k], ii, cnt, l, o.inv_flops[k]});
+        std::copy(o.inv_off[k].begin(), o.inv_off[k].end(), ch.h_inv_off.p + ii);
+        std::copy(o.inv_n[k].begin(), o.inv_n[k].end(), ch.h_inv_n.p + ii);
+        std::copy(o.inv_id[k].begin(), o.inv_id[k].end(), ch.h_inv_id.p + ii);
+        ii += cnt;
+      }
+      auto append = [&](std::vector<Tile> &tl, std::vector<Term> &tm, GemmLaunch &dst, const GemmLaunch &src) {
+        const int32_t base = (int32_t)mi_;
+        std::copy(tm.begin(), tm.end(), ch.h_terms.p + mi_);
+        mi_ += (int64_t)tm.size();
+        dst = src;
+        dst.t0 = ti;
+        for (const Tile &t0 : tl) {
+          Tile t = t0;
+          t.t_begin += base;
+          t.t_end += base;
+          ch.h_tiles.p[ti++] = t;
+        }
+        dst.n = (int64_t)tl.size();
+        std::vector<Tile>().swap(tl);
+        std::vector<Term>().swap(tm);
+      };
+      append(o.ctiles, o.cterms, coefl[l - lo], o.coef);
+      append(o.stiles, o.sterms, schurl[l - lo], o.schur);
+      flops += o.flops;
+    }
+    ch.upload(nt, nm, ni, s);
+    n_tiles_all += nt;
+    n_terms_all += nm;
+    stage_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tst).count();
+    if (c == 0) HIP_CHECK(hipEventRecord(e0, s));
+    size_t q = 0;
+    for (int l = lo; l < hi; ++l) {
+      for (; q < invl.size() && invl[q].level == l; ++q) {
+        const InvLaunch &li = invl[q];
+        const unsigned nb = (unsigned)li.count;
+        const int64_t *po = ch.d_inv_off.p + li.start;
+        const int32_t *pn = ch.d_inv_n.p + li.start, *pi = ch.d_inv_id.p + li.start;
+        Impl::ProfRec *pr = I.prof_begin(3, li.flops, 0.0, li.count);
+        if (li.nc == 32)
+          hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        else if (li.nc == 64)
+          hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        else
+          hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(1024), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
+        HIP_CHECK(hipGetLastError());
+        I.prof_end(pr);
+      }
+      const GemmLaunch &cl = coefl[l - lo], &sl = schurl[l - lo];
+      I.launch_tiles(ch.d_tiles.p + cl.t0, ch.d_terms.p, cl.n, 0, I.F.p, Wd, I.F.p, 1, cl.flops, cl.bytes);
+      I.launch_tiles(ch.d_tiles.p + sl.t0, ch.d_terms.p, sl.n, 1, Wd, I.F.p, Wd, std::min(sl.sub, SUB_Y), sl.flops,
+                     sl.bytes);
+    }
   }
+  sched_split[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+  sched_split[1] = wait_ms;
+  sched_split[2] = stage_ms;
+  sched_split[3] = (double)n_tiles_all;
+  sched_split[4] = (double)n_terms_all;
+  times.inverse_ms = wait_ms + stage_ms;
   HIP_CHECK(hipEventRecord(e1, s));
 
   // the solve schedules are built on the host while the device runs the levels
@@ -2493,8 +2584,8 @@ std::string DeviceState::stats_json() const {
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
   o << ", \"terms\": " << I.terms << ", \"series_tol\": " << I.series_tol << ", \"terms_used\": " << I.terms_used;
-  o << ", \"schedule_split\": {\"build_ms\": " << sched_split[0] << ", \"validate_ms\": " << sched_split[1]
-    << ", \"upload_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
+  o << ", \"schedule_split\": {\"levels_built_ms\": " << sched_split[0] << ", \"wait_ms\": " << sched_split[1]
+    << ", \"stage_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
   o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms
     << ", \"symbolic\": " << times.symbolic_ms
     << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms
