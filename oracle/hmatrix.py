@@ -8,6 +8,11 @@ Everything is indexed in *tree order* (position p holds RWG unknown perm[p]):
 * far blocks (t, s), admissible cluster pairs with t before s in depth-first
   order, hold ACA factors with Z[perm[t], perm[s]] ~= U V^T; the (s, t)
   block is V U^T.
+
+The CFIE matrix (eq. 8) is not symmetric: then ``symmetric`` is False, near
+blocks are stored for every ordered pair (t, s) of touching leaves and far
+blocks for both orders of every admissible pair, each applied only as
+Z[t, s] ~= U V^T.
 """
 
 import numpy as np
@@ -15,16 +20,18 @@ import numpy as np
 from .aca import aca
 from .cluster import build_tree, block_partition
 from .efie import EFIEOperator
+from .mfie import CFIEOperator
 from .rwg import build_rwg, edge_midpoints
 
 
 class HMatrix:
-    def __init__(self, N, perm, groups, near, far):
+    def __init__(self, N, perm, groups, near, far, symmetric=True):
         self.N = N
         self.perm = np.asarray(perm, dtype=np.int64)
         self.groups = np.asarray(groups, dtype=np.int64)        # (M, 2) lo, hi
-        self.near = near    # dict (t, s) -> block, t <= s
+        self.near = near    # dict (t, s) -> block, t <= s (all ordered pairs if not symmetric)
         self.far = far      # list of (tlo, thi, slo, shi, U, V)
+        self.symmetric = symmetric
 
     @property
     def M(self):
@@ -41,7 +48,7 @@ class HMatrix:
         for (t, s), B in self.near.items():
             st, ss = self.group_slice(t), self.group_slice(s)
             y[st] += B @ x[ss]
-            if t != s:
+            if t != s and self.symmetric:
                 y[ss] += B.T @ x[st]
         return y
 
@@ -50,7 +57,8 @@ class HMatrix:
         y = np.zeros_like(x, dtype=np.complex128)
         for tlo, thi, slo, shi, U, V in self.far:
             y[tlo:thi] += U @ (V.T @ x[slo:shi])
-            y[slo:shi] += V @ (U.T @ x[tlo:thi])
+            if self.symmetric:
+                y[slo:shi] += V @ (U.T @ x[tlo:thi])
         return y
 
     def matvec(self, x):
@@ -61,7 +69,8 @@ class HMatrix:
         for (t, s), B in self.near.items():
             st, ss = self.group_slice(t), self.group_slice(s)
             Z[st, ss] = B
-            Z[ss, st] = B.T
+            if self.symmetric:
+                Z[ss, st] = B.T
         return Z
 
     def dense_far(self):
@@ -69,7 +78,8 @@ class HMatrix:
         for tlo, thi, slo, shi, U, V in self.far:
             B = U @ V.T
             Z[tlo:thi, slo:shi] = B
-            Z[slo:shi, tlo:thi] = B.T
+            if self.symmetric:
+                Z[slo:shi, tlo:thi] = B.T
         return Z
 
     def to_tree(self, x_rwg):
@@ -82,7 +92,8 @@ class HMatrix:
 
     def far_entries(self):
         """sum over both triangles of r (m + n): the applied far entries."""
-        return sum(2 * U.shape[1] * (U.shape[0] + V.shape[0]) for _, _, _, _, U, V in self.far)
+        f = 2 if self.symmetric else 1
+        return sum(f * U.shape[1] * (U.shape[0] + V.shape[0]) for _, _, _, _, U, V in self.far)
 
 
 _JOB = {}
@@ -124,7 +135,8 @@ def _run(job, items, workers, chunk=64):
     return [r for c in res for r in c]
 
 
-def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0, open_surface=False):
+def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0, open_surface=False,
+                  formulation="efie", alpha=0.5):
     """Mesh -> RWG -> octree -> near blocks (quadrature) + far blocks (ACA).
 
     With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
@@ -133,10 +145,20 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     arithmetic of each block is unchanged).  ``box_min`` > 0 stops the octree
     at cells of at least that side (metres), whatever their unknown count.
     ``open_surface`` accepts boundary edges (an open PEC sheet such as the
-    square plate of Sec. V.C.2), which carry no unknown.
+    square plate of Sec. V.C.2), which carry no unknown.  ``formulation``
+    "cfie" builds the CFIE matrix of eq. (8) with the given ``alpha`` (closed
+    surfaces only); its H-matrix is not symmetric.
     """
     rwg = build_rwg(xyz, tri, allow_open=open_surface)
-    op = EFIEOperator(rwg, freq_hz)
+    if formulation == "efie":
+        op = EFIEOperator(rwg, freq_hz)
+    elif formulation == "cfie":
+        if open_surface:
+            raise ValueError("the CFIE needs a closed surface")
+        op = CFIEOperator(rwg, freq_hz, alpha)
+    else:
+        raise ValueError("formulation must be 'efie' or 'cfie'")
+    symmetric = formulation == "efie"
     tree = build_tree(edge_midpoints(rwg), leaf_max, box_min)
     perm = tree["perm"]
     leaves = tree["leaves"]
@@ -145,6 +167,10 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     if not eta_far:
         near_pairs = [(a, b) for a in leaves for b in leaves if a.leaf_id <= b.leaf_id]
         far_pairs = []
+    if not symmetric:
+        near_pairs = sorted(near_pairs + [(s, t) for t, s in near_pairs if t.leaf_id != s.leaf_id],
+                            key=lambda p: (p[0].leaf_id, p[1].leaf_id))
+        far_pairs = sorted(far_pairs + [(s, t) for t, s in far_pairs], key=lambda p: (p[0].id, p[1].id))
     _JOB.update(op=op, perm=perm, eps=aca_tol)
     try:
         nb = _run(_near_job, [(t.lo, t.hi, s.lo, s.hi) for t, s in near_pairs], workers)
@@ -153,7 +179,7 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
         _JOB.clear()
     near = {(t.leaf_id, s.leaf_id): B for (t, s), B in zip(near_pairs, nb)}
     far = [(t.lo, t.hi, s.lo, s.hi, U, V) for (t, s), (U, V) in zip(far_pairs, fb)]
-    H = HMatrix(rwg["N"], perm, groups, near, far)
+    H = HMatrix(rwg["N"], perm, groups, near, far, symmetric=symmetric)
     H.rwg, H.op, H.tree = rwg, op, tree
     H.near_pairs, H.far_pairs = near_pairs, far_pairs
     return H

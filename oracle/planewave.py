@@ -77,3 +77,30 @@ def monostatic_rcs(rwg, freq_hz, khat, pol, x):
 
 def dbsm(sigma):
     return 10.0 * np.log10(sigma)
+
+
+def excitation_cfie(rwg, freq_hz, khat, pol, alpha):
+    """CFIE right-hand side (eq. 8): alpha <f_m, E_inc> + eta0 (1 - alpha)
+    <f_m, n x H_inc> with eta0 H_inc = khat x E_inc and n the outward normal of
+    each triangle; b (N, R)."""
+    khat = np.atleast_2d(np.asarray(khat, dtype=np.float64))
+    pol = np.atleast_2d(np.asarray(pol, dtype=np.float64))
+    k = wavenumber(freq_hz)
+    xyz, tri = rwg["xyz"], rwg["tri"]
+    _, area, _ = triangle_geometry(xyz, tri)
+    tv = xyz[tri]
+    nrm = np.cross(tv[:, 1] - tv[:, 0], tv[:, 2] - tv[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    hdir = np.cross(khat, pol)                                  # eta0 H_inc / E_inc
+    out = np.zeros((rwg["N"], len(khat)), dtype=np.complex128)
+    for tkey, vkey, s in (("tplus", "vplus", 1.0), ("tminus", "vminus", -1.0)):
+        t = rwg[tkey]
+        pts = points(tv[t], RULE7)
+        rel = pts - xyz[rwg[vkey]][:, None, :]
+        coef = s * rwg["length"] / 2.0                          # (l / 2A) * A
+        phase = np.exp(-1j * k * np.einsum("nqd,rd->nqr", pts, khat))
+        nxh = np.cross(nrm[t][:, None, :], hdir[None, :, :])    # (N, R, 3)
+        vec = alpha * pol[None, :, :] + (1.0 - alpha) * nxh
+        fdot = np.einsum("nqd,nrd->nqr", rel, vec)
+        out += coef[:, None] * np.einsum("q,nqr->nr", RULE7[1], fdot * phase)
+    return out

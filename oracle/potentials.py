@@ -66,3 +66,53 @@ def triangle_potentials(r, tv):
         I1 += t0 * F - ad * beta
         Irho += 0.5 * u * (R0sq * F + lp * Rp - lm * Rm)[:, None]
     return I1, Irho, rho
+
+
+def triangle_gradient_potential(r, tv):
+    """int_T (r - r') / R^3 dS' (K, 3) for points r (K, 3) and triangles tv.
+
+    With rho, d and the per-edge quantities above, the in-plane part is the
+    surface divergence theorem applied to grad'_s (1/R) = (rho - r') / R^3,
+    sum_i u_i F_i, and the normal part is d int 1/R^3 dS' = sign(d) times the
+    solid-angle sum of the same arctangent terms (Graglia, IEEE TAP 1993):
+
+      int (r - r')/R^3 dS' = sum_i u_i F_i + n sign(d) sum_i beta_i,
+      beta_i = atan(t0 l+ / (R0^2 + |d| R+)) - atan(t0 l- / (R0^2 + |d| R-)).
+
+    This is the static part of the MFIE kernel (see ``mfie``).  Points on the
+    plane of T outside its closure get a zero normal part.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    v0, v1, v2 = tv[:, 0], tv[:, 1], tv[:, 2]
+    n = np.cross(v1 - v0, v2 - v0)
+    n = n / np.sqrt(_dot(n, n))[:, None]
+    d = _dot(r - v0, n)
+    rho = r - d[:, None] * n
+    ad = np.abs(d)
+    out = np.zeros((len(r), 3))
+    bsum = np.zeros(len(r))
+    verts = (v0, v1, v2)
+    for e in range(3):
+        pa, pb = verts[e], verts[(e + 1) % 3]
+        L = pb - pa
+        s = L / np.sqrt(_dot(L, L))[:, None]
+        u = np.cross(s, n)
+        lp = _dot(pb - rho, s)
+        lm = _dot(pa - rho, s)
+        t0 = _dot(pa - rho, u)
+        R0sq = t0 * t0 + d * d
+        Rp = np.sqrt(lp * lp + R0sq)
+        Rm = np.sqrt(lm * lm + R0sq)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            F = np.where(lp + lm >= 0.0,
+                         np.log((Rp + lp) / (Rm + lm)),
+                         np.log((Rm - lm) / (Rp - lp)))
+            F = np.where(R0sq > 0.0, F, 0.0)
+            den_p = R0sq + ad * Rp
+            den_m = R0sq + ad * Rm
+            beta = np.where(den_p > 0.0, np.arctan(t0 * lp / np.where(den_p > 0, den_p, 1.0)), 0.0) \
+                - np.where(den_m > 0.0, np.arctan(t0 * lm / np.where(den_m > 0, den_m, 1.0)), 0.0)
+        out += u * F[:, None]
+        bsum += beta
+    out += n * (np.sign(d) * bsum)[:, None]
+    return out

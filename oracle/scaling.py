@@ -9,7 +9,9 @@ pivot group i with current (already Schur-updated) near-field blocks Z~:
   (N+(i)); this module stores C_ij = Z~_ii^{-1} Z~_ij, so alpha_ij = -C_ij;
 * eq. (18): the left coefficient alpha'_i has blocks -Z~_ji Z~_ii^{-1};
   because Z_N = Z_N^T these are the transposes of the right ones (the
-  paper's reason to store only the right coefficients, end of Sec. III.A);
+  paper's reason to store only the right coefficients, end of Sec. III.A).
+  For a non-symmetric near field (the CFIE of eq. 8) they are kept as
+  L_ij = Z~_ji Z~_ii^{-1}, alpha'_ji = -L_ij;
 * eqs. (19)-(21): alpha'_i Z~ alpha_i zeroes row and column i and replaces
   every pair j, k in N+(i) by Z~_jk - Z~_ji Z~_ii^{-1} Z~_ik.  Pairs that were
   not coupled before become fill-in blocks (kept: "considering fill-in blocks
@@ -67,14 +69,20 @@ def min_degree_order(adj):
 
 
 class Scaling:
-    """Result of the Schur scaling: order, D_i = Z~_ii, D_i^{-1}, C_ij."""
+    """Result of the Schur scaling: order, D_i = Z~_ii, D_i^{-1}, C_ij (and
+    L_ij for a non-symmetric near field)."""
 
-    def __init__(self, order, D, Dinv, C, later):
+    def __init__(self, order, D, Dinv, C, later, L=None):
         self.order = order
         self.D = D            # g -> scaled diagonal block (eq. 23)
         self.Dinv = Dinv      # g -> its inverse
         self.C = C            # (i, j) -> Z~_ii^{-1} Z~_ij, alpha_ij = -C_ij
         self.later = later    # i -> N+(i) in elimination order
+        self.L = L            # (i, j) -> Z~_ji Z~_ii^{-1} (None: C_ij^T)
+
+    def left(self, i, j):
+        """L_ij = Z~_ji Z~_ii^{-1}, so that alpha'_ji = -L_ij (eq. 18)."""
+        return self.C[(i, j)].T if self.L is None else self.L[(i, j)]
 
     def coefficient_entries(self):
         return sum(B.size for B in self.C.values())
@@ -86,15 +94,17 @@ def schur_scaling(H, order, rcond_min=0.0):
     The working matrix keeps both triangles (Z~_ij and Z~_ji) so that eq. (21)
     is applied literally, Z~_jk -= Z~_ji (Z~_ii^{-1} Z~_ik), for all j, k in
     N+(i)."""
+    symmetric = getattr(H, "symmetric", True)
     W = {}
     for (t, s), B in H.near.items():
         W[(t, s)] = B.copy()
-        if t != s:
+        if t != s and symmetric:
             W[(s, t)] = B.T.copy()
     nbr = group_graph(H)
     pos = {g: p for p, g in enumerate(order)}
     done = set()
     D, Dinv, C, later = {}, {}, {}, {}
+    L = None if symmetric else {}
     for i in order:
         Zii = W[(i, i)]
         try:
@@ -107,6 +117,8 @@ def schur_scaling(H, order, rcond_min=0.0):
         D[i], Dinv[i], later[i] = Zii, inv, Ni
         for j in Ni:                                   # eq. (16)
             C[(i, j)] = inv @ W[(i, j)]
+            if L is not None:                          # eq. (18)
+                L[(i, j)] = W[(j, i)] @ inv
         for j in Ni:                                   # eq. (21), incl. fill-in
             Zji = W[(j, i)]
             for k in Ni:
@@ -121,4 +133,4 @@ def schur_scaling(H, order, rcond_min=0.0):
         for j in Ni:                                   # row/column i are now zero
             del W[(i, j)], W[(j, i)]
         del W[(i, i)]
-    return Scaling(list(order), D, Dinv, C, later)
+    return Scaling(list(order), D, Dinv, C, later, L)

@@ -4,7 +4,9 @@ With A = alpha_1 alpha_2 ... alpha_M (right coefficients in elimination
 order) the scaled system is A^T (Z_N + Z_F) A x~ = b~ (eqs. 24, 27-29):
 
 * eq. (25): b~ = alpha_M^T ... alpha_1^T b -- alpha_1^T is applied first; for
-  pivot i it changes only the later groups: b_j <- b_j - C_ij^T b_i;
+  pivot i it changes only the later groups: b_j <- b_j - C_ij^T b_i.  For a
+  non-symmetric near field the left coefficients of eq. (24) are used,
+  b_j <- b_j - L_ij b_i (alpha'_ji = -L_ij, eq. 18);
 * eq. (32): b_o = Z~_N^{-1} b~ (block-diagonal D^{-1});
 * eq. (31): U v = Z~_N^{-1} A^T Z_F A v;
 * eqs. (35)-(36): x~ = b_o - U b_o + U^2 b_o - ..., truncated after ``terms``
@@ -35,7 +37,7 @@ class PowerSeries:
         for i in self.S.order:
             vi = v[self._sl(i)]
             for j in self.S.later[i]:
-                v[self._sl(j)] -= self.S.C[(i, j)].T @ vi
+                v[self._sl(j)] -= self.S.left(i, j) @ vi
         return v
 
     def alpha(self, xt):
