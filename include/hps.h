@@ -96,10 +96,18 @@ typedef struct {
                               near blocks and the ACA samples of the far blocks on it
                               (the host recompresses them); 1: the whole build on
                               host threads */
+  int32_t formulation;     /* 0 (default): EFIE (eqs. 2-3), symmetric matrix, right
+                              coefficients only.  1: CFIE of eq. (8),
+                              cfie_alpha EFIE + eta0 (1 - cfie_alpha) MFIE (eqs. 4-7),
+                              closed surfaces only; the matrix is not symmetric, so
+                              the setup also keeps the left coefficients of eq. (18)
+                              (twice the factor memory) */
+  double cfie_alpha;       /* alpha of eq. (8) in [0, 1] (paper: 0.5 for closed bodies) */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
-   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0, host_near 0.
+   refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0, host_near 0,
+   formulation 0 (EFIE), cfie_alpha 0.5.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 
@@ -157,6 +165,10 @@ hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
                       block b stores U (m x r, column-major) then V (n x r,
                       column-major), m = thi - tlo, n = shi - slo, with
                       Z[t, s] ~= U V^T and Z[s, t] ~= V U^T.
+   With p->formulation = 1 (CFIE, not symmetric) near_ts lists every ordered
+   pair (t, s) of touching groups, t > s included, each block holding
+   Z[t, s] only, and every far block b holds Z[t, s] ~= U V^T only (the
+   (s, t) block is a separate entry).
    p supplies freq_hz (for excitation / RCS) and the solve options.  Groups of
    more than 128 unknowns are cut into consecutive sub-groups (near blocks cut
    to match), as after hps_build_hmatrix. */
@@ -201,13 +213,16 @@ hps_status hps_solve_planewaves(hps_ctx *ctx, int64_t R, const double *khat, con
    RWG order (may not alias); ratio as above (host, nullable). */
 hps_status hps_solve_rhs(hps_ctx *ctx, int64_t R, const void *B, void *X, double *ratio);
 
-/* Plane-wave excitation only: B (N x R c128, DEVICE, RWG order) = <f_m, E_inc>. */
+/* Plane-wave excitation only: B (N x R c128, DEVICE, RWG order) = <f_m, E_inc>
+   (EFIE), or the CFIE right-hand side alpha <f_m, E_inc> + eta0 (1 - alpha)
+   <f_m, n x H_inc> of eq. (8). */
 hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const double *pol,
                           void *B);
 
-/* Y = H X on the device (near blocks + both directions of every far block),
-   X and Y N x R c128 DEVICE pointers in RWG order.  Valid after the H-matrix
-   is installed (before or after setup). */
+/* Y = H X on the device (near blocks + both directions of every far block;
+   for the CFIE every stored block in its own direction),
+   X and Y N x R c128 DEVICE pointers in RWG order.  Valid after hps_setup
+   (its product schedules are built there); HPS_ESTATE before. */
 hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
 /* Per-launch kernel timing: with enable != 0 every grouped-GEMM and inverse

@@ -224,7 +224,7 @@ static void recompress(int64_t m, int64_t n, int64_t k, std::vector<cplx> &U, st
   rank = (int)r;
 }
 
-void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
+void aca_block(const Galerkin &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
                double eps, std::vector<cplx> &U, std::vector<cplx> &V, int &rank) {
   const double limit = (double)(m * n) / (double)(m + n);
   std::vector<cplx> Uc, Vc;     // column-major growing factors
@@ -342,11 +342,20 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
   build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
   block_partition(T, near, far);
-  EFIE op(mesh, p.freq_hz);
+  if (p.formulation == 1) {            // CFIE: not symmetric, both orders of every block
+    const size_t nn0 = near.size(), nf0 = far.size();
+    for (size_t b = 0; b < nn0; ++b)
+      if (near[b].first != near[b].second) near.emplace_back(near[b].second, near[b].first);
+    for (size_t b = 0; b < nf0; ++b) far.emplace_back(far[b].second, far[b].first);
+    std::sort(near.begin(), near.end());
+    std::sort(far.begin(), far.end());
+  }
+  Galerkin op(mesh, p.freq_hz, p.formulation == 1, p.cfie_alpha);
   int threads = p.host_threads > 0 ? p.host_threads : (int)std::thread::hardware_concurrency();
   if (threads < 1) threads = 1;
 
   H.N = mesh.N;
+  H.nonsym = p.formulation == 1;
   H.M = (int64_t)T.leaf_node.size();
   H.perm = T.perm;
   H.gptr.resize(H.M + 1);

@@ -76,6 +76,14 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
     return fail(c, HPS_EINVAL, "leaf_box_min must be >= 0");
   if (!(p->series_tol >= 0.0) || !std::isfinite(p->series_tol))
     return fail(c, HPS_EINVAL, "series_tol must be >= 0");
+  if (p->formulation != 0 && p->formulation != 1) return fail(c, HPS_EINVAL, "formulation must be 0 or 1");
+  if (p->formulation == 1 && !(p->cfie_alpha >= 0.0 && p->cfie_alpha <= 1.0))
+    return fail(c, HPS_EINVAL, "cfie_alpha must be in [0, 1]");
+  if (p->formulation == 1 && c && c->have_mesh) {
+    bool open = c->mesh.open;
+    for (size_t q = 0; q < c->pmesh.size(); ++q) open = open || (c->pmesh_ok[q] && c->pmesh[q].open);
+    if (open) return fail(c, HPS_EINVAL, "the CFIE needs a closed surface (the MFIE part holds on closed surfaces only)");
+  }
   return HPS_OK;
 }
 
@@ -96,7 +104,7 @@ void merge_batch(hps_ctx *c) {
 hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64_t *group_ptr, int64_t n_near,
                                  const int32_t *near_ts, const int64_t *near_off, const double *near_vals,
                                  int64_t n_far, const int64_t *far_rng, const int32_t *far_rank,
-                                 const int64_t *far_off, const double *far_uv) {
+                                 const int64_t *far_off, const double *far_uv, bool nonsym) {
   if (!perm || !group_ptr || M <= 0 || n_near <= 0 || !near_ts || !near_off || !near_vals)
     throw hps::Error{HPS_EINVAL, "missing near-field arrays"};
   if (n_far < 0 || (n_far > 0 && (!far_rng || !far_rank || !far_off || !far_uv)))
@@ -104,6 +112,7 @@ hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64
   hps::HMatrix H;
   H.N = N;
   H.M = M;
+  H.nonsym = nonsym;
   H.perm.assign(perm, perm + N);
   std::vector<char> seen(N, 0);
   for (int64_t i = 0; i < N; ++i) {
@@ -122,7 +131,7 @@ hps::HMatrix read_hmatrix(int64_t N, const int64_t *perm, int64_t M, const int64
   std::vector<char> diag(M, 0);
   for (int64_t b = 0; b < n_near; ++b) {
     const int64_t t = near_ts[2 * b], s = near_ts[2 * b + 1];
-    if (t < 0 || s < 0 || t >= M || s >= M || t > s) throw hps::Error{HPS_EINVAL, "bad near pair"};
+    if (t < 0 || s < 0 || t >= M || s >= M || (t > s && !nonsym)) throw hps::Error{HPS_EINVAL, "bad near pair"};
     if (near_off[b + 1] - near_off[b] != (H.gptr[t + 1] - H.gptr[t]) * (H.gptr[s + 1] - H.gptr[s]))
       throw hps::Error{HPS_EINVAL, "near_off does not match the block sizes"};
     if (t == s) diag[t] = 1;
@@ -178,6 +187,8 @@ hps_status hps_params_default(hps_params *p) {
   p->leaf_box_min = 0.0;
   p->series_tol = 0.0;
   p->host_near = 0;
+  p->formulation = 0;
+  p->cfie_alpha = 0.5;
   return HPS_OK;
 }
 
@@ -337,7 +348,7 @@ hps_status hps_batch_set_hmatrix(hps_ctx *c, int32_t p, const hps_params *prm, i
       return fail(c, HPS_EINVAL, "every problem of a batch takes the same parameters");
   return guarded(c, [&]() {
     hps::HMatrix H = read_hmatrix(N, perm, M, group_ptr, n_near, near_ts, near_off, near_vals, n_far, far_rng,
-                                  far_rank, far_off, far_uv);
+                                  far_rank, far_off, far_uv, prm->formulation == 1);
     c->have_h = false;
     c->have_setup = false;
     c->pH[p] = std::move(H);
@@ -367,9 +378,9 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
       for (int32_t q = 0; q < c->n_prob; ++q) {
         hps::HMatrix H;
         const hps::Mesh &mq = c->pmesh[q];
-        const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(mq, p->freq_hz, h); };
+        const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(mq, p->freq_hz, p->formulation, p->cfie_alpha, h); };
         const hps::FarSample sample = [&](const hps::HMatrix &h, const hps::FarEmit &emit) {
-          c->dev->far_sample(mq, p->freq_hz, h, p->aca_tol, emit);
+          c->dev->far_sample(mq, p->freq_hz, p->formulation, p->cfie_alpha, h, p->aca_tol, emit);
         };
         const bool dev = c->dev && !p->host_near;
         hps::build_hmatrix(mq, *p, H, dev ? &fill : nullptr, dev ? &sample : nullptr);
@@ -380,9 +391,9 @@ hps_status hps_build_hmatrix(hps_ctx *c, const hps_params *p) {
       merge_batch(c);
     } else {
       hps::HMatrix H;
-      const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(c->mesh, p->freq_hz, h); };
+      const hps::NearFill fill = [&](hps::HMatrix &h) { c->dev->near_fill(c->mesh, p->freq_hz, p->formulation, p->cfie_alpha, h); };
       const hps::FarSample sample = [&](const hps::HMatrix &h, const hps::FarEmit &emit) {
-        c->dev->far_sample(c->mesh, p->freq_hz, h, p->aca_tol, emit);
+        c->dev->far_sample(c->mesh, p->freq_hz, p->formulation, p->cfie_alpha, h, p->aca_tol, emit);
       };
       const bool dev = c->dev && !p->host_near;
       hps::build_hmatrix(c->mesh, *p, H, dev ? &fill : nullptr, dev ? &sample : nullptr);
@@ -411,7 +422,7 @@ hps_status hps_set_hmatrix(hps_ctx *c, const hps_params *p, int64_t N, const int
   if (N != c->mesh.N) return fail(c, HPS_EINVAL, "N does not match the mesh");
   return guarded(c, [&]() {
     hps::HMatrix H = read_hmatrix(N, perm, M, group_ptr, n_near, near_ts, near_off, near_vals, n_far, far_rng,
-                                  far_rank, far_off, far_uv);
+                                  far_rank, far_off, far_uv, p->formulation == 1);
     c->have_h = false;
     c->have_setup = false;
     c->H = std::move(H);

@@ -43,6 +43,7 @@ void merge_problems(const std::vector<Mesh> &meshes, const std::vector<HMatrix> 
   h.far_uv.reserve(fe);
   h.gptr.push_back(0);
   h.near_off.push_back(0);
+  h.nonsym = !Hs.empty() && Hs[0].nonsym;
   h.far_off.push_back(0);
   int32_t voff = 0, toff = 0;
   for (size_t p = 0; p < P; ++p) {
@@ -53,6 +54,8 @@ void merge_problems(const std::vector<Mesh> &meshes, const std::vector<HMatrix> 
     for (int32_t v : a.tri) m.tri.push_back(v + voff);
     m.cen.insert(m.cen.end(), a.cen.begin(), a.cen.end());
     m.area.insert(m.area.end(), a.area.begin(), a.area.end());
+    m.nrm.insert(m.nrm.end(), a.nrm.begin(), a.nrm.end());
+    m.open = m.open || a.open;
     m.hmax = std::max(m.hmax, a.hmax);
     for (int32_t v : a.edge) m.edge.push_back(v + voff);
     for (int64_t n = 0; n < a.N; ++n) {
@@ -87,7 +90,8 @@ namespace hps {
 // a larger group is cut into consecutive sub-groups of near-equal size, which
 // the setup eliminates one after the other like any other groups.  The near
 // blocks are cut along the same lines (upper triangle of the group pattern
-// kept); far blocks refer to tree-position ranges and are unchanged.
+// kept, or every sub-block of a non-symmetric H-matrix); far blocks refer to
+// tree-position ranges and are unchanged.
 void split_groups(HMatrix &H, int64_t max_size) {
   const int64_t M = H.M;
   bool any = false;
@@ -114,7 +118,7 @@ void split_groups(HMatrix &H, int64_t max_size) {
     const int64_t ns = H.gptr[s + 1] - H.gptr[s];
     const cplx *blk = H.near_vals.data() + H.near_off[b];
     for (int64_t ta = ng0[t]; ta < ng0[t + 1]; ++ta)
-      for (int64_t sb = (t == s ? ta : ng0[s]); sb < ng0[s + 1]; ++sb) {
+      for (int64_t sb = (t == s && !H.nonsym ? ta : ng0[s]); sb < ng0[s + 1]; ++sb) {
         const int64_t r0 = gptr[ta] - H.gptr[t], r1 = gptr[ta + 1] - H.gptr[t];
         const int64_t c0 = gptr[sb] - H.gptr[s], c1 = gptr[sb + 1] - H.gptr[s];
         for (int64_t r = r0; r < r1; ++r)

@@ -66,10 +66,12 @@ class DeviceState {
   std::string stats_json() const;
   // EFIE entries of the near blocks of H (structure set, values sized) on the
   // device, copied into H.near_vals; synchronous.
-  void near_fill(const Mesh &m, double freq_hz, HMatrix &H);
+  // cfie / alpha select the entries (EFIE, or the CFIE of eq. 8)
+  void near_fill(const Mesh &m, double freq_hz, int cfie, double alpha, HMatrix &H);
   // Raw ACA factors of every far block of H (far_rng set), chunk by chunk
   // to emit, see FarChunk.
-  void far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, const FarEmit &emit);
+  void far_sample(const Mesh &m, double freq_hz, int cfie, double alpha, const HMatrix &H, double eps,
+                  const FarEmit &emit);
   void set_profiling(bool on);
 
   int device;

@@ -626,24 +626,74 @@ __global__ void k_scatter(const c2 *__restrict__ near, c2 *__restrict__ W, const
 
 // b[q, r] = sum over the 14 quadrature points of T+ and T- of
 //           c (r_pt - v).pol exp(-j k khat.r_pt)
+// Quadrature data per unknown, side and point (10 doubles): r (3), r - v (3),
+// the weight (l / 2A) A w with the side's sign, and (r - v) x n (3).
+constexpr int kQD = 10;
+
+// b_m = sum over the 14 points of weight exp(-jk khat.r) [alpha (r - v).pol
+//      + (1 - alpha) ((r - v) x n).(khat x pol)]: the EFIE excitation
+// <f_m, E_inc> (alpha = 1) or the CFIE one of eq. (8), eta0 H_inc = khat x E_inc.
 __global__ void k_rhs(const double *__restrict__ qd, const int64_t *__restrict__ dperm, int64_t N,
-                      int64_t R, const double *__restrict__ kp, double k, c2 *__restrict__ B) {
+                      int64_t R, const double *__restrict__ kp, double k, double alpha, c2 *__restrict__ B) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N * R) return;
   const int64_t q = idx % N, r = idx / N;
   const int64_t m = dperm[q];
   const double *w = kp + 6 * r;
+  const double h[3] = {w[1] * w[5] - w[2] * w[4], w[2] * w[3] - w[0] * w[5], w[0] * w[4] - w[1] * w[3]};
   double re = 0.0, im = 0.0;
   for (int pt = 0; pt < 14; ++pt) {
-    const double *d = qd + (m * 14 + pt) * 7;
+    const double *d = qd + (m * 14 + pt) * kQD;
     const double ph = -k * (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]);
-    const double f = d[6] * (d[3] * w[3] + d[4] * w[4] + d[5] * w[5]);
+    double g = d[3] * w[3] + d[4] * w[4] + d[5] * w[5];
+    if (alpha != 1.0) g = alpha * g + (1.0 - alpha) * (d[7] * h[0] + d[8] * h[1] + d[9] * h[2]);
+    const double f = d[6] * g;
     double sn, cs;
     sincos(ph, &sn, &cs);
     re = fma(f, cs, re);
     im = fma(f, sn, im);
   }
   B[idx] = make_double2(re, im);
+}
+
+// Monostatic RCS from the currents when the right-hand side is not the EFIE
+// excitation (CFIE): amp = sum_q x_q <f_q, pol exp(-jk khat.r)>, block
+// (r, p) -> out[p R + r] = coef |amp|^2 over the unknowns of problem p.
+__global__ __launch_bounds__(256) void k_rcs_proj(const double *__restrict__ qd, const int64_t *__restrict__ dperm,
+                                                  const c2 *__restrict__ X, int64_t N, const int64_t *__restrict__ soff,
+                                                  const double *__restrict__ kp, double k, double coef,
+                                                  double *__restrict__ out) {
+  const int64_t r = blockIdx.x, R = gridDim.x, p = blockIdx.y;
+  const double *w = kp + 6 * r;
+  __shared__ double sx[256], sy[256];
+  double ax = 0.0, ay = 0.0;
+  for (int64_t i = soff[p] + threadIdx.x; i < soff[p + 1]; i += 256) {
+    const int64_t m = dperm[i];
+    double re = 0.0, im = 0.0;
+    for (int pt = 0; pt < 14; ++pt) {
+      const double *d = qd + (m * 14 + pt) * kQD;
+      const double ph = -k * (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]);
+      const double f = d[6] * (d[3] * w[3] + d[4] * w[4] + d[5] * w[5]);
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      re = fma(f, cs, re);
+      im = fma(f, sn, im);
+    }
+    const c2 x = X[r * N + i];
+    ax += re * x.x - im * x.y;
+    ay += re * x.y + im * x.x;
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sx[threadIdx.x] += sx[threadIdx.x + st];
+      sy[threadIdx.x] += sy[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p * R + r] = coef * (sx[0] * sx[0] + sy[0] * sy[0]);
 }
 
 // Per-column, per-problem reductions, block (r, p) -> out[p R + r]:
@@ -737,6 +787,9 @@ struct NearMesh {
   const double *xyz, *cen, *area, *len;
   const int32_t *tri, *tp, *tm, *vp, *vm;
   double k, h, cA, cPhi;          // cA = w mu / 4 and cPhi = -1 / (w eps) times j
+  const double *nrm;              // unit triangle normals (CFIE)
+  int cfie;                       // 0: EFIE entries; 1: alpha EFIE + eta0 (1 - alpha) MFIE
+  double alpha, eta0;
 };
 
 __device__ __forceinline__ double ddot3(const double *a, const double *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
@@ -920,7 +973,162 @@ __device__ c2 efie_entry(const NearMesh &M, int64_t m_, int64_t n_) {
   return make_double2(zr, zi);
 }
 
+// int_T (r - r') / R^3 dS' for observation point r: sum_i u_i F_i (the
+// divergence theorem on grad'_s (1/R)) plus n sign(d) sum_i beta_i (the
+// arctangent terms of tri_potentials).
+__device__ void tri_grad_potential(const NearMesh &M, int32_t t, const double *r, double out[3]) {
+  const double *V[3] = {M.xyz + 3 * M.tri[3 * t], M.xyz + 3 * M.tri[3 * t + 1], M.xyz + 3 * M.tri[3 * t + 2]};
+  double e1[3], e2[3], n[3];
+  for (int d = 0; d < 3; ++d) { e1[d] = V[1][d] - V[0][d]; e2[d] = V[2][d] - V[0][d]; }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nn = sqrt(ddot3(n, n));
+  for (int d = 0; d < 3; ++d) n[d] /= nn;
+  double rv[3], rho[3];
+  for (int d = 0; d < 3; ++d) rv[d] = r[d] - V[0][d];
+  const double h = ddot3(rv, n), ah = fabs(h);
+  for (int d = 0; d < 3; ++d) rho[d] = r[d] - h * n[d];
+  out[0] = out[1] = out[2] = 0.0;
+  double bsum = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double *pa = V[e], *pb = V[(e + 1) % 3];
+    double sv[3], u[3], da[3], db[3];
+    for (int d = 0; d < 3; ++d) sv[d] = pb[d] - pa[d];
+    const double ls = sqrt(ddot3(sv, sv));
+    for (int d = 0; d < 3; ++d) sv[d] /= ls;
+    u[0] = sv[1] * n[2] - sv[2] * n[1];
+    u[1] = sv[2] * n[0] - sv[0] * n[2];
+    u[2] = sv[0] * n[1] - sv[1] * n[0];
+    for (int d = 0; d < 3; ++d) { da[d] = pa[d] - rho[d]; db[d] = pb[d] - rho[d]; }
+    const double lp = ddot3(db, sv), lm = ddot3(da, sv), t0 = ddot3(da, u);
+    const double R0sq = t0 * t0 + h * h;
+    const double Rp = sqrt(lp * lp + R0sq), Rm = sqrt(lm * lm + R0sq);
+    double F = 0.0;
+    if (R0sq > 0.0) F = (lp + lm >= 0.0) ? log((Rp + lp) / (Rm + lm)) : log((Rm - lm) / (Rp - lp));
+    double beta = 0.0;
+    const double dp = R0sq + ah * Rp, dm = R0sq + ah * Rm;
+    if (dp > 0.0) beta += atan(t0 * lp / dp);
+    if (dm > 0.0) beta -= atan(t0 * lm / dm);
+    for (int d = 0; d < 3; ++d) out[d] += u[d] * F;
+    bsum += beta;
+  }
+  const double sg = (h > 0.0) ? 1.0 : (h < 0.0 ? -1.0 : 0.0);
+  for (int d = 0; d < 3; ++d) out[d] += n[d] * sg * bsum;
+}
+
+// MFIE pair term int_P (r - vP) . [n_P x ((r - vQ) x W_Q(r))] dS, P != Q,
+// W_Q(r) = int_Q (r - r') (1 + jkR) exp(-jkR) / (4 pi R^3) dS', written as
+// (a.b)(n.W) - (a.W)(n.b).  Same rules as pair_integral_dev: touching or
+// < 2h: 7-point outer, closed-form static part + 7 points on the remainder;
+// < 4h: 7 x 7; else 3 x 3.
+__device__ c2 mfie_pair_dev(const NearMesh &M, int32_t P, const double *vP, int32_t Q, const double *vQ) {
+  const int32_t *tp = M.tri + 3 * P, *tq = M.tri + 3 * Q;
+  bool share = false;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) share |= (tp[a] == tq[b]);
+  double dc[3];
+  for (int d = 0; d < 3; ++d) dc[d] = M.cen[3 * P + d] - M.cen[3 * Q + d];
+  const double d2 = ddot3(dc, dc);
+  const int rule = (share || d2 < (2.0 * M.h) * (2.0 * M.h)) ? 0 : (d2 < (4.0 * M.h) * (4.0 * M.h) ? 1 : 2);
+  const int nq = rule == 2 ? 3 : 7;
+  double po[7][3], pi[7][3];
+  if (nq == 7) {
+    quad_points<7>(M, P, po);
+    quad_points<7>(M, Q, pi);
+  } else {
+    quad_points<3>(M, P, po);
+    quad_points<3>(M, Q, pi);
+  }
+  const double *nP = M.nrm + 3 * P;
+  const double AQ = M.area[Q], inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+  double acc_re = 0.0, acc_im = 0.0;
+  for (int a = 0; a < nq; ++a) {
+    double W_re[3] = {0.0, 0.0, 0.0}, W_im[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nq; ++b) {
+      double dd[3];
+      for (int d = 0; d < 3; ++d) dd[d] = po[a][d] - pi[b][d];
+      const double R = sqrt(ddot3(dd, dd));
+      const double x = M.k * R;
+      double sx, cx;
+      sincos(x, &sx, &cx);
+      const double den = inv4pi / (R * R * R);
+      // (1 + jx) e^{-jx} - 1, plus 1 for the full kernel
+      const double nre = (cx - 1.0 + x * sx) + (rule == 0 ? 0.0 : 1.0), nim = x * cx - sx;
+      const double f = quad_w(nq, b) * AQ * den;
+      for (int d = 0; d < 3; ++d) {
+        W_re[d] += f * nre * dd[d];
+        W_im[d] += f * nim * dd[d];
+      }
+    }
+    if (rule == 0) {
+      double V[3];
+      tri_grad_potential(M, Q, po[a], V);
+      for (int d = 0; d < 3; ++d) W_re[d] += V[d] * inv4pi;
+    }
+    double am[3], bn[3];
+    for (int d = 0; d < 3; ++d) { am[d] = po[a][d] - vP[d]; bn[d] = po[a][d] - vQ[d]; }
+    const double ab = ddot3(am, bn), nb = ddot3(nP, bn);
+    const double nW_re = ddot3(nP, W_re), nW_im = ddot3(nP, W_im);
+    const double aW_re = ddot3(am, W_re), aW_im = ddot3(am, W_im);
+    const double w = quad_w(nq, a);
+    acc_re += w * (ab * nW_re - aW_re * nb);
+    acc_im += w * (ab * nW_im - aW_im * nb);
+  }
+  return make_double2(M.area[P] * acc_re, M.area[P] * acc_im);
+}
+
+// MFIE entry (eqs. 6-7): 1/2 <f_m, f_n> - <f_m, n x int f_n x grad' G>, over
+// the triangle pairs (+,+), (+,-), (-,+), (-,-) of (m, n).
+__device__ __noinline__ c2 mfie_entry(const NearMesh &M, int64_t m_, int64_t n_) {
+  const int32_t tm_[2] = {M.tp[m_], M.tm[m_]}, tn_[2] = {M.tp[n_], M.tm[n_]};
+  const int32_t vm_[2] = {M.vp[m_], M.vm[m_]}, vn_[2] = {M.vp[n_], M.vm[n_]};
+  double zr = 0.0, zi = 0.0;
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) {
+      const int32_t P = tm_[p], Q = tn_[q];
+      const double *vP = M.xyz + 3 * vm_[p], *vQ = M.xyz + 3 * vn_[q];
+      const double c = ((p == q) ? 1.0 : -1.0) * M.len[m_] * M.len[n_] / (4.0 * M.area[P] * M.area[Q]);
+      double vr, vi;
+      if (P == Q) {
+        double pts[7][3];
+        quad_points<7>(M, P, pts);
+        double acc = 0.0;
+        for (int a = 0; a < 7; ++a) {
+          double am[3], bn[3];
+          for (int d = 0; d < 3; ++d) { am[d] = pts[a][d] - vP[d]; bn[d] = pts[a][d] - vQ[d]; }
+          acc += quad_w(7, a) * ddot3(am, bn);
+        }
+        vr = 0.5 * M.area[P] * acc;
+        vi = 0.0;
+      } else {
+        const c2 t = mfie_pair_dev(M, P, vP, Q, vQ);
+        vr = -t.x;
+        vi = -t.y;
+      }
+      zr += c * vr;
+      zi += c * vi;
+    }
+  return make_double2(zr, zi);
+}
+
+// Galerkin entry Z_mn: the EFIE, or (CFIE) the combination of eq. (8).
+template <bool CFIE>
+__device__ c2 galerkin_entry(const NearMesh &M, int64_t m_, int64_t n_) {
+  const c2 e = efie_entry(M, m_, n_);
+  if (!CFIE) return e;
+  c2 z = make_double2(M.alpha * e.x, M.alpha * e.y);
+  if (M.alpha != 1.0) {
+    const c2 h = mfie_entry(M, m_, n_);
+    const double f = M.eta0 * (1.0 - M.alpha);
+    z.x += f * h.x;
+    z.y += f * h.y;
+  }
+  return z;
+}
+
 // One workgroup per near block (row-major m x n, rows of group t, columns of s).
+template <bool CFIE>
 __global__ __launch_bounds__(256) void k_near(NearMesh M, const int64_t *__restrict__ perm,
                                               const int64_t *__restrict__ gptr, const int32_t *__restrict__ ts,
                                               const int64_t *__restrict__ off, c2 *__restrict__ out) {
@@ -929,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_near(NearMesh M, const int64_t *__restr
   const int64_t m = gptr[t + 1] - gptr[t], n = gptr[s + 1] - gptr[s];
   for (int64_t i = threadIdx.x; i < m * n; i += blockDim.x) {
     const int64_t r = i / n, c = i % n;
-    out[off[b] + i] = efie_entry(M, perm[gptr[t] + r], perm[gptr[s] + c]);
+    out[off[b] + i] = galerkin_entry<CFIE>(M, perm[gptr[t] + r], perm[gptr[s] + c]);
   }
 }
 
@@ -986,6 +1194,7 @@ __device__ c2 block_csum(c2 a, double *sx, double *sy) {
   return r;
 }
 
+template <bool CFIE>
 __global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restrict__ perm,
                                              const AcaBlock *__restrict__ blocks, double eps, c2 *__restrict__ scratch,
                                              int32_t *__restrict__ rank_out) {
@@ -1012,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restri
     if ((double)(k + 1) >= limit || k >= kAcaCap) { result = -1; break; }
     // residual row i into V[:, k]
     for (int64_t j = tid; j < n; j += nt) {
-      c2 z = efie_entry(M, rows[i], cols[j]);
+      c2 z = galerkin_entry<CFIE>(M, rows[i], cols[j]);
       for (int l = 0; l < k; ++l) {
         const c2 u = U[l * m + i], v = V[l * n + j];
         z.x -= u.x * v.x - u.y * v.y;
@@ -1043,7 +1252,7 @@ __global__ __launch_bounds__(256) void k_aca(NearMesh M, const int64_t *__restri
     const c2 pinv = make_double2(piv.x / pd, -piv.y / pd);
     // residual column jp into U[:, k]
     for (int64_t a = tid; a < m; a += nt) {
-      c2 z = efie_entry(M, rows[a], cols[jp]);
+      c2 z = galerkin_entry<CFIE>(M, rows[a], cols[jp]);
       for (int l = 0; l < k; ++l) {
         const c2 v = V[l * n + jp], u = U[l * m + a];
         z.x -= v.x * u.x - v.y * u.y;
@@ -1232,7 +1441,9 @@ struct DeviceState::Impl {
   uint64_t mem_cap = 0;
   // H-matrix on device
   DevArray<c2> near, faruv;
-  DevArray<double> quad;           // N x 14 x 7 (RWG order)
+  DevArray<double> quad;           // N x 14 x kQD (RWG order)
+  bool nonsym = false;             // CFIE: left coefficients kept, far blocks one way
+  double alpha = 1.0;              // CFIE alpha (1: EFIE right-hand side)
   HMatrix hcopy;                   // structure (values not needed after upload)
   std::vector<int64_t> far_m, far_n;
   // plan
@@ -1603,11 +1814,16 @@ struct DeviceState::Impl {
   // RCS of every problem and RHS into red[2 RP, 3 RP).
   void core_pw(int64_t R) {
     const int64_t NR = N * R, RP = R * nseg;
-    hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, s, quad.p, dperm.p, N, R, dkp.p, k, vB.p);
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, s, quad.p, dperm.p, N, R, dkp.p, k, alpha,
+                       vB.p);
     HIP_CHECK(hipGetLastError());
     solve_any(R);
-    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, vB.p, vY.p, N, dsoff.p,
-                       coef_rcs, 1, red.p + 2 * RP);
+    if (alpha == 1.0)          // the right-hand side is the EFIE excitation: sigma from b^T x
+      hipLaunchKernelGGL(k_colreduce, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, vB.p, vY.p, N, dsoff.p,
+                         coef_rcs, 1, red.p + 2 * RP);
+    else
+      hipLaunchKernelGGL(k_rcs_proj, dim3((unsigned)R, (unsigned)nseg), dim3(256), 0, s, quad.p, dperm.p, vY.p, N,
+                         dsoff.p, dkp.p, k, coef_rcs, red.p + 2 * RP);
     HIP_CHECK(hipGetLastError());
   }
   void core_rhs(int64_t R) { solve_any(R); }
@@ -1766,7 +1982,7 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   I.use_graphs = p.graphs != 0;
   graphs = p.graphs;
   I.drop_graphs();
-  const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * 7 * 8;
+  const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * kQD * 8;
   if (I.mem_cap && need > I.mem_cap) throw Error{HPS_ENOMEM, "H-matrix exceeds device_mem_cap"};
   // complex<double> and double2 share their layout: copy straight from the host arrays
   I.near.alloc(H.near_vals.size());
@@ -1778,11 +1994,14 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   HIP_CHECK(hipStreamSynchronize(I.s));
   // structure copy without values
   I.hcopy = HMatrix();
-  I.hcopy.N = H.N; I.hcopy.M = H.M; I.hcopy.perm = H.perm; I.hcopy.gptr = H.gptr;
+  I.hcopy.N = H.N; I.hcopy.M = H.M; I.hcopy.perm = H.perm; I.hcopy.gptr = H.gptr; I.hcopy.nonsym = H.nonsym;
   I.hcopy.near_ts = H.near_ts; I.hcopy.near_off = H.near_off;
   I.hcopy.far_rng = H.far_rng; I.hcopy.far_rank = H.far_rank; I.hcopy.far_off = H.far_off;
   // quadrature data of the RWG functions for the excitation (7-point rule)
-  std::vector<double> qd((size_t)H.N * 14 * 7);
+  I.nonsym = H.nonsym;
+  I.alpha = p.formulation == 1 ? p.cfie_alpha : 1.0;
+  if (H.nonsym && mesh.nrm.size() != 3 * (size_t)mesh.nt) throw Error{HPS_EINVAL, "internal: mesh normals missing"};
+  std::vector<double> qd((size_t)H.N * 14 * kQD);
   {
     const double s15 = std::sqrt(15.0);
     const double a1 = (6.0 - s15) / 21.0, w1 = (155.0 - s15) / 1200.0;
@@ -1800,12 +2019,16 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
                      *P2 = &mesh.xyz[3 * mesh.tri[3 * t + 2]];
         const double *V = &mesh.xyz[3 * v];
         for (int q = 0; q < 7; ++q) {
-          double *d = &qd[((size_t)m * 14 + side * 7 + q) * 7];
+          double *d = &qd[((size_t)m * 14 + side * 7 + q) * kQD];
           for (int c = 0; c < 3; ++c) {
             d[c] = Bc[q][0] * P0[c] + Bc[q][1] * P1[c] + Bc[q][2] * P2[c];
             d[3 + c] = d[c] - V[c];
           }
           d[6] = sg * mesh.len[m] / 2.0 * Wq[q];   // (l / 2A) * A * w
+          const double *n = mesh.nrm.empty() ? nullptr : &mesh.nrm[3 * t];
+          d[7] = n ? d[4] * n[2] - d[5] * n[1] : 0.0;     // (r - v) x n
+          d[8] = n ? d[5] * n[0] - d[3] * n[2] : 0.0;
+          d[9] = n ? d[3] * n[1] - d[4] * n[0] : 0.0;
         }
       }
   }
@@ -1822,7 +2045,13 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   I.ready = false;
   I.built_R = -1;
   const int64_t N = I.N, M = I.M;
-  const uint64_t need = 2ull * (uint64_t)P.panel_elems * sizeof(c2);
+  // working and factor panels; a non-symmetric near field (CFIE) also keeps
+  // the lower blocks, stored transposed in a second copy of the panel layout
+  // at offset PE (Zt_ef = Z~_fe^T, and the left coefficients
+  // Lt_ef = D_e^-T Zt_ef in place of C_ef)
+  const int64_t PE = std::max<int64_t>(P.panel_elems, 1);
+  const int64_t PEt = I.nonsym ? 2 * PE : PE;
+  const uint64_t need = 2ull * (uint64_t)PEt * sizeof(c2);
   if (I.mem_cap && need + (I.near.n + I.faruv.n) * sizeof(c2) > I.mem_cap)
     throw Error{HPS_ENOMEM, "setup plan exceeds device_mem_cap"};
   // elimination-order permutation
@@ -1856,11 +2085,10 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   };
 
   // ---- working panels and factor panels (kept across setups, grow-only)
-  const int64_t PE = std::max<int64_t>(P.panel_elems, 1);
-  I.Wk.alloc(PE);
-  I.F.alloc(PE);
+  I.Wk.alloc(PEt);
+  I.F.alloc(PEt);
   c2 *Wd = I.Wk.p;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, Wd, PE);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, Wd, PEt);
   HIP_CHECK(hipGetLastError());
   std::vector<Scatter> sc(H.n_near());
   for (int64_t b = 0; b < H.n_near(); ++b) {
@@ -1874,13 +2102,13 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
       d.ld = (int32_t)P.size[et];
       d.trans = 0;
-    } else {
-      d.dst = P.panel_off[eu] + col_of(eu, et) * P.size[eu];
+    } else {                     // Z_tu^T: the (u, t) upper block, or the lower block of a non-symmetric field
+      d.dst = (I.nonsym ? PE : 0) + P.panel_off[eu] + col_of(eu, et) * P.size[eu];
       d.ld = (int32_t)P.size[eu];
       d.trans = 1;
     }
     const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
-    if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= P.panel_elems)
+    if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= PEt)
       throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
     sc[b] = d;
   }
@@ -1937,10 +2165,24 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       o.flops += 8.0 * n * n * nF;
       o.coef.flops += 8.0 * n * n * nF;
       o.coef.bytes += 16.0 * (n * n + 2.0 * n * nF);
+      if (I.nonsym) {            // left coefficients (eq. 18), transposed: Lt_eN = D_e^-T Zt_eN
+        const int32_t tl = (int32_t)o.cterms.size();
+        o.cterms.push_back(Term{P.panel_off[e], PE + P.panel_off[e] + n * n, (int32_t)n, (int32_t)n, (int32_t)n, 1});
+        for (int64_t r0 = 0; r0 < n; r0 += TM)
+          for (int64_t c0 = 0; c0 < nF; c0 += TM)
+            o.ctiles.push_back(Tile{PE + P.panel_off[e] + n * n, (int32_t)n, (int32_t)r0, (int32_t)c0, (int32_t)n,
+                                    (int32_t)nF, tl, tl + 1});
+        o.flops += 8.0 * n * n * nF;
+        o.coef.flops += 8.0 * n * n * nF;
+        o.coef.bytes += 16.0 * (n * n + 2.0 * n * nF);
+      }
     }
     // Schur targets (j <= k), eq. (21): id = CSR index of (j, k), or n_up + j
     // for (j, j).  Terms are grouped per target by a counting sort in the
-    // order of first touch; one whole-block tile per target.
+    // order of first touch; one whole-block tile per target.  Symmetric:
+    // Z~_jk -= Z~_ej^T C_ek.  Non-symmetric: Z~_jk -= Zt_ej^T C_ek for j <= k,
+    // and the lower block, stored as Zt_jk = Z~_kj^T, -= Z~_ej^T Lt_ek for
+    // k > j (id n_up + M + CSR index).
     pair_id.clear();
     pair_term.clear();
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
@@ -1968,12 +2210,28 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
           }
           tcount[slot[id]]++;
           pair_id.push_back(slot[id]);
-          pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, P.panel_off[e] + P.col_off[b] * n,
-                                   (int32_t)n, (int32_t)n, (int32_t)n, 1});
+          pair_term.push_back(Term{(I.nonsym ? PE : 0) + P.panel_off[e] + P.col_off[a] * n,
+                                   P.panel_off[e] + P.col_off[b] * n, (int32_t)n, (int32_t)n, (int32_t)n, 1});
           const double f = 8.0 * n * P.size[j] * P.size[kk];
           o.flops += f;
           o.schur.flops += f;
           o.schur.bytes += 16.0 * n * (P.size[j] + P.size[kk]);
+          if (I.nonsym && b != a) {
+            const int64_t lid = n_up + M + id;
+            if (slot[lid] < 0) {
+              slot[lid] = (int32_t)tgt.size();
+              tgt.push_back((int32_t)lid);
+              tcount.push_back(0);
+              tjrow.push_back(j);
+            }
+            tcount[slot[lid]]++;
+            pair_id.push_back(slot[lid]);
+            pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, PE + P.panel_off[e] + P.col_off[b] * n,
+                                     (int32_t)n, (int32_t)n, (int32_t)n, 1});
+            o.flops += f;
+            o.schur.flops += f;
+            o.schur.bytes += 16.0 * n * (P.size[j] + P.size[kk]);
+          }
         }
       }
     }
@@ -1985,7 +2243,11 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     for (size_t x = 0; x < tgt.size(); ++x) {
       const int64_t id = tgt[x], j = tjrow[x];
       int64_t coff, cols;
-      if (id >= n_up) {
+      if (id >= n_up + M) {                 // lower block of a non-symmetric field
+        const int64_t q = id - n_up - M;
+        coff = PE + P.panel_off[j] + P.col_off[q] * P.size[j];
+        cols = P.size[P.later[q]];
+      } else if (id >= n_up) {
         coff = P.panel_off[j];
         cols = P.size[j];
       } else {
@@ -2010,7 +2272,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   std::vector<char> built(L, 0);
   std::atomic<int> next{0};
   auto worker = [&]() {
-    std::vector<int32_t> slot(n_up + M, -1), tgt, tcount, tjrow, pair_id;
+    std::vector<int32_t> slot((I.nonsym ? 2 * n_up : n_up) + M, -1), tgt, tcount, tjrow, pair_id;
     std::vector<Term> pair_term;
     while (true) {
       const int l = next.fetch_add(1);
@@ -2018,8 +2280,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       try {
         build_level(l, slot, tgt, tcount, tjrow, pair_id, pair_term);
         LevelOut &o = lv_out[l];
-        validate(o.ctiles.data(), o.ctiles.size(), o.cterms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
-        validate(o.stiles.data(), o.stiles.size(), o.sterms, P.panel_elems, P.panel_elems, P.panel_elems, "setup");
+        validate(o.ctiles.data(), o.ctiles.size(), o.cterms, PEt, PEt, PEt, "setup");
+        validate(o.stiles.data(), o.stiles.size(), o.sterms, PEt, PEt, PEt, "setup");
       } catch (const Error &e) {
         lv_out[l].err = e.msg;
       }
@@ -2187,8 +2449,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
       const int32_t e = P.level_piv[i];
       for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
-        put(P.later[a], Term{P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N,
-                             (int32_t)P.size[e], 1});
+        put(P.later[a], Term{(I.nonsym ? PE : 0) + P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e],
+                             (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 1});
     }
     flush(I.fwd[l]);
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
@@ -2222,11 +2484,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   std::vector<std::vector<Term>> leaf_terms(M);
   std::vector<int64_t> lv;
   // T is one column-major matrix of t_rows x R: rows [toff, toff + r) hold
-  // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of s)
+  // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of
+  // s); a non-symmetric H-matrix stores both orders as separate blocks, each
+  // applied in dir 0 only
+  const int ndir = I.nonsym ? 1 : 2;
   for (int64_t b = 0; b < nf; ++b)
     for (int dir = 0; dir < 2; ++dir) {
-      I.toff[2 * b + dir] = trow;
-      trow += Hs.far_rank[b];
+      I.toff[2 * b + dir] = dir < ndir ? trow : -1;
+      if (dir < ndir) trow += Hs.far_rank[b];
     }
   I.t_rows = trow;
   const int32_t ldT = (int32_t)std::max<int64_t>(trow, 1);
@@ -2236,7 +2501,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     const int64_t m = thi - tlo, n = shi - slo, r = Hs.far_rank[b];
     if (r == 0) continue;
     const int64_t uo = Hs.far_off[b], vo = Hs.far_off[b] + m * r;
-    for (int dir = 0; dir < 2; ++dir) {
+    for (int dir = 0; dir < ndir; ++dir) {
       add_target(I.far1, I.toff[2 * b + dir], (int32_t)r, ldT);
       const int64_t clo = dir == 0 ? slo : tlo, chi = dir == 0 ? shi : thi;
       const int64_t fo = dir == 0 ? vo : uo, fld = dir == 0 ? n : m;
@@ -2254,11 +2519,13 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       tmu.sidx = (int32_t)(2 * b);
       leaf_terms[g].push_back(tmu);
     }
-    leaves_in(slo, shi, lv);
-    for (int64_t g : lv) {
-      Term tmv{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0};
-      tmv.sidx = (int32_t)(2 * b + 1);
-      leaf_terms[g].push_back(tmv);
+    if (ndir == 2) {
+      leaves_in(slo, shi, lv);
+      for (int64_t g : lv) {
+        Term tmv{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0};
+        tmv.sidx = (int32_t)(2 * b + 1);
+        leaf_terms[g].push_back(tmv);
+      }
     }
   }
   close(I.far1);
@@ -2267,7 +2534,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     I.far2.terms.insert(I.far2.terms.end(), leaf_terms[g].begin(), leaf_terms[g].end());
   }
   close(I.far2);
-  // near-field matvec (both triangles of every stored near block)
+  // near-field matvec (both triangles of every stored near block; every
+  // ordered block once when the field is not symmetric)
   I.nearmv = Impl::Sched();
   std::vector<std::vector<Term>> nt(M);
   for (int64_t b = 0; b < Hs.n_near(); ++b) {
@@ -2275,7 +2543,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     const int64_t mt = Hs.gptr[t + 1] - Hs.gptr[t], mu = Hs.gptr[u + 1] - Hs.gptr[u];
     // row-major mt x mu == column-major mu x mt with ld mu
     nt[t].push_back(Term{Hs.near_off[b], P.uoff[P.pos[u]], (int32_t)mu, (int32_t)N, (int32_t)mu, 1});
-    if (t != u) nt[u].push_back(Term{Hs.near_off[b], P.uoff[P.pos[t]], (int32_t)mu, (int32_t)N, (int32_t)mt, 0});
+    if (t != u && !I.nonsym)
+      nt[u].push_back(Term{Hs.near_off[b], P.uoff[P.pos[t]], (int32_t)mu, (int32_t)N, (int32_t)mt, 0});
   }
   for (int64_t g = 0; g < M; ++g) {
     add_target(I.nearmv, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
@@ -2298,8 +2567,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // ---- precision form: FP32 copies of the factor panels and near blocks,
   // far factors to 16-bit pairs with one FP32 scale per factor per block
   if (I.precision > 0) {
-    I.F32.alloc(PE);
-    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PE, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PE);
+    I.F32.alloc(PEt);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PEt);
     HIP_CHECK(hipGetLastError());
     const int64_t nn = std::max<int64_t>((int64_t)I.near.n, 1);
     I.near32.alloc(nn);
@@ -2433,6 +2702,7 @@ void DeviceState::excitation(int64_t R, const double *khat, const double *pol, v
   const int64_t N = I.N, NR = N * R;
   upload_planewaves(I, R, khat, pol);
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.quad.p, I.dperm.p, N, R, I.dkp.p, I.k,
+                     I.alpha,
                      I.vB.p);
   HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p,
@@ -2469,44 +2739,49 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
 namespace {
 // Mesh arrays on the device for the entry kernels (freed with the object).
 struct DevMesh {
-  DevArray<double> xyz, cen, area, len;
+  DevArray<double> xyz, cen, area, len, nrm;
   DevArray<int32_t> tri, tp, tm, vp, vm;
   NearMesh M;
-  DevMesh(const Mesh &m, double freq_hz, hipStream_t st) {
+  DevMesh(const Mesh &m, double freq_hz, hipStream_t st, int cfie = 0, double alpha = 1.0) {
     const double pi = 3.14159265358979323846, c0 = 299792458.0, mu0 = 4.0e-7 * pi, eps0 = 1.0 / (mu0 * c0 * c0);
     const double w = 2.0 * pi * freq_hz;
     xyz.upload(m.xyz, st); cen.upload(m.cen, st); area.upload(m.area, st); len.upload(m.len, st);
     tri.upload(m.tri, st); tp.upload(m.tp, st); tm.upload(m.tm, st); vp.upload(m.vp, st); vm.upload(m.vm, st);
+    nrm.upload(m.nrm, st);
     M = NearMesh{xyz.p, cen.p, area.p, len.p, tri.p, tp.p, tm.p, vp.p, vm.p, w / c0, m.hmax, w * mu0 / 4.0,
-                 -1.0 / (w * eps0)};
+                 -1.0 / (w * eps0), nrm.p, cfie, alpha, mu0 * c0};
   }
 };
 }  // namespace
 
-void DeviceState::near_fill(const Mesh &m, double freq_hz, HMatrix &H) {
+void DeviceState::near_fill(const Mesh &m, double freq_hz, int cfie, double alpha, HMatrix &H) {
   HIP_CHECK(hipSetDevice(device));
   Impl &I = *impl;
   const int64_t nn = H.n_near();
   if (nn == 0) return;
-  DevMesh dm(m, freq_hz, I.s);
+  DevMesh dm(m, freq_hz, I.s, cfie, alpha);
   DevArray<int32_t> ts;
   DevArray<int64_t> perm, gptr, off;
   DevArray<c2> out;
   perm.upload(H.perm, I.s); gptr.upload(H.gptr, I.s); ts.upload(H.near_ts, I.s); off.upload(H.near_off, I.s);
   const int64_t total = H.near_off[nn];
   out.alloc((size_t)total);
-  hipLaunchKernelGGL(k_near, dim3((unsigned)nn), dim3(256), 0, I.s, dm.M, perm.p, gptr.p, ts.p, off.p, out.p);
+  if (cfie)
+    hipLaunchKernelGGL(k_near<true>, dim3((unsigned)nn), dim3(256), 0, I.s, dm.M, perm.p, gptr.p, ts.p, off.p, out.p);
+  else
+    hipLaunchKernelGGL(k_near<false>, dim3((unsigned)nn), dim3(256), 0, I.s, dm.M, perm.p, gptr.p, ts.p, off.p, out.p);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipMemcpyAsync((void *)H.near_vals.data(), out.p, (size_t)total * sizeof(c2), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
-void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, double eps, const FarEmit &emit) {
+void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alpha, const HMatrix &H, double eps,
+                             const FarEmit &emit) {
   HIP_CHECK(hipSetDevice(device));
   Impl &I = *impl;
   const int64_t nf = H.n_far();
   if (nf == 0) return;
-  DevMesh dm(m, freq_hz, I.s);
+  DevMesh dm(m, freq_hz, I.s, cfie, alpha);
   DevArray<int64_t> perm;
   perm.upload(H.perm, I.s);
   // chunks: at most 4 GiB of scratch, and about a sixteenth of the blocks
@@ -2533,7 +2808,12 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, const HMatrix &H, do
     scratch.alloc((size_t)need);
     dblk.upload(blk, I.s);
     drank.alloc((size_t)nb);
-    hipLaunchKernelGGL(k_aca, dim3((unsigned)nb), dim3(256), 0, I.s, dm.M, perm.p, dblk.p, eps, scratch.p, drank.p);
+    if (cfie)
+      hipLaunchKernelGGL(k_aca<true>, dim3((unsigned)nb), dim3(256), 0, I.s, dm.M, perm.p, dblk.p, eps, scratch.p,
+                         drank.p);
+    else
+      hipLaunchKernelGGL(k_aca<false>, dim3((unsigned)nb), dim3(256), 0, I.s, dm.M, perm.p, dblk.p, eps, scratch.p,
+                         drank.p);
     HIP_CHECK(hipGetLastError());
     FarChunk ch;
     ch.b0 = b0;
@@ -2579,7 +2859,7 @@ std::string DeviceState::stats_json() const {
   if (I.ready) {
     o << ", \"levels\": " << I.P.n_levels << ", \"upper_blocks\": " << I.P.n_upper_blocks
       << ", \"n_U\": " << I.P.n_U << ", \"n_D\": " << I.P.n_D
-      << ", \"factor_bytes\": " << 16.0 * (double)I.P.panel_elems
+      << ", \"factor_bytes\": " << 16.0 * (double)I.P.panel_elems * (I.nonsym ? 2.0 : 1.0)
       << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;

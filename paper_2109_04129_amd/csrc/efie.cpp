@@ -115,7 +115,7 @@ void potentials(const Mesh &m, int32_t t, const double *r, double &I1, double Ir
 
 }  // namespace
 
-EFIE::EFIE(const Mesh &m, double freq_hz) : mesh(&m) {
+Galerkin::Galerkin(const Mesh &m, double freq_hz, bool cfie_, double alpha_) : mesh(&m), cfie(cfie_), alpha(alpha_) {
   omega = 2.0 * kPi * freq_hz;
   k = omega / kC0;
   h = m.hmax;
@@ -126,7 +126,7 @@ EFIE::EFIE(const Mesh &m, double freq_hz) : mesh(&m) {
 namespace {
 
 // (jw mu / 4) II (r - vO).(r' - vI) G - (j / (w eps)) II G over O x I (outer O).
-cplx pair_integral(const EFIE &op, int32_t O, const double *vO, int32_t I, const double *vI) {
+cplx pair_integral(const Galerkin &op, int32_t O, const double *vO, int32_t I, const double *vI) {
   const Mesh &m = *op.mesh;
   const int32_t *to = &m.tri[3 * O], *ti = &m.tri[3 * I];
   bool share = false;
@@ -192,7 +192,7 @@ cplx pair_integral(const EFIE &op, int32_t O, const double *vO, int32_t I, const
 
 }  // namespace
 
-cplx EFIE::entry(int64_t m_, int64_t n_) const {
+cplx Galerkin::efie_entry(int64_t m_, int64_t n_) const {
   const Mesh &m = *mesh;
   const int64_t a = m_ < n_ ? m_ : n_, b = m_ < n_ ? n_ : m_;
   const int32_t ta[2] = {m.tp[a], m.tm[a]}, tb[2] = {m.tp[b], m.tm[b]};
@@ -209,7 +209,153 @@ cplx EFIE::entry(int64_t m_, int64_t n_) const {
   return z;
 }
 
-void EFIE::block(const int64_t *rows, int64_t nr, const int64_t *cols, int64_t nc, cplx *out) const {
+namespace {
+
+// int_T (r - r') / R^3 dS' for observation point r: the in-plane part is the
+// divergence theorem on grad'_s (1/R) = (rho - r') / R^3, sum_i u_i F_i, the
+// normal part sign(d) sum_i beta_i (the arctangent terms of potentials()).
+void grad_potential(const Mesh &m, int32_t t, const double *r, double out[3]) {
+  const double *V[3] = {&m.xyz[3 * m.tri[3 * t]], &m.xyz[3 * m.tri[3 * t + 1]], &m.xyz[3 * m.tri[3 * t + 2]]};
+  double e1[3], e2[3], n[3];
+  for (int d = 0; d < 3; ++d) { e1[d] = V[1][d] - V[0][d]; e2[d] = V[2][d] - V[0][d]; }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nn = std::sqrt(dot3(n, n));
+  for (int d = 0; d < 3; ++d) n[d] /= nn;
+  double rv[3], rho[3];
+  for (int d = 0; d < 3; ++d) rv[d] = r[d] - V[0][d];
+  const double h = dot3(rv, n), ah = std::fabs(h);
+  for (int d = 0; d < 3; ++d) rho[d] = r[d] - h * n[d];
+  out[0] = out[1] = out[2] = 0.0;
+  double bsum = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double *pa = V[e], *pb = V[(e + 1) % 3];
+    double sv[3], u[3], da[3], db[3];
+    for (int d = 0; d < 3; ++d) sv[d] = pb[d] - pa[d];
+    const double ls = std::sqrt(dot3(sv, sv));
+    for (int d = 0; d < 3; ++d) sv[d] /= ls;
+    u[0] = sv[1] * n[2] - sv[2] * n[1];
+    u[1] = sv[2] * n[0] - sv[0] * n[2];
+    u[2] = sv[0] * n[1] - sv[1] * n[0];
+    for (int d = 0; d < 3; ++d) { da[d] = pa[d] - rho[d]; db[d] = pb[d] - rho[d]; }
+    const double lp = dot3(db, sv), lm = dot3(da, sv), t0 = dot3(da, u);
+    const double R0sq = t0 * t0 + h * h;
+    const double Rp = std::sqrt(lp * lp + R0sq), Rm = std::sqrt(lm * lm + R0sq);
+    double F = 0.0;
+    if (R0sq > 0.0)
+      F = (lp + lm >= 0.0) ? std::log((Rp + lp) / (Rm + lm)) : std::log((Rm - lm) / (Rp - lp));
+    double beta = 0.0;
+    const double dp = R0sq + ah * Rp, dm = R0sq + ah * Rm;
+    if (dp > 0.0) beta += std::atan(t0 * lp / dp);
+    if (dm > 0.0) beta -= std::atan(t0 * lm / dm);
+    for (int d = 0; d < 3; ++d) out[d] += u[d] * F;
+    bsum += beta;
+  }
+  const double sg = (h > 0.0) ? 1.0 : (h < 0.0 ? -1.0 : 0.0);
+  for (int d = 0; d < 3; ++d) out[d] += n[d] * sg * bsum;
+}
+
+// MFIE kernel (1 + jkR) exp(-jkR) / (4 pi R^3) (eq. 7 times 1/R) and its part
+// without the static 1/(4 pi R^3).
+inline void mfie_kernel(double k, double R, cplx &g, cplx &gdyn) {
+  const double x = k * R, c = std::cos(x), s = std::sin(x);
+  const cplx num(c - 1.0 + x * s, x * c - s);     // (1 + jx) e^{-jx} - 1
+  const double den = 4.0 * kPi * R * R * R;
+  gdyn = num / den;
+  g = (1.0 + num) / den;
+}
+
+// int_P (r - vP) . [n_P x ((r - vQ) x W_Q(r))] dS with
+// W_Q(r) = int_Q (r - r') g(R) dS', for P != Q; written as
+// (a.b)(n.W) - (a.W)(n.b), a = r - vP, b = r - vQ.  Rules as for the EFIE:
+// touching or < 2h: 7-point outer, closed-form static part + 7 points on the
+// remainder; < 4h: 7 x 7; else 3 x 3.
+cplx mfie_pair(const Galerkin &op, int32_t P, const double *vP, int32_t Q, const double *vQ) {
+  const Mesh &m = *op.mesh;
+  const int32_t *tp = &m.tri[3 * P], *tq = &m.tri[3 * Q];
+  bool share = false;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) share |= (tp[a] == tq[b]);
+  double dc[3];
+  for (int d = 0; d < 3; ++d) dc[d] = m.cen[3 * P + d] - m.cen[3 * Q + d];
+  const double d2 = dot3(dc, dc);
+  const int rule = (share || d2 < (2.0 * op.h) * (2.0 * op.h)) ? 0 : (d2 < (4.0 * op.h) * (4.0 * op.h) ? 1 : 2);
+  const Rule &rr = rule == 2 ? R3 : R7;
+  double po[7][3], pi[7][3];
+  tri_points(m, P, rr, po);
+  tri_points(m, Q, rr, pi);
+  const double *nP = &m.nrm[3 * P];
+  const double AQ = m.area[Q];
+  cplx acc = 0.0;
+  for (int a = 0; a < rr.n; ++a) {
+    cplx W[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < rr.n; ++b) {
+      double dd[3];
+      for (int d = 0; d < 3; ++d) dd[d] = po[a][d] - pi[b][d];
+      const double R = std::sqrt(dot3(dd, dd));
+      cplx g, gdyn;
+      mfie_kernel(op.k, R, g, gdyn);
+      const cplx f = rr.w[b] * AQ * (rule == 0 ? gdyn : g);
+      for (int d = 0; d < 3; ++d) W[d] += f * dd[d];
+    }
+    if (rule == 0) {
+      double V[3];
+      grad_potential(m, Q, po[a], V);
+      for (int d = 0; d < 3; ++d) W[d] += V[d] / (4.0 * kPi);
+    }
+    double am[3], bn[3];
+    for (int d = 0; d < 3; ++d) { am[d] = po[a][d] - vP[d]; bn[d] = po[a][d] - vQ[d]; }
+    const cplx nW = (nP[0] * W[0] + nP[1] * W[1]) + nP[2] * W[2];
+    const cplx aW = (am[0] * W[0] + am[1] * W[1]) + am[2] * W[2];
+    acc += rr.w[a] * (dot3(am, bn) * nW - aW * dot3(nP, bn));
+  }
+  return m.area[P] * acc;
+}
+
+}  // namespace
+
+// MFIE (eqs. 6-7) tested with f_m: 1/2 <f_m, f_n> - <f_m, n x int f_n x grad' G>,
+// summed over the triangle pairs (+,+), (+,-), (-,+), (-,-) of (m, n); on one
+// flat triangle the integral term vanishes.
+cplx Galerkin::mfie_entry(int64_t m_, int64_t n_) const {
+  const Mesh &m = *mesh;
+  const int32_t tm_[2] = {m.tp[m_], m.tm[m_]}, tn_[2] = {m.tp[n_], m.tm[n_]};
+  const int32_t vm_[2] = {m.vp[m_], m.vm[m_]}, vn_[2] = {m.vp[n_], m.vm[n_]};
+  const double sg[2] = {1.0, -1.0};
+  cplx z = 0.0;
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) {
+      const int32_t P = tm_[p], Q = tn_[q];
+      const double *vP = &m.xyz[3 * vm_[p]], *vQ = &m.xyz[3 * vn_[q]];
+      const double c = sg[p] * sg[q] * m.len[m_] * m.len[n_] / (4.0 * m.area[P] * m.area[Q]);
+      cplx v;
+      if (P == Q) {
+        double pts[7][3];
+        tri_points(m, P, R7, pts);
+        double acc = 0.0;
+        for (int a = 0; a < 7; ++a) {
+          double am[3], bn[3];
+          for (int d = 0; d < 3; ++d) { am[d] = pts[a][d] - vP[d]; bn[d] = pts[a][d] - vQ[d]; }
+          acc += R7.w[a] * dot3(am, bn);
+        }
+        v = 0.5 * m.area[P] * acc;
+      } else {
+        v = -mfie_pair(*this, P, vP, Q, vQ);
+      }
+      z += c * v;
+    }
+  return z;
+}
+
+cplx Galerkin::entry(int64_t m_, int64_t n_) const {
+  if (!cfie) return efie_entry(m_, n_);
+  cplx z = alpha * efie_entry(m_, n_);
+  if (alpha != 1.0) z += (kMu0 * kC0) * (1.0 - alpha) * mfie_entry(m_, n_);
+  return z;
+}
+
+void Galerkin::block(const int64_t *rows, int64_t nr, const int64_t *cols, int64_t nc, cplx *out) const {
   for (int64_t i = 0; i < nr; ++i)
     for (int64_t j = 0; j < nc; ++j) out[i * nc + j] = entry(rows[i], cols[j]);
 }

@@ -26,7 +26,9 @@ struct Mesh {
   // per triangle
   std::vector<double> cen;     // nt * 3, (v0 + v1 + v2) / 3
   std::vector<double> area;    // nt
+  std::vector<double> nrm;     // nt * 3, unit normal from the vertex order (outward if counter-clockwise)
   double hmax = 0.0;           // longest edge
+  bool open = false;           // built with rim edges allowed (open sheet)
   // per RWG unknown (RWG order)
   int64_t N = 0;
   std::vector<int32_t> edge;   // N * 2 (min, max vertex)
@@ -65,9 +67,12 @@ void block_partition(const Tree &t, std::vector<std::pair<int32_t, int32_t>> &ne
 // ---------------------------------------------------------------- H-matrix (host copy)
 struct HMatrix {
   int64_t N = 0, M = 0;
+  // false: symmetric (EFIE), near blocks t <= s, far blocks applied both ways.
+  // true (CFIE): every ordered near pair, every far block one way only.
+  bool nonsym = false;
   std::vector<int64_t> perm;          // tree position -> RWG
   std::vector<int64_t> gptr;          // M + 1
-  std::vector<int32_t> near_ts;       // 2 * n_near, t <= s
+  std::vector<int32_t> near_ts;       // 2 * n_near, t <= s unless nonsym
   std::vector<int64_t> near_off;      // n_near + 1
   std::vector<cplx> near_vals;        // row-major blocks
   std::vector<int64_t> far_rng;       // 4 * n_far
@@ -78,20 +83,25 @@ struct HMatrix {
   int64_t n_far() const { return (int64_t)far_rank.size(); }
 };
 
-// EFIE entries of the Galerkin matrix (symmetric by construction).
-struct EFIE {
+// Entries of the Galerkin matrix: the EFIE (symmetric by construction) or,
+// with cfie, alpha EFIE + eta0 (1 - alpha) MFIE (eq. 8, not symmetric).
+struct Galerkin {
   const Mesh *mesh;
   double k, omega, h;
   cplx cA, cPhi;
-  EFIE(const Mesh &m, double freq_hz);
+  bool cfie = false;
+  double alpha = 1.0;
+  Galerkin(const Mesh &m, double freq_hz, bool cfie_ = false, double alpha_ = 1.0);
   cplx entry(int64_t m, int64_t n) const;
+  cplx efie_entry(int64_t m, int64_t n) const;
+  cplx mfie_entry(int64_t m, int64_t n) const;
   // Z[rows[i], cols[j]] into out (row-major rows x cols)
   void block(const int64_t *rows, int64_t nr, const int64_t *cols, int64_t nc, cplx *out) const;
 };
 
 // Re-compressed ACA of one admissible block; U (m x r) and V (n x r)
 // column-major with block ~= U V^T.
-void aca_block(const EFIE &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
+void aca_block(const Galerkin &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
                double eps, std::vector<cplx> &U, std::vector<cplx> &V, int &rank);
 
 // Fills H.near_vals (sized from H.near_off) from the near block list of H;

@@ -27,6 +27,8 @@ void build_rwg(Mesh &m, bool allow_open) {
     if (m.tri[i] < 0 || m.tri[i] >= nv) throw Error{HPS_EINVAL, "vertex index out of range"};
   m.cen.assign(3 * nt, 0.0);
   m.area.assign(nt, 0.0);
+  m.nrm.assign(3 * nt, 0.0);
+  m.open = allow_open;
   double hmax = 0.0;
   for (int64_t t = 0; t < nt; ++t) {
     const double *p[3];
@@ -38,6 +40,11 @@ void build_rwg(Mesh &m, bool allow_open) {
     const double cy = u[2] * v[0] - u[0] * v[2];
     const double cz = u[0] * v[1] - u[1] * v[0];
     m.area[t] = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    if (m.area[t] > 0.0) {
+      m.nrm[3 * t] = cx / (2.0 * m.area[t]);
+      m.nrm[3 * t + 1] = cy / (2.0 * m.area[t]);
+      m.nrm[3 * t + 2] = cz / (2.0 * m.area[t]);
+    }
     for (int e = 0; e < 3; ++e) {
       const double *a = p[e], *b = p[(e + 1) % 3];
       const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
