@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--workload", default="sphere_s5_790MHz")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form leg")
+    ap.add_argument("--no-cfie", action="store_true", help="skip the CFIE leg")
     ap.add_argument("--cpu-rhs", type=int, default=8, help="RHS in the oracle's timed sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
@@ -75,16 +76,17 @@ def parse():
     return ap.parse_args()
 
 
-def build_hmatrix(w):
-    """The H-matrix of the workload, built once (near blocks on the device,
-    far blocks on host threads; not timed as setup) and installed in every
-    leg."""
+def build_hmatrix(w, **extra):
+    """The H-matrix of the workload, built once (near blocks and ACA sampling
+    on the device, recompression on host threads; not timed as setup) and
+    installed in every leg.  ``extra`` selects e.g. the CFIE formulation."""
     import torch
     from paper_2109_04129_amd import hps
     h = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
     try:
         set_mesh(hps, h, w)
-        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1)
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1,
+                                   **extra)
         t0 = time.perf_counter()
         hps.hps_build_hmatrix(h, p)
         build_s = time.perf_counter() - t0
@@ -105,7 +107,7 @@ def install(hps, ctx, p, g):
                         g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
 
 
-def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
+def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None, reference_tol=0.0):
     import torch
     from paper_2109_04129_amd import hps
 
@@ -119,8 +121,10 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
     set_mesh(hps, ctx, w)
-    p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
-                               precision=precision, refine_passes=refine)
+    kw = dict(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2, precision=precision,
+              refine_passes=refine)
+    kw.update(extra or {})
+    p = hps.hps_params_default(**kw)
     install(hps, ctx, p, g)
     N = hps.hps_num_unknowns(ctx)
     khat, pol = w["khat"], w["pol"]
@@ -158,7 +162,7 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
         # series terms
         Xm = X.cpu().numpy()
         del X
-        p.precision, p.refine_passes, p.terms = 0, 0, reference_terms
+        p.precision, p.refine_passes, p.terms, p.series_tol = 0, 0, reference_terms, reference_tol
         ref = hps.hps_create(0, stream.cuda_stream)
         set_mesh(hps, ref, w)
         install(hps, ref, p, g)
@@ -167,8 +171,10 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None):
         _, rcs_r, _ = hps.hps_solve_planewaves(ref, khat, pol, Xr.data_ptr())
         torch.cuda.synchronize()
         Xr = Xr.cpu().numpy()
+        used = hps.hps_stats(ref).get("device", {}).get("terms_used")
         hps.hps_destroy(ref)
-        err = {"terms_of_reference": reference_terms,
+        err = {"terms_of_reference": reference_terms if reference_tol <= 0 else
+               "adaptive to %g (%s terms)" % (reference_tol, used),
                "current_rel_err_max": float(np.max(np.linalg.norm(Xm - Xr, axis=1) / np.linalg.norm(Xr, axis=1))),
                "rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs / rcs_r))))}
     return dict(N=N, R=R, total=total, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
@@ -356,6 +362,33 @@ def main():
                            "accuracy_vs_fp64": gm["err"]}
         mixed = {"form": "FP32 near operands on MFMA, 16-bit far factors with per-block FP32 scale, "
                          "FP64 setup, one FP32 residual pass (= four-term series)", "variants": forms}
+    cfie = None
+    if not args.no_cfie and not w.get("open"):
+        # CFIE of eq. (8), alpha = 0.5, on the same mesh: its own H-matrix
+        # (both orders of every block), left and right coefficients; accuracy
+        # of the two-term series against the converged series
+        extra = {"formulation": 1, "cfie_alpha": 0.5}
+        hc, bc = build_hmatrix(w, **extra)
+        gc = gpu_leg(args, w, hc, extra=extra, reference_terms=60, reference_tol=1e-10)
+        dc = gc["stats"].get("device", {})
+        cfie = {"form": "CFIE alpha 0.5, plain fp64, two terms",
+                "rhs_per_s_step": gc["R"] * args.steps / gc["total"],
+                "ms_per_step": 1e3 * gc["total"] / args.steps,
+                "setup_s": float(np.median(gc["setup"])),
+                "solve_rhs_per_s": float(gc["R"] / np.median(gc["solve"])),
+                "hmatrix_build_s": bc, "ratio_max": float(np.max(gc["ratio"])),
+                "ratio_median": float(np.median(gc["ratio"])),
+                "two_terms_vs_converged_series": gc["err"],
+                "factor_bytes": dc.get("factor_bytes"), "upper_blocks": dc.get("upper_blocks")}
+        # the series run until ||it_t|| / ||it_0|| < 1e-4 for every RHS (eq. 45
+        # ratio control), against the same converged reference
+        ea = dict(extra, terms=40, series_tol=1e-4)
+        ga = gpu_leg(args, w, hc, extra=ea, reference_terms=60, reference_tol=1e-10)
+        cfie["adaptive_series_1e-4"] = {
+            "rhs_per_s_step": ga["R"] * args.steps / ga["total"],
+            "solve_rhs_per_s": float(ga["R"] / np.median(ga["solve"])),
+            "terms_used": ga["stats"].get("device", {}).get("terms_used"),
+            "vs_converged_series": ga["err"]}
     R, K = g["R"], args.steps
     ms_per_step = 1e3 * g["total"] / K
     dev = dict(g["stats"].get("device", {}))
@@ -391,6 +424,7 @@ def main():
         "ratio_max": float(np.max(g["ratio"])),
         "roofline": roofline,
         "precision_form": mixed,
+        "cfie_form": cfie,
         "batching_form": batch_leg(args) if args.batch else None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_leg(args, w),
         "device_stats": dev,

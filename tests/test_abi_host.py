@@ -3,6 +3,7 @@ include/hps.h declares, validates its inputs, and its host-side H-matrix
 build (tree, near/far split, EFIE entries, ACA) agrees with the oracle.
 No device work is launched here."""
 
+import math
 import os
 import re
 import subprocess
@@ -265,3 +266,67 @@ def test_open_plate_matches_oracle():
     for b, k in enumerate(keys):
         blk = L["near_vals"][L["near_off"][b]:L["near_off"][b + 1]].reshape(H.near[k].shape)
         assert np.abs(blk - H.near[k]).max() <= 1e-13 * np.abs(H.near[k]).max()
+
+
+# ---------------------------------------------------------------- CFIE (eq. 8)
+def test_cfie_parameters_checked():
+    from workloads import icosphere, workload
+    xyz, tri = icosphere(1, 1.0)
+    h = hps.hps_create(-1, None)
+    try:
+        hps.hps_set_mesh(h, xyz, tri)
+        for bad in (dict(formulation=2), dict(formulation=1, cfie_alpha=1.5), dict(formulation=1, cfie_alpha=-0.1)):
+            with pytest.raises(hps.HpsError) as e:
+                hps.hps_build_hmatrix(h, hps.hps_params_default(freq_hz=300e6, leaf_max=16, **bad))
+            assert e.value.status == -1
+    finally:
+        hps.hps_destroy(h)
+    w = workload("plate_2lambda_300MHz")
+    h = hps.hps_create(-1, None)
+    try:
+        hps.hps_set_open_mesh(h, w["xyz"], w["tri"])
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_build_hmatrix(h, hps.hps_params_default(freq_hz=300e6, leaf_max=16, formulation=1))
+        assert e.value.status == -1 and "closed" in str(e.value)
+    finally:
+        hps.hps_destroy(h)
+
+
+def test_cfie_host_build_matches_oracle_entries():
+    """Host-built CFIE H-matrix: every ordered near pair is present, the near
+    blocks equal the oracle's CFIE entries to rounding, and the far blocks
+    approximate the dense oracle matrix to the ACA tolerance."""
+    from oracle.mfie import CFIEOperator
+    from oracle.rwg import build_rwg
+    from workloads import ellipsoid_mesh, icosphere
+    xyz, tri = icosphere(2, 1.0)
+    xyz, tri = ellipsoid_mesh(xyz, tri, (1.3, 0.9, 0.6))
+    h = hps.hps_create(-1, None)
+    try:
+        hps.hps_set_mesh(h, xyz, tri)
+        hps.hps_build_hmatrix(h, hps.hps_params_default(freq_hz=300e6, leaf_max=16, aca_tol=1e-3, formulation=1,
+                                                        cfie_alpha=0.5))
+        g = hps.hps_get_hmatrix(h)
+    finally:
+        hps.hps_destroy(h)
+    Z = CFIEOperator(build_rwg(xyz, tri), 300e6, 0.5).dense()
+    perm, gp, ts = g["perm"], g["group_ptr"], g["near_ts"].reshape(-1, 2)
+    pairs = set(map(tuple, ts))
+    assert all((s, t) in pairs for t, s in pairs)
+    assert np.any(ts[:, 0] > ts[:, 1])
+    worst = 0.0
+    for b, (t, s) in enumerate(ts):
+        B = g["near_vals"][g["near_off"][b]:g["near_off"][b + 1]].reshape(gp[t + 1] - gp[t], gp[s + 1] - gp[s])
+        ref = Z[np.ix_(perm[gp[t]:gp[t + 1]], perm[gp[s]:gp[s + 1]])]
+        worst = max(worst, np.abs(B - ref).max() / np.abs(ref).max())
+    assert worst < 1e-12
+    fr = g["far_rng"].reshape(-1, 4)
+    num = den = 0.0
+    for b, (a0, a1, b0, b1) in enumerate(fr):
+        r, o = g["far_rank"][b], g["far_off"][b]
+        U = g["far_uv"][o:o + (a1 - a0) * r].reshape(r, a1 - a0).T
+        V = g["far_uv"][o + (a1 - a0) * r:o + (a1 - a0 + b1 - b0) * r].reshape(r, b1 - b0).T
+        ref = Z[np.ix_(perm[a0:a1], perm[b0:b1])]
+        num += np.linalg.norm(U @ V.T - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    assert math.sqrt(num / den) < 2e-3
