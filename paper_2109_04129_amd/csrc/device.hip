@@ -59,8 +59,9 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // ------------------------------------------------------------------ grouped GEMM
 // Complex FP64 on the matrix cores: each wave owns one 16 x 16 block of a
 // 32 x 32 workgroup tile and accumulates op(A) B with V_MFMA_F64_16X16X4_F64
-// in the real 4M split (Ar Br, Ai Bi, Ar Bi, Ai Br in four independent
-// accumulators; re = rr - ii, im = ri + ir).  Operand layout of the
+// in the real 3M split (Gauss: Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) in three
+// accumulators; re = rr - ii, im = ss - rr - ii), three products per complex
+// step instead of four.  Operand layout of the
 // instruction: lane l supplies A[l % 16][k slot l / 16] and B[k slot
 // l / 16][l % 16]; result register r of lane l is D[l / 16 + 4 r][l % 16].
 // In step s of a chunk of 16 the lane groups take k = k0 + 4 s + l / 16, so
@@ -121,9 +122,9 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
         }
       }
     }
-    d4 rr[NB], ii[NB], ri[NB], ir[NB];
+    d4 rr[NB], ii[NB], ss[NB];      // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ss[j] = d4{0.0, 0.0, 0.0, 0.0};
     for (int q = t.t_begin; q < t.t_end; ++q) {
       const Term tm = terms[q];
       const c2 *Ab = A + tm.a_off;
@@ -144,14 +145,15 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
           }
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) {
+          const double as = av[s].x + av[s].y;
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
             rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
             ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
-            ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
-            ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+            ss[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bv[j][s].x + bv[j][s].y, ss[j], 0, 0, 0);
           }
+        }
       }
       // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
       for (int kt = kfull; kt < tm.k; kt += 4) {
@@ -166,8 +168,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
           if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
           rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
           ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
-          ri[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ri[j], 0, 0, 0);
-          ir[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, ir[j], 0, 0, 0);
+          ss[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, bv.x + bv.y, ss[j], 0, 0, 0);
         }
       }
     }
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
       for (int r = 0; r < 4; ++r) {
         const int crow = row0 + lg + 4 * r;
         if (crow >= t.m) continue;
-        const c2 acc = make_double2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
+        const c2 acc = make_double2(rr[j][r] - ii[j][r], ss[j][r] - rr[j][r] - ii[j][r]);
         c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
         if (MODE == 0) {
           *p = acc;
