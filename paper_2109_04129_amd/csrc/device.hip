@@ -1555,6 +1555,24 @@ struct DeviceState::Impl {
     }
   };
   std::deque<Chunk> chunks;       // a deque: growing never relocates the arrays
+  // second stream of the setup (default priority) and per-level events
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> lev_ev;  // 2 per level: coefficients done, far Schur part done
+  void setup_streams(int L) {
+    if (!s2) HIP_CHECK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    while ((int)lev_ev.size() < 2 * L) {
+      hipEvent_t e;
+      HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      lev_ev.push_back(e);
+    }
+  }
+  ~Impl() {
+    for (hipEvent_t e : lev_ev) (void)hipEventDestroy(e);
+    if (s2) {
+      (void)hipStreamSynchronize(s2);
+      (void)hipStreamDestroy(s2);
+    }
+  }
   Pool spool;                      // solve schedules (independent of R)
   int64_t built_R = -1;
   std::vector<Built> b_fwd, b_bwd;
@@ -2124,21 +2142,23 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // independent), then concatenated in level order into one pool
   const auto th0 = std::chrono::steady_clock::now();
   const int L = P.n_levels;
+  I.setup_streams(L);
   struct InvLaunch { int nc; int64_t start, count; int level; double flops; };
   struct GemmLaunch { int64_t t0, n; int sub = 1; double flops = 0.0, bytes = 0.0; };
   struct LevelOut {
     std::vector<int64_t> inv_off[3];
     std::vector<int32_t> inv_n[3], inv_id[3];
     double inv_flops[3] = {0, 0, 0};
-    std::vector<Tile> ctiles, stiles;
+    std::vector<Tile> ctiles, stiles, stiles2;   // stiles: targets in rows of the next level; stiles2: the rest
     std::vector<Term> cterms, sterms;
-    GemmLaunch coef, schur;
+    GemmLaunch coef, schur, schur2;
     double flops = 0.0;
     std::string err;
   };
   std::vector<LevelOut> lv_out(L);
   const int64_t n_up = P.n_upper_blocks;
-  auto build_level = [&](int l, std::vector<int32_t> &slot, std::vector<int32_t> &tgt, std::vector<int32_t> &tcount,
+  auto build_level = [&](int l, std::vector<double> &tflop, std::vector<int32_t> &slot, std::vector<int32_t> &tgt,
+                         std::vector<int32_t> &tcount,
                          std::vector<int32_t> &tjrow, std::vector<int32_t> &pair_id, std::vector<Term> &pair_term) {
     LevelOut &o = lv_out[l];
     for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
@@ -2208,6 +2228,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
             tgt.push_back((int32_t)id);
             tcount.push_back(0);
             tjrow.push_back(j);
+            tflop.push_back(0.0);
           }
           tcount[slot[id]]++;
           pair_id.push_back(slot[id]);
@@ -2215,8 +2236,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
                                    P.panel_off[e] + P.col_off[b] * n, (int32_t)n, (int32_t)n, (int32_t)n, 1});
           const double f = 8.0 * n * P.size[j] * P.size[kk];
           o.flops += f;
-          o.schur.flops += f;
-          o.schur.bytes += 16.0 * n * (P.size[j] + P.size[kk]);
+          tflop[slot[id]] += f;
           if (I.nonsym && b != a) {
             const int64_t lid = n_up + M + id;
             if (slot[lid] < 0) {
@@ -2224,14 +2244,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
               tgt.push_back((int32_t)lid);
               tcount.push_back(0);
               tjrow.push_back(j);
+              tflop.push_back(0.0);
             }
             tcount[slot[lid]]++;
             pair_id.push_back(slot[lid]);
             pair_term.push_back(Term{P.panel_off[e] + P.col_off[a] * n, PE + P.panel_off[e] + P.col_off[b] * n,
                                      (int32_t)n, (int32_t)n, (int32_t)n, 1});
             o.flops += f;
-            o.schur.flops += f;
-            o.schur.bytes += 16.0 * n * (P.size[j] + P.size[kk]);
+            tflop[slot[lid]] += f;
           }
         }
       }
@@ -2255,15 +2275,22 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         coff = P.panel_off[j] + P.col_off[id] * P.size[j];
         cols = P.size[P.later[id]];
       }
-      o.stiles.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols, start[x],
-                              start[x + 1]});
-      o.schur.bytes += 32.0 * P.size[j] * cols;
-      o.schur.sub = std::max<int>(o.schur.sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
+      // targets in rows of the next level are needed by its pivots first
+      const bool next = P.level[j] == l + 1;
+      std::vector<Tile> &tl = next ? o.stiles : o.stiles2;
+      GemmLaunch &gl = next ? o.schur : o.schur2;
+      tl.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols, start[x], start[x + 1]});
+      gl.flops += tflop[x];
+      for (int32_t q = start[x]; q < start[x + 1]; ++q)
+        gl.bytes += 16.0 * o.sterms[q].k * ((double)P.size[j] + (double)cols);
+      gl.bytes += 32.0 * P.size[j] * cols;
+      gl.sub = std::max<int>(gl.sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
       slot[id] = -1;
     }
     tgt.clear();
     tcount.clear();
     tjrow.clear();
+    tflop.clear();
   };
   // Levels are built on worker threads in level order while this thread
   // uploads and launches them in chunks of growing size (2, 4, 8, ... levels),
@@ -2275,14 +2302,16 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   auto worker = [&]() {
     std::vector<int32_t> slot((I.nonsym ? 2 * n_up : n_up) + M, -1), tgt, tcount, tjrow, pair_id;
     std::vector<Term> pair_term;
+    std::vector<double> tflop;
     while (true) {
       const int l = next.fetch_add(1);
       if (l >= L) break;
       try {
-        build_level(l, slot, tgt, tcount, tjrow, pair_id, pair_term);
+        build_level(l, tflop, slot, tgt, tcount, tjrow, pair_id, pair_term);
         LevelOut &o = lv_out[l];
         validate(o.ctiles.data(), o.ctiles.size(), o.cterms, PEt, PEt, PEt, "setup");
         validate(o.stiles.data(), o.stiles.size(), o.sterms, PEt, PEt, PEt, "setup");
+        validate(o.stiles2.data(), o.stiles2.size(), o.sterms, PEt, PEt, PEt, "setup");
       } catch (const Error &e) {
         lv_out[l].err = e.msg;
       }
@@ -2335,14 +2364,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     int64_t nt = 0, nm = 0, ni = 0;
     for (int l = lo; l < hi; ++l) {
       const LevelOut &o = lv_out[l];
-      nt += (int64_t)(o.ctiles.size() + o.stiles.size());
+      nt += (int64_t)(o.ctiles.size() + o.stiles.size() + o.stiles2.size());
       nm += (int64_t)(o.cterms.size() + o.sterms.size());
       for (int k = 0; k < 3; ++k) ni += (int64_t)o.inv_off[k].size();
     }
     ch.reserve(nt, nm, ni);
     // concatenate into the chunk's pinned staging arrays (term indices rebased)
     std::vector<InvLaunch> invl;
-    std::vector<GemmLaunch> coefl(hi - lo), schurl(hi - lo);
+    std::vector<GemmLaunch> coefl(hi - lo), schurl(hi - lo), schur2l(hi - lo);
     int64_t ti = 0, mi_ = 0, ii = 0;
     for (int l = lo; l < hi; ++l) {
       LevelOut &o = lv_out[l];
@@ -2355,10 +2384,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         std::copy(o.inv_id[k].begin(), o.inv_id[k].end(), ch.h_inv_id.p + ii);
         ii += cnt;
       }
-      auto append = [&](std::vector<Tile> &tl, std::vector<Term> &tm, GemmLaunch &dst, const GemmLaunch &src) {
+      auto append_terms = [&](std::vector<Term> &tm) {
         const int32_t base = (int32_t)mi_;
         std::copy(tm.begin(), tm.end(), ch.h_terms.p + mi_);
         mi_ += (int64_t)tm.size();
+        std::vector<Term>().swap(tm);
+        return base;
+      };
+      auto append_tiles = [&](std::vector<Tile> &tl, int32_t base, GemmLaunch &dst, const GemmLaunch &src) {
         dst = src;
         dst.t0 = ti;
         for (const Tile &t0 : tl) {
@@ -2369,10 +2402,11 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         }
         dst.n = (int64_t)tl.size();
         std::vector<Tile>().swap(tl);
-        std::vector<Term>().swap(tm);
       };
-      append(o.ctiles, o.cterms, coefl[l - lo], o.coef);
-      append(o.stiles, o.sterms, schurl[l - lo], o.schur);
+      append_tiles(o.ctiles, append_terms(o.cterms), coefl[l - lo], o.coef);
+      const int32_t sb = append_terms(o.sterms);
+      append_tiles(o.stiles, sb, schurl[l - lo], o.schur);
+      append_tiles(o.stiles2, sb, schur2l[l - lo], o.schur2);
       flops += o.flops;
     }
     ch.upload(nt, nm, ni, s);
@@ -2382,6 +2416,13 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     if (c == 0) HIP_CHECK(hipEventRecord(e0, s));
     size_t q = 0;
     for (int l = lo; l < hi; ++l) {
+      // The Schur updates of level l into rows of level l + 1 (S1) run on the
+      // main stream; the rest (S2, rows of levels >= l + 2) on the second
+      // stream, overlapping the inverses and coefficients of the next level.
+      // Orders: S2(l) after COEF(l); INV(l) after S2(l - 2) (the last update
+      // of its rows from the second stream); S1(l) after S2(l - 1) (both write
+      // rows of level l + 1).
+      if (l >= 2) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (l - 2) + 1], 0));
       for (; q < invl.size() && invl[q].level == l; ++q) {
         const InvLaunch &li = invl[q];
         const unsigned nb = (unsigned)li.count;
@@ -2397,12 +2438,29 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         HIP_CHECK(hipGetLastError());
         I.prof_end(pr);
       }
-      const GemmLaunch &cl = coefl[l - lo], &sl = schurl[l - lo];
+      const GemmLaunch &cl = coefl[l - lo], &sl = schurl[l - lo], &sl2 = schur2l[l - lo];
       I.launch_tiles(ch.d_tiles.p + cl.t0, ch.d_terms.p, cl.n, 0, I.F.p, Wd, I.F.p, 1, cl.flops, cl.bytes);
+      HIP_CHECK(hipEventRecord(I.lev_ev[2 * l], s));
+      if (l >= 1) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (l - 1) + 1], 0));
       I.launch_tiles(ch.d_tiles.p + sl.t0, ch.d_terms.p, sl.n, 1, Wd, I.F.p, Wd, std::min(sl.sub, SUB_Y), sl.flops,
                      sl.bytes);
+      HIP_CHECK(hipStreamWaitEvent(I.s2, I.lev_ev[2 * l], 0));
+      {
+        const hipStream_t main_s = I.s;
+        I.s = I.s2;                      // launch_tiles and its timing events use I.s
+        try {
+          I.launch_tiles(ch.d_tiles.p + sl2.t0, ch.d_terms.p, sl2.n, 1, Wd, I.F.p, Wd, std::min(sl2.sub, SUB_Y),
+                         sl2.flops, sl2.bytes);
+        } catch (...) {
+          I.s = main_s;
+          throw;
+        }
+        I.s = main_s;
+      }
+      HIP_CHECK(hipEventRecord(I.lev_ev[2 * l + 1], I.s2));
     }
   }
+  if (L > 0) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (L - 1) + 1], 0));   // join the second stream
   sched_split[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
   sched_split[1] = wait_ms;
   sched_split[2] = stage_ms;
