@@ -154,6 +154,16 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None,
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     stats = hps.hps_stats(ctx)
+    # the same steps without per-launch events (solves replayed from their
+    # captured graph, the production mode); reported beside the timed value
+    hps.hps_profile(ctx, False)
+    step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    total_unprofiled = time.perf_counter() - t1
     hps.hps_destroy(ctx)
     err = None
     if reference_terms:
@@ -177,7 +187,8 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None,
                "adaptive to %g (%s terms)" % (reference_tol, used),
                "current_rel_err_max": float(np.max(np.linalg.norm(Xm - Xr, axis=1) / np.linalg.norm(Xr, axis=1))),
                "rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs / rcs_r))))}
-    return dict(N=N, R=R, total=total, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
+    return dict(N=N, R=R, total=total, total_unprofiled=total_unprofiled, setup=np.array(setup_t),
+                solve=np.array(solve_t), rcs=rcs,
                 ratio=ratio, stats=stats, err=err)
 
 
@@ -420,6 +431,10 @@ def main():
                    "aca_tol": w["aca_tol"], "freq_hz": w["freq_hz"], "form": "plain fp64", "terms": 2},
         "setup_s": float(np.median(g["setup"])),
         "solve_rhs_per_s": float(R / np.median(g["solve"])),
+        "unprofiled": {"ms_per_step": 1e3 * g["total_unprofiled"] / K,
+                       "rhs_per_s": R * K / g["total_unprofiled"],
+                       "note": "the same K steps after the timed ones, without the per-launch HIP events "
+                               "(solves replayed from their captured graph)"},
         "hmatrix_build_s": build_s,
         "ratio_max": float(np.max(g["ratio"])),
         "roofline": roofline,
