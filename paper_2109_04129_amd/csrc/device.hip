@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
 }
 
 // ------------------------------------------------------------------ precision form
-// Complex FP32 products on V_MFMA_F32_16X16X4_F32 (4M split, FP32
+// Complex FP32 products on V_MFMA_F32_16X16X4_F32 (3M split as k_gemm, FP32
 // accumulation).  Same tile/term scheme and k permutation as k_gemm; the
 // result register r of lane l is D[4 (l / 16) + r][l % 16] for this
 // instruction.  AT selects the A operand: 0 complex FP32, 1 BF16 pairs,
@@ -250,9 +250,9 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       }
     }
   }
-  f4 rr[NB], ii[NB], ri[NB], ir[NB];
+  f4 rr[NB], ii[NB], ss[NB];          // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
-  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ri[j] = ir[j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ss[j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int q = t.t_begin; q < t.t_end; ++q) {
     const Term tm = terms[q];
     const float sc = (AT != 0 && tm.sidx >= 0) ? scales[tm.sidx] : 1.0f;
@@ -277,14 +277,15 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
         }
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s) {
+        const float as = av[s].x + av[s].y;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
           ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
-          ri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[j][s].y, ri[j], 0, 0, 0);
-          ir[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[j][s].x, ir[j], 0, 0, 0);
+          ss[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bv[j][s].x + bv[j][s].y, ss[j], 0, 0, 0);
         }
+      }
     }
     for (int kt = kfull; kt < tm.k; kt += 4) {
       const int k = kt + lg;
@@ -303,8 +304,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
         if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
         rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, rr[j], 0, 0, 0);
         ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, ii[j], 0, 0, 0);
-        ri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, ri[j], 0, 0, 0);
-        ir[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.x, ir[j], 0, 0, 0);
+        ss[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bv.x + bv.y, ss[j], 0, 0, 0);
       }
     }
   }
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
     for (int r = 0; r < 4; ++r) {
       const int crow = row0 + 4 * lg + r;
       if (crow >= t.m) continue;
-      const float2 acc = make_float2(rr[j][r] - ii[j][r], ri[j][r] + ir[j][r]);
+      const float2 acc = make_float2(rr[j][r] - ii[j][r], ss[j][r] - rr[j][r] - ii[j][r]);
       float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
       if (MODE == 0) {
         *p = acc;

@@ -222,3 +222,34 @@ def test_cfie_converged_series_matches_mie():
           flush=True)
     assert ratio[0] < 0.5
     assert abs(db) < 0.3
+
+
+def test_cfie_groups_above_128():
+    """CFIE with leaves of up to 300 unknowns: the library cuts groups above
+    128 into consecutive pivots, every sub-block of a cut diagonal block kept
+    (non-symmetric); currents and RCS do not depend on that blocking."""
+    xyz, tri = icosphere(3, 1.0)
+    xyz, tri = ellipsoid_mesh(xyz, tri, (1.3, 0.9, 0.6))
+    H = build_hmatrix(xyz, tri, FREQ, 300, 1e-3, workers=8, formulation="cfie", alpha=ALPHA)
+    sizes = H.groups[:, 1] - H.groups[:, 0]
+    print("case: CFIE ellipsoid 1,920 unknowns, leaves <= 300 (max %d)" % sizes.max(), flush=True)
+    assert sizes.max() > 128
+    khat, pol = _angles()
+    ctx = _ctx()
+    try:
+        hps.hps_set_mesh(ctx, xyz, tri)
+        a = hmatrix_arrays(H)
+        hps.hps_set_hmatrix(ctx, _params(leaf_max=300), a["N"], a["perm"], a["group_ptr"], a["near_ts"],
+                            a["near_off"], a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(ctx)
+        assert hps.hps_stats(ctx)["device"]["groups"] > H.M
+        st, X, rcs, ratio = _solve(ctx, H.N, khat, pol)
+    finally:
+        hps.hps_destroy(ctx)
+    b = excitation_cfie(H.rwg, FREQ, khat, pol, ALPHA)
+    x, _ = PowerSeries(H, schur_scaling(H, min_degree_order(group_graph(H)))).solve_rwg(b, 2)
+    sig = monostatic_rcs(H.rwg, FREQ, khat, pol, x)
+    err = per_rhs_rel(X, x).max()
+    print("current err %.2e" % err, flush=True)
+    assert err < 1e-10
+    assert np.abs(10 * np.log10(rcs / sig)).max() < 1e-6
