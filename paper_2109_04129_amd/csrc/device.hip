@@ -1355,6 +1355,14 @@ struct DevArray {
     p = nullptr;
     n = 0;
   }
+  DevArray() = default;
+  DevArray(const DevArray &) = delete;            // owns its allocation
+  DevArray &operator=(const DevArray &) = delete;
+  DevArray(DevArray &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevArray &operator=(DevArray &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
   ~DevArray() { release(); }
 };
 
@@ -1638,14 +1646,15 @@ struct DeviceState::Impl {
     ev_free.pop_back();
     return e;
   }
-  ProfRec *prof_begin(int kind, double flops, double bytes = 0.0, int64_t units = 0) {
-    if (!prof) return nullptr;
+  // index of the new record (events on the current stream), -1 when off
+  int64_t prof_begin(int kind, double flops, double bytes = 0.0, int64_t units = 0) {
+    if (!prof) return -1;
     prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes, units});
     HIP_CHECK(hipEventRecord(prof_recs.back().a, s));
-    return &prof_recs.back();
+    return (int64_t)prof_recs.size() - 1;
   }
-  void prof_end(ProfRec *r) {
-    if (r) HIP_CHECK(hipEventRecord(r->b, s));
+  void prof_end(int64_t r) {
+    if (r >= 0) HIP_CHECK(hipEventRecord(prof_recs[(size_t)r].b, s));
   }
   void prof_collect() {     // after a stream synchronisation
     for (ProfRec &r : prof_recs) {
@@ -1666,7 +1675,7 @@ struct DeviceState::Impl {
                     c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false, int ncols = 0) {
     if (n_tiles == 0) return;
     dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
-    ProfRec *pr = prof_begin(mode, flops, bytes, n_tiles);
+    const int64_t pr = prof_begin(mode, flops, bytes, n_tiles);
     if (wide) {
       if (mode == 0)
         hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
@@ -1728,7 +1737,7 @@ struct DeviceState::Impl {
   void g32(const Tile *tiles, const Term *terms, int64_t n, int at, const void *A, const float2 *B, float2 *C,
            double flops, double bytes) {
     if (n == 0) return;
-    ProfRec *pr = prof_begin(MODE, flops, bytes, n);
+    const int64_t pr = prof_begin(MODE, flops, bytes, n);
     dim3 g((unsigned)n, (unsigned)cdiv(cur_R, TN_SOLVE)), blk(256);
     const int nc = (int)cur_R;
     if (at == 0)
@@ -2428,7 +2437,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         const unsigned nb = (unsigned)li.count;
         const int64_t *po = ch.d_inv_off.p + li.start;
         const int32_t *pn = ch.d_inv_n.p + li.start, *pi = ch.d_inv_id.p + li.start;
-        Impl::ProfRec *pr = I.prof_begin(3, li.flops, 0.0, li.count);
+        const int64_t pr = I.prof_begin(3, li.flops, 0.0, li.count);
         if (li.nc == 32)
           hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
         else if (li.nc == 64)
