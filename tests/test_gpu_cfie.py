@@ -10,6 +10,8 @@ coefficients, eq. 18) against the oracle, through the C ABI.
   against the host-built one;
 * the precision form against the FP64 four-term series (1e-3);
 * a batch of two CFIE problems against single contexts (bitwise);
+* random right-hand sides against the oracle, graph replays against eager
+  launches (bitwise);
 * the converged series (adaptive, many terms) against the Mie series on a
   sphere: the CFIE's series contracts where the EFIE's does not.
 """
@@ -253,3 +255,40 @@ def test_cfie_groups_above_128():
     print("current err %.2e" % err, flush=True)
     assert err < 1e-10
     assert np.abs(10 * np.log10(rcs / sig)).max() < 1e-6
+
+
+def test_cfie_arbitrary_rhs_and_graph_replay(oracle_cfie):
+    """hps_solve_rhs on random right-hand sides against the oracle series
+    (left and right coefficients), and repeated graph replays of that solve
+    against eager launches, bit for bit."""
+    xyz, tri, H = oracle_cfie
+    R = 19
+    print("case: CFIE arbitrary RHS (R=19), graph replays vs eager", flush=True)
+    g = torch.Generator().manual_seed(11)
+    Bh = torch.complex(torch.randn(R, H.N, generator=g, dtype=torch.float64),
+                       torch.randn(R, H.N, generator=g, dtype=torch.float64))
+    a = hmatrix_arrays(H)
+    outs = {}
+    for graphs in (0, 1):
+        ctx = _ctx()
+        try:
+            hps.hps_set_mesh(ctx, xyz, tri)
+            hps.hps_set_hmatrix(ctx, _params(graphs=graphs), a["N"], a["perm"], a["group_ptr"], a["near_ts"],
+                                a["near_off"], a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"],
+                                a["far_uv"])
+            hps.hps_setup(ctx)
+            B = Bh.cuda()
+            outs[graphs] = []
+            for _ in range(3):
+                X = torch.zeros_like(B)
+                hps.hps_solve_rhs(ctx, R, B.data_ptr(), X.data_ptr())
+                torch.cuda.synchronize()
+                outs[graphs].append(X.cpu().numpy().T.copy())
+        finally:
+            hps.hps_destroy(ctx)
+    for o in outs[0][1:] + outs[1]:
+        assert np.array_equal(o, outs[0][0])
+    x, _ = PowerSeries(H, schur_scaling(H, min_degree_order(group_graph(H)))).solve_rwg(Bh.numpy().T, 2)
+    err = per_rhs_rel(outs[1][0], x).max()
+    print("current err %.2e" % err, flush=True)
+    assert err < 1e-10
