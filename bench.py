@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 # dominant kernel: the grouped complex GEMM in subtract mode (Schur updates of
-# the setup, forward and back sweeps of the solve), FP64 MFMA 16x16x4 (4M)
+# the setup, forward and back sweeps of the solve), FP64 MFMA 16x16x4 (3M split)
 DOMINANT = "gemm_sub"
 
 
@@ -364,15 +364,26 @@ def main():
     mixed = None
     if not args.no_mixed:
         forms = {}
+
+        def form(gm, **more):
+            return dict({"rhs_per_s_step": gm["R"] * args.steps / gm["total"],
+                         "rhs_per_s_step_unprofiled": gm["R"] * args.steps / gm["total_unprofiled"],
+                         "setup_s": float(np.median(gm["setup"])),
+                         "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
+                         "speedup_solve_vs_plain_fp64": float(np.median(g["solve"]) / np.median(gm["solve"])),
+                         "speedup_step_unprofiled_vs_plain_fp64": float(g["total_unprofiled"] /
+                                                                        gm["total_unprofiled"]),
+                         "accuracy_vs_fp64": gm["err"]}, **more)
+
         for prec, name in ((1, "bf16_far"), (2, "fp16_far")):
-            gm = gpu_leg(args, w, hm, precision=prec, refine=1, reference_terms=4)
-            forms[name] = {"rhs_per_s_step": gm["R"] * args.steps / gm["total"],
-                           "setup_s": float(np.median(gm["setup"])),
-                           "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
-                           "speedup_solve_vs_plain_fp64": float(np.median(g["solve"]) / np.median(gm["solve"])),
-                           "accuracy_vs_fp64": gm["err"]}
+            forms[name] = form(gpu_leg(args, w, hm, precision=prec, refine=1, reference_terms=4), residual_passes=1)
+        # the same FP32 / FP16 operands without the residual pass: the
+        # two-term series itself, against the FP64 two-term series
+        forms["fp16_far_two_terms"] = form(gpu_leg(args, w, hm, precision=2, refine=0, reference_terms=2),
+                                           residual_passes=0)
         mixed = {"form": "FP32 near operands on MFMA, 16-bit far factors with per-block FP32 scale, "
-                         "FP64 setup, one FP32 residual pass (= four-term series)", "variants": forms}
+                         "FP64 setup; bf16_far / fp16_far add one FP32 residual pass (= four-term series)",
+                 "variants": forms}
     cfie = None
     if not args.no_cfie and not w.get("open"):
         # CFIE of eq. (8), alpha = 0.5, on the same mesh: its own H-matrix
@@ -405,15 +416,27 @@ def main():
     dev = dict(g["stats"].get("device", {}))
     dev.pop("launch_log", None)
     k = dev.get("kernels", {}).get(DOMINANT, {})
-    achieved = k["flops"] / (k["ms"] * 1e-3) if k.get("ms") else None
-    roofline = {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": "mfma",
-                "achieved": achieved / 1e12 if achieved else None, "peak": PEAK["fp64"] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"] if achieved else None,
-                "traffic": counted_traffic(args.workload),
-                "algorithmic_bytes_per_launch": k["bytes"] / k["launches"] if k.get("launches") else None,
-                "launches_per_step": k.get("launches", 0) / K,
-                "avg_launch_us": 1e3 * k["ms"] / k["launches"] if k.get("launches") else None,
-                "flops_per_launch": k["flops"] / k["launches"] if k.get("launches") else None}
+    roofline = None
+    if k.get("ms") and k.get("bytes"):
+        sec = k["ms"] * 1e-3
+        flop_rate, byte_rate = k["flops"] / sec, k["bytes"] / sec
+        # roofline of the kernel: its algorithmic intensity (flops per
+        # algorithmic byte) against the ridge point of FP64 MFMA over HBM
+        intensity = k["flops"] / k["bytes"]
+        ridge = PEAK["fp64"] / PEAK["hbm"]
+        if intensity < ridge:
+            bound, achieved, peak, unit = "hbm", byte_rate / 1e9, PEAK["hbm"] / 1e9, "GB/s"
+        else:
+            bound, achieved, peak, unit = "mfma", flop_rate / 1e12, PEAK["fp64"] / 1e12, "TFLOP/s"
+        roofline = {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": bound,
+                    "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                    "traffic": counted_traffic(args.workload),
+                    "algorithmic_bytes_per_launch": k["bytes"] / k["launches"],
+                    "flops_per_launch": k["flops"] / k["launches"],
+                    "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                    "attainable_tflops": min(PEAK["fp64"], intensity * PEAK["hbm"]) / 1e12,
+                    "achieved_tflops": flop_rate / 1e12, "frac_of_fp64_mfma_peak": flop_rate / PEAK["fp64"],
+                    "launches_per_step": k["launches"] / K, "avg_launch_us": 1e3 * k["ms"] / k["launches"]}
     out = {
         "metric": "RHS solved/sec + setup s at <=1e-3 rel err vs FP64; mixed/batched vs plain FP64",
         "value": R * K / g["total"],
