@@ -190,6 +190,36 @@ hps_status hps_get_hmatrix(const hps_ctx *ctx, int64_t *perm, int64_t *group_ptr
                            int64_t *near_off, double *near_vals, int64_t *far_rng,
                            int32_t *far_rank, int64_t *far_off, double *far_uv);
 
+/* The RWG functions of the current mesh (Sec. II: one unknown per interior
+   edge, with the two triangles sharing it), in RWG order, i.e. the order of
+   the unknowns in X, B and the currents: edges sorted by (smaller vertex id,
+   larger vertex id).  Host arrays of N x 2 int32 (N from hps_num_unknowns),
+   caller-owned, any of them NULL if not wanted:
+     edge_v[2n], edge_v[2n+1]  the edge's vertex ids, smaller first;
+     tri_pm[2n], tri_pm[2n+1]  T+ (the triangle that runs along the edge from
+                              the smaller to the larger vertex id) and T-;
+     free_v[2n], free_v[2n+1]  the vertex of T+ and of T- opposite the edge.
+   Batch contexts: the problems' functions in problem order, with vertex and
+   triangle ids counted in the concatenation of the meshes.
+   HPS_ESTATE before a mesh is set. */
+hps_status hps_rwg(const hps_ctx *ctx, int32_t *edge_v, int32_t *tri_pm, int32_t *free_v);
+
+/* Write the installed H-matrix and its parameters to a file, and read one
+   back in place of hps_build_hmatrix / hps_set_hmatrix (same structure as
+   hps_get_hmatrix).  Layout, little-endian: the 8 bytes "HPSHMAT1"; int64
+   header N, M, n_near, near_elems, n_far, far_elems, nonsym (0/1),
+   sizeof(hps_params); the hps_params struct as stored; then perm (N int64),
+   group_ptr (M+1 int64), near_ts (2 n_near int32), near_off (n_near+1
+   int64), near_vals (near_elems c128), far_rng (4 n_far int64), far_rank
+   (n_far int32), far_off (n_far+1 int64), far_uv (far_elems c128).
+   Single-problem contexts only (HPS_EINVAL for a batch).  Export: HPS_ESTATE
+   without an H-matrix, HPS_EIO if the file cannot be written.  Import: needs
+   the same mesh set first (N must match, else HPS_EINVAL); HPS_EIO for a
+   missing, truncated or foreign file; the arrays are checked as in
+   hps_set_hmatrix; a file or format error leaves the context as it was. */
+hps_status hps_export_hmatrix(const hps_ctx *ctx, const char *path);
+hps_status hps_import_hmatrix(hps_ctx *ctx, const char *path);
+
 /* Setup ("setup time", Sec. III.A and IV.A): host symbolic phase (fill-reducing
    nested-dissection order of the groups, fill-in pattern, elimination-tree
    levels), then on the device, level by level: LU with partial pivoting and

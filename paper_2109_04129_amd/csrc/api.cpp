@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -463,6 +464,145 @@ hps_status hps_get_hmatrix(const hps_ctx *c, int64_t *perm, int64_t *group_ptr, 
   if (far_off) std::memcpy(far_off, H.far_off.data(), H.far_off.size() * 8);
   if (far_uv) std::memcpy(far_uv, H.far_uv.data(), H.far_uv.size() * 16);
   return HPS_OK;
+}
+
+hps_status hps_rwg(const hps_ctx *c, int32_t *edge_v, int32_t *tri_pm, int32_t *free_v) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_mesh) return HPS_ESTATE;
+  std::vector<const hps::Mesh *> ms;
+  if (c->n_prob)
+    for (const hps::Mesh &m : c->pmesh) ms.push_back(&m);
+  else
+    ms.push_back(&c->mesh);
+  int64_t o = 0, voff = 0, toff = 0;
+  for (const hps::Mesh *m : ms) {
+    for (int64_t n = 0; n < m->N; ++n, ++o) {
+      if (edge_v) {
+        edge_v[2 * o] = (int32_t)(m->edge[2 * n] + voff);
+        edge_v[2 * o + 1] = (int32_t)(m->edge[2 * n + 1] + voff);
+      }
+      if (tri_pm) {
+        tri_pm[2 * o] = (int32_t)(m->tp[n] + toff);
+        tri_pm[2 * o + 1] = (int32_t)(m->tm[n] + toff);
+      }
+      if (free_v) {
+        free_v[2 * o] = (int32_t)(m->vp[n] + voff);
+        free_v[2 * o + 1] = (int32_t)(m->vm[n] + voff);
+      }
+    }
+    voff += m->nv;
+    toff += m->nt;
+  }
+  return HPS_OK;
+}
+
+namespace {
+
+const char kHmatMagic[8] = {'H', 'P', 'S', 'H', 'M', 'A', 'T', '1'};
+
+struct File {
+  std::FILE *f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+
+}  // namespace
+
+hps_status hps_export_hmatrix(const hps_ctx *cc, const char *path) {
+  if (!cc) return HPS_EINVAL;
+  hps_ctx *c = const_cast<hps_ctx *>(cc);     // only the error text is written
+  if (!path) return fail(c, HPS_EINVAL, "path is NULL");
+  if (c->n_prob) return fail(c, HPS_EINVAL, "batch context: export the problems one by one");
+  if (!c->have_h) return fail(c, HPS_ESTATE, "no H-matrix installed");
+  return guarded(c, [&]() {
+    const hps::HMatrix &H = c->H;
+    const std::string name(path);
+    File out;
+    out.f = std::fopen(name.c_str(), "wb");
+    if (!out.f) throw hps::Error{HPS_EIO, "cannot open " + name + " for writing"};
+    bool ok = std::fwrite(kHmatMagic, 1, 8, out.f) == 8;
+    const int64_t hdr[8] = {H.N, H.M, H.n_near(), (int64_t)H.near_vals.size(), H.n_far(),
+                            (int64_t)H.far_uv.size(), H.nonsym ? 1 : 0, (int64_t)sizeof(hps_params)};
+    ok = ok && std::fwrite(hdr, 8, 8, out.f) == 8;
+    ok = ok && std::fwrite(&c->params, sizeof(hps_params), 1, out.f) == 1;
+    auto put = [&](const void *p, size_t bytes) {
+      ok = ok && (bytes == 0 || std::fwrite(p, 1, bytes, out.f) == bytes);
+    };
+    put(H.perm.data(), H.perm.size() * 8);
+    put(H.gptr.data(), H.gptr.size() * 8);
+    put(H.near_ts.data(), H.near_ts.size() * 4);
+    put(H.near_off.data(), H.near_off.size() * 8);
+    put(H.near_vals.data(), H.near_vals.size() * 16);
+    put(H.far_rng.data(), H.far_rng.size() * 8);
+    put(H.far_rank.data(), H.far_rank.size() * 4);
+    put(H.far_off.data(), H.far_off.size() * 8);
+    put(H.far_uv.data(), H.far_uv.size() * 16);
+    ok = ok && std::fflush(out.f) == 0;
+    const int rc = std::fclose(out.f);
+    out.f = nullptr;
+    if (!ok || rc != 0) throw hps::Error{HPS_EIO, "write to " + name + " failed"};
+    return HPS_OK;
+  });
+}
+
+hps_status hps_import_hmatrix(hps_ctx *c, const char *path) {
+  if (!c) return HPS_EINVAL;
+  if (!path) return fail(c, HPS_EINVAL, "path is NULL");
+  if (c->n_prob) return fail(c, HPS_EINVAL, "batch context: use hps_batch_set_hmatrix");
+  if (!c->have_mesh) return fail(c, HPS_ESTATE, "hps_set_mesh first");
+  hps_params prm{};
+  std::vector<int64_t> perm, gptr, near_off, far_rng, far_off;
+  std::vector<int32_t> near_ts, far_rank;
+  std::vector<double> near_vals, far_uv;
+  int64_t hdr[8] = {0};
+  {
+    File in;
+    in.f = std::fopen(path, "rb");
+    if (!in.f) return fail(c, HPS_EIO, std::string("cannot open ") + path);
+    char magic[8];
+    if (std::fread(magic, 1, 8, in.f) != 8 || std::memcmp(magic, kHmatMagic, 8) != 0)
+      return fail(c, HPS_EIO, std::string(path) + " is not an H-matrix file");
+    if (std::fread(hdr, 8, 8, in.f) != 8) return fail(c, HPS_EIO, std::string(path) + ": truncated header");
+    const int64_t N = hdr[0], M = hdr[1], nn = hdr[2], ne = hdr[3], nf = hdr[4], fe = hdr[5];
+    if (hdr[7] != (int64_t)sizeof(hps_params))
+      return fail(c, HPS_EIO, std::string(path) + ": written with another hps_params layout");
+    if (N != c->mesh.N) return fail(c, HPS_EINVAL, "N of the file does not match the mesh");
+    if (M < 1 || M > N || nn < 1 || ne < 1 || nf < 0 || fe < 0 || (hdr[6] != 0 && hdr[6] != 1))
+      return fail(c, HPS_EIO, std::string(path) + ": bad header");
+    // sizes against the file length before allocating
+    const long here = std::ftell(in.f);
+    if (here < 0 || std::fseek(in.f, 0, SEEK_END) != 0) return fail(c, HPS_EIO, "cannot seek in " + std::string(path));
+    const long end = std::ftell(in.f);
+    if (std::fseek(in.f, here, SEEK_SET) != 0) return fail(c, HPS_EIO, "cannot seek in " + std::string(path));
+    const double need = (double)sizeof(hps_params) + 8.0 * (N + M + 1 + nn + 1 + 4 * nf + nf + 1) + 4.0 * (2 * nn + nf) +
+                        16.0 * ((double)ne + (double)fe);
+    if ((double)(end - here) != need) return fail(c, HPS_EIO, std::string(path) + ": truncated or oversized");
+    bool ok = std::fread(&prm, sizeof(hps_params), 1, in.f) == 1;
+    hps_status st = guarded(c, [&]() {
+      perm.resize(N); gptr.resize(M + 1); near_ts.resize(2 * nn); near_off.resize(nn + 1);
+      near_vals.resize(2 * ne); far_rng.resize(4 * nf); far_rank.resize(nf); far_off.resize(nf + 1);
+      far_uv.resize(2 * fe);
+      return HPS_OK;
+    });
+    if (st != HPS_OK) return st;
+    auto get = [&](void *p, size_t bytes) { ok = ok && (bytes == 0 || std::fread(p, 1, bytes, in.f) == bytes); };
+    get(perm.data(), perm.size() * 8);
+    get(gptr.data(), gptr.size() * 8);
+    get(near_ts.data(), near_ts.size() * 4);
+    get(near_off.data(), near_off.size() * 8);
+    get(near_vals.data(), near_vals.size() * 8);
+    get(far_rng.data(), far_rng.size() * 8);
+    get(far_rank.data(), far_rank.size() * 4);
+    get(far_off.data(), far_off.size() * 8);
+    get(far_uv.data(), far_uv.size() * 8);
+    if (!ok) return fail(c, HPS_EIO, std::string(path) + ": read failed");
+  }
+  if ((prm.formulation == 1) != (hdr[6] == 1)) return fail(c, HPS_EIO, std::string(path) + ": inconsistent symmetry flag");
+  // offsets of the file must stay inside the arrays read
+  if (near_off.back() != hdr[3] || far_off.back() != hdr[5]) return fail(c, HPS_EIO, std::string(path) + ": offsets do not match the sizes");
+  return hps_set_hmatrix(c, &prm, hdr[0], perm.data(), hdr[1], gptr.data(), hdr[2], near_ts.data(), near_off.data(),
+                         near_vals.data(), hdr[4], far_rng.data(), far_rank.data(), far_off.data(), far_uv.data());
 }
 
 hps_status hps_setup(hps_ctx *c) {

@@ -22,7 +22,7 @@ EXPORTS = ["hps_params_default", "hps_create", "hps_destroy", "hps_last_error", 
            "hps_get_hmatrix", "hps_setup", "hps_solve_planewaves", "hps_solve_rhs",
            "hps_excitation", "hps_hmatvec", "hps_profile", "hps_stats", "hps_batch_create",
            "hps_batch_set_mesh", "hps_batch_set_hmatrix", "hps_num_problems", "hps_problem_unknowns",
-           "hps_set_open_mesh"]
+           "hps_set_open_mesh", "hps_rwg", "hps_export_hmatrix", "hps_import_hmatrix"]
 
 
 class HpsError(RuntimeError):
@@ -89,6 +89,9 @@ def lib():
                                             i64, vp, vp, vp, vp]
         L.hps_num_problems.argtypes = [ctx, P(i32)]
         L.hps_problem_unknowns.argtypes = [ctx, i32, P(i64)]
+        L.hps_rwg.argtypes = [ctx, vp, vp, vp]
+        L.hps_export_hmatrix.argtypes = [ctx, ctypes.c_char_p]
+        L.hps_import_hmatrix.argtypes = [ctx, ctypes.c_char_p]
         for name in EXPORTS:
             if name not in ("hps_destroy", "hps_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -227,6 +230,22 @@ def hps_get_hmatrix(ctx):
     _check(ctx, lib().hps_get_hmatrix(ctx, *[_ptr(out[k]) for k in (
         "perm", "group_ptr", "near_ts", "near_off", "near_vals", "far_rng", "far_rank", "far_off", "far_uv")]))
     return out
+
+
+def hps_rwg(ctx):
+    """(edge_v, tri_pm, free_v), each N x 2 int32, RWG order."""
+    N = hps_num_unknowns(ctx)
+    out = [np.empty((N, 2), np.int32) for _ in range(3)]
+    _check(ctx, lib().hps_rwg(ctx, *[_ptr(a) for a in out]))
+    return tuple(out)
+
+
+def hps_export_hmatrix(ctx, path):
+    return _check(ctx, lib().hps_export_hmatrix(ctx, os.fsencode(path)))
+
+
+def hps_import_hmatrix(ctx, path):
+    return _check(ctx, lib().hps_import_hmatrix(ctx, os.fsencode(path)))
 
 
 def hps_setup(ctx):

@@ -330,3 +330,102 @@ def test_cfie_host_build_matches_oracle_entries():
         num += np.linalg.norm(U @ V.T - ref) ** 2
         den += np.linalg.norm(ref) ** 2
     assert math.sqrt(num / den) < 2e-3
+
+
+# ---------------------------------------------------------------- RWG table and H-matrix files
+def test_rwg_table_matches_oracle():
+    """hps_rwg: the library's RWG functions (edge vertices, T+ / T-, free
+    vertices) equal the oracle's, for a closed sphere, an open plate and a
+    batch of two meshes (ids counted in the concatenated meshes)."""
+    from oracle.rwg import build_rwg
+    from workloads import workload
+    xyz, tri = icosphere(2)
+    w = workload("plate_2lambda_300MHz")
+    cases = [(xyz, tri, False), (w["xyz"], w["tri"], True)]
+    for x, t, open_ in cases:
+        o = build_rwg(x, t, allow_open=open_)
+        ctx = hps.hps_create(-1)
+        try:
+            with pytest.raises(hps.HpsError) as e:
+                hps.hps_rwg(ctx)
+            assert e.value.status == -5                 # ESTATE: no mesh yet
+            (hps.hps_set_open_mesh if open_ else hps.hps_set_mesh)(ctx, x, t)
+            ev, tpm, fv = hps.hps_rwg(ctx)
+        finally:
+            hps.hps_destroy(ctx)
+        assert np.array_equal(ev, o["edges"])
+        assert np.array_equal(tpm, np.stack([o["tplus"], o["tminus"]], 1))
+        assert np.array_equal(fv, np.stack([o["vplus"], o["vminus"]], 1))
+    x2, t2 = icosphere(1, 0.5)
+    b = hps.hps_batch_create(2, -1)
+    try:
+        hps.hps_batch_set_mesh(b, 0, xyz, tri)
+        hps.hps_batch_set_mesh(b, 1, x2, t2)
+        ev, tpm, fv = hps.hps_rwg(b)
+    finally:
+        hps.hps_destroy(b)
+    o0, o1 = build_rwg(xyz, tri), build_rwg(x2, t2)
+    assert np.array_equal(ev, np.r_[o0["edges"], o1["edges"] + len(xyz)])
+    assert np.array_equal(tpm[:, 0], np.r_[o0["tplus"], o1["tplus"] + len(tri)])
+    assert np.array_equal(fv[:, 1], np.r_[o0["vminus"], o1["vminus"] + len(xyz)])
+
+
+@pytest.mark.parametrize("formulation", [0, 1])
+def test_hmatrix_file_round_trip(tmp_path, formulation):
+    """hps_export_hmatrix / hps_import_hmatrix: the imported H-matrix equals
+    the exported one bit for bit (EFIE and CFIE layouts); missing, foreign
+    and truncated files give HPS_EIO, a file for another mesh HPS_EINVAL, and
+    a failed import leaves the installed H-matrix in place."""
+    xyz, tri = icosphere(2)
+    p = hps.hps_params_default(freq_hz=300e6, leaf_max=16, formulation=formulation, cfie_alpha=0.3)
+    path = str(tmp_path / "h.bin")
+    a = hps.hps_create(-1)
+    try:
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_export_hmatrix(a, path)
+        assert e.value.status == -5                     # nothing to export yet
+        hps.hps_set_mesh(a, xyz, tri)
+        hps.hps_build_hmatrix(a, p)
+        hps.hps_export_hmatrix(a, path)
+        ref = hps.hps_get_hmatrix(a)
+    finally:
+        hps.hps_destroy(a)
+    b = hps.hps_create(-1)
+    try:
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_import_hmatrix(b, path)
+        assert e.value.status == -5                     # mesh first
+        hps.hps_set_mesh(b, xyz, tri)
+        hps.hps_import_hmatrix(b, path)
+        got = hps.hps_get_hmatrix(b)
+        for k in ref:
+            assert ref[k].dtype == got[k].dtype and np.array_equal(ref[k], got[k]), k
+        data = open(path, "rb").read()
+        bad = [(str(tmp_path / "missing.bin"), None), (str(tmp_path / "foreign.bin"), b"NOTHMAT1" + data[8:]),
+               (str(tmp_path / "short.bin"), data[:-16]), (str(tmp_path / "long.bin"), data + b"\0" * 8)]
+        for name, content in bad:
+            if content is not None:
+                open(name, "wb").write(content)
+            with pytest.raises(hps.HpsError) as e:
+                hps.hps_import_hmatrix(b, name)
+            assert e.value.status == -6, name
+        assert np.array_equal(hps.hps_get_hmatrix(b)["near_vals"], ref["near_vals"])
+    finally:
+        hps.hps_destroy(b)
+    c = hps.hps_create(-1)
+    try:
+        x3, t3 = icosphere(1)
+        hps.hps_set_mesh(c, x3, t3)
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_import_hmatrix(c, path)
+        assert e.value.status == -1                     # another mesh
+    finally:
+        hps.hps_destroy(c)
+    bt = hps.hps_batch_create(1, -1)
+    try:
+        hps.hps_batch_set_mesh(bt, 0, xyz, tri)
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_import_hmatrix(bt, path)
+        assert e.value.status == -1                     # batch context
+    finally:
+        hps.hps_destroy(bt)

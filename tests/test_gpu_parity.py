@@ -347,3 +347,31 @@ def test_device_hmatrix_build(c0_workload, c0_hmatrix, c0_dense):
     assert worst_o <= 1e-12 and worst_h <= 1e-12
     assert errs["device"] <= 2e-3 and errs["host"] <= 2e-3
     assert abs(G["far_rank"].mean() - C["far_rank"].mean()) <= 0.1 * C["far_rank"].mean()
+
+def test_exported_hmatrix_solves_identically(small, tmp_path):
+    """An H-matrix written by hps_export_hmatrix and read back by
+    hps_import_hmatrix into a fresh device context gives the same setup and
+    solve, bit for bit, as the context it came from; the library's RWG table
+    names the unknowns of the currents."""
+    xyz, tri, H = small
+    print("case: export / import of a 480-unknown H-matrix, device contexts", flush=True)
+    khat, pol = monostatic_angles([0.0, 60.0, 135.0], [0.0, 90.0, 200.0])
+    path = str(tmp_path / "small.hmat")
+    a = _ctx()
+    try:
+        _install(a, H, xyz, tri, 300e6, leaf=16)
+        hps.hps_export_hmatrix(a, path)
+        _, Xa, rcs_a, rat_a = _solve(a, H.N, khat, pol)
+        ev, _, _ = hps.hps_rwg(a)
+    finally:
+        hps.hps_destroy(a)
+    b = _ctx()
+    try:
+        hps.hps_set_mesh(b, xyz, tri)
+        hps.hps_import_hmatrix(b, path)
+        hps.hps_setup(b)
+        _, Xb, rcs_b, rat_b = _solve(b, H.N, khat, pol)
+    finally:
+        hps.hps_destroy(b)
+    assert np.array_equal(Xa, Xb) and np.array_equal(rcs_a, rcs_b) and np.array_equal(rat_a, rat_b)
+    assert np.array_equal(ev, H.rwg["edges"])
