@@ -1455,6 +1455,16 @@ struct DeviceState::Impl {
   double alpha = 1.0;              // CFIE alpha (1: EFIE right-hand side)
   HMatrix hcopy;                   // structure (values not needed after upload)
   std::vector<int64_t> far_m, far_n;
+  // Far factors on the device are grouped by the cluster they multiply in
+  // stage 1 (dir 0: V_b over the source range of block b; dir 1: U_b over
+  // its target range): the factors of one group are contiguous, each still
+  // column-major (cluster size x rank), so the group reads as one row-major
+  // (sum of ranks) x (cluster size) matrix V^T / U^T.  fu / fv: device
+  // offsets of U_b and V_b.
+  struct FarGroup { int64_t lo, hi, off, rows; int32_t m0, m1; };
+  std::vector<FarGroup> fgroups;
+  std::vector<std::pair<int32_t, int32_t>> fmembers;   // (block, dir), group by group
+  std::vector<int64_t> fu, fv;
   // plan
   bool ready = false;
   Plan P;
@@ -2016,10 +2026,56 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   I.near.alloc(H.near_vals.size());
   if (!H.near_vals.empty())
     HIP_CHECK(hipMemcpyAsync(I.near.p, H.near_vals.data(), H.near_vals.size() * sizeof(c2), hipMemcpyHostToDevice, I.s));
-  I.faruv.alloc(H.far_uv.size());
-  if (!H.far_uv.empty())
-    HIP_CHECK(hipMemcpyAsync(I.faruv.p, H.far_uv.data(), H.far_uv.size() * sizeof(c2), hipMemcpyHostToDevice, I.s));
-  HIP_CHECK(hipStreamSynchronize(I.s));
+  {
+    const int64_t nf = H.n_far();
+    const int ndir = H.nonsym ? 1 : 2;
+    std::map<std::pair<int64_t, int64_t>, std::vector<std::pair<int32_t, int32_t>>> grp;
+    for (int64_t b = 0; b < nf; ++b) {
+      if (H.far_rank[b] == 0) continue;
+      for (int dir = 0; dir < ndir; ++dir) {
+        const int64_t lo = H.far_rng[4 * b + (dir == 0 ? 2 : 0)], hi = H.far_rng[4 * b + (dir == 0 ? 3 : 1)];
+        grp[{lo, hi}].push_back({(int32_t)b, dir});
+      }
+    }
+    I.fu.assign(nf, 0);
+    I.fv.assign(nf, 0);
+    I.fgroups.clear();
+    I.fmembers.clear();
+    std::vector<char> placed_u(nf, 0), placed_v(nf, 0);
+    int64_t off = 0;
+    for (const auto &g : grp) {
+      Impl::FarGroup fg{g.first.first, g.first.second, off, 0, (int32_t)I.fmembers.size(), 0};
+      for (const auto &bd : g.second) {
+        const int64_t b = bd.first, r = H.far_rank[b];
+        const int64_t len = (g.first.second - g.first.first) * r;
+        if (bd.second == 0) { I.fv[b] = off; placed_v[b] = 1; }
+        else { I.fu[b] = off; placed_u[b] = 1; }
+        off += len;
+        fg.rows += r;
+        I.fmembers.push_back(bd);
+      }
+      fg.m1 = (int32_t)I.fmembers.size();
+      I.fgroups.push_back(fg);
+    }
+    for (int64_t b = 0; b < nf; ++b) {       // factors stage 1 does not read (U_b of a one-way field; rank 0)
+      const int64_t m = H.far_rng[4 * b + 1] - H.far_rng[4 * b], n = H.far_rng[4 * b + 3] - H.far_rng[4 * b + 2];
+      if (!placed_u[b]) { I.fu[b] = off; off += m * H.far_rank[b]; }
+      if (!placed_v[b]) { I.fv[b] = off; off += n * H.far_rank[b]; }
+    }
+    if (off != (int64_t)H.far_uv.size()) throw Error{HPS_EINVAL, "internal: far factor layout does not cover the factors"};
+    std::vector<cplx> reord(H.far_uv.size());
+    for (int64_t b = 0; b < nf; ++b) {
+      const int64_t m = H.far_rng[4 * b + 1] - H.far_rng[4 * b], n = H.far_rng[4 * b + 3] - H.far_rng[4 * b + 2];
+      const int64_t r = H.far_rank[b];
+      std::copy(H.far_uv.begin() + H.far_off[b], H.far_uv.begin() + H.far_off[b] + m * r, reord.begin() + I.fu[b]);
+      std::copy(H.far_uv.begin() + H.far_off[b] + m * r, H.far_uv.begin() + H.far_off[b] + (m + n) * r,
+                reord.begin() + I.fv[b]);
+    }
+    I.faruv.alloc(reord.size());
+    if (!reord.empty())
+      HIP_CHECK(hipMemcpyAsync(I.faruv.p, reord.data(), reord.size() * sizeof(c2), hipMemcpyHostToDevice, I.s));
+    HIP_CHECK(hipStreamSynchronize(I.s));
+  }
   // structure copy without values
   I.hcopy = HMatrix();
   I.hcopy.N = H.N; I.hcopy.M = H.M; I.hcopy.perm = H.perm; I.hcopy.gptr = H.gptr; I.hcopy.nonsym = H.nonsym;
@@ -2537,12 +2593,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     I.dinv.terms.push_back(Term{P.panel_off[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 0});
   }
   close(I.dinv);
-  // far field: stage 1 targets = (block, direction) rank x R, stage 2 = leaves
+  // far field: stage 1 targets = the rank rows of one factor group (FP64) or
+  // of one (block, direction) (precision form: one 16-bit scale per factor
+  // and term) x R; stage 2 targets = leaves
   const HMatrix &Hs = I.hcopy;
   const int64_t nf = Hs.n_far();
   I.far1 = Impl::Sched();
   I.far2 = Impl::Sched();
-  I.toff.assign(2 * nf, 0);
+  I.toff.assign(2 * nf, -1);
   int64_t trow = 0;
   auto leaves_in = [&](int64_t lo, int64_t hi, std::vector<int64_t> &out) {
     out.clear();
@@ -2554,33 +2612,46 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // T is one column-major matrix of t_rows x R: rows [toff, toff + r) hold
   // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of
   // s); a non-symmetric H-matrix stores both orders as separate blocks, each
-  // applied in dir 0 only
+  // applied in dir 0 only.  The rows of one factor group are contiguous.
   const int ndir = I.nonsym ? 1 : 2;
-  for (int64_t b = 0; b < nf; ++b)
-    for (int dir = 0; dir < 2; ++dir) {
-      I.toff[2 * b + dir] = dir < ndir ? trow : -1;
-      if (dir < ndir) trow += Hs.far_rank[b];
+  for (const Impl::FarGroup &fg : I.fgroups)
+    for (int32_t q = fg.m0; q < fg.m1; ++q) {
+      const auto bd = I.fmembers[q];
+      I.toff[2 * bd.first + bd.second] = trow;
+      trow += Hs.far_rank[bd.first];
     }
   I.t_rows = trow;
   const int32_t ldT = (int32_t)std::max<int64_t>(trow, 1);
+  for (const Impl::FarGroup &fg : I.fgroups) {
+    const int32_t clen = (int32_t)(fg.hi - fg.lo);
+    leaves_in(fg.lo, fg.hi, lv);
+    if (I.precision == 0) {
+      // one target: rows of every factor of the group, terms over the leaves
+      const auto first = I.fmembers[fg.m0];
+      add_target(I.far1, I.toff[2 * first.first + first.second], (int32_t)fg.rows, ldT);
+      for (int64_t g : lv)
+        I.far1.terms.push_back(Term{fg.off + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N,
+                                    (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1});
+      continue;
+    }
+    for (int32_t q = fg.m0; q < fg.m1; ++q) {
+      const int64_t bb = I.fmembers[q].first;
+      const int dir = I.fmembers[q].second;
+      add_target(I.far1, I.toff[2 * bb + dir], (int32_t)Hs.far_rank[bb], ldT);
+      const int64_t fo = dir == 0 ? I.fv[bb] : I.fu[bb];
+      for (int64_t g : lv) {
+        Term tmv{fo + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N, (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
+        tmv.sidx = (int32_t)(2 * bb + (dir == 0 ? 1 : 0));
+        I.far1.terms.push_back(tmv);
+      }
+    }
+  }
   for (int64_t b = 0; b < nf; ++b) {
     const int64_t tlo = Hs.far_rng[4 * b], thi = Hs.far_rng[4 * b + 1];
     const int64_t slo = Hs.far_rng[4 * b + 2], shi = Hs.far_rng[4 * b + 3];
     const int64_t m = thi - tlo, n = shi - slo, r = Hs.far_rank[b];
     if (r == 0) continue;
-    const int64_t uo = Hs.far_off[b], vo = Hs.far_off[b] + m * r;
-    for (int dir = 0; dir < ndir; ++dir) {
-      add_target(I.far1, I.toff[2 * b + dir], (int32_t)r, ldT);
-      const int64_t clo = dir == 0 ? slo : tlo, chi = dir == 0 ? shi : thi;
-      const int64_t fo = dir == 0 ? vo : uo, fld = dir == 0 ? n : m;
-      leaves_in(clo, chi, lv);
-      for (int64_t g : lv) {
-        const int64_t e = P.pos[g];
-        Term tmv{fo + (Hs.gptr[g] - clo), P.uoff[e], (int32_t)fld, (int32_t)N, (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
-        tmv.sidx = (int32_t)(2 * b + (dir == 0 ? 1 : 0));
-        I.far1.terms.push_back(tmv);
-      }
-    }
+    const int64_t uo = I.fu[b], vo = I.fv[b];
     leaves_in(tlo, thi, lv);
     for (int64_t g : lv) {
       Term tmu{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0};
@@ -2647,9 +2718,10 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     for (int64_t b = 0; b < Hf.n_far(); ++b) {
       const int64_t m = Hf.far_rng[4 * b + 1] - Hf.far_rng[4 * b], n = Hf.far_rng[4 * b + 3] - Hf.far_rng[4 * b + 2];
       const int64_t r = Hf.far_rank[b];
-      parts[2 * b] = FarPart{Hf.far_off[b], m * r};
-      parts[2 * b + 1] = FarPart{Hf.far_off[b] + m * r, n * r};
-      if (Hf.far_off[b] + (m + n) * r > (int64_t)I.faruv.n) throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
+      parts[2 * b] = FarPart{I.fu[b], m * r};
+      parts[2 * b + 1] = FarPart{I.fv[b], n * r};
+      if (I.fu[b] + m * r > (int64_t)I.faruv.n || I.fv[b] + n * r > (int64_t)I.faruv.n)
+        throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
     }
     I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
     I.fscale.alloc(std::max<size_t>(parts.size(), 1));
