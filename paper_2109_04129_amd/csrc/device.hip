@@ -75,25 +75,40 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 template <int MODE, int NB>
 __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
-                                              const Term *__restrict__ terms, int ncols) {
+                                              const Term *__restrict__ terms, int ncols, int ntiles, int ny,
+                                              int xcd_order) {
   // workgroup tile: 32 rows x (32 NB) columns; wave w owns rows 16 (w / 2)
   // and NB column blocks of 16 starting at 16 NB (w % 2)
   constexpr int TN = 32 * NB;
-  const Tile t = tiles[blockIdx.x];
+  // Workgroup -> (tile bx, part by).  Plain order: grid (ntiles, ny), tile
+  // = blockIdx.x.  XCD-aware order: a one-dimensional grid of
+  // 8 ceil(ntiles / 8) ny workgroups; consecutive workgroups go to the 8
+  // XCDs in turn, so workgroup w takes tile 8 (q / ny) + w % 8 and part
+  // q % ny, q = w / 8: the ny workgroups of one tile (the RHS column tiles
+  // of a solve, which read the same factor rows) run one after another on
+  // one XCD and share its L2.
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (xcd_order) {
+    const int q = (int)(blockIdx.x >> 3);
+    by = q % ny;
+    bx = 8 * (q / ny) + (int)(blockIdx.x & 7);
+    if (bx >= ntiles) return;
+  }
+  const Tile t = tiles[bx];
   // r0 < 0: the tile stands for the whole m x n block; workgroup y takes its
-  // sub-tiles y, y + gridDim.y, ...  c0 < 0: one row tile over ncols
-  // columns, blockIdx.y picks the column tile.  Else one explicit tile.
+  // sub-tiles y, y + ny, ...  c0 < 0: one row tile over ncols columns, y
+  // picks the column tile.  Else one explicit tile.
   int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
   if (t.r0 < 0) {
     nsc = (t.n + TN - 1) / TN;
     nsub = ((t.m + TM - 1) / TM) * nsc;
-    st0 = blockIdx.y;
-    sstep = gridDim.y;
+    st0 = by;
+    sstep = ny;
   } else if (t.c0 < 0) {
     tn = ncols;
-    cb0 = blockIdx.y * TN;
+    cb0 = by * TN;
     if (cb0 >= tn) return;
-  } else if (blockIdx.y > 0) {
+  } else if (by > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1684,22 +1699,30 @@ struct DeviceState::Impl {
   void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
                     c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false, int ncols = 0) {
     if (n_tiles == 0) return;
-    dim3 g((unsigned)n_tiles, (unsigned)sub), blk(256);
+    // The store-mode launches of a solve (far field, D^-1: long term lists
+    // over shared factor rows) take the kernel's XCD-aware order on a
+    // one-dimensional grid, where it measured faster; the sweeps and the
+    // setup keep the plain (ntiles, sub) grid
+    const int xo = (wide && mode == 0) ? 1 : 0;
+    const int64_t nwg = cdiv(n_tiles, 8) * 8 * (int64_t)sub;
+    if (n_tiles > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
+    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n_tiles, (unsigned)sub), blk(256);
+    const int nt = (int)n_tiles;
     const int64_t pr = prof_begin(mode, flops, bytes, n_tiles);
     if (wide) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
       else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
       else
-        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
     } else {
       if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
       else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
       else
-        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols);
+        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
     }
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
