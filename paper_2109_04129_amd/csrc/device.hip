@@ -488,6 +488,26 @@ __device__ __forceinline__ double group_bcast(double v, int src_lane) {
   return __shfl(v, src_lane, 64);
 }
 
+// One Gauss-Jordan update: row PR of the source lane's pair is the pivot row
+// (PR is block-uniform, so the caller branches instead of selecting per
+// element); a[r][j] -= mi[r] rp[j].
+template <int RT, int CT, int RB, int PR>
+__device__ __forceinline__ void gj_update(c2 (&a)[RT][CT], const c2 (&mi)[RT], int src_lane) {
+  c2 rp[CT];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) {
+    rp[j].x = group_bcast<RB>(a[PR][j].x, src_lane);
+    rp[j].y = group_bcast<RB>(a[PR][j].y, src_lane);
+  }
+#pragma unroll
+  for (int j = 0; j < CT; ++j)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      a[r][j].x = fma(-mi[r].x, rp[j].x, fma(mi[r].y, rp[j].y, a[r][j].x));
+      a[r][j].y = fma(-mi[r].x, rp[j].y, fma(-mi[r].y, rp[j].x, a[r][j].y));
+    }
+}
+
 template <int NC>
 __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2 *__restrict__ F,
                                                     const int64_t *__restrict__ off,
@@ -521,83 +541,79 @@ __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2
 #pragma unroll
   for (int r = 0; r < RT; ++r)
     if (rg * RT + r >= n) used |= 1u << r;
+  // A wave whose columns all lie beyond the block (n below the size class)
+  // holds zeros that every step leaves at zero: it skips the updates and
+  // only joins the barriers.  Wave-uniform.
+  const bool wave_live = wave * GW * CT < n;
   bool singular = false;
-  for (int k = 0; k < n; ++k) {
-    const int s = k & 1;
-    const int cgk = k / CT, kc = k % CT;
-    if (wave == cgk / GW) {
-      // Pivot search on column k, at raised wave priority: the other waves of
-      // this SIMD are still in the previous update.  Key = |z|^2 with its last
-      // 7 mantissa bits replaced by (127 - row): largest modulus, lowest row
-      // on ties.
-      __builtin_amdgcn_s_setprio(3);
-      const bool mine = (cg == cgk);
-      uint64_t key = 0;
-      c2 v[RT];
+  // Steps in runs of CT, so that the pivot column's register slot kc is a
+  // compile-time index (no select chains over the tile).
+  for (int kb = 0; kb < n && !singular; kb += CT) {
+    const int cgk = kb / CT;            // column group holding columns kb .. kb + CT - 1
 #pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        v[r] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < CT; ++j)
-          if (j == kc) v[r] = a[r][j];
-        const int row = rg * RT + r;
-        if (mine) colbuf[s][row] = v[r];
-        const double m = v[r].x * v[r].x + v[r].y * v[r].y;
-        const uint64_t kr = ((uint64_t)__double_as_longlong(m) & ~(uint64_t)0x7F) | (uint64_t)(0x7F - row);
-        key = (mine && !((used >> r) & 1u)) ? umax64(key, kr) : key;
-      }
-      key = group_max<RB>(key);
-      const uint32_t klo = __shfl((uint32_t)key, gbase + RB - 1, 64);
-      const uint32_t khi = __shfl((uint32_t)(key >> 32), gbase + RB - 1, 64);
-      const uint64_t K = ((uint64_t)khi << 32) | klo;
-      const int p = (K >> 7) ? 0x7F - (int)(K & 0x7F) : -1;
-      if (mine) {
-        // column k becomes 1 on the pivot row, 0 elsewhere; the update then
-        // leaves -multiplier in the other rows
-        const bool isp = (p >= 0) && (rg == p / RT);
+    for (int kc = 0; kc < CT; ++kc) {
+      const int k = kb + kc;
+      if (k >= n) break;                // block-uniform
+      const int s = k & 1;
+      if (wave == cgk / GW) {
+        // Pivot search on column k, at raised wave priority: the other waves
+        // of this SIMD are still in the previous update.  Key = |z|^2 with
+        // its last 7 mantissa bits replaced by (127 - row): largest modulus,
+        // lowest row on ties.
+        __builtin_amdgcn_s_setprio(3);
+        const bool mine = (cg == cgk);
+        uint64_t key = 0;
+        c2 v[RT];
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-          const c2 nv = (isp && r == p % RT) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-#pragma unroll
-          for (int j = 0; j < CT; ++j)
-            if (j == kc) a[r][j] = nv;
+          v[r] = a[r][kc];
+          const int row = rg * RT + r;
+          if (mine) colbuf[s][row] = v[r];
+          const double m = v[r].x * v[r].x + v[r].y * v[r].y;
+          const uint64_t kr = ((uint64_t)__double_as_longlong(m) & ~(uint64_t)0x7F) | (uint64_t)(0x7F - row);
+          key = (mine && !((used >> r) & 1u)) ? umax64(key, kr) : key;
         }
-        if (isp) {
-          const c2 iv = cinv((p % RT) ? v[1] : v[0]);
-          pinv[s] = iv;
-          rowinv[p] = iv;
-          colbuf[s][p] = make_double2(0.0, 0.0);    // the pivot row is not updated
-          pbuf[s] = p;
-          pivrow[k] = p;
-          stepof[p] = k;
+        key = group_max<RB>(key);
+        const uint32_t klo = __shfl((uint32_t)key, gbase + RB - 1, 64);
+        const uint32_t khi = __shfl((uint32_t)(key >> 32), gbase + RB - 1, 64);
+        const uint64_t K = ((uint64_t)khi << 32) | klo;
+        const int p = (K >> 7) ? 0x7F - (int)(K & 0x7F) : -1;
+        if (mine) {
+          // column k becomes 1 on the pivot row, 0 elsewhere; the update then
+          // leaves -multiplier in the other rows
+          const bool isp = (p >= 0) && (rg == p / RT);
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            a[r][kc] = (isp && r == p % RT) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+          if (isp) {
+            const c2 iv = cinv((p % RT) ? v[1] : v[0]);
+            pinv[s] = iv;
+            rowinv[p] = iv;
+            colbuf[s][p] = make_double2(0.0, 0.0);    // the pivot row is not updated
+            pbuf[s] = p;
+            pivrow[k] = p;
+            stepof[p] = k;
+          }
+          if (p < 0 && rg == 0) pbuf[s] = -1;
         }
-        if (p < 0 && rg == 0) pbuf[s] = -1;
+        __builtin_amdgcn_s_setprio(0);
       }
-      __builtin_amdgcn_s_setprio(0);
-    }
-    __syncthreads();
-    const int p = pbuf[s];
-    if (p < 0) { singular = true; break; }
-    const c2 inv = pinv[s];
-    c2 mi[RT];
+      __syncthreads();
+      const int p = pbuf[s];
+      if (p < 0) { singular = true; break; }
+      const int pr = p % RT;
+      if (wave_live) {
+        const c2 inv = pinv[s];
+        c2 mi[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) mi[r] = cmul(colbuf[s][rg * RT + r], inv);
-    const int pr = p % RT, src_lane = gbase + p / RT;
-    c2 rp[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      const c2 v = pr ? a[1][j] : a[0][j];
-      rp[j].x = group_bcast<RB>(v.x, src_lane);
-      rp[j].y = group_bcast<RB>(v.y, src_lane);
-    }
-#pragma unroll
-    for (int j = 0; j < CT; ++j)
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        a[r][j].x = fma(-mi[r].x, rp[j].x, fma(mi[r].y, rp[j].y, a[r][j].x));
-        a[r][j].y = fma(-mi[r].x, rp[j].y, fma(-mi[r].y, rp[j].x, a[r][j].y));
+        for (int r = 0; r < RT; ++r) mi[r] = cmul(colbuf[s][rg * RT + r], inv);
+        const int src_lane = gbase + p / RT;
+        static_assert(RT == 2, "the update branches on the pivot row's slot");
+        if (pr) gj_update<RT, CT, RB, 1>(a, mi, src_lane);
+        else gj_update<RT, CT, RB, 0>(a, mi, src_lane);
       }
-    if (rg == p / RT) used |= 1u << pr;
+      if (rg == p / RT) used |= 1u << pr;
+    }
   }
   if (singular) {
     if (tid == 0) atomicMax(status, ids[blk] + 1);
