@@ -229,20 +229,29 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
 template <int MODE, int AT, int NB>
 __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
-                                                const Term *__restrict__ terms, const float *__restrict__ scales, int ncols) {
+                                                const Term *__restrict__ terms, const float *__restrict__ scales, int ncols,
+                                                int ntiles, int ny, int xcd_order) {
   constexpr int TN = 32 * NB;
-  const Tile t = tiles[blockIdx.x];
+  // workgroup -> (tile bx, part by): plain or XCD-aware order, as in k_gemm
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (xcd_order) {
+    const int q = (int)(blockIdx.x >> 3);
+    by = q % ny;
+    bx = 8 * (q / ny) + (int)(blockIdx.x & 7);
+    if (bx >= ntiles) return;
+  }
+  const Tile t = tiles[bx];
   int rb = t.r0, cb = t.c0, tn = t.n;
   if (t.r0 < 0) {
     const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
-    if ((int)blockIdx.y >= nsr * nsc) return;
-    rb = (blockIdx.y / nsc) * TM;
-    cb = (blockIdx.y % nsc) * TN;
-  } else if (t.c0 < 0) {             // one row tile over ncols columns, blockIdx.y picks the column tile
+    if (by >= nsr * nsc) return;
+    rb = (by / nsc) * TM;
+    cb = (by % nsc) * TN;
+  } else if (t.c0 < 0) {             // one row tile over ncols columns, by picks the column tile
     tn = ncols;
-    cb = blockIdx.y * TN;
+    cb = by * TN;
     if (cb >= tn) return;
-  } else if (blockIdx.y > 0) {
+  } else if (by > 0) {
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1787,14 +1796,18 @@ struct DeviceState::Impl {
            double flops, double bytes) {
     if (n == 0) return;
     const int64_t pr = prof_begin(MODE, flops, bytes, n);
-    dim3 g((unsigned)n, (unsigned)cdiv(cur_R, TN_SOLVE)), blk(256);
-    const int nc = (int)cur_R;
+    // store mode (far field, D^-1) in the XCD-aware order, as in launch_tiles
+    const int ny = (int)cdiv(cur_R, TN_SOLVE), xo = MODE == 0 ? 1 : 0;
+    const int64_t nwg = cdiv(n, 8) * 8 * (int64_t)ny;
+    if (n > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
+    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n, (unsigned)ny), blk(256);
+    const int nc = (int)cur_R, nt = (int)n;
     if (at == 0)
-      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
+      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
     else if (at == 1)
-      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
+      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
     else
-      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc);
+      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
@@ -2177,73 +2190,10 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   const uint64_t need = 2ull * (uint64_t)PEt * sizeof(c2);
   if (I.mem_cap && need + (I.near.n + I.faruv.n) * sizeof(c2) > I.mem_cap)
     throw Error{HPS_ENOMEM, "setup plan exceeds device_mem_cap"};
-  // elimination-order permutation
-  std::vector<int64_t> dperm(N), t2e(N);
-  for (int64_t e = 0; e < M; ++e) {
-    const int32_t g = P.order[e];
-    for (int64_t i = 0; i < P.size[e]; ++i) {
-      dperm[P.uoff[e] + i] = H.perm[H.gptr[g] + i];
-      t2e[H.gptr[g] + i] = P.uoff[e] + i;
-    }
-  }
-  // every problem of a batch must own one contiguous range of elimination
-  // positions (the per-problem reductions and layouts rely on it)
-  for (int64_t e = 0; e < M; ++e) {
-    const int64_t lo = H.gptr[P.order[e]];
-    const int64_t p = std::upper_bound(I.soff.begin(), I.soff.end(), lo) - I.soff.begin() - 1;
-    if (p < 0 || p >= I.nseg || P.uoff[e] < I.soff[p] || P.uoff[e] + P.size[e] > I.soff[p + 1] ||
-        H.gptr[P.order[e] + 1] > I.soff[p + 1])
-      throw Error{HPS_EINVAL, "internal: a problem of the batch is not contiguous in elimination order"};
-  }
-  I.tree2elim = t2e;
-  I.dperm.upload(dperm, s);
-
-  // column-offset lookup: block (e, f) of panel e
-  auto col_of = [&](int64_t e, int64_t f) -> int64_t {
-    if (e == f) return 0;
-    const int32_t *b = &P.later[P.later_ptr[e]], *en = &P.later[P.later_ptr[e + 1]];
-    const int32_t *it = std::lower_bound(b, en, (int32_t)f);
-    if (it == en || *it != f) throw Error{HPS_EINVAL, "internal: block missing from fill pattern"};
-    return P.col_off[it - &P.later[0]];
-  };
-
-  // ---- working panels and factor panels (kept across setups, grow-only)
-  I.Wk.alloc(PEt);
-  I.F.alloc(PEt);
-  c2 *Wd = I.Wk.p;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, Wd, PEt);
-  HIP_CHECK(hipGetLastError());
-  std::vector<Scatter> sc(H.n_near());
-  for (int64_t b = 0; b < H.n_near(); ++b) {
-    const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
-    const int64_t et = P.pos[t], eu = P.pos[u];
-    Scatter d;
-    d.src = H.near_off[b];
-    d.m = (int32_t)(H.gptr[t + 1] - H.gptr[t]);
-    d.n = (int32_t)(H.gptr[u + 1] - H.gptr[u]);
-    if (et <= eu) {
-      d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
-      d.ld = (int32_t)P.size[et];
-      d.trans = 0;
-    } else {                     // Z_tu^T: the (u, t) upper block, or the lower block of a non-symmetric field
-      d.dst = (I.nonsym ? PE : 0) + P.panel_off[eu] + col_of(eu, et) * P.size[eu];
-      d.ld = (int32_t)P.size[eu];
-      d.trans = 1;
-    }
-    const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
-    if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= PEt)
-      throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
-    sc[b] = d;
-  }
-  DevArray<Scatter> dsc;
-  dsc.upload(sc, s);
-  if (!sc.empty()) {
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd, dsc.p);
-    HIP_CHECK(hipGetLastError());
-  }
-
   // ---- per-level schedules: built per level on host threads (levels are
-  // independent), then concatenated in level order into one pool
+  // independent), then concatenated in level order into one pool.  The
+  // workers start first, so the first levels are built while this thread
+  // prepares the panels below.
   const auto th0 = std::chrono::steady_clock::now();
   const int L = P.n_levels;
   I.setup_streams(L);
@@ -2397,7 +2347,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     tflop.clear();
   };
   // Levels are built on worker threads in level order while this thread
-  // uploads and launches them in chunks of growing size (2, 4, 8, ... levels),
+  // uploads and launches them in chunks of growing size (1, 2, 4, ... levels),
   // so the device starts on the first levels while later ones are built.
   std::mutex mu;
   std::condition_variable cv;
@@ -2438,8 +2388,73 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   } joiner{pool_threads, next, L};
   for (int t = 0; t < nthreads; ++t) pool_threads.emplace_back(worker);
 
+  // elimination-order permutation
+  std::vector<int64_t> dperm(N), t2e(N);
+  for (int64_t e = 0; e < M; ++e) {
+    const int32_t g = P.order[e];
+    for (int64_t i = 0; i < P.size[e]; ++i) {
+      dperm[P.uoff[e] + i] = H.perm[H.gptr[g] + i];
+      t2e[H.gptr[g] + i] = P.uoff[e] + i;
+    }
+  }
+  // every problem of a batch must own one contiguous range of elimination
+  // positions (the per-problem reductions and layouts rely on it)
+  for (int64_t e = 0; e < M; ++e) {
+    const int64_t lo = H.gptr[P.order[e]];
+    const int64_t p = std::upper_bound(I.soff.begin(), I.soff.end(), lo) - I.soff.begin() - 1;
+    if (p < 0 || p >= I.nseg || P.uoff[e] < I.soff[p] || P.uoff[e] + P.size[e] > I.soff[p + 1] ||
+        H.gptr[P.order[e] + 1] > I.soff[p + 1])
+      throw Error{HPS_EINVAL, "internal: a problem of the batch is not contiguous in elimination order"};
+  }
+  I.tree2elim = t2e;
+  I.dperm.upload(dperm, s);
+
+  // column-offset lookup: block (e, f) of panel e
+  auto col_of = [&](int64_t e, int64_t f) -> int64_t {
+    if (e == f) return 0;
+    const int32_t *b = &P.later[P.later_ptr[e]], *en = &P.later[P.later_ptr[e + 1]];
+    const int32_t *it = std::lower_bound(b, en, (int32_t)f);
+    if (it == en || *it != f) throw Error{HPS_EINVAL, "internal: block missing from fill pattern"};
+    return P.col_off[it - &P.later[0]];
+  };
+
+  // ---- working panels and factor panels (kept across setups, grow-only)
+  I.Wk.alloc(PEt);
+  I.F.alloc(PEt);
+  c2 *Wd = I.Wk.p;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, Wd, PEt);
+  HIP_CHECK(hipGetLastError());
+  std::vector<Scatter> sc(H.n_near());
+  for (int64_t b = 0; b < H.n_near(); ++b) {
+    const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
+    const int64_t et = P.pos[t], eu = P.pos[u];
+    Scatter d;
+    d.src = H.near_off[b];
+    d.m = (int32_t)(H.gptr[t + 1] - H.gptr[t]);
+    d.n = (int32_t)(H.gptr[u + 1] - H.gptr[u]);
+    if (et <= eu) {
+      d.dst = P.panel_off[et] + col_of(et, eu) * P.size[et];
+      d.ld = (int32_t)P.size[et];
+      d.trans = 0;
+    } else {                     // Z_tu^T: the (u, t) upper block, or the lower block of a non-symmetric field
+      d.dst = (I.nonsym ? PE : 0) + P.panel_off[eu] + col_of(eu, et) * P.size[eu];
+      d.ld = (int32_t)P.size[eu];
+      d.trans = 1;
+    }
+    const int64_t last = d.trans ? d.dst + (int64_t)(d.m - 1) * d.ld + (d.n - 1) : d.dst + (int64_t)(d.n - 1) * d.ld + (d.m - 1);
+    if (d.src < 0 || d.src + (int64_t)d.m * d.n > (int64_t)I.near.n || d.dst < 0 || last >= PEt)
+      throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
+    sc[b] = d;
+  }
+  DevArray<Scatter> dsc;
+  dsc.upload(sc, s);
+  if (!sc.empty()) {
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd, dsc.p);
+    HIP_CHECK(hipGetLastError());
+  }
+
   std::vector<int> cut{0};
-  for (int w = 2; cut.back() < L; w *= 2) cut.push_back(std::min(L, cut.back() + w));
+  for (int w = 1; cut.back() < L; w *= 2) cut.push_back(std::min(L, cut.back() + w));
   const int n_chunks = (int)cut.size() - 1;
   if ((int)I.chunks.size() < n_chunks) I.chunks.resize(n_chunks);
   double flops = 0.0, wait_ms = 0.0, stage_ms = 0.0;
