@@ -26,7 +26,7 @@ struct Tile {
 struct Term {
   int64_t a_off, b_off;
   int32_t lda, ldb, k, trans;
-  int32_t sidx = -1, pad = 0;
+  int32_t sidx = -1, pad = 0;   // 16-bit A: scale index, or -2 for the per-row scale of the target's rows
 };
 
 // A batch of tiles for one launch: C = alpha * sum op(A) B + beta * C with

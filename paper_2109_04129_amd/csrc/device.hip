@@ -229,8 +229,9 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
 template <int MODE, int AT, int NB>
 __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
-                                                const Term *__restrict__ terms, const float *__restrict__ scales, int ncols,
-                                                int ntiles, int ny, int xcd_order) {
+                                                const Term *__restrict__ terms, const float *__restrict__ scales,
+                                                const int32_t *__restrict__ rowpart, int ncols, int ntiles, int ny,
+                                                int xcd_order) {
   constexpr int TN = 32 * NB;
   // workgroup -> (tile bx, part by): plain or XCD-aware order, as in k_gemm
   int bx = (int)blockIdx.x, by = (int)blockIdx.y;
@@ -260,6 +261,11 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
   const int li = lane & 15, lg = lane >> 4;
   const int arow = row0 + li;
   const bool arow_ok = arow < t.m;
+  // terms with sidx -2 (a factor group of the first far stage) scale each A
+  // row by its own factor's scale: row arow of the target is T row c_off + arow
+  float sc_row = 1.0f;
+  if (AT != 0 && rowpart != nullptr && arow_ok && t.t_begin < t.t_end && terms[t.t_begin].sidx == -2)
+    sc_row = scales[rowpart[t.c_off + arow]];
   // read-modify-write modes: fetch C now, so its latency hides behind the products
   float2 cold[NB][4];
   if (MODE != 0) {
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
   for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ss[j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int q = t.t_begin; q < t.t_end; ++q) {
     const Term tm = terms[q];
-    const float sc = (AT != 0 && tm.sidx >= 0) ? scales[tm.sidx] : 1.0f;
+    const float sc = AT == 0 ? 1.0f : (tm.sidx >= 0 ? scales[tm.sidx] : (tm.sidx == -2 ? sc_row : 1.0f));
     const int kfull = tm.k & ~15;
     for (int k0 = 0; k0 < kfull; k0 += 16) {
       float2 av[4], bv[NB][4];
@@ -1789,6 +1795,7 @@ struct DeviceState::Impl {
   DevArray<float2> F32, near32;
   DevArray<uint32_t> far16;
   DevArray<float> fscale;
+  DevArray<int32_t> rowpart;   // first far stage, precision form: scale index of each T row
   DevArray<float2> wB, wY, wW, wS, wI, wX, wT, wR, wZ;
 
   template <int MODE>
@@ -1803,11 +1810,11 @@ struct DeviceState::Impl {
     dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n, (unsigned)ny), blk(256);
     const int nc = (int)cur_R, nt = (int)n;
     if (at == 0)
-      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
+      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     else if (at == 1)
-      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
+      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     else
-      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, nc, nt, ny, xo);
+      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
@@ -2679,26 +2686,27 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   for (const Impl::FarGroup &fg : I.fgroups) {
     const int32_t clen = (int32_t)(fg.hi - fg.lo);
     leaves_in(fg.lo, fg.hi, lv);
-    if (I.precision == 0) {
-      // one target: rows of every factor of the group, terms over the leaves
-      const auto first = I.fmembers[fg.m0];
-      add_target(I.far1, I.toff[2 * first.first + first.second], (int32_t)fg.rows, ldT);
-      for (int64_t g : lv)
-        I.far1.terms.push_back(Term{fg.off + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N,
-                                    (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1});
-      continue;
+    // one target: rows of every factor of the group, terms over the leaves;
+    // the precision form scales each row by its factor's 16-bit scale
+    const auto first = I.fmembers[fg.m0];
+    add_target(I.far1, I.toff[2 * first.first + first.second], (int32_t)fg.rows, ldT);
+    for (int64_t g : lv) {
+      Term tm{fg.off + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N,
+              (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
+      tm.sidx = -2;
+      I.far1.terms.push_back(tm);
     }
-    for (int32_t q = fg.m0; q < fg.m1; ++q) {
-      const int64_t bb = I.fmembers[q].first;
-      const int dir = I.fmembers[q].second;
-      add_target(I.far1, I.toff[2 * bb + dir], (int32_t)Hs.far_rank[bb], ldT);
-      const int64_t fo = dir == 0 ? I.fv[bb] : I.fu[bb];
-      for (int64_t g : lv) {
-        Term tmv{fo + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N, (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
-        tmv.sidx = (int32_t)(2 * bb + (dir == 0 ? 1 : 0));
-        I.far1.terms.push_back(tmv);
+  }
+  if (I.precision > 0) {
+    std::vector<int32_t> rp((size_t)std::max<int64_t>(trow, 1), 0);
+    for (const Impl::FarGroup &fg : I.fgroups)
+      for (int32_t q = fg.m0; q < fg.m1; ++q) {
+        const int64_t bb = I.fmembers[q].first;
+        const int dir = I.fmembers[q].second;
+        for (int64_t i = 0; i < Hs.far_rank[bb]; ++i)
+          rp[I.toff[2 * bb + dir] + i] = (int32_t)(2 * bb + (dir == 0 ? 1 : 0));
       }
-    }
+    I.rowpart.upload(rp, s);
   }
   for (int64_t b = 0; b < nf; ++b) {
     const int64_t tlo = Hs.far_rng[4 * b], thi = Hs.far_rng[4 * b + 1];
