@@ -1667,11 +1667,13 @@ struct DeviceState::Impl {
     validate(pl.tiles.data() + out.t0, (size_t)out.n_tiles, pl.terms, na, nb, nc, what);
   }
   // host side of the solve schedules; upload_solve_pool() copies them
-  void build_solve_pool() {
+  // nF: length of the factor panels (F may still be allocated by another
+  // thread while this runs)
+  void build_solve_pool(int64_t nF) {
     spool.clear();
     b_fwd.assign(fwd.size(), Built());
     b_bwd.assign(bwd.size(), Built());
-    const int64_t nF = (int64_t)F.n, nT = std::max<int64_t>(t_rows, 1);
+    const int64_t nT = std::max<int64_t>(t_rows, 1);
     for (size_t l = 0; l < fwd.size(); ++l) build(fwd[l], spool, b_fwd[l], nF, N, N, "forward sweep");
     for (size_t l = 0; l < bwd.size(); ++l) build(bwd[l], spool, b_bwd[l], nF, N, N, "back sweep");
     build(dinv, spool, b_dinv, nF, N, N, "D^-1");
@@ -2197,6 +2199,183 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   const uint64_t need = 2ull * (uint64_t)PEt * sizeof(c2);
   if (I.mem_cap && need + (I.near.n + I.faruv.n) * sizeof(c2) > I.mem_cap)
     throw Error{HPS_ENOMEM, "setup plan exceeds device_mem_cap"};
+  // ---- solve schedules: host work only (the plan and the H-matrix
+  // structure), on a thread of their own while the levels are built and run
+  std::string sched_err;
+  std::vector<int32_t> rowpart_host;
+  std::thread sched_thread([&]() {
+    try {
+      const int L = P.n_levels;
+      // ---- solve schedules (terms independent of R)
+      auto add_target = [](Impl::Sched &sc, int64_t coff, int32_t m, int32_t ld) {
+        sc.targets.push_back({coff, m});
+        sc.ld.push_back(ld);
+        sc.t_ptr.push_back((int32_t)sc.terms.size());
+      };
+      auto close = [](Impl::Sched &sc) { sc.t_ptr.push_back((int32_t)sc.terms.size()); };
+      // Right-looking (push) sweeps: the launch of level l applies the blocks of
+      // the pivots at level l to every group they couple to, one term per pivot,
+      // so a launch has many short tiles instead of a few long ones.
+      //   forward (eq. 25), levels ascending:   b_f -= C_ef^T b_e, e at level l, f in N+(e);
+      //   back (eq. 26), levels descending:     x_e -= C_ef x_f,  f at level l, f in N+(e).
+      std::vector<std::vector<std::pair<int32_t, int64_t>>> contrib(M);
+      for (int64_t e = 0; e < M; ++e)
+        for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
+      I.fwd.assign(L, Impl::Sched());
+      I.bwd.assign(L, Impl::Sched());
+      std::vector<int32_t> slot(M, -1), tgt;
+      std::vector<std::vector<Term>> bucket(M);
+      auto flush = [&](Impl::Sched &sc) {
+        for (int32_t g : tgt) {
+          add_target(sc, P.uoff[g], (int32_t)P.size[g], (int32_t)N);
+          std::vector<Term> &bk = bucket[slot[g]];
+          sc.terms.insert(sc.terms.end(), bk.begin(), bk.end());
+          bk.clear();
+        }
+        for (int32_t g : tgt) slot[g] = -1;
+        tgt.clear();
+        close(sc);
+      };
+      auto put = [&](int32_t g, const Term &t) {
+        if (slot[g] < 0) { slot[g] = (int32_t)tgt.size(); tgt.push_back(g); }
+        bucket[slot[g]].push_back(t);
+      };
+      for (int l = 0; l < L; ++l) {
+        for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+          const int32_t e = P.level_piv[i];
+          for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
+            put(P.later[a], Term{(I.nonsym ? PE : 0) + P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e],
+                                 (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 1});
+        }
+        flush(I.fwd[l]);
+        for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+          const int32_t f = P.level_piv[i];
+          for (auto &ce : contrib[f]) {
+            const int32_t e = ce.first;
+            put(e, Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[f], (int32_t)P.size[e], (int32_t)N,
+                        (int32_t)P.size[f], 0});
+          }
+        }
+        flush(I.bwd[l]);
+      }
+      I.dinv = Impl::Sched();
+      for (int64_t e = 0; e < M; ++e) {
+        add_target(I.dinv, P.uoff[e], (int32_t)P.size[e], (int32_t)N);
+        I.dinv.terms.push_back(Term{P.panel_off[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 0});
+      }
+      close(I.dinv);
+      // far field: stage 1 targets = the rank rows of one factor group (FP64) or
+      // of one (block, direction) (precision form: one 16-bit scale per factor
+      // and term) x R; stage 2 targets = leaves
+      const HMatrix &Hs = I.hcopy;
+      const int64_t nf = Hs.n_far();
+      I.far1 = Impl::Sched();
+      I.far2 = Impl::Sched();
+      I.toff.assign(2 * nf, -1);
+      int64_t trow = 0;
+      auto leaves_in = [&](int64_t lo, int64_t hi, std::vector<int64_t> &out) {
+        out.clear();
+        int64_t g = std::upper_bound(Hs.gptr.begin(), Hs.gptr.end(), lo) - Hs.gptr.begin() - 1;
+        for (; g < Hs.M && Hs.gptr[g] < hi; ++g) out.push_back(g);
+      };
+      std::vector<std::vector<Term>> leaf_terms(M);
+      std::vector<int64_t> lv;
+      // T is one column-major matrix of t_rows x R: rows [toff, toff + r) hold
+      // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of
+      // s); a non-symmetric H-matrix stores both orders as separate blocks, each
+      // applied in dir 0 only.  The rows of one factor group are contiguous.
+      const int ndir = I.nonsym ? 1 : 2;
+      for (const Impl::FarGroup &fg : I.fgroups)
+        for (int32_t q = fg.m0; q < fg.m1; ++q) {
+          const auto bd = I.fmembers[q];
+          I.toff[2 * bd.first + bd.second] = trow;
+          trow += Hs.far_rank[bd.first];
+        }
+      I.t_rows = trow;
+      const int32_t ldT = (int32_t)std::max<int64_t>(trow, 1);
+      for (const Impl::FarGroup &fg : I.fgroups) {
+        const int32_t clen = (int32_t)(fg.hi - fg.lo);
+        leaves_in(fg.lo, fg.hi, lv);
+        // one target: rows of every factor of the group, terms over the leaves;
+        // the precision form scales each row by its factor's 16-bit scale
+        const auto first = I.fmembers[fg.m0];
+        add_target(I.far1, I.toff[2 * first.first + first.second], (int32_t)fg.rows, ldT);
+        for (int64_t g : lv) {
+          Term tm{fg.off + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N,
+                  (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
+          tm.sidx = -2;
+          I.far1.terms.push_back(tm);
+        }
+      }
+      if (I.precision > 0) {
+        std::vector<int32_t> rp((size_t)std::max<int64_t>(trow, 1), 0);
+        for (const Impl::FarGroup &fg : I.fgroups)
+          for (int32_t q = fg.m0; q < fg.m1; ++q) {
+            const int64_t bb = I.fmembers[q].first;
+            const int dir = I.fmembers[q].second;
+            for (int64_t i = 0; i < Hs.far_rank[bb]; ++i)
+              rp[I.toff[2 * bb + dir] + i] = (int32_t)(2 * bb + (dir == 0 ? 1 : 0));
+          }
+        rowpart_host = std::move(rp);
+      }
+      for (int64_t b = 0; b < nf; ++b) {
+        const int64_t tlo = Hs.far_rng[4 * b], thi = Hs.far_rng[4 * b + 1];
+        const int64_t slo = Hs.far_rng[4 * b + 2], shi = Hs.far_rng[4 * b + 3];
+        const int64_t m = thi - tlo, n = shi - slo, r = Hs.far_rank[b];
+        if (r == 0) continue;
+        const int64_t uo = I.fu[b], vo = I.fv[b];
+        leaves_in(tlo, thi, lv);
+        for (int64_t g : lv) {
+          Term tmu{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0};
+          tmu.sidx = (int32_t)(2 * b);
+          leaf_terms[g].push_back(tmu);
+        }
+        if (ndir == 2) {
+          leaves_in(slo, shi, lv);
+          for (int64_t g : lv) {
+            Term tmv{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0};
+            tmv.sidx = (int32_t)(2 * b + 1);
+            leaf_terms[g].push_back(tmv);
+          }
+        }
+      }
+      close(I.far1);
+      for (int64_t g = 0; g < M; ++g) {
+        add_target(I.far2, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
+        I.far2.terms.insert(I.far2.terms.end(), leaf_terms[g].begin(), leaf_terms[g].end());
+      }
+      close(I.far2);
+      // near-field matvec (both triangles of every stored near block; every
+      // ordered block once when the field is not symmetric)
+      I.nearmv = Impl::Sched();
+      std::vector<std::vector<Term>> nt(M);
+      for (int64_t b = 0; b < Hs.n_near(); ++b) {
+        const int32_t t = Hs.near_ts[2 * b], u = Hs.near_ts[2 * b + 1];
+        const int64_t mt = Hs.gptr[t + 1] - Hs.gptr[t], mu = Hs.gptr[u + 1] - Hs.gptr[u];
+        // row-major mt x mu == column-major mu x mt with ld mu
+        nt[t].push_back(Term{Hs.near_off[b], P.uoff[P.pos[u]], (int32_t)mu, (int32_t)N, (int32_t)mu, 1});
+        if (t != u && !I.nonsym)
+          nt[u].push_back(Term{Hs.near_off[b], P.uoff[P.pos[t]], (int32_t)mu, (int32_t)N, (int32_t)mt, 0});
+      }
+      for (int64_t g = 0; g < M; ++g) {
+        add_target(I.nearmv, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
+        I.nearmv.terms.insert(I.nearmv.terms.end(), nt[g].begin(), nt[g].end());
+      }
+      close(I.nearmv);
+      I.build_solve_pool(PEt);
+    } catch (const Error &e) {
+      sched_err = e.msg;
+    } catch (const std::exception &e) {
+      sched_err = e.what();
+    }
+  });
+  struct SchedJoin {
+    std::thread &t;
+    ~SchedJoin() {
+      if (t.joinable()) t.join();
+    }
+  } sched_join{sched_thread};
+
   // ---- per-level schedules: built per level on host threads (levels are
   // independent), then concatenated in level order into one pool.  The
   // workers start first, so the first levels are built while this thread
@@ -2595,164 +2774,9 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   times.inverse_ms = wait_ms + stage_ms;
   HIP_CHECK(hipEventRecord(e1, s));
 
-  // the solve schedules are built on the host while the device runs the levels
-  // ---- solve schedules (terms independent of R)
-  auto add_target = [](Impl::Sched &sc, int64_t coff, int32_t m, int32_t ld) {
-    sc.targets.push_back({coff, m});
-    sc.ld.push_back(ld);
-    sc.t_ptr.push_back((int32_t)sc.terms.size());
-  };
-  auto close = [](Impl::Sched &sc) { sc.t_ptr.push_back((int32_t)sc.terms.size()); };
-  // Right-looking (push) sweeps: the launch of level l applies the blocks of
-  // the pivots at level l to every group they couple to, one term per pivot,
-  // so a launch has many short tiles instead of a few long ones.
-  //   forward (eq. 25), levels ascending:   b_f -= C_ef^T b_e, e at level l, f in N+(e);
-  //   back (eq. 26), levels descending:     x_e -= C_ef x_f,  f at level l, f in N+(e).
-  std::vector<std::vector<std::pair<int32_t, int64_t>>> contrib(M);
-  for (int64_t e = 0; e < M; ++e)
-    for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
-  I.fwd.assign(L, Impl::Sched());
-  I.bwd.assign(L, Impl::Sched());
-  std::vector<int32_t> slot(M, -1), tgt;
-  std::vector<std::vector<Term>> bucket(M);
-  auto flush = [&](Impl::Sched &sc) {
-    for (int32_t g : tgt) {
-      add_target(sc, P.uoff[g], (int32_t)P.size[g], (int32_t)N);
-      std::vector<Term> &bk = bucket[slot[g]];
-      sc.terms.insert(sc.terms.end(), bk.begin(), bk.end());
-      bk.clear();
-    }
-    for (int32_t g : tgt) slot[g] = -1;
-    tgt.clear();
-    close(sc);
-  };
-  auto put = [&](int32_t g, const Term &t) {
-    if (slot[g] < 0) { slot[g] = (int32_t)tgt.size(); tgt.push_back(g); }
-    bucket[slot[g]].push_back(t);
-  };
-  for (int l = 0; l < L; ++l) {
-    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
-      const int32_t e = P.level_piv[i];
-      for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
-        put(P.later[a], Term{(I.nonsym ? PE : 0) + P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e],
-                             (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 1});
-    }
-    flush(I.fwd[l]);
-    for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
-      const int32_t f = P.level_piv[i];
-      for (auto &ce : contrib[f]) {
-        const int32_t e = ce.first;
-        put(e, Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[f], (int32_t)P.size[e], (int32_t)N,
-                    (int32_t)P.size[f], 0});
-      }
-    }
-    flush(I.bwd[l]);
-  }
-  I.dinv = Impl::Sched();
-  for (int64_t e = 0; e < M; ++e) {
-    add_target(I.dinv, P.uoff[e], (int32_t)P.size[e], (int32_t)N);
-    I.dinv.terms.push_back(Term{P.panel_off[e], P.uoff[e], (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 0});
-  }
-  close(I.dinv);
-  // far field: stage 1 targets = the rank rows of one factor group (FP64) or
-  // of one (block, direction) (precision form: one 16-bit scale per factor
-  // and term) x R; stage 2 targets = leaves
-  const HMatrix &Hs = I.hcopy;
-  const int64_t nf = Hs.n_far();
-  I.far1 = Impl::Sched();
-  I.far2 = Impl::Sched();
-  I.toff.assign(2 * nf, -1);
-  int64_t trow = 0;
-  auto leaves_in = [&](int64_t lo, int64_t hi, std::vector<int64_t> &out) {
-    out.clear();
-    int64_t g = std::upper_bound(Hs.gptr.begin(), Hs.gptr.end(), lo) - Hs.gptr.begin() - 1;
-    for (; g < Hs.M && Hs.gptr[g] < hi; ++g) out.push_back(g);
-  };
-  std::vector<std::vector<Term>> leaf_terms(M);
-  std::vector<int64_t> lv;
-  // T is one column-major matrix of t_rows x R: rows [toff, toff + r) hold
-  // T0 = V^T Y[s] (dir 0, feeds the rows of t) or T1 = U^T Y[t] (dir 1, rows of
-  // s); a non-symmetric H-matrix stores both orders as separate blocks, each
-  // applied in dir 0 only.  The rows of one factor group are contiguous.
-  const int ndir = I.nonsym ? 1 : 2;
-  for (const Impl::FarGroup &fg : I.fgroups)
-    for (int32_t q = fg.m0; q < fg.m1; ++q) {
-      const auto bd = I.fmembers[q];
-      I.toff[2 * bd.first + bd.second] = trow;
-      trow += Hs.far_rank[bd.first];
-    }
-  I.t_rows = trow;
-  const int32_t ldT = (int32_t)std::max<int64_t>(trow, 1);
-  for (const Impl::FarGroup &fg : I.fgroups) {
-    const int32_t clen = (int32_t)(fg.hi - fg.lo);
-    leaves_in(fg.lo, fg.hi, lv);
-    // one target: rows of every factor of the group, terms over the leaves;
-    // the precision form scales each row by its factor's 16-bit scale
-    const auto first = I.fmembers[fg.m0];
-    add_target(I.far1, I.toff[2 * first.first + first.second], (int32_t)fg.rows, ldT);
-    for (int64_t g : lv) {
-      Term tm{fg.off + (Hs.gptr[g] - fg.lo), P.uoff[P.pos[g]], clen, (int32_t)N,
-              (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), 1};
-      tm.sidx = -2;
-      I.far1.terms.push_back(tm);
-    }
-  }
-  if (I.precision > 0) {
-    std::vector<int32_t> rp((size_t)std::max<int64_t>(trow, 1), 0);
-    for (const Impl::FarGroup &fg : I.fgroups)
-      for (int32_t q = fg.m0; q < fg.m1; ++q) {
-        const int64_t bb = I.fmembers[q].first;
-        const int dir = I.fmembers[q].second;
-        for (int64_t i = 0; i < Hs.far_rank[bb]; ++i)
-          rp[I.toff[2 * bb + dir] + i] = (int32_t)(2 * bb + (dir == 0 ? 1 : 0));
-      }
-    I.rowpart.upload(rp, s);
-  }
-  for (int64_t b = 0; b < nf; ++b) {
-    const int64_t tlo = Hs.far_rng[4 * b], thi = Hs.far_rng[4 * b + 1];
-    const int64_t slo = Hs.far_rng[4 * b + 2], shi = Hs.far_rng[4 * b + 3];
-    const int64_t m = thi - tlo, n = shi - slo, r = Hs.far_rank[b];
-    if (r == 0) continue;
-    const int64_t uo = I.fu[b], vo = I.fv[b];
-    leaves_in(tlo, thi, lv);
-    for (int64_t g : lv) {
-      Term tmu{uo + (Hs.gptr[g] - tlo), I.toff[2 * b], (int32_t)m, ldT, (int32_t)r, 0};
-      tmu.sidx = (int32_t)(2 * b);
-      leaf_terms[g].push_back(tmu);
-    }
-    if (ndir == 2) {
-      leaves_in(slo, shi, lv);
-      for (int64_t g : lv) {
-        Term tmv{vo + (Hs.gptr[g] - slo), I.toff[2 * b + 1], (int32_t)n, ldT, (int32_t)r, 0};
-        tmv.sidx = (int32_t)(2 * b + 1);
-        leaf_terms[g].push_back(tmv);
-      }
-    }
-  }
-  close(I.far1);
-  for (int64_t g = 0; g < M; ++g) {
-    add_target(I.far2, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
-    I.far2.terms.insert(I.far2.terms.end(), leaf_terms[g].begin(), leaf_terms[g].end());
-  }
-  close(I.far2);
-  // near-field matvec (both triangles of every stored near block; every
-  // ordered block once when the field is not symmetric)
-  I.nearmv = Impl::Sched();
-  std::vector<std::vector<Term>> nt(M);
-  for (int64_t b = 0; b < Hs.n_near(); ++b) {
-    const int32_t t = Hs.near_ts[2 * b], u = Hs.near_ts[2 * b + 1];
-    const int64_t mt = Hs.gptr[t + 1] - Hs.gptr[t], mu = Hs.gptr[u + 1] - Hs.gptr[u];
-    // row-major mt x mu == column-major mu x mt with ld mu
-    nt[t].push_back(Term{Hs.near_off[b], P.uoff[P.pos[u]], (int32_t)mu, (int32_t)N, (int32_t)mu, 1});
-    if (t != u && !I.nonsym)
-      nt[u].push_back(Term{Hs.near_off[b], P.uoff[P.pos[t]], (int32_t)mu, (int32_t)N, (int32_t)mt, 0});
-  }
-  for (int64_t g = 0; g < M; ++g) {
-    add_target(I.nearmv, P.uoff[P.pos[g]], (int32_t)(Hs.gptr[g + 1] - Hs.gptr[g]), (int32_t)N);
-    I.nearmv.terms.insert(I.nearmv.terms.end(), nt[g].begin(), nt[g].end());
-  }
-  close(I.nearmv);
-  I.build_solve_pool();
+  sched_thread.join();
+  if (!sched_err.empty()) throw Error{HPS_EINVAL, sched_err};
+  if (I.precision > 0) I.rowpart.upload(rowpart_host, s);
   HIP_CHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
