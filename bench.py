@@ -414,8 +414,20 @@ def main():
     R, K = g["R"], args.steps
     ms_per_step = 1e3 * g["total"] / K
     dev = dict(g["stats"].get("device", {}))
-    dev.pop("launch_log", None)
+    log = dev.pop("launch_log", None) or []
     k = dev.get("kernels", {}).get(DOMINANT, {})
+    # the dominant kernel's launches by size (algorithmic bytes per launch):
+    # large ones stream, small ones (chain levels, few tiles) are latency-bound
+    classes = []
+    sub = [x for x in log if x[0] == 1 and len(x) >= 5]
+    for lo, hi in ((0, 1e7), (1e7, 1e8), (1e8, 1e9), (1e9, float("inf"))):
+        sel = [x for x in sub if lo <= x[3] < hi]
+        if sel:
+            b, f, t = sum(x[3] for x in sel), sum(x[2] for x in sel), sum(x[4] for x in sel) * 1e-3
+            classes.append({"bytes_per_launch": [lo, hi if hi != float("inf") else None],
+                            "launches_per_step": len(sel) / args.steps, "ms_per_step": 1e3 * t / args.steps,
+                            "achieved_gb_s": b / t / 1e9, "hbm_frac": b / t / PEAK["hbm"],
+                            "achieved_tflops": f / t / 1e12, "intensity_flop_per_byte": f / b})
     roofline = None
     if k.get("ms") and k.get("bytes"):
         sec = k["ms"] * 1e-3
@@ -436,7 +448,8 @@ def main():
                     "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
                     "attainable_tflops": min(PEAK["fp64"], intensity * PEAK["hbm"]) / 1e12,
                     "achieved_tflops": flop_rate / 1e12, "frac_of_fp64_mfma_peak": flop_rate / PEAK["fp64"],
-                    "launches_per_step": k["launches"] / K, "avg_launch_us": 1e3 * k["ms"] / k["launches"]}
+                    "launches_per_step": k["launches"] / K, "avg_launch_us": 1e3 * k["ms"] / k["launches"],
+                    "by_launch_size": classes}
     out = {
         "metric": "RHS solved/sec + setup s at <=1e-3 rel err vs FP64; mixed/batched vs plain FP64",
         "value": R * K / g["total"],

@@ -1688,7 +1688,7 @@ struct DeviceState::Impl {
   // kinds: 0..2 = k_gemm<mode>, 3 = k_inverse
   bool prof = false;
   struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; int64_t units; };
-  struct LaunchLog { int kind; int64_t units; double flops, ms; };
+  struct LaunchLog { int kind; int64_t units; double flops, bytes, ms; };
   std::vector<LaunchLog> launch_log;   // every timed launch since profiling was switched on
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_free;
@@ -1722,7 +1722,7 @@ struct DeviceState::Impl {
       kstat[r.kind].ms += ms;
       kstat[r.kind].flops += r.flops;
       kstat[r.kind].bytes += r.bytes;
-      if (launch_log.size() < 100000) launch_log.push_back(LaunchLog{r.kind, r.units, r.flops, (double)ms});
+      if (launch_log.size() < 100000) launch_log.push_back(LaunchLog{r.kind, r.units, r.flops, r.bytes, (double)ms});
       ev_free.push_back(r.a);
       ev_free.push_back(r.b);
     }
@@ -3104,11 +3104,11 @@ std::string DeviceState::stats_json() const {
         << ", \"ms\": " << I.kstat[k].ms << ", \"flops\": " << I.kstat[k].flops
         << ", \"bytes\": " << I.kstat[k].bytes << "}";
     o << ", \"profiling\": " << (I.prof ? 1 : 0) << "}";
-    if (I.prof) {   // kind (0..2 GEMM mode, 3 inverse), work units (tiles / blocks), flops, ms
+    if (I.prof) {   // kind (0..2 GEMM mode, 3 inverse), work units (tiles / blocks), flops, algorithmic bytes, ms
       o << ", \"launch_log\": [";
       for (size_t i = 0; i < I.launch_log.size(); ++i) {
         const auto &L = I.launch_log[i];
-        o << (i ? ", " : "") << "[" << L.kind << ", " << L.units << ", " << L.flops << ", " << L.ms << "]";
+        o << (i ? ", " : "") << "[" << L.kind << ", " << L.units << ", " << L.flops << ", " << L.bytes << ", " << L.ms << "]";
       }
       o << "]";
     }
