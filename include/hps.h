@@ -257,9 +257,11 @@ hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
 /* Per-launch kernel timing: with enable != 0 every grouped-GEMM and inverse
    launch is bracketed by HIP events on the context's stream; hps_stats then
-   reports launches, summed device ms and algorithmic flops per kernel class
-   since the call.  Counters reset on every call.  Adds two event records per
-   launch. */
+   reports launches, summed device ms, algorithmic flops and bytes per kernel
+   class since the call, and a launch log ([kind, work units, flops,
+   algorithmic bytes, ms] per launch; kind 0-2 the grouped GEMM in store /
+   subtract / add mode, 3 the inverse).  Counters reset on every call.  Adds
+   two event records per launch. */
 hps_status hps_profile(hps_ctx *ctx, int enable);
 
 /* JSON statistics (sizes, ranks, fill, bytes, per-stage device times of the
