@@ -64,7 +64,9 @@ typedef struct {
   int32_t precision;       /* 0: FP64 throughout.  1: FP32 solve (D^-1, scaling
                               blocks, vectors) with BF16 far factors and a per-block
                               FP32 scale, FP64 setup, plus refine_passes residual
-                              passes in FP32 */
+                              passes in FP32.  2: as 1 with FP16 far factors.  The
+                              residual passes (b - H x and the correction series)
+                              use FP32 copies of the far factors */
   int32_t terms;           /* power-series terms, >= 1 (paper: 2) */
   int32_t refine_passes;   /* residual-correction passes (precision form), >= 0 */
   double ratio_warn;       /* HPS_WRATIO threshold on eq. (45) (paper: 0.1) */
@@ -103,11 +105,17 @@ typedef struct {
                               the setup also keeps the left coefficients of eq. (18)
                               (twice the factor memory) */
   double cfie_alpha;       /* alpha of eq. (8) in [0, 1] (paper: 0.5 for closed bodies) */
+  double eta;              /* admissibility constant of eq. (10), >= 0: two octree
+                              cells form a far block when eta dist >= min(dia), dia the
+                              cell diagonal and dist the gap between the closed cells.
+                              Any eta >= sqrt(3) (default 2) means "the cells do not
+                              touch"; smaller values keep more leaf pairs near; 0 makes
+                              every leaf pair near (no far field) */
 } hps_params;
 
 /* Fill *p with defaults: leaf_max 128, aca_tol 1e-3, precision 0, terms 2,
    refine_passes 0, ratio_warn 0.1, no cap, host_threads 0, ordering 0, graphs 1, verbose 0, leaf_box_min 0, series_tol 0, host_near 0,
-   formulation 0 (EFIE), cfie_alpha 0.5.
+   formulation 0 (EFIE), cfie_alpha 0.5, eta 2.
    freq_hz = 0 (must be set). */
 hps_status hps_params_default(hps_params *p);
 
@@ -226,12 +234,20 @@ hps_status hps_import_hmatrix(hps_ctx *ctx, const char *path);
    inverse of each scaled diagonal block Z~_ii (eq. 16), the right coefficients
    C_ij = Z~_ii^-1 Z~_ij, and the Schur updates Z~_jk -= Z~_ij^T C_ik including
    fill-in blocks (eq. 21).  Precision form: also converts the solve operands.
-   HPS_ESINGULAR if a pivot block is singular (zero pivot column). */
+   HPS_ENOMEM, before any device allocation, when device_mem_cap is set and the
+   plan's device memory (H-matrix, two panel sets, precision-form copies)
+   exceeds it; this check runs on host-only contexts too (then HPS_EDEVICE
+   follows only when the plan fits).
+   HPS_ESINGULAR if a pivot block is numerically singular: LU with partial
+   pivoting of Z~_ii meets a pivot of modulus below n eps max|Z~_ii|
+   (n the block size, eps = 2^-52). */
 hps_status hps_setup(hps_ctx *ctx);
 
 /* Solve R plane-wave right-hand sides (Sec. V): wave r travels along khat[r]
    with polarisation pol[r] (host arrays R x 3, unit, orthogonal).  Writes:
-     X     N x R c128 currents (RWG order), DEVICE pointer, or NULL;
+     X     N x R c128 currents (RWG order), host or device pointer (found
+           with hipPointerGetAttributes; a host block is staged through a
+           device buffer of the context), or NULL;
      rcs   R doubles (host): monostatic co-polar RCS in m^2 in the direction
            -khat[r] (sigma = k^2 eta^2 / 4pi |b_r^T x_r|^2), or NULL;
      ratio R doubles (host): ||it_1|| / ||it_0|| of eq. (45), or NULL.
@@ -239,11 +255,12 @@ hps_status hps_setup(hps_ctx *ctx);
 hps_status hps_solve_planewaves(hps_ctx *ctx, int64_t R, const double *khat, const double *pol,
                                 void *X, double *rcs, double *ratio);
 
-/* Solve arbitrary right-hand sides: B and X are N x R c128 DEVICE pointers in
-   RWG order (may not alias); ratio as above (host, nullable). */
+/* Solve arbitrary right-hand sides: B and X are N x R c128 blocks in RWG
+   order, host or device as X above (may not alias); ratio as above (host,
+   nullable). */
 hps_status hps_solve_rhs(hps_ctx *ctx, int64_t R, const void *B, void *X, double *ratio);
 
-/* Plane-wave excitation only: B (N x R c128, DEVICE, RWG order) = <f_m, E_inc>
+/* Plane-wave excitation only: B (N x R c128, host or device, RWG order) = <f_m, E_inc>
    (EFIE), or the CFIE right-hand side alpha <f_m, E_inc> + eta0 (1 - alpha)
    <f_m, n x H_inc> of eq. (8). */
 hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const double *pol,
@@ -251,7 +268,8 @@ hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const dou
 
 /* Y = H X on the device (near blocks + both directions of every far block;
    for the CFIE every stored block in its own direction),
-   X and Y N x R c128 DEVICE pointers in RWG order.  Valid after hps_setup
+   X and Y N x R c128 blocks (host or device) in RWG order.  The precision
+   form computes it in FP32 (FP32 near blocks and far factors).  Valid after hps_setup
    (its product schedules are built there); HPS_ESTATE before. */
 hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 

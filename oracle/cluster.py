@@ -17,12 +17,15 @@ fix the leaf size by unknown count, so the tree is an octree:
 * unknowns inside a leaf are ordered by RWG index; the tree order of the
   unknowns is the depth-first order of the leaves.
 
-Admissibility: with cubic cells, dia = cell diagonal = sqrt(3) * side and
-dist = the gap between the cells, any eta >= sqrt(3) makes eq. (10) equivalent
-to "the two closed cubes do not touch" (gap >= the smaller side).  That exact
-integer test is used.  Block-cluster recursion from (root, root): a pair that
-does not touch is far; two touching leaves are near; otherwise the non-leaf
-(the coarser one, or both at equal depth) is split.
+Admissibility (eq. 10): eta * dist >= min(dia), with cubic cells, dia = the
+cell diagonal = sqrt(3) * side and dist = the Euclidean gap between the two
+closed cubes, evaluated on the integer coordinates (units of the finest
+grid) as 3 s^2 <= eta^2 d^2, s the smaller side, d^2 the squared gap.  With
+eta >= sqrt(3) (default 2) this is "the two closed cubes do not touch" (their
+gap along some axis is at least the smaller side); eta = 0 admits nothing.
+Block-cluster recursion from (root, root): an admissible pair is far; two
+inadmissible leaves are near; otherwise the non-leaf (the coarser one, or
+both at equal depth) is split.
 """
 
 import numpy as np
@@ -119,14 +122,24 @@ def touch(a, b):
     return True
 
 
-def block_partition(tree):
+def admissible(a, b, eta):
+    """eq. (10) for two cells: eta * gap >= sqrt(3) * (smaller side)."""
+    d2 = 0
+    for (alo, ahi), (blo, bhi) in zip(a.span(), b.span()):
+        gap = max(0, blo - ahi, alo - bhi)
+        d2 += gap * gap
+    side = 1 << (DEPTH_MAX - max(a.depth, b.depth))
+    return eta * eta * float(d2) >= 3.0 * float(side * side)
+
+
+def block_partition(tree, eta=2.0):
     """Return (near, far): near = list of (leaf t, leaf s) with t.leaf_id <=
     s.leaf_id, far = list of (node t, node s) with t.id < s.id."""
     near, far = [], []
     stack = [(tree["root"], tree["root"])]
     while stack:
         t, s = stack.pop()
-        if not touch(t, s):
+        if admissible(t, s, eta):
             if t.id < s.id:
                 far.append((t, s))
             continue

@@ -136,12 +136,13 @@ def _run(job, items, workers, chunk=64):
 
 
 def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1, box_min=0.0, open_surface=False,
-                  formulation="efie", alpha=0.5):
+                  formulation="efie", alpha=0.5, eta=2.0):
     """Mesh -> RWG -> octree -> near blocks (quadrature) + far blocks (ACA).
 
     With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
     near block (Z_F = 0), used to pin the series against a dense LU solve.
-    ``workers`` > 1 evaluates independent blocks in forked processes (the
+    ``eta`` is the admissibility constant of eq. (10) (any value >= sqrt(3):
+    far = cells that do not touch).  ``workers`` > 1 evaluates independent blocks in forked processes (the
     arithmetic of each block is unchanged).  ``box_min`` > 0 stops the octree
     at cells of at least that side (metres), whatever their unknown count.
     ``open_surface`` accepts boundary edges (an open PEC sheet such as the
@@ -163,7 +164,7 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     perm = tree["perm"]
     leaves = tree["leaves"]
     groups = np.array([(nd.lo, nd.hi) for nd in leaves], dtype=np.int64)
-    near_pairs, far_pairs = block_partition(tree)
+    near_pairs, far_pairs = block_partition(tree, eta)
     if not eta_far:
         near_pairs = [(a, b) for a in leaves for b in leaves if a.leaf_id <= b.leaf_id]
         far_pairs = []

@@ -22,17 +22,28 @@ pivot group i with current (already Schur-updated) near-field blocks Z~:
 
 Reading (the paper is silent): the inverse of Z~_ii is LAPACK's LU with
 partial pivoting inside the block (numpy.linalg.inv -> zgesv); no pivoting
-across blocks.  The elimination order is any fill-reducing order; this module
+across blocks.  Breakdown: a block is numerically singular when a pivot of
+that LU (a diagonal entry of U) has modulus below n eps max|Z~_ii| (n the
+block size, eps = 2^-52); the elimination stops there with an error.  The elimination order is any fill-reducing order; this module
 uses minimum degree on the group graph (or the natural order), deliberately
 not the order of the GPU library.  The full two-term result does not depend
 on the order (Z_N = U^T D U exactly, see ``series``).
 """
 
 import numpy as np
+import scipy.linalg
 
 
 class SingularBlock(ArithmeticError):
     pass
+
+
+def pivots_ok(Z):
+    """True when every pivot of LU with partial pivoting of the square block Z
+    has modulus at least n eps max|Z| (eps = 2^-52)."""
+    n = Z.shape[0]
+    lu, _ = scipy.linalg.lu_factor(Z, check_finite=False)
+    return bool(np.min(np.abs(np.diag(lu))) >= n * 2.0 ** -52 * np.max(np.abs(Z)))
 
 
 def group_graph(H):
@@ -107,6 +118,8 @@ def schur_scaling(H, order, rcond_min=0.0):
     L = None if symmetric else {}
     for i in order:
         Zii = W[(i, i)]
+        if not np.any(Zii) or not pivots_ok(Zii):
+            raise SingularBlock("group %d" % i)
         try:
             inv = np.linalg.inv(Zii)
         except np.linalg.LinAlgError as e:

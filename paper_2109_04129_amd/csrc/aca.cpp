@@ -341,7 +341,7 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
   Tree T;
   build_tree(mesh, p.leaf_max, p.leaf_box_min, T);
   std::vector<std::pair<int32_t, int32_t>> near, far;
-  block_partition(T, near, far);
+  block_partition(T, p.eta, near, far);
   if (p.formulation == 1) {            // CFIE: not symmetric, both orders of every block
     const size_t nn0 = near.size(), nf0 = far.size();
     for (size_t b = 0; b < nn0; ++b)

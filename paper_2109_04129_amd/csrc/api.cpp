@@ -77,6 +77,7 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
     return fail(c, HPS_EINVAL, "leaf_box_min must be >= 0");
   if (!(p->series_tol >= 0.0) || !std::isfinite(p->series_tol))
     return fail(c, HPS_EINVAL, "series_tol must be >= 0");
+  if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(c, HPS_EINVAL, "eta must be >= 0");
   if (p->formulation != 0 && p->formulation != 1) return fail(c, HPS_EINVAL, "formulation must be 0 or 1");
   if (p->formulation == 1 && !(p->cfie_alpha >= 0.0 && p->cfie_alpha <= 1.0))
     return fail(c, HPS_EINVAL, "cfie_alpha must be in [0, 1]");
@@ -190,6 +191,7 @@ hps_status hps_params_default(hps_params *p) {
   p->host_near = 0;
   p->formulation = 0;
   p->cfie_alpha = 0.5;
+  p->eta = 2.0;
   return HPS_OK;
 }
 
@@ -605,15 +607,31 @@ hps_status hps_import_hmatrix(hps_ctx *c, const char *path) {
                          near_vals.data(), hdr[4], far_rng.data(), far_rank.data(), far_off.data(), far_uv.data());
 }
 
+// Device bytes a setup with plan P holds: the H-matrix (near blocks, far
+// factors, excitation quadrature data), the working and factor panel sets
+// (both triangles for a non-symmetric field) and, in the precision form, the
+// FP32 panels, FP32 near blocks and the FP32 and 16-bit far factors.
+static uint64_t plan_device_bytes(const hps::Plan &P, const hps::HMatrix &H, const hps_params &prm) {
+  const uint64_t near = H.near_vals.size(), far = H.far_uv.size();
+  const uint64_t pe = (uint64_t)std::max<int64_t>(P.panel_elems, 1) * (H.nonsym ? 2 : 1);
+  uint64_t b = 16 * (near + far) + (uint64_t)H.N * 14 * 10 * 8 + 2 * 16 * pe;
+  if (prm.precision > 0) b += 8 * pe + 8 * near + 8 * far + 4 * far + 8 * (uint64_t)H.n_far();
+  return b;
+}
+
 hps_status hps_setup(hps_ctx *c) {
   if (!c) return HPS_EINVAL;
   if (!c->have_h) return fail(c, HPS_ESTATE, "install an H-matrix first");
-  if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context cannot run the setup");
   return guarded(c, [&]() {
     const double t0 = now_ms();
     hps::Plan P;
     hps::make_plan(c->H, c->mesh, c->params.ordering, c->gseg, P);
     const double t1 = now_ms();
+    const uint64_t need = plan_device_bytes(P, c->H, c->params);
+    if (c->params.device_mem_cap && need > c->params.device_mem_cap)
+      throw hps::Error{HPS_ENOMEM, "setup plan needs " + std::to_string(need) + " device bytes, over device_mem_cap " +
+                                       std::to_string(c->params.device_mem_cap)};
+    if (!c->dev) throw hps::Error{HPS_EDEVICE, "host-only context cannot run the setup"};
     c->dev->times.symbolic_ms = t1 - t0;
     c->have_setup = false;
     c->dev->setup(P, c->H);

@@ -467,6 +467,11 @@ __global__ __launch_bounds__(256) void k_far16(const c2 *__restrict__ in, uint32
 // its pivot-column entry is stored as 1, and the store multiplies row r by
 // 1 / piv_r.  So the step is one rank-1 update of all rows with the pivot
 // row's multiplier set to zero.
+//
+// The chosen pivots are those of LU with partial pivoting (the rows not yet
+// pivoted hold the Schur complement of the pivoted ones).  A block is
+// flagged as numerically singular when a pivot's modulus falls below
+// n eps max|D_ij| (eps = 2^-52, max over the block as loaded).
 
 // 64-bit DPP move inside a wave; lanes outside the 16-lane row or the row
 // mask read 0.
@@ -544,14 +549,25 @@ __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2
   __shared__ int pbuf[2];
   __shared__ int pivrow[NC], stepof[NC];
   __shared__ c2 rowinv[NC];             // 1 / pivot of each row
+  __shared__ double wmax[8 * NC / 64];  // per-wave max |D_ij|^2
   c2 a[RT][CT];
+  double amax = 0.0;
 #pragma unroll
   for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
       const int row = rg * RT + r, col = cg * CT + j;
       a[r][j] = (row < n && col < n) ? src[(int64_t)col * n + row] : make_double2(0.0, 0.0);
+      amax = fmax(amax, a[r][j].x * a[r][j].x + a[r][j].y * a[r][j].y);
     }
+  // singularity threshold on |pivot|^2: (n eps max|D_ij|)^2
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) wmax[wave] = amax;
+  __syncthreads();
+  for (int w = 0; w < 8 * NC / 64; ++w) amax = fmax(amax, wmax[w]);
+  const double tol = (double)n * 0x1p-52;
+  const double thr2 = tol * tol * amax;
   uint32_t used = 0;
 #pragma unroll
   for (int r = 0; r < RT; ++r)
@@ -592,7 +608,10 @@ __global__ __launch_bounds__(8 * NC) void k_inverse(const c2 *__restrict__ W, c2
         const uint32_t klo = __shfl((uint32_t)key, gbase + RB - 1, 64);
         const uint32_t khi = __shfl((uint32_t)(key >> 32), gbase + RB - 1, 64);
         const uint64_t K = ((uint64_t)khi << 32) | klo;
-        const int p = (K >> 7) ? 0x7F - (int)(K & 0x7F) : -1;
+        // no pivot: the column is zero, or its largest |z|^2 (without the
+        // row bits) is below the threshold
+        const bool ok = (K >> 7) && __longlong_as_double((long long)(K & ~(uint64_t)0x7F)) >= thr2;
+        const int p = ok ? 0x7F - (int)(K & 0x7F) : -1;
         if (mine) {
           // column k becomes 1 on the pivot row, 0 elsewhere; the update then
           // leaves -multiplier in the other rows
@@ -1795,6 +1814,7 @@ struct DeviceState::Impl {
   // ---- precision form (FP32 solve operands, 16-bit far factors)
   int precision = 0, refine = 0;
   DevArray<float2> F32, near32;
+  DevArray<float2> farf32;     // FP32 copy of the far factors (residual pass)
   DevArray<uint32_t> far16;
   DevArray<float> fscale;
   DevArray<int32_t> rowpart;   // first far stage, precision form: scale index of each T row
@@ -1831,13 +1851,17 @@ struct DeviceState::Impl {
     wB.alloc(NR); wY.alloc(NR); wW.alloc(NR); wS.alloc(NR); wI.alloc(NR); wX.alloc(NR); wR.alloc(NR); wZ.alloc(NR);
     wT.alloc((size_t)std::max<int64_t>(t_rows, 1) * R);
   }
-  void far32(const float2 *y, float2 *out, int mode) {
-    launch32(b_far1, 0, precision, far16.p, y, wT.p);
-    launch32(b_far2, mode, precision, far16.p, wT.p, out);
+  // Far field in FP32 arithmetic: with the 16-bit factors (at = precision)
+  // or with their FP32 copies (at = 0).
+  void far32(const float2 *y, float2 *out, int mode, int at) {
+    const void *f = at == 0 ? (const void *)farf32.p : (const void *)far16.p;
+    launch32(b_far1, 0, at, f, y, wT.p);
+    launch32(b_far2, mode, at, f, wT.p, out);
   }
   // out = power series applied to in (FP32); in is kept.  With want_ratio
   // the eq. (45) ratios go to rat (device).  No host synchronisation.
-  void series32(int64_t R, const float2 *in, float2 *out, bool want_ratio, int nterms) {
+  // far_at: far factors of the series (precision: 16-bit, 0: FP32).
+  void series32(int64_t R, const float2 *in, float2 *out, bool want_ratio, int nterms, int far_at) {
     const int64_t NR = N * R, RP = R * nseg;
     const unsigned gb = (unsigned)cdiv(NR, 256);
     const dim3 gn((unsigned)R, (unsigned)nseg);
@@ -1855,7 +1879,7 @@ struct DeviceState::Impl {
     float2 *wa = wW.p, *wb = wX.p;
     if (want_ratio) terms_used = 1;
     for (int t = 1; t < nterms; ++t) {
-      far32(wprev, wS.p, 0);
+      far32(wprev, wS.p, 0, far_at);
       for (size_t l = 0; l < b_fwd.size(); ++l) launch32(b_fwd[l], 1, 0, F32.p, wS.p, wS.p);
       launch32(b_dinv, 0, 0, F32.p, wS.p, wI.p);
       if (want_ratio && (t == 1 || adapt)) {
@@ -1873,21 +1897,27 @@ struct DeviceState::Impl {
       if (adapt && converged(RP)) break;
     }
   }
+  // H x in FP32 arithmetic with FP32 near blocks and FP32 far factors.
   void hmatvec32(const float2 *x, float2 *out) {
     launch32(b_near, 0, 0, near32.p, x, out);
-    far32(x, out, 2);
+    far32(x, out, 2, 0);
   }
-  // Precision form of the solve: x = P b, then refine passes
-  // x <- x + P (b - H x); b in wB, x left in wY.
+  // Precision form of the solve: x = P16 b (the series with 16-bit far
+  // factors), then refine passes x <- x + P32 (b - H x), where the residual
+  // and the correction series use the FP32 far factors.  In exact arithmetic
+  // one pass gives the four-term series; the far-factor rounding of the first
+  // pass, x1 - P b = dP b, leaves the pass as (I - P H) dP b = K^2 dP b, so
+  // the pass removes it where the series contracts (||K|| < 1) and cannot
+  // where it does not.  b in wB, x left in wY.
   void solve32(int64_t R) {
     const int64_t NR = N * R;
     const unsigned gb = (unsigned)cdiv(NR, 256);
-    series32(R, wB.p, wY.p, true, terms);
+    series32(R, wB.p, wY.p, true, terms, precision);
     for (int it = 0; it < refine; ++it) {
       hmatvec32(wY.p, wZ.p);
       hipLaunchKernelGGL(k_sub32, dim3(gb), dim3(256), 0, s, wB.p, wZ.p, wR.p, NR);
       HIP_CHECK(hipGetLastError());
-      series32(R, wR.p, wZ.p, false, terms_used);   // the residual pass uses as many terms
+      series32(R, wR.p, wZ.p, false, terms_used, 0);   // the residual pass uses as many terms
       hipLaunchKernelGGL(k_axpy32, dim3(gb), dim3(256), 0, s, wY.p, wZ.p, 1.0f, NR);
       HIP_CHECK(hipGetLastError());
     }
@@ -2809,6 +2839,12 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       if (I.fu[b] + m * r > (int64_t)I.faruv.n || I.fv[b] + n * r > (int64_t)I.faruv.n)
         throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
     }
+    I.farf32.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
+    if (I.faruv.n) {
+      hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv((int64_t)I.faruv.n, 256)), dim3(256), 0, s, I.faruv.p, I.farf32.p,
+                         (int64_t)I.faruv.n);
+      HIP_CHECK(hipGetLastError());
+    }
     I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
     I.fscale.alloc(std::max<size_t>(parts.size(), 1));
     if (!parts.empty()) {
@@ -2852,6 +2888,41 @@ static void check_ready(const DeviceState::Impl *I) {
   if (!I->ready) throw Error{HPS_ESTATE, "setup has not been run"};
 }
 
+// True for memory that kernels address directly (device or managed
+// allocations); false for host memory, which is staged through a copy.
+static bool device_pointer(const void *p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();          // plain host memory unknown to the runtime
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Caller block (its layout, N x R c128) -> internal order in dst; a host
+// block is copied into stage first.
+static void caller_to_internal(DeviceState::Impl &I, const void *src, c2 *dst, c2 *stage, int64_t R) {
+  const int64_t N = I.N, NR = N * R;
+  const c2 *in = (const c2 *)src;
+  if (!device_pointer(src)) {
+    HIP_CHECK(hipMemcpyAsync(stage, src, NR * sizeof(c2), hipMemcpyHostToDevice, I.s));
+    in = stage;
+  }
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, in, dst, I.dperm.p, I.dsoff.p,
+                     I.nseg, N, R, 0);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Internal src -> caller block dst (device, or host through stage).
+static void internal_to_caller(DeviceState::Impl &I, const c2 *src, void *dst, c2 *stage, int64_t R) {
+  const int64_t N = I.N, NR = N * R;
+  const bool dev = device_pointer(dst);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, src, dev ? (c2 *)dst : stage,
+                     I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
+  HIP_CHECK(hipGetLastError());
+  if (!dev) HIP_CHECK(hipMemcpyAsync(dst, stage, NR * sizeof(c2), hipMemcpyDeviceToHost, I.s));
+}
+
 static void upload_planewaves(DeviceState::Impl &I, int64_t R, const double *khat, const double *pol) {
   std::vector<double> kp(6 * R);
   for (int64_t r = 0; r < R; ++r)
@@ -2876,11 +2947,7 @@ void DeviceState::solve_planewaves(int64_t R, const double *khat, const double *
   HIP_CHECK(hipEventRecord(e0.e, I.s));
   I.run(I.g_pw, R, &Impl::core_pw);
   HIP_CHECK(hipEventRecord(e1.e, I.s));
-  if (X) {
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p,
-                       I.dsoff.p, I.nseg, N, R, 1);
-    HIP_CHECK(hipGetLastError());
-  }
+  if (X) internal_to_caller(I, I.vY.p, X, I.vS.p, R);
   HIP_CHECK(hipEventRecord(e2.e, I.s));
   if (rcs) HIP_CHECK(hipMemcpyAsync(rcs, I.red.p + 2 * RP, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
   if (ratio && terms > 1) HIP_CHECK(hipMemcpyAsync(ratio, I.rat.p, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
@@ -2904,13 +2971,9 @@ void DeviceState::solve_rhs(int64_t R, const void *B, void *X, double *ratio) {
   const int64_t N = I.N, NR = N * R, RP = R * I.nseg;
   Ev e0, e1;
   HIP_CHECK(hipEventRecord(e0.e, I.s));
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, (const c2 *)B, I.vB.p, I.dperm.p,
-                     I.dsoff.p, I.nseg, N, R, 0);
-  HIP_CHECK(hipGetLastError());
+  caller_to_internal(I, B, I.vB.p, I.vS.p, R);
   I.run(I.g_rhs, R, &Impl::core_rhs);
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vY.p, (c2 *)X, I.dperm.p,
-                     I.dsoff.p, I.nseg, N, R, 1);
-  HIP_CHECK(hipGetLastError());
+  internal_to_caller(I, I.vY.p, X, I.vS.p, R);
   HIP_CHECK(hipEventRecord(e1.e, I.s));
   if (ratio && terms > 1) HIP_CHECK(hipMemcpyAsync(ratio, I.rat.p, RP * sizeof(double), hipMemcpyDeviceToHost, I.s));
   HIP_CHECK(hipStreamSynchronize(I.s));
@@ -2931,9 +2994,7 @@ void DeviceState::excitation(int64_t R, const double *khat, const double *pol, v
                      I.alpha,
                      I.vB.p);
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)cdiv(NR, 256)), dim3(256), 0, I.s, I.vB.p, (c2 *)B, I.dperm.p,
-                     I.dsoff.p, I.nseg, N, R, 1);
-  HIP_CHECK(hipGetLastError());
+  internal_to_caller(I, I.vB.p, B, I.vS.p, R);
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
@@ -2945,20 +3006,18 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   I.ensure_R(R);
   const int64_t N = I.N, NR = N * R;
   const unsigned g = (unsigned)cdiv(NR, 256);
-  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, I.vS.p, I.dperm.p, I.dsoff.p, I.nseg, N, R, 0);
-  HIP_CHECK(hipGetLastError());
+  caller_to_internal(I, X, I.vS.p, I.vW.p, R);
   if (I.precision == 0) {
     I.launch(I.b_near, 0, I.near.p, I.vS.p, I.vI.p);
     I.far_apply(I.vS.p, I.vI.p, 2);
-  } else {                                  // FP32 near blocks, 16-bit far factors
+  } else {                                  // FP32 near blocks and far factors
     I.ensure32(R);
     hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, I.s, I.vS.p, I.wS.p, NR);
     I.hmatvec32(I.wS.p, I.wI.p);
     hipLaunchKernelGGL(k_to64, dim3(g), dim3(256), 0, I.s, I.wI.p, I.vI.p, NR);
     HIP_CHECK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, I.vI.p, (c2 *)Y, I.dperm.p, I.dsoff.p, I.nseg, N, R, 1);
-  HIP_CHECK(hipGetLastError());
+  internal_to_caller(I, I.vI.p, Y, I.vW.p, R);
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 

@@ -61,7 +61,9 @@ struct Tree {
 // box_min > 0: cells narrower than box_min (metres) are never created.
 void build_tree(const Mesh &m, int leaf_max, double box_min, Tree &t);
 bool cells_touch(const TreeNode &a, const TreeNode &b);
-void block_partition(const Tree &t, std::vector<std::pair<int32_t, int32_t>> &near_leaves,
+// eq. (10): eta dist >= min(dia) for the two cells
+bool admissible(const TreeNode &a, const TreeNode &b, double eta);
+void block_partition(const Tree &t, double eta, std::vector<std::pair<int32_t, int32_t>> &near_leaves,
                      std::vector<std::pair<int32_t, int32_t>> &far_nodes);
 
 // ---------------------------------------------------------------- H-matrix (host copy)

@@ -1,8 +1,12 @@
 // Octree clusters and the near / far split (host).
 //
-// Admissibility (eq. 10) on cubic cells: with dia = sqrt(3) * side and any
-// eta >= sqrt(3), "eta * dist >= min(dia)" holds exactly when the two closed
-// cells do not touch, which is decided on integer cell coordinates.
+// Admissibility (eq. 10) on cubic cells, eta dist >= min(dia), with
+// dia = sqrt(3) * side and dist = the Euclidean gap between the two closed
+// cells, decided on integer cell coordinates (units of the finest grid):
+// 3 s^2 <= eta^2 d^2 with s the smaller side and d^2 the squared gap.  Two
+// cells that do not touch have a gap of at least the smaller side along some
+// axis, so for eta >= sqrt(3) the test is "the cells do not touch"; eta = 0
+// admits nothing (no far field).
 //
 // Cell coordinates: q = floor((p - lo) / s * 2^21), lo = per-axis minimum of
 // the edge midpoints, s = largest extent * (1 + 2^-20).  A cell splits while it
@@ -116,7 +120,19 @@ bool cells_touch(const TreeNode &a, const TreeNode &b) {
   return true;
 }
 
-void block_partition(const Tree &T, std::vector<std::pair<int32_t, int32_t>> &near,
+bool admissible(const TreeNode &a, const TreeNode &b, double eta) {
+  int64_t d2 = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int64_t alo = a.ijk[d] << (kDepth - a.depth), ahi = (a.ijk[d] + 1) << (kDepth - a.depth);
+    const int64_t blo = b.ijk[d] << (kDepth - b.depth), bhi = (b.ijk[d] + 1) << (kDepth - b.depth);
+    const int64_t gap = std::max<int64_t>(0, std::max(blo - ahi, alo - bhi));
+    d2 += gap * gap;
+  }
+  const int64_t side = (int64_t)1 << (kDepth - std::max(a.depth, b.depth));
+  return eta * eta * (double)d2 >= 3.0 * (double)(side * side);
+}
+
+void block_partition(const Tree &T, double eta, std::vector<std::pair<int32_t, int32_t>> &near,
                      std::vector<std::pair<int32_t, int32_t>> &far) {
   near.clear();
   far.clear();
@@ -125,7 +141,7 @@ void block_partition(const Tree &T, std::vector<std::pair<int32_t, int32_t>> &ne
     auto [t, s] = st.back();
     st.pop_back();
     const TreeNode &a = T.nodes[t], &b = T.nodes[s];
-    if (!cells_touch(a, b)) {
+    if (admissible(a, b, eta)) {
       if (t < s) far.push_back({t, s});
       continue;
     }

@@ -40,7 +40,7 @@ class hps_params(ctypes.Structure):
                 ("graphs", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("leaf_box_min", ctypes.c_double), ("series_tol", ctypes.c_double),
                 ("host_near", ctypes.c_int32), ("formulation", ctypes.c_int32),
-                ("cfie_alpha", ctypes.c_double)]
+                ("cfie_alpha", ctypes.c_double), ("eta", ctypes.c_double)]
 
 
 _lib = None

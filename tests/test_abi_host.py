@@ -429,3 +429,53 @@ def test_hmatrix_file_round_trip(tmp_path, formulation):
         assert e.value.status == -1                     # batch context
     finally:
         hps.hps_destroy(bt)
+
+
+@pytest.mark.parametrize("eta", [0.0, 1.0])
+def test_eta_partition_matches_oracle(eta):
+    """hps_params.eta (eq. 10): below sqrt(3) the library's near / far split
+    of the 480-unknown sphere equals the oracle's (more near blocks than the
+    touch test; eta = 0 leaves no far block), and its near field equals the
+    oracle's entries."""
+    from oracle.hmatrix import build_hmatrix
+    from hmat_io import dense_near_from_arrays
+    xyz, tri = icosphere(2, 1.0)
+    H = build_hmatrix(xyz, tri, 300e6, 16, 1e-3, workers=min(8, os.cpu_count() or 1), eta=eta)
+    ctx = hps.hps_create(-1)
+    try:
+        hps.hps_set_mesh(ctx, xyz, tri)
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=300e6, leaf_max=16, eta=-1.0))
+        assert e.value.status == -1
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=300e6, leaf_max=16, aca_tol=1e-3, eta=eta))
+        L = hps.hps_get_hmatrix(ctx)
+    finally:
+        hps.hps_destroy(ctx)
+    assert np.array_equal(L["perm"], H.perm)
+    assert [tuple(x) for x in L["near_ts"].reshape(-1, 2)] == sorted(H.near)
+    assert np.array_equal(L["far_rng"].reshape(-1, 4), np.array([f[:4] for f in H.far], dtype=np.int64).reshape(-1, 4))
+    if eta == 0.0:
+        assert len(H.far) == 0
+    Zo = H.dense_near()
+    assert np.abs(dense_near_from_arrays(L) - Zo).max() <= 1e-13 * np.abs(Zo).max()
+
+
+def test_device_mem_cap_enomem_before_device():
+    """device_mem_cap: hps_setup plans on the host and returns HPS_ENOMEM
+    before touching a device when the plan's device memory exceeds the cap
+    (here on a host-only context, which would otherwise fail with
+    HPS_EDEVICE); a cap the plan fits under gets to the device check."""
+    xyz, tri = icosphere(2, 1.0)
+    ctx = hps.hps_create(-1)
+    try:
+        hps.hps_set_mesh(ctx, xyz, tri)
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=300e6, leaf_max=16, device_mem_cap=1 << 20))
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_setup(ctx)
+        assert e.value.status == -2 and "device_mem_cap" in str(e.value)
+        hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=300e6, leaf_max=16, device_mem_cap=1 << 40))
+        with pytest.raises(hps.HpsError) as e:
+            hps.hps_setup(ctx)
+        assert e.value.status == -3
+    finally:
+        hps.hps_destroy(ctx)

@@ -3,7 +3,7 @@
 import numpy as np
 
 from oracle.aca import aca, recompress
-from oracle.cluster import build_tree, block_partition, touch, Node, DEPTH_MAX
+from oracle.cluster import admissible, build_tree, block_partition, touch, Node, DEPTH_MAX
 from oracle.rwg import build_rwg, edge_midpoints
 from workloads import icosphere
 from conftest import rel
@@ -53,6 +53,69 @@ def test_touch_integer_geometry():
     assert touch(a, node(4, (6, 4, 4)))          # finer cell on the face
     assert not touch(a, node(4, (7, 4, 4)))
     assert DEPTH_MAX == 21
+
+
+def _node(depth, ijk):
+    return Node(depth, ijk, np.zeros(0, dtype=np.int64))
+
+
+def test_admissibility_eq10_worked_cases():
+    """eq. (10), eta dist >= min(dia), on cells of side 1 (depth 21 units):
+    a gap of one side along one axis is dist 1, dia sqrt(3), so the pair is
+    admissible iff eta >= sqrt(3); a diagonal gap of (1, 1, 1) sides is
+    dist sqrt(3), admissible iff eta >= 1; touching cells never are; a cell
+    of side 2 at gap 3 from a unit cell: dist 3, min(dia) sqrt(3),
+    admissible iff eta >= 1/sqrt(3)."""
+    a = _node(21, (10, 10, 10))
+    b = _node(21, (12, 10, 10))
+    r3 = np.sqrt(3.0)
+    assert not admissible(a, b, 1.73) and admissible(a, b, 1.7321)
+    c = _node(21, (12, 12, 12))
+    assert not admissible(a, c, 0.999) and admissible(a, c, 1.0)
+    assert not any(admissible(a, _node(21, (11, 11, 11)), e) for e in (0.0, 2.0, 1e6))
+    d = _node(20, (7, 5, 5))                      # spans [14, 16) x [10, 12) x [10, 12)
+    assert not admissible(a, d, 1.0 / r3 - 1e-9) and admissible(a, d, 1.0 / r3 + 1e-9)
+    assert not admissible(a, b, 0.0)
+
+
+def test_admissibility_above_sqrt3_is_no_touch():
+    """For any eta >= sqrt(3) eq. (10) is the touch test (gap >= the smaller
+    side along some axis when the closed cells do not touch), on random pairs
+    of cells at random depths."""
+    rng = np.random.default_rng(17)
+    for _ in range(4000):
+        da, db = rng.integers(2, 6, size=2)
+        a = _node(int(da), tuple(int(x) for x in rng.integers(0, 1 << da, 3)))
+        b = _node(int(db), tuple(int(x) for x in rng.integers(0, 1 << db, 3)))
+        for eta in (1.7320508075688774, 2.0, 9.0):
+            assert admissible(a, b, eta) == (not touch(a, b))
+
+
+def test_small_eta_partition_by_brute_force():
+    """eta = 1 (below sqrt(3)): the split still covers every (i, j) once; far
+    blocks are admissible, near leaf pairs are not, and some near pairs do
+    not touch; eta = 0 leaves no far block (every leaf pair near)."""
+    xyz, tri = icosphere(3)
+    rwg = build_rwg(xyz, tri)
+    tree = build_tree(edge_midpoints(rwg), 32)
+    N = rwg["N"]
+    near, far = block_partition(tree, 1.0)
+    cover = np.zeros((N, N), dtype=np.int32)
+    for t, s in near:
+        cover[t.lo:t.hi, s.lo:s.hi] += 1
+        if t is not s:
+            cover[s.lo:s.hi, t.lo:t.hi] += 1
+        assert not admissible(t, s, 1.0)
+    for t, s in far:
+        cover[t.lo:t.hi, s.lo:s.hi] += 1
+        cover[s.lo:s.hi, t.lo:t.hi] += 1
+        assert admissible(t, s, 1.0)
+    assert np.all(cover == 1)
+    near2, _ = block_partition(tree, 2.0)
+    assert len(near) > len(near2) and any(not touch(t, s) for t, s in near)
+    n0, f0 = block_partition(tree, 0.0)
+    L = len(tree["leaves"])
+    assert not f0 and len(n0) == L * (L + 1) // 2
 
 
 def test_aca_recovers_exact_low_rank():

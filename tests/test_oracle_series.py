@@ -166,3 +166,51 @@ def test_singular_block_detected():
     near[(2, 3)] = np.zeros_like(near[(2, 3)])
     with pytest.raises(SingularBlock):
         schur_scaling(HMatrix(H.N, H.perm, H.groups, near, []), [0, 1, 2, 3])
+
+
+def test_pivot_threshold_two_by_two():
+    """Numerical singularity = an LU pivot below n eps max|Z|.  For a 2 x 2
+    block with |a| >= |c| partial pivoting keeps row 0, and the pivots are a
+    and d - c b / a in closed form: a second pivot of half the threshold is
+    singular, twice the threshold is not."""
+    from oracle.scaling import pivots_ok
+    a, b, c = 4.0 + 1.0j, 1.0 - 2.0j, 2.0 + 0.5j
+    thr = 2 * 2.0 ** -52 * abs(a)              # max |Z| = |a| here
+    for t, ok in ((0.5, False), (2.0, True)):
+        d = c * b / a + t * thr
+        Z = np.array([[a, b], [c, d]])
+        assert np.max(np.abs(Z)) == abs(a)
+        assert pivots_ok(Z) is ok
+
+
+def test_pivot_threshold_known_lu():
+    """A = L U with |L_ij| < 1 keeps its row order under partial pivoting, so
+    its pivots are diag(U): a pivot of 1e-20 max|A| is flagged, 1e-8 is not."""
+    from oracle.scaling import pivots_ok
+    rng = np.random.default_rng(3)
+    n = 6
+    L = np.tril(0.4 * (rng.uniform(-1, 1, (n, n)) + 1j * rng.uniform(-1, 1, (n, n))), -1) + np.eye(n)
+    U = np.triu(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)), 1)
+    for small, ok in ((1e-20, False), (1e-8, True)):
+        d = np.full(n, 3.0 + 0.0j)
+        d[4] = small
+        A = L @ (U + np.diag(d))
+        assert pivots_ok(A) is ok
+
+
+def test_near_singular_block_detected():
+    """A symmetric diagonal block whose rows 0 and 1 differ in one entry by
+    1e-18 of the block's size is numerically singular: the elimination stops
+    with an error (the exactly singular case is test_singular_block_detected)."""
+    H = _four_block()
+    near = dict(H.near)
+    B = near[(0, 0)].copy()
+    B[0, 1] = B[1, 0] = B[0, 0]
+    B[1, 2] = B[2, 1] = B[0, 2]
+    B[1, 1] = B[0, 0] + 1e-18 * np.abs(B).max()
+    assert np.array_equal(B, B.T)
+    near[(0, 0)] = B
+    with pytest.raises(SingularBlock):
+        schur_scaling(HMatrix(H.N, H.perm, H.groups, near, []), [0, 1, 2, 3])
+    # the untouched matrix factors without complaint
+    schur_scaling(H, [0, 1, 2, 3])

@@ -27,9 +27,11 @@ def theta_hat(theta, phi):
 
 
 def monostatic_angles(theta_deg, phi_deg):
-    """(khat, pol) arrays (R, 3) for monostatic looks at the given angles."""
+    """(khat, pol) arrays (R, 3) for monostatic looks at the given angles.
+    phi is reduced to [0, 360) degrees first, so phi = 360 gives exactly the
+    vectors of phi = 0 (a full azimuth sweep lists that look twice)."""
     t = np.deg2rad(np.asarray(theta_deg, dtype=np.float64))
-    p = np.deg2rad(np.asarray(phi_deg, dtype=np.float64))
+    p = np.deg2rad(np.mod(np.asarray(phi_deg, dtype=np.float64), 360.0))
     t, p = np.broadcast_arrays(t, p)
     return -r_hat(t, p), theta_hat(t, p)
 
