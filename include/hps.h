@@ -273,6 +273,27 @@ hps_status hps_excitation(hps_ctx *ctx, int64_t R, const double *khat, const dou
    (its product schedules are built there); HPS_ESTATE before. */
 hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
+/* Size of the fixed device scratch array used by hps_hmatvec_noalloc (one
+   copy per GPU the library runs on, held until the process ends). */
+#define HPS_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the product
+   of hps_hmatvec, Y = H X, with every work vector in a fixed device scratch
+   array of HPS_SCRATCH_BYTES instead of context buffers sized on demand.  It
+   calls no hipMalloc / hipFree and no host copy, and does not synchronise:
+   the result is in Y once the context's stream reaches this call.
+   X and Y: N x R c128, RWG order, caller-owned DEVICE memory (host memory
+   gives HPS_EINVAL).  The results are bitwise those of hps_hmatvec.
+   Scratch need: 16 (2 N R + t R) bytes for FP64 (t = far rank rows,
+   hps_stats "device" "far_T_rows"), 8 (6 N R + t R) in the precision form, each
+   part rounded up to 256 bytes; a larger
+   R gives HPS_EINVAL naming the largest R that fits.  Every call on a GPU
+   shares that GPU's array: calls that overlap on one GPU (two contexts, two
+   streams, two host threads) race and give wrong results.  Valid after
+   hps_setup; HPS_ESTATE before. */
+hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
+
 /* Per-launch kernel timing: with enable != 0 every grouped-GEMM and inverse
    launch is bracketed by HIP events on the context's stream; hps_stats then
    reports launches, summed device ms, algorithmic flops and bytes per kernel

@@ -698,6 +698,16 @@ hps_status hps_hmatvec(hps_ctx *c, int64_t R, const void *X, void *Y) {
   });
 }
 
+hps_status hps_hmatvec_noalloc(hps_ctx *c, int64_t R, const void *X, void *Y) {
+  if (!c) return HPS_EINVAL;
+  if (!c->have_setup) return fail(c, HPS_ESTATE, "hps_setup first");
+  if (R <= 0 || !X || !Y || X == Y) return fail(c, HPS_EINVAL, "bad matvec arguments");
+  return guarded(c, [&]() {
+    c->dev->hmatvec_noalloc(R, X, Y);
+    return HPS_OK;
+  });
+}
+
 hps_status hps_profile(hps_ctx *c, int enable) {
   if (!c) return HPS_EINVAL;
   if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context");

@@ -63,6 +63,8 @@ class DeviceState {
   void solve_rhs(int64_t R, const void *B, void *X, double *ratio);
   void excitation(int64_t R, const double *khat, const double *pol, void *B);
   void hmatvec(int64_t R, const void *X, void *Y);
+  // hmatvec with its work vectors in the fixed scratch array (no allocation)
+  void hmatvec_noalloc(int64_t R, const void *X, void *Y);
   std::string stats_json() const;
   // EFIE entries of the near blocks of H (structure set, values sized) on the
   // device, copied into H.near_vals; synchronous.

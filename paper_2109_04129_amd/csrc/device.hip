@@ -1503,6 +1503,7 @@ void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, 
 
 struct DeviceState::Impl {
   hipStream_t s;
+  void *scratch = nullptr;         // this device's address of the file-scope scratch array
   // problem
   int64_t N = 0, M = 0, R_cap = 0;
   int nseg = 1;                    // independent problems (batch)
@@ -1822,15 +1823,16 @@ struct DeviceState::Impl {
 
   template <int MODE>
   void g32(const Tile *tiles, const Term *terms, int64_t n, int at, const void *A, const float2 *B, float2 *C,
-           double flops, double bytes) {
+           double flops, double bytes, int64_t ncols = -1) {
     if (n == 0) return;
+    if (ncols < 0) ncols = cur_R;
     const int64_t pr = prof_begin(MODE, flops, bytes, n);
     // store mode (far field, D^-1) in the XCD-aware order, as in launch_tiles
-    const int ny = (int)cdiv(cur_R, TN_SOLVE), xo = MODE == 0 ? 1 : 0;
+    const int ny = (int)cdiv(ncols, TN_SOLVE), xo = MODE == 0 ? 1 : 0;
     const int64_t nwg = cdiv(n, 8) * 8 * (int64_t)ny;
     if (n > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
     dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n, (unsigned)ny), blk(256);
-    const int nc = (int)cur_R, nt = (int)n;
+    const int nc = (int)ncols, nt = (int)n;
     if (at == 0)
       hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     else if (at == 1)
@@ -1840,11 +1842,11 @@ struct DeviceState::Impl {
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
-  void launch32(const Built &b, int mode, int at, const void *A, const float2 *B, float2 *C) {
+  void launch32(const Built &b, int mode, int at, const void *A, const float2 *B, float2 *C, int64_t ncols = -1) {
     const Tile *t = spool.dtiles.p + b.t0;
-    if (mode == 0) g32<0>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
-    else if (mode == 1) g32<1>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
-    else g32<2>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes);
+    if (mode == 0) g32<0>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
+    else if (mode == 1) g32<1>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
+    else g32<2>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
   }
   void ensure32(int64_t R) {
     const int64_t NR = N * R;
@@ -2061,6 +2063,28 @@ struct DeviceState::Impl {
   }
 };
 
+// ------------------------------------------------------------------ fixed scratch
+// Work vectors of the allocation-free H-matrix product (hmatvec_noalloc):
+// one file-scope array per device, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in); it takes each device's address from hipGetSymbolAddress once,
+// with that device current, and uses that address everywhere.
+static __device__ __align__(256) unsigned char scratch[HPS_SCRATCH_BYTES];
+
+static void *scratch_address(int dev) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;       // device ordinal -> address of its copy
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw Error{HPS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  addr[dev] = ptr;
+  return ptr;
+}
+
 DeviceState::DeviceState(int dev, void *strm) : device(dev), stream(strm), own_stream(false) {
   HIP_CHECK(hipSetDevice(dev));
   impl.reset(new Impl());
@@ -2072,6 +2096,7 @@ DeviceState::DeviceState(int dev, void *strm) : device(dev), stream(strm), own_s
   }
   impl->s = (hipStream_t)stream;
   impl->status.alloc(1);
+  impl->scratch = scratch_address(dev);
 }
 
 DeviceState::~DeviceState() {
@@ -3019,6 +3044,85 @@ void DeviceState::hmatvec(int64_t R, const void *X, void *Y) {
   }
   internal_to_caller(I, I.vI.p, Y, I.vW.p, R);
   HIP_CHECK(hipStreamSynchronize(I.s));
+}
+
+// Scratch bytes hmatvec_noalloc needs for R columns (each part 256-byte
+// aligned): FP64 x, y (internal order) and the far intermediate T; the
+// precision form adds FP32 copies of x and y and keeps T in FP32.
+static int64_t noalloc_bytes(const DeviceState::Impl &I, int64_t R, int64_t part[5]) {
+  auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  const int64_t NR = I.N * R, TR = std::max<int64_t>(I.t_rows, 1) * R;
+  const bool f32 = I.precision != 0;
+  part[0] = up(NR * (int64_t)sizeof(c2));                     // x
+  part[1] = up(NR * (int64_t)sizeof(c2));                     // y
+  part[2] = f32 ? up(NR * (int64_t)sizeof(float2)) : 0;       // x, FP32
+  part[3] = f32 ? up(NR * (int64_t)sizeof(float2)) : 0;       // y, FP32
+  part[4] = up(TR * (int64_t)(f32 ? sizeof(float2) : sizeof(c2)));
+  return part[0] + part[1] + part[2] + part[3] + part[4];
+}
+
+// The product of hmatvec on the same kernels, with every work vector in
+// the device's scratch array: no allocation, no host copy, no stream
+// synchronisation (the result is in Y once the context's stream reaches
+// this point).  X and Y must be device memory.
+void DeviceState::hmatvec_noalloc(int64_t R, const void *X, void *Y) {
+  Impl &I = *impl;
+  check_ready(&I);
+  HIP_CHECK(hipSetDevice(device));
+  if (!device_pointer(X) || !device_pointer(Y))
+    throw Error{HPS_EINVAL, "hps_hmatvec_noalloc: X and Y must be device memory"};
+  if (cdiv(R, TN_SOLVE) > 65535 || R > (int64_t)INT32_MAX / 2) throw Error{HPS_EINVAL, "too many columns"};
+  int64_t part[5];
+  const int64_t need = noalloc_bytes(I, R, part);
+  if (need > (int64_t)HPS_SCRATCH_BYTES) {
+    std::ostringstream o;
+    o << "hps_hmatvec_noalloc: " << R << " columns need " << need << " bytes of scratch, the limit is "
+      << (int64_t)HPS_SCRATCH_BYTES << " (at most " << (int64_t)HPS_SCRATCH_BYTES * R / need
+      << " columns for this problem)";
+    throw Error{HPS_EINVAL, o.str()};
+  }
+  unsigned char *base = (unsigned char *)I.scratch;
+  if (!base) throw Error{HPS_EDEVICE, "scratch address not set"};
+  c2 *x = (c2 *)base, *y = (c2 *)(base + part[0]);
+  float2 *xs = (float2 *)(base + part[0] + part[1]), *ys = (float2 *)(base + part[0] + part[1] + part[2]);
+  void *T = base + part[0] + part[1] + part[2] + part[3];
+  order_after_caller(*this);
+  const bool prof_was = I.prof;        // no timing events here
+  I.prof = false;
+  try {
+    const int64_t NR = I.N * R;
+    const unsigned g = (unsigned)cdiv(NR, 256);
+    const int ny = (int)cdiv(R, TN_SOLVE);
+    hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, x, I.dperm.p, I.dsoff.p, I.nseg,
+                       I.N, R, 0);
+    HIP_CHECK(hipGetLastError());
+    // every tile of the near product and of far stage 1 is written in store
+    // mode (every row has its diagonal block; T rows are all covered), so
+    // nothing left in the scratch by an earlier call is read
+    if (I.precision == 0) {
+      const Tile *tl = I.spool.dtiles.p;
+      const Term *tm = I.spool.dterms.p;
+      I.launch_tiles(tl + I.b_near.t0, tm, I.b_near.n_tiles, 0, I.near.p, x, y, ny, 0.0, 0.0, true, (int)R);
+      I.launch_tiles(tl + I.b_far1.t0, tm, I.b_far1.n_tiles, 0, I.faruv.p, x, (c2 *)T, ny, 0.0, 0.0, true, (int)R);
+      I.launch_tiles(tl + I.b_far2.t0, tm, I.b_far2.n_tiles, 2, I.faruv.p, (const c2 *)T, y, ny, 0.0, 0.0, true,
+                     (int)R);
+    } else {
+      hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, I.s, (const c2 *)x, xs, NR);
+      HIP_CHECK(hipGetLastError());
+      I.launch32(I.b_near, 0, 0, I.near32.p, xs, ys, R);
+      I.launch32(I.b_far1, 0, 0, I.farf32.p, xs, (float2 *)T, R);
+      I.launch32(I.b_far2, 2, 0, I.farf32.p, (const float2 *)T, ys, R);
+      hipLaunchKernelGGL(k_to64, dim3(g), dim3(256), 0, I.s, (const float2 *)ys, y, NR);
+      HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)y, (c2 *)Y, I.dperm.p, I.dsoff.p,
+                       I.nseg, I.N, R, 1);
+    HIP_CHECK(hipGetLastError());
+  } catch (...) {
+    I.prof = prof_was;
+    throw;
+  }
+  I.prof = prof_was;
 }
 
 namespace {
