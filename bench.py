@@ -62,18 +62,34 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sphere_s5_790MHz")
+    ap.add_argument("--workload", default="ellipsoid_4x2x1_300MHz")
+    ap.add_argument("--leg-steps", type=int, default=1,
+                    help="timed steps of each secondary leg (precision forms, CFIE, the second workload)")
+    ap.add_argument("--second-workload", default="sphere_s5_790MHz",
+                    help="secondary workload (plain, precision form and single-RHS legs); '' for none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form legs")
     ap.add_argument("--no-cfie", action="store_true", help="skip the CFIE leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 32-ellipsoid batching leg")
+    ap.add_argument("--cpu-sample-unknowns", type=int, default=16384,
+                    help="largest cluster of the workload the oracle sample may take")
     ap.add_argument("--cpu-rhs", type=int, default=8, help="RHS in the oracle's timed sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
-    ap.add_argument("--batch", action="store_true",
-                    help="also run the batching form on the 32-ellipsoid workload (host H-matrix build "
-                         "of 735k unknowns takes a few minutes)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="headline leg only (for profiler runs): no secondary legs, no baseline")
     ap.add_argument("--batch-workload", default="ellipsoids32_600MHz")
+    ap.add_argument("--leaf-study", action="store_true",
+                    help="run only the leaf-size study (Sec. V.A): two-term and converged-series error against "
+                         "the direct solution vs leaf size, EFIE and CFIE; prints its own JSON line")
     return ap.parse_args()
+
+
+T_START = time.perf_counter()
+
+
+def log(msg):
+    print("[bench %7.1f s] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
 
 
 def build_hmatrix(w, **extra):
@@ -107,7 +123,12 @@ def install(hps, ctx, p, g):
                         g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
 
 
-def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None, reference_tol=0.0):
+def gpu_leg(args, w, g, steps, warmup, precision=0, refine=0, reference_terms=None, extra=None,
+            reference_tol=0.0, profile=True):
+    """`steps` timed steps (hps_setup + the whole sweep's hps_solve_planewaves)
+    after `warmup` untimed ones, unprofiled: solves are replayed from their
+    captured graph, as in production.  Then, with `profile`, one more step
+    with HIP events around every launch, for the per-kernel figures."""
     import torch
     from paper_2109_04129_amd import hps
 
@@ -130,6 +151,7 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None,
     khat, pol = w["khat"], w["pol"]
     R = len(khat)
     X = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
+    status = []
 
     def step():
         ts = time.perf_counter()
@@ -137,33 +159,32 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None,
         tm = time.perf_counter()
         st, rcs, ratio = hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
         te = time.perf_counter()
+        status.append(st)
         return tm - ts, te - tm, rcs, ratio
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
-        print("[bench] warmup step done", file=sys.stderr, flush=True)
+        log("warmup step done")
     torch.cuda.synchronize()
-    hps.hps_profile(ctx, True)          # HIP events around every kernel launch of the timed steps
     setup_t, solve_t = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         a, b, rcs, ratio = step()
         setup_t.append(a)
         solve_t.append(b)
-        print("[bench] step done", file=sys.stderr, flush=True)
+        log("step done")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     stats = hps.hps_stats(ctx)
-    # the same steps without per-launch events (solves replayed from their
-    # captured graph, the production mode); reported beside the timed value
-    hps.hps_profile(ctx, False)
-    step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
+    if profile:
+        # one step with HIP events around every kernel launch (no graph
+        # replay): per-kernel time, algorithmic flops and bytes, launch log
+        hps.hps_profile(ctx, True)
         step()
-    torch.cuda.synchronize()
-    total_unprofiled = time.perf_counter() - t1
+        torch.cuda.synchronize()
+        stats = hps.hps_stats(ctx)
+        hps.hps_profile(ctx, False)
+        log("profiled step done")
     hps.hps_destroy(ctx)
     err = None
     if reference_terms:
@@ -183,13 +204,77 @@ def gpu_leg(args, w, g, precision=0, refine=0, reference_terms=None, extra=None,
         Xr = Xr.cpu().numpy()
         used = hps.hps_stats(ref).get("device", {}).get("terms_used")
         hps.hps_destroy(ref)
+        log("reference solve done")
         err = {"terms_of_reference": reference_terms if reference_tol <= 0 else
                "adaptive to %g (%s terms)" % (reference_tol, used),
                "current_rel_err_max": float(np.max(np.linalg.norm(Xm - Xr, axis=1) / np.linalg.norm(Xr, axis=1))),
+               "current_rel_err_median": float(np.median(np.linalg.norm(Xm - Xr, axis=1) /
+                                                         np.linalg.norm(Xr, axis=1))),
                "rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs / rcs_r))))}
-    return dict(N=N, R=R, total=total, total_unprofiled=total_unprofiled, setup=np.array(setup_t),
-                solve=np.array(solve_t), rcs=rcs,
-                ratio=ratio, stats=stats, err=err)
+    return dict(N=N, R=R, total=total, steps=steps, setup=np.array(setup_t), solve=np.array(solve_t), rcs=rcs,
+                ratio=ratio, status=status[-1], stats=stats, err=err)
+
+
+def single_rhs_leg(args, w, g, precision=0, reps=10):
+    """One right-hand side (the sweep's first direction): the solve is a
+    chain of matrix-vector products, bound by HBM bandwidth.  Device time of
+    the solve (HIP events around its graph replay, median of `reps`), then
+    one profiled solve for the per-kernel algorithmic bytes."""
+    import torch
+    from paper_2109_04129_amd import hps
+    stream = torch.cuda.current_stream()
+    ctx = hps.hps_create(0, stream.cuda_stream)
+    try:
+        set_mesh(hps, ctx, w)
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
+                                   precision=precision, refine_passes=1 if precision else 0)
+        install(hps, ctx, p, g)
+        hps.hps_setup(ctx)
+        N = hps.hps_num_unknowns(ctx)
+        khat, pol = w["khat"][:1], w["pol"][:1]
+        X = torch.zeros((1, N), dtype=torch.complex128, device="cuda")
+        dev_ms, wall = [], []
+        for i in range(reps + 2):          # direct launch, graph capture, then replays
+            t0 = time.perf_counter()
+            hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+            t1 = time.perf_counter()
+            if i >= 2:
+                dev_ms.append(hps.hps_stats(ctx)["device"]["times_ms"]["solve"])
+                wall.append(t1 - t0)
+        hps.hps_profile(ctx, True)
+        hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+        torch.cuda.synchronize()
+        st = hps.hps_stats(ctx)
+        hps.hps_profile(ctx, False)
+    finally:
+        hps.hps_destroy(ctx)
+    dev = st["device"]
+    ks = dev.get("kernels", {})
+    gemm_bytes = sum(ks.get(k, {}).get("bytes", 0.0) for k in ("gemm_store", "gemm_sub", "gemm_add"))
+    gemm_ms = sum(ks.get(k, {}).get("ms", 0.0) for k in ("gemm_store", "gemm_sub", "gemm_add"))
+    solve_ms = float(np.median(dev_ms))
+    esz = 8 if precision else 16
+    # SURVEY-style per-RHS count: every coefficient entry read in each of the
+    # four sweeps, D^-1 twice, every stored far entry twice (one far product:
+    # stage 1 and stage 2 each read every factor once)
+    formula = esz * (4.0 * dev["n_U"] + 2.0 * dev["n_D"]) + (4 if precision else 16) * 2.0 * dev["far_elems"]
+    k = ks.get("gemm_sub", {})
+    sub = None
+    if k.get("ms"):
+        sub = {"kernel": "k_gemm<1> (sweeps)", "bound": "hbm", "achieved": k["bytes"] / (k["ms"] * 1e-3) / 1e9,
+               "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+               "frac": k["bytes"] / (k["ms"] * 1e-3) / PEAK["hbm"],
+               "launches": k["launches"], "avg_launch_us": 1e3 * k["ms"] / k["launches"],
+               "algorithmic_bytes_per_launch": k["bytes"] / k["launches"]}
+    return {"workload": w["name"], "precision": precision, "N": N,
+            "solve_ms_device": solve_ms, "solve_ms_wall": 1e3 * float(np.median(wall)),
+            "rhs_per_s": 1e3 / solve_ms,
+            "algorithmic_bytes": formula,
+            "achieved_gb_s": formula / (solve_ms * 1e-3) / 1e9,
+            "hbm_frac": formula / (solve_ms * 1e-3) / PEAK["hbm"],
+            "gemm_launch_bytes": gemm_bytes, "gemm_launch_ms": gemm_ms,
+            "gemm_achieved_gb_s": gemm_bytes / (gemm_ms * 1e-3) / 1e9 if gemm_ms else None,
+            "dominant_kernel": sub}
 
 
 def batch_leg(args):
@@ -243,12 +328,14 @@ def batch_leg(args):
             su.append(tb - ta)
         return np.array(su), np.array(so), rcs, ratio
 
+    K = args.leg_steps
+
     def run_batch(c, precision):
         Xb = torch.zeros(R * NT, dtype=torch.complex128, device="cuda")
-        timed(c, Xb, args.warmup)
+        timed(c, Xb, 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        su, so, rcs, ratio = timed(c, Xb, args.steps)
+        su, so, rcs, ratio = timed(c, Xb, K)
         torch.cuda.synchronize()
         return dict(total=time.perf_counter() - t0, setup=su, solve=so, rcs=rcs, X=Xb.cpu().numpy())
 
@@ -273,10 +360,10 @@ def batch_leg(args):
         hps.hps_set_hmatrix(c, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
                             a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
         Xp = torch.zeros((R, Ns[p]), dtype=torch.complex128, device="cuda")
-        timed(c, Xp, args.warmup)
+        timed(c, Xp, 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        su, so, rcs_p, _ = timed(c, Xp, args.steps)
+        su, so, rcs_p, _ = timed(c, Xp, K)
         torch.cuda.synchronize()
         seq_total += time.perf_counter() - t0
         seq_setup += float(np.median(su))
@@ -301,7 +388,6 @@ def batch_leg(args):
         off += Ns[p]
         hps.hps_destroy(c)
         print("[bench] plain problem %d/%d done" % (p + 1, P), file=sys.stderr, flush=True)
-    K = args.steps
     out = {"workload": bw["name"], "problems": P, "rhs_per_problem": R, "unknowns": NT,
            "unknowns_min_max": [min(Ns), max(Ns)], "hmatrix_build_s": build_s,
            "plain_sequential": {"rhs_per_s_step": P * R * K / seq_total, "setup_s": seq_setup,
@@ -319,34 +405,264 @@ def batch_leg(args):
     return out
 
 
+def oracle_work(sizes, adj, order):
+    """The oracle's own arithmetic, in complex multiply-adds, of its block
+    elimination (eqs. 16-21, both triangles of every Schur update, as its
+    schur_scaling does) in the given order, and of one right-hand side of its
+    two-term solve without the far field: returns (setup MACs, 4 n_U + 2 n_D)."""
+    nbr = {g: set(v) for g, v in adj.items()}
+    done, setup, nU, nD = set(), 0.0, 0.0, 0.0
+    for i in order:
+        later = [j for j in nbr[i] if j not in done]
+        ni = float(sizes[i])
+        nF = float(sum(sizes[j] for j in later))
+        setup += ni ** 3 + ni * ni * nF + ni * nF * nF
+        nU += ni * nF
+        nD += ni * ni
+        for j in later:
+            nbr[j].update(k for k in later if k != j)
+        done.add(i)
+    return setup, 4.0 * nU + 2.0 * nD
+
+
 def cpu_leg(args, w):
-    """The oracle, untuned, on the host cores: its own H-matrix (untimed),
-    its setup (timed) and the solve of the first --cpu-rhs RHS (timed)."""
+    """The oracle, untuned, on the host cores, on a bounded sample of the
+    same workload: the principal sub-H-matrix of one octree cluster (the
+    largest with at most --cpu-sample-unknowns unknowns; its near and far
+    blocks as the oracle builds them, untimed), its setup (timed) and the
+    two-term solve of the first --cpu-rhs directions restricted to the
+    cluster (timed).  Both times are scaled to the whole problem by the
+    oracle's own operation counts (minimum-degree elimination of the full
+    group graph vs the cluster's); far products by the summed far-block
+    sizes.  The result is an extrapolation and is labelled so."""
     from threadpoolctl import threadpool_info
-    from oracle.hmatrix import build_hmatrix
+    from oracle.hmatrix import build_hmatrix_cluster
     from oracle.planewave import excitation
     from oracle.scaling import group_graph, min_degree_order, schur_scaling
     from oracle.series import PowerSeries
     workers = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
-    H = build_hmatrix(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"], workers=workers,
-                      open_surface=w.get("open", False))
-    print("[bench] oracle H-matrix built in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    H, info = build_hmatrix_cluster(w["xyz"], w["tri"], w["freq_hz"], w["leaf_max"], w["aca_tol"],
+                                    args.cpu_sample_unknowns, workers=workers)
+    log("oracle cluster sample (%d of %d unknowns, %d groups) built in %.1f s"
+        % (H.N, info["N"], H.M, time.perf_counter() - t0))
     t0 = time.perf_counter()
-    S = schur_scaling(H, min_degree_order(group_graph(H)))
+    order = min_degree_order(group_graph(H))
+    S = schur_scaling(H, order)
     setup_s = time.perf_counter() - t0
-    print("[bench] oracle setup %.1f s" % setup_s, file=sys.stderr, flush=True)
+    log("oracle sample setup %.1f s" % setup_s)
     R = args.cpu_rhs
-    b = excitation(H.rwg, w["freq_hz"], w["khat"][:R], w["pol"][:R])
+    b = excitation(info["rwg"], w["freq_hz"], w["khat"][:R], w["pol"][:R])[H.rwg_index]
     t0 = time.perf_counter()
-    PowerSeries(H, S).solve_rwg(b, 2)
+    PowerSeries(H, S).solve(b, 2)
     solve_s = time.perf_counter() - t0
+    log("oracle sample solve %.2f s" % solve_s)
+    # operation counts of the sample and of the whole problem, oracle's order
+    gs = [int(hi - lo) for lo, hi in H.groups]
+    su_s, near_s = oracle_work(gs, group_graph(H), order)
+    adj = {g: set() for g in range(len(info["leaf_sizes"]))}
+    for t, u in info["near_pairs"]:
+        if t != u:
+            adj[t].add(u)
+            adj[u].add(t)
+    su_f, near_f = oracle_work(info["leaf_sizes"], adj, min_degree_order(adj))
+    far_s = float(sum(2 * U.shape[1] * (U.shape[0] + V.shape[0]) for *_, U, V in H.far))
+    msum_s = float(sum((thi - tlo) + (shi - slo) for tlo, thi, slo, shi, _, _ in H.far))
+    msum_f = float(sum(m + n for m, n in info["far_sizes"]))
+    far_f = far_s * msum_f / max(msum_s, 1.0)
+    setup_full = setup_s * su_f / su_s
+    per_rhs_full = solve_s / R * (near_f + far_f) / (near_s + far_s)
+    RT = len(w["khat"])
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": R / solve_s, "unit": "RHS/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of the %d RHS (theta = 0..%d deg) of the same workload, two-term solve "
-                      "after the oracle's own H-matrix build (%d worker processes, untimed) and setup"
-                      % (R, len(w["khat"]), R - 1, workers),
-            "setup_s": setup_s, "host_cpus": os.cpu_count()}
+    return {"value": RT / (setup_full + RT * per_rhs_full), "unit": "RHS/s", "cores": threads, "kind": "oracle",
+            "sample": ("extrapolation: the oracle (untuned) on the principal sub-H-matrix of one octree cluster "
+                       "of the same workload (%d of %d unknowns, %d of %d groups), setup timed %.1f s and the "
+                       "two-term solve of the first %d of its %d directions timed %.2f s, scaled by the oracle's "
+                       "own operation counts (minimum-degree block elimination of the full group graph: setup "
+                       "x%.1f, near solve per RHS x%.1f; far products by summed far-block sizes); value = "
+                       "whole-sweep RHS / (extrapolated setup + %d x extrapolated per-RHS solve)"
+                       % (H.N, info["N"], H.M, len(info["leaf_sizes"]), setup_s, R, RT, solve_s, su_f / su_s,
+                          near_f / near_s, RT)),
+            "extrapolated_setup_s": setup_full, "extrapolated_solve_rhs_per_s": 1.0 / per_rhs_full,
+            "sample_setup_s": setup_s, "sample_solve_s": solve_s, "sample_unknowns": H.N,
+            "host_cpus": os.cpu_count()}
+
+
+def roofline_from(stats, steps=1):
+    """Roofline object of the dominant kernel (k_gemm<1>: Schur updates and
+    sweeps, complex FP64 on MFMA) from one profiled step.  Setup Schur
+    updates and multi-RHS sweeps are dense contractions: bound = FP64 MFMA;
+    the per-launch algorithmic bytes are reported beside it."""
+    dev = dict(stats.get("device", {}))
+    log_ = dev.pop("launch_log", None) or []
+    k = dev.get("kernels", {}).get(DOMINANT, {})
+    if not (k.get("ms") and k.get("bytes")):
+        return None, dev
+    classes = []
+    sub = [x for x in log_ if x[0] == 1 and len(x) >= 5]
+    for lo, hi in ((0, 1e7), (1e7, 1e8), (1e8, 1e9), (1e9, float("inf"))):
+        sel = [x for x in sub if lo <= x[3] < hi]
+        if sel:
+            b, f, t = sum(x[3] for x in sel), sum(x[2] for x in sel), sum(x[4] for x in sel) * 1e-3
+            classes.append({"bytes_per_launch": [lo, hi if hi != float("inf") else None],
+                            "launches_per_step": len(sel) / steps, "ms_per_step": 1e3 * t / steps,
+                            "achieved_gb_s": b / t / 1e9, "hbm_frac": b / t / PEAK["hbm"],
+                            "achieved_tflops": f / t / 1e12, "intensity_flop_per_byte": f / b})
+    sec = k["ms"] * 1e-3
+    flop_rate, byte_rate = k["flops"] / sec, k["bytes"] / sec
+    return {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": "mfma",
+            "achieved": flop_rate / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+            "frac": flop_rate / PEAK["fp64"],
+            "flops_per_launch": k["flops"] / k["launches"],
+            "algorithmic_bytes_per_launch": k["bytes"] / k["launches"],
+            "achieved_gb_s_algorithmic": byte_rate / 1e9, "hbm_frac_algorithmic": byte_rate / PEAK["hbm"],
+            "intensity_flop_per_byte": k["flops"] / k["bytes"], "ridge_flop_per_byte": PEAK["fp64"] / PEAK["hbm"],
+            "launches_per_step": k["launches"] / steps, "avg_launch_us": 1e3 * k["ms"] / k["launches"],
+            "by_launch_size": classes}, dev
+
+
+def form_summary(gm, base):
+    """Figures of one leg, with its speed against the plain FP64 leg."""
+    rate = gm["R"] * gm["steps"] / gm["total"]
+    return {"rhs_per_s_step": rate, "ms_per_step": 1e3 * gm["total"] / gm["steps"], "steps": gm["steps"],
+            "setup_s": float(np.median(gm["setup"])),
+            "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
+            "speedup_step_vs_plain_fp64": rate / (base["R"] * base["steps"] / base["total"]),
+            "speedup_solve_vs_plain_fp64": float(np.median(base["solve"]) / np.median(gm["solve"])),
+            "ratio_max": float(np.max(gm["ratio"])), "status": gm["status"],
+            "accuracy_vs_fp64": gm["err"]}
+
+
+def precision_legs(args, w, hm, base, variants=((1, "bf16_far"), (2, "fp16_far"))):
+    """The precision form (FP32 solve operands on MFMA, 16-bit far factors
+    with per-block FP32 scale, FP64 setup) with one FP32 residual pass, i.e.
+    the four-term series: BF16 far factors (the configured form) and FP16;
+    accuracy against the FP64 four-term series on the same H-matrix."""
+    forms = {}
+    for prec, name in variants:
+        gm = gpu_leg(args, w, hm, args.leg_steps, 1, precision=prec, refine=1, reference_terms=4, profile=False)
+        forms[name] = dict(form_summary(gm, base), residual_passes=1)
+        log("precision form %s done" % name)
+    return {"form": "FP32 near operands on MFMA, 16-bit far factors with per-block FP32 scale, FP64 setup, "
+                    "one FP32 residual pass (= four-term series), against the FP64 four-term series",
+            "variants": forms}
+
+
+def cfie_leg(args, w):
+    """CFIE of eq. (8), alpha = 0.5, on the same mesh: its own H-matrix
+    (both orders of every block), left and right coefficients; accuracy of
+    the two-term series against the converged series."""
+    extra = {"formulation": 1, "cfie_alpha": 0.5}
+    hc, bc = build_hmatrix(w, **extra)
+    gc = gpu_leg(args, w, hc, args.leg_steps, 1, extra=extra, reference_terms=60, reference_tol=1e-10, profile=False)
+    dc = gc["stats"].get("device", {})
+    out = {"form": "CFIE alpha 0.5, plain fp64, two terms", "workload": w["name"],
+           "rhs_per_s_step": gc["R"] * gc["steps"] / gc["total"],
+           "ms_per_step": 1e3 * gc["total"] / gc["steps"],
+           "setup_s": float(np.median(gc["setup"])),
+           "solve_rhs_per_s": float(gc["R"] / np.median(gc["solve"])),
+           "hmatrix_build_s": bc, "ratio_max": float(np.max(gc["ratio"])),
+           "ratio_median": float(np.median(gc["ratio"])),
+           "two_terms_vs_converged_series": gc["err"],
+           "factor_bytes": dc.get("factor_bytes"), "upper_blocks": dc.get("upper_blocks")}
+    ea = dict(extra, terms=40, series_tol=1e-4)
+    ga = gpu_leg(args, w, hc, args.leg_steps, 1, extra=ea, reference_terms=60, reference_tol=1e-10, profile=False)
+    out["adaptive_series_1e-4"] = {
+        "rhs_per_s_step": ga["R"] * ga["steps"] / ga["total"],
+        "solve_rhs_per_s": float(ga["R"] / np.median(ga["solve"])),
+        "terms_used": ga["stats"].get("device", {}).get("terms_used"),
+        "vs_converged_series": ga["err"]}
+    return out
+
+
+def secondary_leg(args, name):
+    """The 30,720-unknown sphere: plain FP64 step, precision forms, R = 1."""
+    from workloads import workload
+    w = workload(name)
+    w["name"] = name
+    hm, build_s = build_hmatrix(w)
+    g = gpu_leg(args, w, hm, max(args.leg_steps, 3), 1)
+    roof, dev = roofline_from(g["stats"])
+    out = {"workload": name, "N": g["N"], "rhs": g["R"], "hmatrix_build_s": build_s,
+           "rhs_per_s_step": g["R"] * g["steps"] / g["total"], "ms_per_step": 1e3 * g["total"] / g["steps"],
+           "setup_s": float(np.median(g["setup"])), "solve_rhs_per_s": float(g["R"] / np.median(g["solve"])),
+           "ratio_max": float(np.max(g["ratio"])), "roofline": roof,
+           "device_stats": {k: dev.get(k) for k in ("levels", "upper_blocks", "n_U", "n_D", "setup_flops",
+                                                     "factor_bytes", "far_elems")}}
+    if not args.no_mixed:
+        out["precision_form"] = precision_legs(args, w, hm, g)
+    out["single_rhs"] = single_rhs_leg(args, w, hm)
+    log("secondary workload done")
+    if not args.no_cfie:
+        out["cfie_form"] = cfie_leg(args, w)
+        log("CFIE leg done")
+    return out
+
+
+def leaf_study(args):
+    """Sec. V.A (Fig. 4): accuracy of the two-term series against the direct
+    solution of the same discretisation as the leaves grow, with the eq. (45)
+    ratio.  Sphere r = 1 m, icosphere subdivision 4 (7,680 unknowns) at
+    400 MHz (edges about lambda/10).  The direct solution is the library's own
+    with eta = 0 (nothing admissible: Z_F = 0, every leaf pair a near block,
+    so the setup is a block LDL^T of the full MoM matrix and one series term
+    solves exactly).  Leaves by unknown count (octree split while a cell has
+    more than leaf_max) and by electrical size (cells never narrower than
+    leaf_box_min).  Error = max over RHS of ||x - x_dir|| / ||x_dir||, for two
+    terms and for the series run until ||it_t|| / ||it_0|| < 1e-8 (at most 60
+    terms; it only converges where the ratio is below one)."""
+    import torch
+    from paper_2109_04129_amd import hps
+    from workloads import icosphere, monostatic_angles
+    freq = 400e6
+    lam = 299792458.0 / freq
+    xyz, tri = icosphere(4, 1.0)
+    khat, pol = monostatic_angles([0.0, 45.0, 90.0, 135.0, 180.0], [0.0, 0.0, 0.0, 0.0, 0.0])
+    R = len(khat)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def solve(form, leaf, box, eta, terms, tol=0.0):
+        ctx = hps.hps_create(0, stream)
+        try:
+            hps.hps_set_mesh(ctx, xyz, tri)
+            p = hps.hps_params_default(freq_hz=freq, leaf_max=leaf, aca_tol=1e-3, terms=terms, series_tol=tol,
+                                       leaf_box_min=box, eta=eta, formulation=form, cfie_alpha=0.5)
+            hps.hps_build_hmatrix(ctx, p)
+            hps.hps_setup(ctx)
+            N = hps.hps_num_unknowns(ctx)
+            X = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
+            st, rcs, ratio = hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+            torch.cuda.synchronize()
+            d = hps.hps_stats(ctx)
+            dev = d.get("device", {})
+            return X.cpu().numpy(), ratio, rcs, dict(groups=(d.get("hmatrix") or {}).get("groups"), terms_used=dev.get("terms_used"),
+                                                     far_blocks=(d.get("hmatrix") or {}).get("far_blocks"))
+        finally:
+            hps.hps_destroy(ctx)
+
+    def err(x, ref):
+        return float(np.max(np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+
+    rows = []
+    cases = [("count", lf, 0.0) for lf in (32, 64, 128, 256, 512)] + \
+            [("box", 1024, f * lam) for f in (0.25, 0.5, 0.75, 1.0)]
+    for form, fname in ((0, "EFIE"), (1, "CFIE alpha 0.5")):
+        xd, _, rcs_d, _ = solve(form, 128, 0.0, 0.0, 1)
+        log("leaf study %s: direct solution done" % fname)
+        for kind, leaf, box in cases:
+            x2, ratio, rcs2, info = solve(form, leaf, box, 2.0, 2)
+            xc, _, _, infoc = solve(form, leaf, box, 2.0, 60, 1e-8)
+            rows.append({"formulation": fname, "leaves": kind, "leaf_max": leaf, "leaf_box_min_lambda": box / lam,
+                         "groups": info["groups"], "mean_unknowns_per_group": 7680.0 / max(info["groups"] or 1, 1),
+                         "ratio_eq45_max": float(np.max(ratio)), "ratio_eq45_median": float(np.median(ratio)),
+                         "two_term_err_vs_direct": err(x2, xd),
+                         "two_term_rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs2 / rcs_d)))),
+                         "series_1e-8_err_vs_direct": err(xc, xd), "series_terms_used": infoc["terms_used"]})
+            log("leaf study %s %s %s done" % (fname, kind, leaf if kind == "count" else box / lam))
+    return {"study": "leaf size (Sec. V.A, Fig. 4 metric)", "workload": "sphere r=1 m, icosphere subdiv 4, "
+            "7,680 unknowns, 400 MHz (lambda %.4f m), ACA 1e-3, 5 monostatic RHS theta = 0..180 step 45" % lam,
+            "direct": "library, eta = 0 (no far blocks: block LDL^T of the full MoM matrix, one term)",
+            "rows": rows}
 
 
 def main():
@@ -355,101 +671,34 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.leaf_study:
+        print(json.dumps(leaf_study(args)), flush=True)
+        return
     from workloads import workload
     w = workload(args.workload)
+    w["name"] = args.workload
     hm, build_s = build_hmatrix(w)
-    print("[bench] workload %s: %d unknowns, %d RHS" % (args.workload, hm["N"], len(w["khat"])), file=sys.stderr,
-          flush=True)
-    g = gpu_leg(args, w, hm)
-    mixed = None
-    if not args.no_mixed:
-        forms = {}
-
-        def form(gm, **more):
-            return dict({"rhs_per_s_step": gm["R"] * args.steps / gm["total"],
-                         "rhs_per_s_step_unprofiled": gm["R"] * args.steps / gm["total_unprofiled"],
-                         "setup_s": float(np.median(gm["setup"])),
-                         "solve_rhs_per_s": float(gm["R"] / np.median(gm["solve"])),
-                         "speedup_solve_vs_plain_fp64": float(np.median(g["solve"]) / np.median(gm["solve"])),
-                         "speedup_step_unprofiled_vs_plain_fp64": float(g["total_unprofiled"] /
-                                                                        gm["total_unprofiled"]),
-                         "accuracy_vs_fp64": gm["err"]}, **more)
-
-        for prec, name in ((1, "bf16_far"), (2, "fp16_far")):
-            forms[name] = form(gpu_leg(args, w, hm, precision=prec, refine=1, reference_terms=4), residual_passes=1)
-        # the same FP32 / FP16 operands without the residual pass: the
-        # two-term series itself, against the FP64 two-term series
-        forms["fp16_far_two_terms"] = form(gpu_leg(args, w, hm, precision=2, refine=0, reference_terms=2),
-                                           residual_passes=0)
-        mixed = {"form": "FP32 near operands on MFMA, 16-bit far factors with per-block FP32 scale, "
-                         "FP64 setup; bf16_far / fp16_far add one FP32 residual pass (= four-term series)",
-                 "variants": forms}
-    cfie = None
-    if not args.no_cfie and not w.get("open"):
-        # CFIE of eq. (8), alpha = 0.5, on the same mesh: its own H-matrix
-        # (both orders of every block), left and right coefficients; accuracy
-        # of the two-term series against the converged series
-        extra = {"formulation": 1, "cfie_alpha": 0.5}
-        hc, bc = build_hmatrix(w, **extra)
-        gc = gpu_leg(args, w, hc, extra=extra, reference_terms=60, reference_tol=1e-10)
-        dc = gc["stats"].get("device", {})
-        cfie = {"form": "CFIE alpha 0.5, plain fp64, two terms",
-                "rhs_per_s_step": gc["R"] * args.steps / gc["total"],
-                "ms_per_step": 1e3 * gc["total"] / args.steps,
-                "setup_s": float(np.median(gc["setup"])),
-                "solve_rhs_per_s": float(gc["R"] / np.median(gc["solve"])),
-                "hmatrix_build_s": bc, "ratio_max": float(np.max(gc["ratio"])),
-                "ratio_median": float(np.median(gc["ratio"])),
-                "two_terms_vs_converged_series": gc["err"],
-                "factor_bytes": dc.get("factor_bytes"), "upper_blocks": dc.get("upper_blocks")}
-        # the series run until ||it_t|| / ||it_0|| < 1e-4 for every RHS (eq. 45
-        # ratio control), against the same converged reference
-        ea = dict(extra, terms=40, series_tol=1e-4)
-        ga = gpu_leg(args, w, hc, extra=ea, reference_terms=60, reference_tol=1e-10)
-        cfie["adaptive_series_1e-4"] = {
-            "rhs_per_s_step": ga["R"] * args.steps / ga["total"],
-            "solve_rhs_per_s": float(ga["R"] / np.median(ga["solve"])),
-            "terms_used": ga["stats"].get("device", {}).get("terms_used"),
-            "vs_converged_series": ga["err"]}
+    log("workload %s: %d unknowns, %d RHS" % (args.workload, hm["N"], len(w["khat"])))
+    g = gpu_leg(args, w, hm, args.steps, args.warmup)
+    log("headline leg done")
     R, K = g["R"], args.steps
-    ms_per_step = 1e3 * g["total"] / K
-    dev = dict(g["stats"].get("device", {}))
-    log = dev.pop("launch_log", None) or []
-    k = dev.get("kernels", {}).get(DOMINANT, {})
-    # the dominant kernel's launches by size (algorithmic bytes per launch):
-    # large ones stream, small ones (chain levels, few tiles) are latency-bound
-    classes = []
-    sub = [x for x in log if x[0] == 1 and len(x) >= 5]
-    for lo, hi in ((0, 1e7), (1e7, 1e8), (1e8, 1e9), (1e9, float("inf"))):
-        sel = [x for x in sub if lo <= x[3] < hi]
-        if sel:
-            b, f, t = sum(x[3] for x in sel), sum(x[2] for x in sel), sum(x[4] for x in sel) * 1e-3
-            classes.append({"bytes_per_launch": [lo, hi if hi != float("inf") else None],
-                            "launches_per_step": len(sel) / args.steps, "ms_per_step": 1e3 * t / args.steps,
-                            "achieved_gb_s": b / t / 1e9, "hbm_frac": b / t / PEAK["hbm"],
-                            "achieved_tflops": f / t / 1e12, "intensity_flop_per_byte": f / b})
-    roofline = None
-    if k.get("ms") and k.get("bytes"):
-        sec = k["ms"] * 1e-3
-        flop_rate, byte_rate = k["flops"] / sec, k["bytes"] / sec
-        # roofline of the kernel: its algorithmic intensity (flops per
-        # algorithmic byte) against the ridge point of FP64 MFMA over HBM
-        intensity = k["flops"] / k["bytes"]
-        ridge = PEAK["fp64"] / PEAK["hbm"]
-        if intensity < ridge:
-            bound, achieved, peak, unit = "hbm", byte_rate / 1e9, PEAK["hbm"] / 1e9, "GB/s"
-        else:
-            bound, achieved, peak, unit = "mfma", flop_rate / 1e12, PEAK["fp64"] / 1e12, "TFLOP/s"
-        roofline = {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": bound,
-                    "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                    "traffic": counted_traffic(args.workload),
-                    "algorithmic_bytes_per_launch": k["bytes"] / k["launches"],
-                    "flops_per_launch": k["flops"] / k["launches"],
-                    "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
-                    "attainable_tflops": min(PEAK["fp64"], intensity * PEAK["hbm"]) / 1e12,
-                    "achieved_tflops": flop_rate / 1e12, "frac_of_fp64_mfma_peak": flop_rate / PEAK["fp64"],
-                    "launches_per_step": k["launches"] / K, "avg_launch_us": 1e3 * k["ms"] / k["launches"],
-                    "by_launch_size": classes}
+    roofline, dev = roofline_from(g["stats"])
+    if roofline is not None:
+        roofline["traffic"] = counted_traffic(args.workload)
+    single = mixed = second = batch = cpu = None
+    if not args.only_headline:
+        single = single_rhs_leg(args, w, hm)
+        log("single-RHS leg done")
+        if not args.no_mixed:
+            mixed = precision_legs(args, w, hm, g, variants=((1, "bf16_far"),))
+        del hm
+        if args.second_workload:
+            second = secondary_leg(args, args.second_workload)
+        if not args.no_batch:
+            batch = batch_leg(args)
+            log("batching leg done")
+        if not args.no_cpu_baseline:
+            cpu = cpu_leg(args, w)
     out = {
         "metric": "RHS solved/sec + setup s at <=1e-3 rel err vs FP64; mixed/batched vs plain FP64",
         "value": R * K / g["total"],
@@ -457,7 +706,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * g["total"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -467,17 +716,19 @@ def main():
                    "aca_tol": w["aca_tol"], "freq_hz": w["freq_hz"], "form": "plain fp64", "terms": 2},
         "setup_s": float(np.median(g["setup"])),
         "solve_rhs_per_s": float(R / np.median(g["solve"])),
-        "unprofiled": {"ms_per_step": 1e3 * g["total_unprofiled"] / K,
-                       "rhs_per_s": R * K / g["total_unprofiled"],
-                       "note": "the same K steps after the timed ones, without the per-launch HIP events "
-                               "(solves replayed from their captured graph)"},
+        "timing": "value and ms_per_step: the K timed steps without per-launch events (solves replayed "
+                  "from their captured HIP graph); roofline: one further step with HIP events around "
+                  "every launch",
         "hmatrix_build_s": build_s,
+        "status": g["status"],
         "ratio_max": float(np.max(g["ratio"])),
+        "ratio_ge_warn_fraction": float(np.mean(np.asarray(g["ratio"]) >= 0.1)),
         "roofline": roofline,
+        "single_rhs": single,
         "precision_form": mixed,
-        "cfie_form": cfie,
-        "batching_form": batch_leg(args) if args.batch else None,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_leg(args, w),
+        "batching_form": batch,
+        "second_workload": second,
+        "cpu_baseline": cpu,
         "device_stats": dev,
     }
     print(json.dumps(out), flush=True)

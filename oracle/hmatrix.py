@@ -184,3 +184,49 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     H.rwg, H.op, H.tree = rwg, op, tree
     H.near_pairs, H.far_pairs = near_pairs, far_pairs
     return H
+
+
+def build_hmatrix_cluster(xyz, tri, freq_hz, leaf_max, aca_tol, max_unknowns, workers=1, eta=2.0):
+    """The principal sub-H-matrix of one cluster of the full problem (a
+    bounded sample of a large workload): the octree and block partition of
+    the whole mesh are built as in ``build_hmatrix``; the cluster is the
+    largest tree node with at most ``max_unknowns`` unknowns (the first in
+    depth-first order among equals).  Its near blocks (both leaves inside the
+    cluster) and far blocks (both clusters inside it) are evaluated exactly as
+    ``build_hmatrix`` evaluates them, re-indexed from 0.
+
+    Returns (H_sub, info): H_sub in the cluster's local tree order, with
+    ``rwg_index`` = the global RWG numbers of its unknowns in that order;
+    info = the full problem's leaf sizes, near leaf pairs and far cluster
+    pairs (sizes m, n), for scaling the sample's cost to the whole problem."""
+    rwg = build_rwg(xyz, tri)
+    op = EFIEOperator(rwg, freq_hz)
+    tree = build_tree(edge_midpoints(rwg), leaf_max)
+    perm, leaves, nodes = tree["perm"], tree["leaves"], tree["nodes"]
+    near_pairs, far_pairs = block_partition(tree, eta)
+    size = [nd.hi - nd.lo for nd in nodes]
+    best = max((nd for nd in nodes if size[nd.id] <= max_unknowns), key=lambda nd: (size[nd.id], -nd.id))
+    lo, hi = best.lo, best.hi
+
+    def inside(nd):
+        return nd.lo >= lo and nd.hi <= hi
+
+    sub_leaves = [nd for nd in leaves if inside(nd)]
+    l0 = sub_leaves[0].leaf_id
+    sub_near = [(t, s) for t, s in near_pairs if inside(t) and inside(s)]
+    sub_far = [(t, s) for t, s in far_pairs if inside(t) and inside(s)]
+    _JOB.update(op=op, perm=perm, eps=aca_tol)
+    try:
+        nb = _run(_near_job, [(t.lo, t.hi, s.lo, s.hi) for t, s in sub_near], workers)
+        fb = _run(_far_job, [(t.lo, t.hi, s.lo, s.hi) for t, s in sub_far], workers, chunk=16)
+    finally:
+        _JOB.clear()
+    groups = np.array([(nd.lo - lo, nd.hi - lo) for nd in sub_leaves], dtype=np.int64)
+    near = {(t.leaf_id - l0, s.leaf_id - l0): B for (t, s), B in zip(sub_near, nb)}
+    far = [(t.lo - lo, t.hi - lo, s.lo - lo, s.hi - lo, U, V) for (t, s), (U, V) in zip(sub_far, fb)]
+    H = HMatrix(hi - lo, np.arange(hi - lo), groups, near, far)
+    H.rwg_index = perm[lo:hi].copy()
+    info = dict(N=int(rwg["N"]), leaf_sizes=[nd.hi - nd.lo for nd in leaves],
+                near_pairs=[(t.leaf_id, s.leaf_id) for t, s in near_pairs],
+                far_sizes=[(t.hi - t.lo, s.hi - s.lo) for t, s in far_pairs], rwg=rwg)
+    return H, info

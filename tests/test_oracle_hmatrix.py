@@ -179,3 +179,24 @@ def test_minimum_box_side_stops_the_tree():
     # box_min = 0 is the plain count rule
     a, b = build_tree(pts, 16), build_tree(pts, 16, 0.0)
     assert np.array_equal(a["perm"], b["perm"]) and len(a["leaves"]) == len(b["leaves"])
+
+
+def test_cluster_sample_is_the_principal_sub_hmatrix():
+    """build_hmatrix_cluster (the bounded sample the CPU baseline times) is
+    the principal sub-H-matrix of one cluster of the full H-matrix: its near
+    and far blocks equal the full build's blocks inside the cluster, and its
+    dense near + far field equals the full one restricted to the cluster's
+    unknowns."""
+    from oracle.hmatrix import build_hmatrix, build_hmatrix_cluster
+    xyz, tri = icosphere(3, 1.0)
+    full = build_hmatrix(xyz, tri, 200e6, 32, 1e-3, workers=4)
+    sub, info = build_hmatrix_cluster(xyz, tri, 200e6, 32, 1e-3, 600, workers=4)
+    assert info["N"] == full.N and len(info["leaf_sizes"]) == full.M
+    assert 0 < sub.N <= 600
+    idx = sub.rwg_index
+    pos = {int(r): p for p, r in enumerate(full.perm)}
+    lo = pos[int(idx[0])]
+    assert [pos[int(r)] for r in idx] == list(range(lo, lo + sub.N))     # one contiguous tree range
+    Zf = full.dense_near() + full.dense_far()
+    Zs = sub.dense_near() + sub.dense_far()
+    assert np.array_equal(Zs, Zf[lo:lo + sub.N, lo:lo + sub.N])
