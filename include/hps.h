@@ -294,13 +294,31 @@ hps_status hps_hmatvec(hps_ctx *ctx, int64_t R, const void *X, void *Y);
    hps_setup; HPS_ESTATE before. */
 hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
+/* Tile shapes of the grouped complex GEMM (batching form: tile shapes chosen
+   by the project's autotuner, paper_2109_04129_amd/autotune.py).  path: a JSON
+   table {"entries": [{"class": C, "rhs_max": R, "group_max": G, "shape": S},
+   ...]}, C one of "sweep", "dinv", "far1", "far2", "near" (solve launches),
+   "schur" (setup Schur updates); S 0-4 = workgroup tiles of 32 rows x 32, 64,
+   64, 128, 128 columns (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32,
+   16 x 64 outputs).  A launch takes the first entry of its class whose
+   rhs_max bounds its column count and whose group_max bounds the mean pivot
+   size (unknowns per group); shape 0 when none does.  NULL or "" restores
+   the built-in table (shape 0 everywhere).  Every shape gives bitwise the
+   same results.  hps_create loads tuning/gfx950.json from the library's
+   directory when that file exists (a malformed one fails hps_create with
+   HPS_EINVAL).  Takes effect at the next hps_setup / solve.  Errors:
+   HPS_EIO (file), HPS_EINVAL (content), HPS_EDEVICE (host-only context). */
+hps_status hps_set_tuning(hps_ctx *ctx, const char *path);
+
 /* Per-launch kernel timing: with enable != 0 every grouped-GEMM and inverse
    launch is bracketed by HIP events on the context's stream; hps_stats then
    reports launches, summed device ms, algorithmic flops and bytes per kernel
    class since the call, and a launch log ([kind, work units, flops,
-   algorithmic bytes, ms] per launch; kind 0-2 the grouped GEMM in store /
-   subtract / add mode, 3 the inverse).  Counters reset on every call.  Adds
-   two event records per launch. */
+   algorithmic bytes, ms, tuning class] per launch; kind 0-2 the grouped GEMM
+   in store / subtract / add mode, 3 the inverse; tuning class as in
+   hps_set_tuning: 0 sweep, 1 dinv, 2 far1, 3 far2, 4 near, 5 schur, -1 for
+   launches without one).  Counters reset on every call.  Adds two event
+   records per launch. */
 hps_status hps_profile(hps_ctx *ctx, int enable);
 
 /* JSON statistics (sizes, ranks, fill, bytes, per-stage device times of the

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libhps.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SRC = ["mesh.cpp", "tree.cpp", "efie.cpp", "aca.cpp", "symbolic.cpp", "batch.cpp", "api.cpp"]
+HOST_SRC = ["mesh.cpp", "tree.cpp", "efie.cpp", "aca.cpp", "symbolic.cpp", "batch.cpp", "tune.cpp", "api.cpp"]
 DEVICE_SRC = ["device.hip"]
 
 HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-pthread", "-Wall",
@@ -56,7 +56,7 @@ def build(verbose=False):
                 print(o)
     objs = [os.path.join(OUT, f + ".o") for f in HOST_SRC + DEVICE_SRC]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-pthread"])
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-pthread", "-ldl"])
     shutil.move(tmp, LIB)
     return LIB
 

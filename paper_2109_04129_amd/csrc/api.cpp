@@ -1,5 +1,7 @@
 // C ABI of the hps library (include/hps.h).  Argument checking, call-order
 // state and error capture; the work is in the host modules and device.hip.
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -195,6 +197,15 @@ hps_status hps_params_default(hps_params *p) {
   return HPS_OK;
 }
 
+// <directory of this library>/tuning/gfx950.json, or "" when unknown.
+static std::string default_tuning_path() {
+  Dl_info info;
+  if (!dladdr((void *)&hps_create, &info) || !info.dli_fname) return "";
+  std::string lib(info.dli_fname);
+  const size_t slash = lib.rfind('/');
+  return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning/gfx950.json";
+}
+
 hps_status hps_create(hps_ctx **out, int device, void *stream) {
   if (!out) return HPS_EINVAL;
   *out = nullptr;
@@ -205,6 +216,16 @@ hps_status hps_create(hps_ctx **out, int device, void *stream) {
   if (device >= 0) {
     hps_status st = guarded(c, [&]() {
       c->dev.reset(new hps::DeviceState(device, stream));
+      // the tile-shape table written by the autotuner, if the library's
+      // directory holds one (tuning/gfx950.json next to libhps.so)
+      const std::string path = default_tuning_path();
+      if (!path.empty()) {
+        FILE *f = std::fopen(path.c_str(), "rb");
+        if (f) {
+          std::fclose(f);
+          c->dev->set_tuning(hps::read_tuning(path), path);
+        }
+      }
       return HPS_OK;
     });
     if (st != HPS_OK) {
@@ -704,6 +725,18 @@ hps_status hps_hmatvec_noalloc(hps_ctx *c, int64_t R, const void *X, void *Y) {
   if (R <= 0 || !X || !Y || X == Y) return fail(c, HPS_EINVAL, "bad matvec arguments");
   return guarded(c, [&]() {
     c->dev->hmatvec_noalloc(R, X, Y);
+    return HPS_OK;
+  });
+}
+
+hps_status hps_set_tuning(hps_ctx *c, const char *path) {
+  if (!c) return HPS_EINVAL;
+  return guarded(c, [&]() {
+    // the file is read and checked first, so a bad table is reported as such
+    std::vector<hps::TuneEntry> t;
+    if (path && *path) t = hps::read_tuning(path);
+    if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context");
+    c->dev->set_tuning(t, (path && *path) ? std::string(path) : std::string("built-in (all 32 x 32)"));
     return HPS_OK;
   });
 }

@@ -41,6 +41,24 @@ struct GemmBatch {
   double flops = 0.0;                     // algorithmic, 8 per complex MAC
 };
 
+// Launch classes of the grouped GEMM whose tile shape is chosen by the
+// tuning table (solve: sweeps, D^-1, far stages, near product; setup: Schur
+// updates), and one entry of the table: `shape` for launches of class `cls`
+// with at most rhs_max columns on a problem whose mean pivot size is at
+// most group_max unknowns.  Shapes 0-4: workgroup tiles of 32 rows x 32, 64,
+// 64, 128, 128 columns (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32, 16 x 64).
+enum { TC_SWEEP = 0, TC_DINV, TC_FAR1, TC_FAR2, TC_NEAR, TC_SCHUR, TC_COUNT };
+constexpr int TUNE_SHAPES = 5;
+struct TuneEntry {
+  int cls;
+  int64_t rhs_max;
+  double group_max;
+  int shape;
+};
+
+// Reads a tuning table (JSON, see tune.cpp); throws Error.
+std::vector<TuneEntry> read_tuning(const std::string &path);
+
 struct StageTimes {
   double setup_ms = 0, inverse_ms = 0, coef_ms = 0, schur_ms = 0, symbolic_ms = 0;
   double solve_ms = 0, rhs_ms = 0, sweep_ms = 0, far_ms = 0, rcs_ms = 0;
@@ -75,6 +93,10 @@ class DeviceState {
   void far_sample(const Mesh &m, double freq_hz, int cfie, double alpha, const HMatrix &H, double eps,
                   const FarEmit &emit);
   void set_profiling(bool on);
+  // tile-shape table (applies from the next hps_setup / solve) and where it came from
+  void set_tuning(const std::vector<TuneEntry> &t, const std::string &src);
+  std::vector<TuneEntry> tune;
+  std::string tune_src = "built-in (all 32 x 32)";
 
   int device;
   void *stream;     // hipStream_t

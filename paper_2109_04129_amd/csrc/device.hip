@@ -57,29 +57,40 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 }
 
 // ------------------------------------------------------------------ grouped GEMM
-// Complex FP64 on the matrix cores: each wave owns one 16 x 16 block of a
-// 32 x 32 workgroup tile and accumulates op(A) B with V_MFMA_F64_16X16X4_F64
-// in the real 3M split (Gauss: Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) in three
+// Complex FP64 on the matrix cores: a workgroup of 4 waves owns a tile of 32
+// rows and TN columns and accumulates op(A) B with V_MFMA_F64_16X16X4_F64 in
+// the real 3M split (Gauss: Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) in three
 // accumulators; re = rr - ii, im = ss - rr - ii), three products per complex
-// step instead of four.  Operand layout of the
-// instruction: lane l supplies A[l % 16][k slot l / 16] and B[k slot
-// l / 16][l % 16]; result register r of lane l is D[l / 16 + 4 r][l % 16].
-// In step s of a chunk of 16 the lane groups take k = k0 + 4 s + l / 16, so
-// one load instruction reads four consecutive elements of each of 16 rows
-// (A) or columns (B).  Operands come straight from L2 (no LDS).
+// step instead of four.  Tile shape (template WR, NB): WR waves along the 32
+// rows (WR = 2: a wave takes 16 rows; WR = 1: a wave takes all 32 as two
+// 16-row blocks, so one B fragment serves two MFMA rows) and 4 / WR waves
+// along the columns, NB column blocks of 16 each; TN = 16 NB (4 / WR).
+// Operand layout of the instruction: lane l supplies A[l % 16][k slot l / 16]
+// and B[k slot l / 16][l % 16]; result register r of lane l is
+// D[l / 16 + 4 r][l % 16].  In step s of a chunk of 16 the lane groups take
+// k = k0 + 4 s + l / 16, so one load instruction reads four consecutive
+// elements of each of 16 rows (A) or columns (B).  Operands come straight
+// from L2 (no LDS).  The tile shape of each launch class is a run-time choice
+// (a tuning table written by the autotuner); every shape gives bitwise the
+// same result (each output element sums the same products in the same order).
 constexpr int TM = 32;
-constexpr int NB_SOLVE = 1, TN_SOLVE = 32 * NB_SOLVE;   // solve tiles: 32 rows x 32 RHS
 constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops over its share of sub-tiles)
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int MODE, int NB>
+// tile shapes: (WR, NB) and the workgroup tile's column count
+static_assert(TUNE_SHAPES == 5, "tile shapes 0-4");
+__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 ? 1 : 2; }
+__host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 ? 2 : (v == 4 ? 4 : 1); }
+__host__ __device__ constexpr int shape_tn(int v) { return 16 * shape_nb(v) * (4 / shape_wr(v)); }
+
+template <int MODE, int WR, int NB>
 __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
                                               const Term *__restrict__ terms, int ncols, int ntiles, int ny,
                                               int xcd_order) {
-  // workgroup tile: 32 rows x (32 NB) columns; wave w owns rows 16 (w / 2)
-  // and NB column blocks of 16 starting at 16 NB (w % 2)
-  constexpr int TN = 32 * NB;
+  constexpr int RB = 2 / WR;           // 16-row blocks per wave
+  constexpr int WC = 4 / WR;           // waves along the columns
+  constexpr int TN = 16 * NB * WC;
   // Workgroup -> (tile bx, part by).  Plain order: grid (ntiles, ny), tile
   // = blockIdx.x.  XCD-aware order: a one-dimensional grid of
   // 8 ceil(ntiles / 8) ny workgroups; consecutive workgroups go to the 8
@@ -97,7 +108,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
   const Tile t = tiles[bx];
   // r0 < 0: the tile stands for the whole m x n block; workgroup y takes its
   // sub-tiles y, y + ny, ...  c0 < 0: one row tile over ncols columns, y
-  // picks the column tile.  Else one explicit tile.
+  // picks the column tile.  Else one explicit tile (TN = 32 shapes only).
   int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
   if (t.r0 < 0) {
     nsc = (t.n + TN - 1) / TN;
@@ -113,45 +124,55 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
+  const int wr = WR == 2 ? (wave >> 1) : 0, wc = WR == 2 ? (wave & 1) : wave;
   for (int st = st0; st < nsub; st += sstep) {
     int rb = rb0, cb = cb0;
     if (t.r0 < 0) {
       rb = (st / nsc) * TM;
       cb = (st % nsc) * TN;
     }
-    const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
+    const int row0 = rb + 16 * RB * wr, col0 = cb + 16 * NB * wc;
     if (row0 >= t.m || col0 >= tn) continue;           // wave-uniform
-    const int arow = row0 + li;
-    const bool arow_ok = arow < t.m;
+    bool arow_ok[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) arow_ok[i] = row0 + 16 * i + li < t.m;
     // read-modify-write modes: fetch C now, so its latency hides behind the products
-    c2 cold[NB][4];
+    c2 cold[RB][NB][4];
     if (MODE != 0) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int ccol = col0 + 16 * j + li;
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int crow = row0 + lg + 4 * r;
-          cold[j][r] = make_double2(0.0, 0.0);
-          if (ccol < tn && crow < t.m) cold[j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+        for (int j = 0; j < NB; ++j) {
+          const int ccol = col0 + 16 * j + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int crow = row0 + 16 * i + lg + 4 * r;
+            cold[i][j][r] = make_double2(0.0, 0.0);
+            if (ccol < tn && crow < t.m) cold[i][j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+          }
         }
-      }
     }
-    d4 rr[NB], ii[NB], ss[NB];      // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
+    d4 rr[RB][NB], ii[RB][NB], ss[RB][NB];      // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ss[j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rr[i][j] = ii[i][j] = ss[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     for (int q = t.t_begin; q < t.t_end; ++q) {
       const Term tm = terms[q];
       const c2 *Ab = A + tm.a_off;
       // full chunks of 16: in step s lane group g reads k = k0 + 4 s + g
       const int kfull = tm.k & ~15;
       for (int k0 = 0; k0 < kfull; k0 += 16) {
-        c2 av[4], bv[NB][4];
+        c2 av[RB][4], bv[NB][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = k0 + 4 * s + lg;
-          av[s] = make_double2(0.0, 0.0);
-          if (arow_ok) av[s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int arow = row0 + 16 * i + li;
+            av[i][s] = make_double2(0.0, 0.0);
+            if (arow_ok[i]) av[i][s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+          }
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
             const int bcol = col0 + 16 * j + li;
@@ -161,12 +182,15 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const double as = av[s].x + av[s].y;
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
-            rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
-            ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
-            ss[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bv[j][s].x + bv[j][s].y, ss[j], 0, 0, 0);
+            const double bs = bv[j][s].x + bv[j][s].y;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+              rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
+              ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
+              ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+            }
           }
         }
       }
@@ -174,38 +198,48 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
       for (int kt = kfull; kt < tm.k; kt += 4) {
         const int k = kt + lg;
         const bool kok = k < tm.k;
-        c2 av = make_double2(0.0, 0.0);
-        if (kok && arow_ok) av = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+        c2 av[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int arow = row0 + 16 * i + li;
+          av[i] = make_double2(0.0, 0.0);
+          if (kok && arow_ok[i]) av[i] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+        }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           const int bcol = col0 + 16 * j + li;
           c2 bv = make_double2(0.0, 0.0);
           if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-          rr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[j], 0, 0, 0);
-          ii[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[j], 0, 0, 0);
-          ss[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, bv.x + bv.y, ss[j], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i][j], 0, 0, 0);
+            ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv.y, ii[i][j], 0, 0, 0);
+            ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
+          }
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int ccol = col0 + 16 * j + li;
-      if (ccol >= tn) continue;
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int crow = row0 + lg + 4 * r;
-        if (crow >= t.m) continue;
-        const c2 acc = make_double2(rr[j][r] - ii[j][r], ss[j][r] - rr[j][r] - ii[j][r]);
-        c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
-        if (MODE == 0) {
-          *p = acc;
-        } else if (MODE == 1) {
-          *p = make_double2(cold[j][r].x - acc.x, cold[j][r].y - acc.y);
-        } else {
-          *p = make_double2(cold[j][r].x + acc.x, cold[j][r].y + acc.y);
+      for (int j = 0; j < NB; ++j) {
+        const int ccol = col0 + 16 * j + li;
+        if (ccol >= tn) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int crow = row0 + 16 * i + lg + 4 * r;
+          if (crow >= t.m) continue;
+          const c2 acc = make_double2(rr[i][j][r] - ii[i][j][r], ss[i][j][r] - rr[i][j][r] - ii[i][j][r]);
+          c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+          if (MODE == 0) {
+            *p = acc;
+          } else if (MODE == 1) {
+            *p = make_double2(cold[i][j][r].x - acc.x, cold[i][j][r].y - acc.y);
+          } else {
+            *p = make_double2(cold[i][j][r].x + acc.x, cold[i][j][r].y + acc.y);
+          }
         }
       }
-    }
   }
 }
 
@@ -226,13 +260,14 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
   return make_float2(__low2float(h), __high2float(h));
 }
 
-template <int MODE, int AT, int NB>
+template <int MODE, int AT, int WR, int NB>
 __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
                                                 const Term *__restrict__ terms, const float *__restrict__ scales,
                                                 const int32_t *__restrict__ rowpart, int ncols, int ntiles, int ny,
                                                 int xcd_order) {
-  constexpr int TN = 32 * NB;
+  constexpr int RB = 2 / WR, WC = 4 / WR;   // tile shapes as in k_gemm
+  constexpr int TN = 16 * NB * WC;
   // workgroup -> (tile bx, part by): plain or XCD-aware order, as in k_gemm
   int bx = (int)blockIdx.x, by = (int)blockIdx.y;
   if (xcd_order) {
@@ -256,48 +291,66 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = rb + 16 * (wave >> 1), col0 = cb + 16 * NB * (wave & 1);
+  const int wr = WR == 2 ? (wave >> 1) : 0, wc = WR == 2 ? (wave & 1) : wave;
+  const int row0 = rb + 16 * RB * wr, col0 = cb + 16 * NB * wc;
   if (row0 >= t.m || col0 >= tn) return;
   const int li = lane & 15, lg = lane >> 4;
-  const int arow = row0 + li;
-  const bool arow_ok = arow < t.m;
+  bool arow_ok[RB];
   // terms with sidx -2 (a factor group of the first far stage) scale each A
   // row by its own factor's scale: row arow of the target is T row c_off + arow
-  float sc_row = 1.0f;
-  if (AT != 0 && rowpart != nullptr && arow_ok && t.t_begin < t.t_end && terms[t.t_begin].sidx == -2)
-    sc_row = scales[rowpart[t.c_off + arow]];
+  float sc_row[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int arow = row0 + 16 * i + li;
+    arow_ok[i] = arow < t.m;
+    sc_row[i] = 1.0f;
+    if (AT != 0 && rowpart != nullptr && arow_ok[i] && t.t_begin < t.t_end && terms[t.t_begin].sidx == -2)
+      sc_row[i] = scales[rowpart[t.c_off + arow]];
+  }
   // read-modify-write modes: fetch C now, so its latency hides behind the products
-  float2 cold[NB][4];
+  float2 cold[RB][NB][4];
   if (MODE != 0) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int ccol = col0 + 16 * j + li;
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int crow = row0 + 4 * lg + r;
-        cold[j][r] = make_float2(0.f, 0.f);
-        if (ccol < tn && crow < t.m) cold[j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+      for (int j = 0; j < NB; ++j) {
+        const int ccol = col0 + 16 * j + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int crow = row0 + 16 * i + 4 * lg + r;
+          cold[i][j][r] = make_float2(0.f, 0.f);
+          if (ccol < tn && crow < t.m) cold[i][j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+        }
       }
-    }
   }
-  f4 rr[NB], ii[NB], ss[NB];          // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
+  f4 rr[RB][NB], ii[RB][NB], ss[RB][NB];          // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
-  for (int j = 0; j < NB; ++j) rr[j] = ii[j] = ss[j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) rr[i][j] = ii[i][j] = ss[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int q = t.t_begin; q < t.t_end; ++q) {
     const Term tm = terms[q];
-    const float sc = AT == 0 ? 1.0f : (tm.sidx >= 0 ? scales[tm.sidx] : (tm.sidx == -2 ? sc_row : 1.0f));
+    float sc[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      sc[i] = AT == 0 ? 1.0f : (tm.sidx >= 0 ? scales[tm.sidx] : (tm.sidx == -2 ? sc_row[i] : 1.0f));
     const int kfull = tm.k & ~15;
     for (int k0 = 0; k0 < kfull; k0 += 16) {
-      float2 av[4], bv[NB][4];
+      float2 av[RB][4], bv[NB][4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = k0 + 4 * s + lg;
-        av[s] = make_float2(0.f, 0.f);
-        if (arow_ok) {
-          const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
-          av[s] = load_a<AT>(A, idx);
-          av[s].x *= sc;
-          av[s].y *= sc;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int arow = row0 + 16 * i + li;
+          av[i][s] = make_float2(0.f, 0.f);
+          if (arow_ok[i]) {
+            const int64_t idx =
+                tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+            av[i][s] = load_a<AT>(A, idx);
+            av[i][s].x *= sc[i];
+            av[i][s].y *= sc[i];
+          }
         }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -308,55 +361,68 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const float as = av[s].x + av[s].y;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-          rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[j][s].x, rr[j], 0, 0, 0);
-          ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[j][s].y, ii[j], 0, 0, 0);
-          ss[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bv[j][s].x + bv[j][s].y, ss[j], 0, 0, 0);
+          const float bs = bv[j][s].x + bv[j][s].y;
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
+            ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
+            ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+          }
         }
       }
     }
     for (int kt = kfull; kt < tm.k; kt += 4) {
       const int k = kt + lg;
       const bool kok = k < tm.k;
-      float2 av = make_float2(0.f, 0.f);
-      if (kok && arow_ok) {
-        const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
-        av = load_a<AT>(A, idx);
-        av.x *= sc;
-        av.y *= sc;
+      float2 av[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int arow = row0 + 16 * i + li;
+        av[i] = make_float2(0.f, 0.f);
+        if (kok && arow_ok[i]) {
+          const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+          av[i] = load_a<AT>(A, idx);
+          av[i].x *= sc[i];
+          av[i].y *= sc[i];
+        }
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int bcol = col0 + 16 * j + li;
         float2 bv = make_float2(0.f, 0.f);
         if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-        rr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, rr[j], 0, 0, 0);
-        ii[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, ii[j], 0, 0, 0);
-        ss[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bv.x + bv.y, ss[j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv.x, rr[i][j], 0, 0, 0);
+          ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv.y, ii[i][j], 0, 0, 0);
+          ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
+        }
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int ccol = col0 + 16 * j + li;
-    if (ccol >= tn) continue;
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int crow = row0 + 4 * lg + r;
-      if (crow >= t.m) continue;
-      const float2 acc = make_float2(rr[j][r] - ii[j][r], ss[j][r] - rr[j][r] - ii[j][r]);
-      float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
-      if (MODE == 0) {
-        *p = acc;
-      } else if (MODE == 1) {
-        *p = make_float2(cold[j][r].x - acc.x, cold[j][r].y - acc.y);
-      } else {
-        *p = make_float2(cold[j][r].x + acc.x, cold[j][r].y + acc.y);
+    for (int j = 0; j < NB; ++j) {
+      const int ccol = col0 + 16 * j + li;
+      if (ccol >= tn) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int crow = row0 + 16 * i + 4 * lg + r;
+        if (crow >= t.m) continue;
+        const float2 acc = make_float2(rr[i][j][r] - ii[i][j][r], ss[i][j][r] - rr[i][j][r] - ii[i][j][r]);
+        float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+        if (MODE == 0) {
+          *p = acc;
+        } else if (MODE == 1) {
+          *p = make_float2(cold[i][j][r].x - acc.x, cold[i][j][r].y - acc.y);
+        } else {
+          *p = make_float2(cold[i][j][r].x + acc.x, cold[i][j][r].y + acc.y);
+        }
       }
     }
-  }
 }
 
 __global__ void k_to32(const c2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
@@ -1501,6 +1567,43 @@ void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, 
 
 }  // namespace
 
+// Launch of the grouped GEMM in tile shape `shape` (see shape_wr / shape_nb).
+template <int MODE>
+static void gemm64_launch(int shape, dim3 g, hipStream_t s, const c2 *A, const c2 *B, c2 *C, const Tile *tiles,
+                          const Term *terms, int ncols, int nt, int ny, int xo) {
+  const dim3 blk(256);
+  switch (shape) {
+    case 1: hipLaunchKernelGGL((k_gemm<MODE, 2, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 2: hipLaunchKernelGGL((k_gemm<MODE, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 3: hipLaunchKernelGGL((k_gemm<MODE, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 4: hipLaunchKernelGGL((k_gemm<MODE, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+  }
+}
+template <int MODE, int AT>
+static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const float2 *B, float2 *C,
+                          const Tile *tiles, const Term *terms, const float *sc, const int32_t *rp, int ncols, int nt,
+                          int ny, int xo) {
+  const dim3 blk(256);
+  switch (shape) {
+    case 1:
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+  }
+}
+
 struct DeviceState::Impl {
   hipStream_t s;
   void *scratch = nullptr;         // this device's address of the file-scope scratch array
@@ -1596,6 +1699,7 @@ struct DeviceState::Impl {
   };
   struct Built {
     int64_t t0 = 0, n_tiles = 0;
+    int cls = TC_SWEEP;                // launch class (tile shape from the tuning table)
     // per-RHS sums: sum m k over terms (m = rows of the target), sum m over
     // targets, sum k over terms
     double smk = 0.0, sm = 0.0, sk = 0.0;
@@ -1666,10 +1770,11 @@ struct DeviceState::Impl {
   // Append the tiles of schedule sc (one per 32 target rows; the RHS
   // columns are split over blockIdx.y at launch) and its terms to pool pl.
   // na: elements of A; nb, nc: per-column sizes of the B and C buffers.
-  void build(const Sched &sc, Pool &pl, Built &out, int64_t na, int64_t nb, int64_t nc, const char *what) {
+  void build(const Sched &sc, Pool &pl, Built &out, int64_t na, int64_t nb, int64_t nc, const char *what, int cls) {
     const int32_t base = (int32_t)pl.terms.size();
     pl.terms.insert(pl.terms.end(), sc.terms.begin(), sc.terms.end());
     out = Built();
+    out.cls = cls;
     out.t0 = (int64_t)pl.tiles.size();
     for (size_t t = 0; t < sc.targets.size(); ++t) {
       const int64_t coff = sc.targets[t].first;
@@ -1694,12 +1799,12 @@ struct DeviceState::Impl {
     b_fwd.assign(fwd.size(), Built());
     b_bwd.assign(bwd.size(), Built());
     const int64_t nT = std::max<int64_t>(t_rows, 1);
-    for (size_t l = 0; l < fwd.size(); ++l) build(fwd[l], spool, b_fwd[l], nF, N, N, "forward sweep");
-    for (size_t l = 0; l < bwd.size(); ++l) build(bwd[l], spool, b_bwd[l], nF, N, N, "back sweep");
-    build(dinv, spool, b_dinv, nF, N, N, "D^-1");
-    build(far1, spool, b_far1, (int64_t)faruv.n, N, nT, "far stage 1");
-    build(far2, spool, b_far2, (int64_t)faruv.n, nT, N, "far stage 2");
-    build(nearmv, spool, b_near, (int64_t)near.n, N, N, "near matvec");
+    for (size_t l = 0; l < fwd.size(); ++l) build(fwd[l], spool, b_fwd[l], nF, N, N, "forward sweep", TC_SWEEP);
+    for (size_t l = 0; l < bwd.size(); ++l) build(bwd[l], spool, b_bwd[l], nF, N, N, "back sweep", TC_SWEEP);
+    build(dinv, spool, b_dinv, nF, N, N, "D^-1", TC_DINV);
+    build(far1, spool, b_far1, (int64_t)faruv.n, N, nT, "far stage 1", TC_FAR1);
+    build(far2, spool, b_far2, (int64_t)faruv.n, nT, N, "far stage 2", TC_FAR2);
+    build(nearmv, spool, b_near, (int64_t)near.n, N, N, "near matvec", TC_NEAR);
     built_R = -1;
   }
   void upload_solve_pool() { spool.upload(s); }
@@ -1707,8 +1812,8 @@ struct DeviceState::Impl {
   // ---- optional per-launch timing with HIP events on the library stream
   // kinds: 0..2 = k_gemm<mode>, 3 = k_inverse
   bool prof = false;
-  struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; int64_t units; };
-  struct LaunchLog { int kind; int64_t units; double flops, bytes, ms; };
+  struct ProfRec { hipEvent_t a, b; int kind; double flops, bytes; int64_t units; int cls; };
+  struct LaunchLog { int kind; int64_t units; double flops, bytes, ms; int cls; };
   std::vector<LaunchLog> launch_log;   // every timed launch since profiling was switched on
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_free;
@@ -1725,9 +1830,9 @@ struct DeviceState::Impl {
     return e;
   }
   // index of the new record (events on the current stream), -1 when off
-  int64_t prof_begin(int kind, double flops, double bytes = 0.0, int64_t units = 0) {
+  int64_t prof_begin(int kind, double flops, double bytes = 0.0, int64_t units = 0, int cls = -1) {
     if (!prof) return -1;
-    prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes, units});
+    prof_recs.push_back(ProfRec{ev_get(), ev_get(), kind, flops, bytes, units, cls});
     HIP_CHECK(hipEventRecord(prof_recs.back().a, s));
     return (int64_t)prof_recs.size() - 1;
   }
@@ -1742,7 +1847,8 @@ struct DeviceState::Impl {
       kstat[r.kind].ms += ms;
       kstat[r.kind].flops += r.flops;
       kstat[r.kind].bytes += r.bytes;
-      if (launch_log.size() < 100000) launch_log.push_back(LaunchLog{r.kind, r.units, r.flops, r.bytes, (double)ms});
+      if (launch_log.size() < 100000)
+        launch_log.push_back(LaunchLog{r.kind, r.units, r.flops, r.bytes, (double)ms, r.cls});
       ev_free.push_back(r.a);
       ev_free.push_back(r.b);
     }
@@ -1750,7 +1856,8 @@ struct DeviceState::Impl {
   }
 
   void launch_tiles(const Tile *tiles, const Term *terms, int64_t n_tiles, int mode, const c2 *A, const c2 *B,
-                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false, int ncols = 0) {
+                    c2 *C, int sub = 1, double flops = 0.0, double bytes = 0.0, bool wide = false, int ncols = 0,
+                    int shape = 0, int cls = -1) {
     if (n_tiles == 0) return;
     // The store-mode launches of a solve (far field, D^-1: long term lists
     // over shared factor rows) take the kernel's XCD-aware order on a
@@ -1759,30 +1866,34 @@ struct DeviceState::Impl {
     const int xo = (wide && mode == 0) ? 1 : 0;
     const int64_t nwg = cdiv(n_tiles, 8) * 8 * (int64_t)sub;
     if (n_tiles > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
-    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n_tiles, (unsigned)sub), blk(256);
+    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n_tiles, (unsigned)sub);
     const int nt = (int)n_tiles;
-    const int64_t pr = prof_begin(mode, flops, bytes, n_tiles);
-    if (wide) {
-      if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-      else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-      else
-        hipLaunchKernelGGL((k_gemm<2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-    } else {
-      if (mode == 0)
-        hipLaunchKernelGGL((k_gemm<0, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-      else if (mode == 1)
-        hipLaunchKernelGGL((k_gemm<1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-      else
-        hipLaunchKernelGGL((k_gemm<2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
-    }
+    const int64_t pr = prof_begin(mode, flops, bytes, n_tiles, cls);
+    if (mode == 0)
+      gemm64_launch<0>(shape, g, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
+    else if (mode == 1)
+      gemm64_launch<1>(shape, g, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
+    else
+      gemm64_launch<2>(shape, g, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
+  // Tile shape of each launch class for the current RHS count (solve
+  // classes) or for the setup (TC_SCHUR), from the tuning table: the first
+  // entry of the class whose rhs_max and group_max bound R and the mean
+  // pivot size; shape 0 (32 x 32) when none does.
+  std::vector<TuneEntry> tune;
+  int shape_of[TC_COUNT] = {0, 0, 0, 0, 0, 0};
+  int pick_shape(int cls, int64_t R) const {
+    const double g = P.M > 0 ? (double)N / (double)P.M : 0.0;
+    for (const TuneEntry &e : tune)
+      if (e.cls == cls && R <= e.rhs_max && g <= e.group_max) return e.shape;
+    return 0;
+  }
   void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
-    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, (int)cdiv(cur_R, TN_SOLVE), b.flops,
-                 b.bytes, true, (int)cur_R);
+    const int sh = shape_of[b.cls];
+    launch_tiles(spool.dtiles.p + b.t0, spool.dterms.p, b.n_tiles, mode, A, B, C, (int)cdiv(cur_R, shape_tn(sh)),
+                 b.flops, b.bytes, true, (int)cur_R, sh, b.cls);
   }
 
   // Sizes the vectors for R RHS and the launches' work counts; the tile
@@ -1790,9 +1901,10 @@ struct DeviceState::Impl {
   int64_t cur_R = 0;
   void ensure_R(int64_t R) {
     if (R == built_R) return;
-    if (R > (int64_t)INT32_MAX / 2 || cdiv(R, TN_SOLVE) > 65535) throw Error{HPS_EINVAL, "too many right-hand sides"};
+    if (R > (int64_t)INT32_MAX / 2 || cdiv(R, TM) > 65535) throw Error{HPS_EINVAL, "too many right-hand sides"};
     drop_graphs();
     cur_R = R;
+    for (int c = 0; c < TC_SCHUR; ++c) shape_of[c] = pick_shape(c, R);
     solve_flops_parts.assign(4, 0.0);
     for (auto &b : b_fwd) { b.at(R); solve_flops_parts[0] += b.flops; }
     for (auto &b : b_bwd) { b.at(R); solve_flops_parts[1] += b.flops; }
@@ -1823,30 +1935,32 @@ struct DeviceState::Impl {
 
   template <int MODE>
   void g32(const Tile *tiles, const Term *terms, int64_t n, int at, const void *A, const float2 *B, float2 *C,
-           double flops, double bytes, int64_t ncols = -1) {
+           double flops, double bytes, int64_t ncols, int shape, int cls) {
     if (n == 0) return;
     if (ncols < 0) ncols = cur_R;
-    const int64_t pr = prof_begin(MODE, flops, bytes, n);
+    const int64_t pr = prof_begin(MODE, flops, bytes, n, cls);
     // store mode (far field, D^-1) in the XCD-aware order, as in launch_tiles
-    const int ny = (int)cdiv(ncols, TN_SOLVE), xo = MODE == 0 ? 1 : 0;
+    const int ny = (int)cdiv(ncols, shape_tn(shape)), xo = MODE == 0 ? 1 : 0;
     const int64_t nwg = cdiv(n, 8) * 8 * (int64_t)ny;
     if (n > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
-    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n, (unsigned)ny), blk(256);
+    dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n, (unsigned)ny);
     const int nc = (int)ncols, nt = (int)n;
     if (at == 0)
-      hipLaunchKernelGGL((k_gemm32<MODE, 0, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
+      gemm32_launch<MODE, 0>(shape, g, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     else if (at == 1)
-      hipLaunchKernelGGL((k_gemm32<MODE, 1, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
+      gemm32_launch<MODE, 1>(shape, g, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     else
-      hipLaunchKernelGGL((k_gemm32<MODE, 2, NB_SOLVE>), g, blk, 0, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
+      gemm32_launch<MODE, 2>(shape, g, s, A, B, C, tiles, terms, fscale.p, rowpart.p, nc, nt, ny, xo);
     HIP_CHECK(hipGetLastError());
     prof_end(pr);
   }
-  void launch32(const Built &b, int mode, int at, const void *A, const float2 *B, float2 *C, int64_t ncols = -1) {
+  void launch32(const Built &b, int mode, int at, const void *A, const float2 *B, float2 *C, int64_t ncols = -1,
+                int shape = -1) {
     const Tile *t = spool.dtiles.p + b.t0;
-    if (mode == 0) g32<0>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
-    else if (mode == 1) g32<1>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
-    else g32<2>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols);
+    const int sh = shape >= 0 ? shape : shape_of[b.cls];
+    if (mode == 0) g32<0>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols, sh, b.cls);
+    else if (mode == 1) g32<1>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols, sh, b.cls);
+    else g32<2>(t, spool.dterms.p, b.n_tiles, at, A, B, C, b.flops, b.bytes, ncols, sh, b.cls);
   }
   void ensure32(int64_t R) {
     const int64_t NR = N * R;
@@ -2244,6 +2358,9 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   I.P = P;
   I.ready = false;
   I.built_R = -1;
+  I.tune = tune;
+  const int schur_shape = I.pick_shape(TC_SCHUR, 0);
+  I.shape_of[TC_SCHUR] = schur_shape;
   const int64_t N = I.N, M = I.M;
   // working and factor panels; a non-symmetric near field (CFIE) also keeps
   // the lower blocks, stored transposed in a second copy of the panel layout
@@ -2803,14 +2920,14 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       HIP_CHECK(hipEventRecord(I.lev_ev[2 * l], s));
       if (l >= 1) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (l - 1) + 1], 0));
       I.launch_tiles(ch.d_tiles.p + sl.t0, ch.d_terms.p, sl.n, 1, Wd, I.F.p, Wd, std::min(sl.sub, SUB_Y), sl.flops,
-                     sl.bytes);
+                     sl.bytes, false, 0, schur_shape, TC_SCHUR);
       HIP_CHECK(hipStreamWaitEvent(I.s2, I.lev_ev[2 * l], 0));
       {
         const hipStream_t main_s = I.s;
         I.s = I.s2;                      // launch_tiles and its timing events use I.s
         try {
           I.launch_tiles(ch.d_tiles.p + sl2.t0, ch.d_terms.p, sl2.n, 1, Wd, I.F.p, Wd, std::min(sl2.sub, SUB_Y),
-                         sl2.flops, sl2.bytes);
+                         sl2.flops, sl2.bytes, false, 0, schur_shape, TC_SCHUR);
         } catch (...) {
           I.s = main_s;
           throw;
@@ -3071,7 +3188,7 @@ void DeviceState::hmatvec_noalloc(int64_t R, const void *X, void *Y) {
   HIP_CHECK(hipSetDevice(device));
   if (!device_pointer(X) || !device_pointer(Y))
     throw Error{HPS_EINVAL, "hps_hmatvec_noalloc: X and Y must be device memory"};
-  if (cdiv(R, TN_SOLVE) > 65535 || R > (int64_t)INT32_MAX / 2) throw Error{HPS_EINVAL, "too many columns"};
+  if (cdiv(R, TM) > 65535 || R > (int64_t)INT32_MAX / 2) throw Error{HPS_EINVAL, "too many columns"};
   int64_t part[5];
   const int64_t need = noalloc_bytes(I, R, part);
   if (need > (int64_t)HPS_SCRATCH_BYTES) {
@@ -3092,7 +3209,6 @@ void DeviceState::hmatvec_noalloc(int64_t R, const void *X, void *Y) {
   try {
     const int64_t NR = I.N * R;
     const unsigned g = (unsigned)cdiv(NR, 256);
-    const int ny = (int)cdiv(R, TN_SOLVE);
     hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, I.s, (const c2 *)X, x, I.dperm.p, I.dsoff.p, I.nseg,
                        I.N, R, 0);
     HIP_CHECK(hipGetLastError());
@@ -3102,16 +3218,20 @@ void DeviceState::hmatvec_noalloc(int64_t R, const void *X, void *Y) {
     if (I.precision == 0) {
       const Tile *tl = I.spool.dtiles.p;
       const Term *tm = I.spool.dterms.p;
-      I.launch_tiles(tl + I.b_near.t0, tm, I.b_near.n_tiles, 0, I.near.p, x, y, ny, 0.0, 0.0, true, (int)R);
-      I.launch_tiles(tl + I.b_far1.t0, tm, I.b_far1.n_tiles, 0, I.faruv.p, x, (c2 *)T, ny, 0.0, 0.0, true, (int)R);
-      I.launch_tiles(tl + I.b_far2.t0, tm, I.b_far2.n_tiles, 2, I.faruv.p, (const c2 *)T, y, ny, 0.0, 0.0, true,
-                     (int)R);
+      // tile shapes of the classes for this R, as hmatvec would take them
+      const int sn = I.pick_shape(TC_NEAR, R), s1 = I.pick_shape(TC_FAR1, R), s2 = I.pick_shape(TC_FAR2, R);
+      I.launch_tiles(tl + I.b_near.t0, tm, I.b_near.n_tiles, 0, I.near.p, x, y, (int)cdiv(R, shape_tn(sn)), 0.0, 0.0,
+                     true, (int)R, sn);
+      I.launch_tiles(tl + I.b_far1.t0, tm, I.b_far1.n_tiles, 0, I.faruv.p, x, (c2 *)T, (int)cdiv(R, shape_tn(s1)), 0.0,
+                     0.0, true, (int)R, s1);
+      I.launch_tiles(tl + I.b_far2.t0, tm, I.b_far2.n_tiles, 2, I.faruv.p, (const c2 *)T, y,
+                     (int)cdiv(R, shape_tn(s2)), 0.0, 0.0, true, (int)R, s2);
     } else {
       hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, I.s, (const c2 *)x, xs, NR);
       HIP_CHECK(hipGetLastError());
-      I.launch32(I.b_near, 0, 0, I.near32.p, xs, ys, R);
-      I.launch32(I.b_far1, 0, 0, I.farf32.p, xs, (float2 *)T, R);
-      I.launch32(I.b_far2, 2, 0, I.farf32.p, (const float2 *)T, ys, R);
+      I.launch32(I.b_near, 0, 0, I.near32.p, xs, ys, R, I.pick_shape(TC_NEAR, R));
+      I.launch32(I.b_far1, 0, 0, I.farf32.p, xs, (float2 *)T, R, I.pick_shape(TC_FAR1, R));
+      I.launch32(I.b_far2, 2, 0, I.farf32.p, (const float2 *)T, ys, R, I.pick_shape(TC_FAR2, R));
       hipLaunchKernelGGL(k_to64, dim3(g), dim3(256), 0, I.s, (const float2 *)ys, y, NR);
       HIP_CHECK(hipGetLastError());
     }
@@ -3231,6 +3351,18 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alp
   }
 }
 
+void DeviceState::set_tuning(const std::vector<TuneEntry> &t, const std::string &src) {
+  Impl &I = *impl;
+  HIP_CHECK(hipStreamSynchronize(I.s));
+  tune = t;
+  tune_src = src;
+  I.tune = t;
+  if (I.ready) {                 // re-resolve the solve shapes at the next solve (captured graphs dropped)
+    I.drop_graphs();
+    I.built_R = -1;
+  }
+}
+
 void DeviceState::set_profiling(bool on) {
   Impl &I = *impl;
   HIP_CHECK(hipStreamSynchronize(I.s));
@@ -3252,6 +3384,12 @@ std::string DeviceState::stats_json() const {
       << ", \"setup_flops\": " << I.P.setup_flops << ", \"far_T_rows\": " << I.t_rows;
   }
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
+  {
+    const char *cn[TC_COUNT] = {"sweep", "dinv", "far1", "far2", "near", "schur"};
+    o << ", \"tuning\": {\"source\": \"" << tune_src << "\", \"entries\": " << tune.size() << ", \"shapes\": {";
+    for (int c = 0; c < TC_COUNT; ++c) o << (c ? ", " : "") << "\"" << cn[c] << "\": " << I.shape_of[c];
+    o << "}}";
+  }
   o << ", \"terms\": " << I.terms << ", \"series_tol\": " << I.series_tol << ", \"terms_used\": " << I.terms_used;
   o << ", \"schedule_split\": {\"levels_built_ms\": " << sched_split[0] << ", \"wait_ms\": " << sched_split[1]
     << ", \"stage_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
@@ -3267,11 +3405,13 @@ std::string DeviceState::stats_json() const {
         << ", \"ms\": " << I.kstat[k].ms << ", \"flops\": " << I.kstat[k].flops
         << ", \"bytes\": " << I.kstat[k].bytes << "}";
     o << ", \"profiling\": " << (I.prof ? 1 : 0) << "}";
-    if (I.prof) {   // kind (0..2 GEMM mode, 3 inverse), work units (tiles / blocks), flops, algorithmic bytes, ms
+    if (I.prof) {   // kind (0..2 GEMM mode, 3 inverse), work units (tiles / blocks), flops, algorithmic bytes, ms,
+                    // tuning class (0 sweep, 1 D^-1, 2-3 far stages, 4 near product, 5 Schur; -1 none)
       o << ", \"launch_log\": [";
       for (size_t i = 0; i < I.launch_log.size(); ++i) {
         const auto &L = I.launch_log[i];
-        o << (i ? ", " : "") << "[" << L.kind << ", " << L.units << ", " << L.flops << ", " << L.bytes << ", " << L.ms << "]";
+        o << (i ? ", " : "") << "[" << L.kind << ", " << L.units << ", " << L.flops << ", " << L.bytes << ", " << L.ms
+          << ", " << L.cls << "]";
       }
       o << "]";
     }

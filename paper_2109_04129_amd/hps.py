@@ -20,7 +20,7 @@ STATUS = {0: "HPS_OK", 1: "HPS_WRATIO", -1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: 
 EXPORTS = ["hps_params_default", "hps_create", "hps_destroy", "hps_last_error", "hps_set_mesh",
            "hps_num_unknowns", "hps_build_hmatrix", "hps_set_hmatrix", "hps_hmatrix_sizes",
            "hps_get_hmatrix", "hps_setup", "hps_solve_planewaves", "hps_solve_rhs",
-           "hps_excitation", "hps_hmatvec", "hps_hmatvec_noalloc", "hps_profile", "hps_stats", "hps_batch_create",
+           "hps_excitation", "hps_hmatvec", "hps_hmatvec_noalloc", "hps_set_tuning", "hps_profile", "hps_stats", "hps_batch_create",
            "hps_batch_set_mesh", "hps_batch_set_hmatrix", "hps_num_problems", "hps_problem_unknowns",
            "hps_set_open_mesh", "hps_rwg", "hps_export_hmatrix", "hps_import_hmatrix"]
 
@@ -82,6 +82,7 @@ def lib():
         L.hps_excitation.argtypes = [ctx, i64, vp, vp, vp]
         L.hps_hmatvec.argtypes = [ctx, i64, vp, vp]
         L.hps_hmatvec_noalloc.argtypes = [ctx, i64, vp, vp]
+        L.hps_set_tuning.argtypes = [ctx, ctypes.c_char_p]
         L.hps_stats.argtypes = [ctx, ctypes.c_char_p, ctypes.c_size_t]
         L.hps_profile.argtypes = [ctx, ctypes.c_int]
         L.hps_batch_create.argtypes = [P(ctx), ctypes.c_int, vp, i32]
@@ -291,6 +292,10 @@ def hps_hmatvec(ctx, R, X_ptr, Y_ptr):
 
 def hps_hmatvec_noalloc(ctx, R, X_ptr, Y_ptr):
     return _check(ctx, lib().hps_hmatvec_noalloc(ctx, int(R), ctypes.c_void_p(X_ptr), ctypes.c_void_p(Y_ptr)))
+
+
+def hps_set_tuning(ctx, path):
+    return _check(ctx, lib().hps_set_tuning(ctx, None if path is None else str(path).encode()))
 
 
 def hps_profile(ctx, enable=True):

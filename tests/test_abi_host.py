@@ -479,3 +479,39 @@ def test_device_mem_cap_enomem_before_device():
         assert e.value.status == -3
     finally:
         hps.hps_destroy(ctx)
+
+
+def test_tuning_table_reader(tmp_path):
+    """hps_set_tuning reads and checks the tile-shape table before it needs a
+    device: a missing file is HPS_EIO, malformed JSON or bad entries
+    HPS_EINVAL, a valid table reaches the device check (HPS_EDEVICE on a
+    host-only context).  The committed table, if present, is valid."""
+    ctx = hps.hps_create(-1)
+
+    def status(text=None, path=None):
+        if path is None:
+            path = tmp_path / "t.json"
+            path.write_text(text)
+        try:
+            hps.hps_set_tuning(ctx, str(path))
+        except hps.HpsError as e:
+            return e.status, str(e)
+        return 0, ""
+
+    try:
+        assert status(path=tmp_path / "absent.json")[0] == -6
+        for bad in ('{"entries": [', '[1, 2]', '{"entries": 3}', '{"entries": [{"class": "gemm", "shape": 0}]}',
+                    '{"entries": [{"class": "sweep", "shape": 5}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
+                    '{"entries": [{"class": "sweep", "shape": 0, "rhs_max": -1}]}', '{"entries": []} x'):
+            st, msg = status(bad)
+            assert st == -1, (bad, st, msg)
+        ok = ('{"arch": "gfx950", "shapes": {"0": "32 x 32"}, "entries": ['
+              '{"class": "sweep", "rhs_max": 64, "group_max": 48.5, "shape": 3}, '
+              '{"class": "schur", "rhs_max": null, "group_max": null, "shape": 2}], "measured": [1, true, null]}')
+        st, msg = status(ok)
+        assert st == -3 and "host-only" in msg, (st, msg)
+        committed = os.path.join(ROOT, "paper_2109_04129_amd", "tuning", "gfx950.json")
+        if os.path.exists(committed):
+            assert status(path=committed)[0] == -3
+    finally:
+        hps.hps_destroy(ctx)

@@ -1,0 +1,71 @@
+"""Tile shapes of the grouped complex GEMM (the autotuner's choices): every
+shape sums the same products in the same order for each output element, so
+setup and solve results are bitwise those of the 32 x 32 shape.  Checked on
+the oracle's H-matrix of the 1,920-unknown sphere with 37 RHS (two column
+tiles of 32, one of them ragged; one ragged 64- and 128-column tile), FP64
+and the FP32 precision form, with every class (Schur updates, sweeps, D^-1,
+far stages, near product) forced to each shape; the FP64 result is also held
+against the oracle's two-term series (1e-10)."""
+
+import json
+
+import numpy as np
+import pytest
+
+from oracle.planewave import excitation
+from oracle.scaling import group_graph, min_degree_order, schur_scaling
+from oracle.series import PowerSeries
+from workloads import monostatic_angles
+from hmat_io import hmatrix_arrays, per_rhs_rel
+
+torch = pytest.importorskip("torch")
+from paper_2109_04129_amd import hps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = ["sweep", "dinv", "far1", "far2", "near", "schur"]
+
+
+def _run(w, H, shape, precision, tmp_path):
+    path = tmp_path / ("shape%d.json" % shape)
+    path.write_text(json.dumps({"entries": [{"class": c, "shape": shape} for c in CLASSES]}))
+    ctx = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        hps.hps_set_tuning(ctx, str(path))
+        hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=1e-3, terms=2,
+                                   precision=precision, refine_passes=1 if precision else 0)
+        a = hmatrix_arrays(H)
+        hps.hps_set_hmatrix(ctx, p, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
+                            a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(ctx)
+        th = np.linspace(0.0, 180.0, 37)
+        khat, pol = monostatic_angles(th, np.zeros_like(th))
+        X = torch.zeros((37, H.N), dtype=torch.complex128, device="cuda")
+        st, rcs, ratio = hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+        Y = torch.zeros_like(X)
+        hps.hps_hmatvec(ctx, 37, X.data_ptr(), Y.data_ptr())
+        torch.cuda.synchronize()
+        used = hps.hps_stats(ctx)["device"]["tuning"]["shapes"]
+        assert all(v == shape for v in used.values()), used
+        return X.cpu().numpy(), Y.cpu().numpy(), rcs, ratio, khat, pol
+    finally:
+        hps.hps_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+def test_tile_shapes_bitwise(c0_workload, c0_hmatrix, precision, tmp_path):
+    w, H = c0_workload, c0_hmatrix
+    print("case: tile shapes 0-4, sphere 1,920 unknowns, 37 RHS, precision %d" % precision, flush=True)
+    X0, Y0, rcs0, ratio0, khat, pol = _run(w, H, 0, precision, tmp_path)
+    for shape in range(1, 5):
+        X, Y, rcs, ratio, _, _ = _run(w, H, shape, precision, tmp_path)
+        assert np.array_equal(X, X0), "shape %d: currents differ (max %.3e)" % (shape, np.max(np.abs(X - X0)))
+        assert np.array_equal(Y, Y0), "shape %d: H x differs" % shape
+        assert np.array_equal(rcs, rcs0) and np.array_equal(ratio, ratio0), "shape %d" % shape
+    if precision == 0:
+        b = excitation(H.rwg, w["freq_hz"], khat, pol)
+        x_ref, _ = PowerSeries(H, schur_scaling(H, min_degree_order(group_graph(H)))).solve_rwg(b, 2)
+        err = per_rhs_rel(X0.T, x_ref).max()
+        print("shape 0 vs oracle: %.2e" % err, flush=True)
+        assert err < 1e-10
