@@ -95,9 +95,10 @@ typedef struct {
                               Solves are then launched without graphs.  0 (default):
                               exactly `terms` terms */
   int32_t host_near;       /* 0 (default): with a device, hps_build_hmatrix computes the
-                              near blocks and the ACA samples of the far blocks on it
-                              (the host recompresses them); 1: the whole build on
-                              host threads */
+                              near blocks, the ACA samples of the far blocks and
+                              their recompression on it (host threads solve only
+                              the k x k eigenproblems of the recompression, k <= 48);
+                              1: the whole build on host threads */
   int32_t formulation;     /* 0 (default): EFIE (eqs. 2-3), symmetric matrix, right
                               coefficients only.  1: CFIE of eq. (8),
                               cfie_alpha EFIE + eta0 (1 - cfie_alpha) MFIE (eqs. 4-7),
@@ -152,9 +153,10 @@ hps_status hps_num_unknowns(const hps_ctx *ctx, int64_t *N);
    most leaf_max unknowns per leaf; near blocks = touching leaf pairs (EFIE
    Galerkin quadrature, Z = Z^T exactly); far blocks = non-touching cluster
    pairs, re-compressed ACA to aca_tol (eqs. 10-12).  With a device (see
-   host_near) the near blocks and the ACA sampling run on it and the host
-   recompresses the far factors; the blocks are then held on both sides.  Not
-   part of "setup". */
+   host_near) the near blocks, the ACA sampling and the recompression run on
+   it (recompression through the Gram matrices of the ACA factors: the same
+   truncation rule as QR + SVD, to about 1e-8 of the block norm); the blocks
+   are then held on both sides.  Not part of "setup". */
 hps_status hps_build_hmatrix(hps_ctx *ctx, const hps_params *p);
 
 /* Install an H-matrix built elsewhere instead (same meaning as above), all
@@ -296,13 +298,15 @@ hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
 
 /* Tile shapes of the grouped complex GEMM (batching form: tile shapes chosen
    by the project's autotuner, paper_2109_04129_amd/autotune.py).  path: a JSON
-   table {"entries": [{"class": C, "rhs_max": R, "group_max": G, "shape": S},
-   ...]}, C one of "sweep", "dinv", "far1", "far2", "near" (solve launches),
+   table {"entries": [{"class": C, "rhs_max": R, "group_max": G, "precision": P,
+   "shape": S}, ...]} (R, G, P optional: no bound / any precision), C one of "sweep", "dinv", "far1", "far2", "near" (solve launches),
    "schur" (setup Schur updates); S 0-4 = workgroup tiles of 32 rows x 32, 64,
    64, 128, 128 columns (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32,
-   16 x 64 outputs).  A launch takes the first entry of its class whose
-   rhs_max bounds its column count and whose group_max bounds the mean pivot
-   size (unknowns per group); shape 0 when none does.  NULL or "" restores
+   16 x 64 outputs), 5 = 32 x 64 with both operands staged in LDS,
+   double-buffered (FP64 launches; FP32 ones take shape 2 for it).  A launch takes the first entry of its class whose
+   rhs_max bounds its column count, whose group_max bounds the mean pivot
+   size (unknowns per group) and whose precision (0, 1, 2 as in hps_params;
+   the setup counts as 0) matches; shape 0 when none does.  NULL or "" restores
    the built-in table (shape 0 everywhere).  Every shape gives bitwise the
    same results.  hps_create loads tuning/gfx950.json from the library's
    directory when that file exists (a malformed one fails hps_create with

@@ -7,10 +7,12 @@ For each workload the library builds the H-matrix once on the device; then
 
 * setup: hps_setup is timed (wall clock, median of --reps, no per-launch
   events) with the Schur-update class forced to each tile shape in turn;
-* solve: for each RHS count (0 = the workload's whole sweep) and each shape,
-  one solve with every solve class forced to that shape runs with per-launch
-  HIP events; the launch log's tuning class then gives each class's summed
-  kernel time under each shape.
+* solve: for each solve form (FP64; the FP32 form with BF16 far factors and
+  its residual pass, whose kernels the FP16 form shares), each RHS count
+  (0 = the workload's whole sweep) and each shape, one solve with every
+  solve class forced to that shape runs with per-launch HIP events; the
+  launch log's tuning class then gives each class's summed kernel time
+  under each shape.
 
 Each class takes its fastest shape.  The table (JSON, read by hps_set_tuning
 and loaded by hps_create from tuning/gfx950.json next to libhps.so) holds one
@@ -31,10 +33,11 @@ import time
 
 CLASSES = ["sweep", "dinv", "far1", "far2", "near", "schur"]
 SOLVE_CLASSES = CLASSES[:5]
-SHAPES = 5
+SHAPES = 6
 SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16", 1: "32 x 64 tile, waves 2 x 2 of 16 x 32",
              2: "32 x 64 tile, waves 1 x 4 of 32 x 16", 3: "32 x 128 tile, waves 1 x 4 of 32 x 32",
-             4: "32 x 128 tile, waves 2 x 2 of 16 x 64"}
+             4: "32 x 128 tile, waves 2 x 2 of 16 x 64",
+             5: "32 x 64 tile, waves 1 x 4 of 32 x 16, operands staged in LDS (FP64; FP32 takes shape 2)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning", "gfx950.json")
 
@@ -50,76 +53,100 @@ def _table(entries):
     return path
 
 
-def tune_workload(name, rhs_list, reps):
+def _context(hps, torch, w, hm=None, precision=0):
+    """A device context on the workload's mesh with its H-matrix: built on
+    the device when hm is None, else installed from hm."""
+    ctx = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        (hps.hps_set_open_mesh if w.get("open") else hps.hps_set_mesh)(ctx, w["xyz"], w["tri"])
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
+                                   precision=precision, refine_passes=1 if precision else 0)
+        if hm is None:
+            hps.hps_build_hmatrix(ctx, p)
+        else:
+            hps.hps_set_hmatrix(ctx, p, hm["N"], hm["perm"], hm["group_ptr"], hm["near_ts"], hm["near_off"],
+                                hm["near_vals"], hm["far_rng"], hm["far_rank"], hm["far_off"], hm["far_uv"])
+        return ctx
+    except BaseException:
+        hps.hps_destroy(ctx)
+        raise
+
+
+def tune_workload(name, rhs_list, reps, precisions=(0, 1)):
     import numpy as np
     import torch
     from paper_2109_04129_amd import hps
     from workloads import workload
     w = workload(name)
-    stream = torch.cuda.current_stream().cuda_stream
-    ctx = hps.hps_create(0, stream)
     tmp = []
-    try:
-        (hps.hps_set_open_mesh if w.get("open") else hps.hps_set_mesh)(ctx, w["xyz"], w["tri"])
-        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2)
-        hps.hps_build_hmatrix(ctx, p)
-        N = hps.hps_num_unknowns(ctx)
-        hps.hps_set_tuning(ctx, None)
-        hps.hps_setup(ctx)
-        st = hps.hps_stats(ctx)
-        groups = st["device"]["groups"]
-        g = N / groups
-        _log("%s: %d unknowns, %d pivot groups (mean %.1f)" % (name, N, groups, g))
-        res = {"workload": name, "N": N, "pivot_groups": groups, "mean_pivot": g, "setup_ms": {}, "solve_ms": {}}
-        # setup: Schur class
-        for sh in range(SHAPES):
-            path = _table([{"class": "schur", "shape": sh}])
-            tmp.append(path)
-            hps.hps_set_tuning(ctx, path)
-            hps.hps_setup(ctx)
-            ts = []
-            for _ in range(reps):
-                t0 = time.perf_counter()
-                hps.hps_setup(ctx)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            res["setup_ms"][sh] = 1e3 * float(np.median(ts))
-            _log("%s setup, Schur shape %d: %.2f ms" % (name, sh, res["setup_ms"][sh]))
-        best_schur = min(res["setup_ms"], key=res["setup_ms"].get)
-        path = _table([{"class": "schur", "shape": best_schur}])
+
+    def table(entries):
+        path = _table(entries)
         tmp.append(path)
-        hps.hps_set_tuning(ctx, path)
-        hps.hps_setup(ctx)
-        # solve classes, per RHS count
-        Rs = sorted(set(len(w["khat"]) if r == 0 else r for r in rhs_list))
-        for R in Rs:
-            idx = np.arange(R) % len(w["khat"])
-            khat, pol = w["khat"][idx], w["pol"][idx]
-            X = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
-            per = {c: {} for c in SOLVE_CLASSES}
+        return path
+
+    try:
+        # setup (FP64 in every form): the Schur class, by setup wall time
+        ctx = _context(hps, torch, w)
+        try:
+            N = hps.hps_num_unknowns(ctx)
+            hm = hps.hps_get_hmatrix(ctx)
+            hm["N"] = N
+            hps.hps_set_tuning(ctx, None)
+            hps.hps_setup(ctx)
+            groups = hps.hps_stats(ctx)["device"]["groups"]
+            g = N / groups
+            _log("%s: %d unknowns, %d pivot groups (mean %.1f)" % (name, N, groups, g))
+            res = {"workload": name, "N": N, "pivot_groups": groups, "mean_pivot": g, "setup_ms": {},
+                   "solve_ms": {}}
             for sh in range(SHAPES):
-                path = _table([{"class": c, "shape": sh} for c in SOLVE_CLASSES] +
-                              [{"class": "schur", "shape": best_schur}])
-                tmp.append(path)
-                hps.hps_set_tuning(ctx, path)
-                hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())     # warm
-                hps.hps_profile(ctx, True)
-                hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
-                torch.cuda.synchronize()
-                log = hps.hps_stats(ctx)["device"].get("launch_log", [])
-                hps.hps_profile(ctx, False)
-                for c, cname in enumerate(SOLVE_CLASSES):
-                    per[cname][sh] = sum(x[4] for x in log if len(x) >= 6 and x[5] == c)
-                _log("%s R=%d shape %d: %s" % (name, R, sh, ", ".join("%s %.2f ms" % (c, per[c][sh])
-                                                                      for c in SOLVE_CLASSES)))
-            res["solve_ms"][R] = per
-            del X
-        res["best"] = {"schur": best_schur,
-                       "solve": {R: {c: min(res["solve_ms"][R][c], key=res["solve_ms"][R][c].get)
-                                     for c in SOLVE_CLASSES} for R in Rs}}
+                hps.hps_set_tuning(ctx, table([{"class": "schur", "shape": sh}]))
+                hps.hps_setup(ctx)
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    hps.hps_setup(ctx)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                res["setup_ms"][sh] = 1e3 * float(np.median(ts))
+                _log("%s setup, Schur shape %d: %.2f ms" % (name, sh, res["setup_ms"][sh]))
+        finally:
+            hps.hps_destroy(ctx)
+        res["best"] = {"schur": min(res["setup_ms"], key=res["setup_ms"].get), "solve": {}}
+        # solve classes, per solve precision (0: FP64; 1: the FP32 form with
+        # BF16 far factors and its residual pass) and RHS count, by summed
+        # per-class launch time (HIP events)
+        Rs = sorted(set(len(w["khat"]) if r == 0 else r for r in rhs_list))
+        for prec in precisions:
+            ctx = _context(hps, torch, w, hm, prec)
+            try:
+                hps.hps_setup(ctx)
+                for R in Rs:
+                    idx = np.arange(R) % len(w["khat"])
+                    khat, pol = w["khat"][idx], w["pol"][idx]
+                    X = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
+                    per = {c: {} for c in SOLVE_CLASSES}
+                    for sh in range(SHAPES):
+                        hps.hps_set_tuning(ctx, table([{"class": c, "shape": sh} for c in SOLVE_CLASSES]))
+                        hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())     # warm
+                        hps.hps_profile(ctx, True)
+                        hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+                        torch.cuda.synchronize()
+                        log = hps.hps_stats(ctx)["device"].get("launch_log", [])
+                        hps.hps_profile(ctx, False)
+                        for c, cname in enumerate(SOLVE_CLASSES):
+                            per[cname][sh] = sum(x[4] for x in log if len(x) >= 6 and x[5] == c)
+                        _log("%s precision %d R=%d shape %d: %s" % (
+                            name, prec, R, sh, ", ".join("%s %.2f ms" % (c, per[c][sh]) for c in SOLVE_CLASSES)))
+                    res["solve_ms"]["%d/%d" % (prec, R)] = per
+                    # a class with no launches in this form keeps shape 0
+                    res["best"]["solve"].setdefault(prec, {})[R] = {
+                        c: (min(per[c], key=per[c].get) if any(per[c].values()) else 0) for c in SOLVE_CLASSES}
+                    del X
+            finally:
+                hps.hps_destroy(ctx)
         return res
     finally:
-        hps.hps_destroy(ctx)
         for path in tmp:
             try:
                 os.remove(path)
@@ -128,17 +155,21 @@ def tune_workload(name, rhs_list, reps):
 
 
 def make_table(results):
-    """Entries in match order: workloads by mean pivot size, then RHS buckets."""
+    """Entries in match order: workloads by mean pivot size, then solve
+    precision, then RHS buckets; the FP32 tuning (BF16 far factors) also
+    serves the FP16 form, which runs the same kernels."""
     results = sorted(results, key=lambda r: r["mean_pivot"])
     entries = []
     for i, r in enumerate(results):
         gmax = None if i + 1 == len(results) else 0.5 * (r["mean_pivot"] + results[i + 1]["mean_pivot"])
-        Rs = sorted(r["best"]["solve"])
-        for j, R in enumerate(Rs):
-            rmax = None if j + 1 == len(Rs) else int(math.floor(math.sqrt(R * Rs[j + 1])))
-            for c in SOLVE_CLASSES:
-                entries.append({"class": c, "rhs_max": rmax, "group_max": gmax,
-                                "shape": int(r["best"]["solve"][R][c])})
+        for prec, best in sorted(r["best"]["solve"].items()):
+            Rs = sorted(best)
+            for pr in ((0,) if prec == 0 else (1, 2)):
+                for j, R in enumerate(Rs):
+                    rmax = None if j + 1 == len(Rs) else int(math.floor(math.sqrt(R * Rs[j + 1])))
+                    for c in SOLVE_CLASSES:
+                        entries.append({"class": c, "rhs_max": rmax, "group_max": gmax, "precision": pr,
+                                        "shape": int(best[R][c])})
         entries.append({"class": "schur", "rhs_max": None, "group_max": gmax, "shape": int(r["best"]["schur"])})
     return entries
 
@@ -149,12 +180,14 @@ def main():
     ap.add_argument("--rhs", nargs="+", type=int, default=[1, 32, 0],
                     help="RHS counts to tune the solve at (0 = the workload's whole sweep)")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--precisions", nargs="+", type=int, default=[0, 1],
+                    help="solve forms to tune (0 FP64, 1 FP32 with BF16 far factors; 1 also serves 2)")
     ap.add_argument("--out", default=DEFAULT_OUT)
     a = ap.parse_args()
     root = os.path.dirname(HERE)
     if root not in sys.path:
         sys.path.insert(0, root)
-    results = [tune_workload(n, a.rhs, a.reps) for n in a.workloads]
+    results = [tune_workload(n, a.rhs, a.reps, tuple(a.precisions)) for n in a.workloads]
     table = {"arch": "gfx950", "shapes": SHAPE_DOC,
              "note": "written by paper_2109_04129_amd/autotune.py; entries match in order (first match wins)",
              "entries": make_table(results), "measured": results}

@@ -224,6 +224,69 @@ static void recompress(int64_t m, int64_t n, int64_t k, std::vector<cplx> &U, st
   rank = (int)r;
 }
 
+// Recompression from the Gram matrices of the ACA factors (the device path,
+// which forms G_U = U^H U and G_V = V^H V and then U T_U, V T_V).  With
+// G_V = P diag(l) P^H (Jacobi), V = Q_V S P^H, S = diag(sqrt(l)), Q_V
+// orthonormal; the block U V^T = B Q_V^T with B = U conj(P) S, and
+// B^H B = S P^T G_U conj(P) S = Y diag(s^2) Y^H (Jacobi), s the singular
+// values of the block.  The best rank-r approximation (the truncation rule
+// of the QR + SVD route) is (B Y_r)(Q_V conj(Y_r))^T, so
+//   T_U = conj(P) S Y_r,   T_V = P S^-1 conj(Y_r)   (k x r each).
+// Directions of V with sqrt(l) <= 1e-12 of the largest carry no weight and
+// are dropped (S^-1 = 0 there).  The squared conditioning of the Gram route
+// limits the accuracy to about 1e-8 of the block norm, far below the ACA
+// tolerance.
+void recompress_from_grams(int64_t k, const cplx *GU, const cplx *GV, double eps, std::vector<cplx> &TU,
+                           std::vector<cplx> &TV, int &rank) {
+  TU.clear();
+  TV.clear();
+  rank = 0;
+  if (k <= 0) return;
+  std::vector<cplx> W, P, Y;
+  std::vector<double> l;
+  jacobi_svd(k, GV, W, l, P);               // Hermitian PSD: singular values = eigenvalues
+  std::vector<double> sv(k), si(k);
+  const double lmax = l.empty() ? 0.0 : std::max(l[0], 0.0);
+  for (int64_t j = 0; j < k; ++j) {
+    const double x = std::sqrt(std::max(l[j], 0.0));
+    const bool keep = lmax > 0.0 && x > 1e-12 * std::sqrt(lmax);
+    sv[j] = keep ? x : 0.0;
+    si[j] = keep ? 1.0 / x : 0.0;
+  }
+  // H = S P^T G_U conj(P) S
+  std::vector<cplx> T(k * k, 0.0), H(k * k, 0.0);
+  for (int64_t c = 0; c < k; ++c)          // T = G_U conj(P)
+    for (int64_t i = 0; i < k; ++i) {
+      cplx acc = 0.0;
+      for (int64_t q = 0; q < k; ++q) acc += GU[q * k + i] * std::conj(P[c * k + q]);
+      T[c * k + i] = acc;
+    }
+  for (int64_t c = 0; c < k; ++c)
+    for (int64_t i = 0; i < k; ++i) {
+      cplx acc = 0.0;
+      for (int64_t q = 0; q < k; ++q) acc += P[i * k + q] * T[c * k + q];     // (P^T)_iq = P_qi
+      H[c * k + i] = sv[i] * acc * sv[c];
+    }
+  std::vector<double> s2;
+  jacobi_svd(k, H.data(), W, s2, Y);
+  std::vector<double> s(k);
+  for (int64_t j = 0; j < k; ++j) s[j] = std::sqrt(std::max(s2[j], 0.0));
+  const int64_t r = trunc_rank(s, eps);
+  TU.assign(k * r, 0.0);
+  TV.assign(k * r, 0.0);
+  for (int64_t c = 0; c < r; ++c)
+    for (int64_t i = 0; i < k; ++i) {
+      cplx au = 0.0, av = 0.0;
+      for (int64_t q = 0; q < k; ++q) {
+        au += std::conj(P[q * k + i]) * sv[q] * Y[c * k + q];
+        av += P[q * k + i] * si[q] * std::conj(Y[c * k + q]);
+      }
+      TU[c * k + i] = au;
+      TV[c * k + i] = av;
+    }
+  rank = (int)r;
+}
+
 void aca_block(const Galerkin &op, const int64_t *rows, int64_t m, const int64_t *cols, int64_t n,
                double eps, std::vector<cplx> &U, std::vector<cplx> &V, int &rank) {
   const double limit = (double)(m * n) / (double)(m + n);
@@ -391,6 +454,7 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
   std::deque<FarChunk> chunks;              // stable element addresses
   std::vector<const cplx *> src(far_sample ? nf : 0);
   std::vector<int32_t> raw_rank(far_sample ? nf : 0);
+  std::vector<char> is_final(far_sample ? nf : 0, 0);
   int64_t ready = 0;                        // far blocks [0, ready) have arrived
   bool dev_done = false;
   std::thread dev_thread;
@@ -407,6 +471,7 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
             for (int64_t b = c.b0; b < c.b1; ++b) {
               raw_rank[b] = c.rank[b - c.b0];
               src[b] = c.uv.data() + c.off[b - c.b0];
+              is_final[b] = (char)(c.final && raw_rank[b] >= 0);
             }
             ready = c.b1;
             cv.notify_all();
@@ -455,7 +520,12 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
         const int64_t slo = H.far_rng[4 * b + 2], shi = H.far_rng[4 * b + 3];
         const int64_t m = thi - tlo, n = shi - slo, k = raw_rank[b];
         int r = 0;
-        if (k < 0) {
+        if (is_final[b]) {                    // recompressed on the device: copy
+          r = (int)k;
+          const cplx *u = src[b];
+          Us[b].assign(u, u + m * k);
+          Vs[b].assign(u + m * k, u + (m + n) * k);
+        } else if (k < 0) {
           aca_block(op, &H.perm[tlo], m, &H.perm[slo], n, p.aca_tol, Us[b], Vs[b], r);
         } else if (k > 0) {
           const cplx *u = src[b];

@@ -45,15 +45,19 @@ struct GemmBatch {
 // tuning table (solve: sweeps, D^-1, far stages, near product; setup: Schur
 // updates), and one entry of the table: `shape` for launches of class `cls`
 // with at most rhs_max columns on a problem whose mean pivot size is at
-// most group_max unknowns.  Shapes 0-4: workgroup tiles of 32 rows x 32, 64,
-// 64, 128, 128 columns (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32, 16 x 64).
+// most group_max unknowns (and, when given, solve precision `precision`).
+// Shapes 0-4: workgroup tiles of 32 rows x 32, 64, 64, 128, 128 columns
+// (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32, 16 x 64); shape 5: 32 x 64
+// with the operands staged in LDS, double-buffered (FP64; the FP32 kernels
+// take shape 2 for it).
 enum { TC_SWEEP = 0, TC_DINV, TC_FAR1, TC_FAR2, TC_NEAR, TC_SCHUR, TC_COUNT };
-constexpr int TUNE_SHAPES = 5;
+constexpr int TUNE_SHAPES = 6;
 struct TuneEntry {
   int cls;
   int64_t rhs_max;
   double group_max;
   int shape;
+  int precision = -1;     // solve arithmetic the entry applies to (0 FP64, 1-2 FP32); -1 any
 };
 
 // Reads a tuning table (JSON, see tune.cpp); throws Error.

@@ -78,8 +78,8 @@ constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops ove
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // tile shapes: (WR, NB) and the workgroup tile's column count
-static_assert(TUNE_SHAPES == 5, "tile shapes 0-4");
-__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 ? 1 : 2; }
+static_assert(TUNE_SHAPES == 6, "tile shapes 0-5 (5: the LDS-staged 32 x 64 kernel)");
+__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 ? 1 : 2; }
 __host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 ? 2 : (v == 4 ? 4 : 1); }
 __host__ __device__ constexpr int shape_tn(int v) { return 16 * shape_nb(v) * (4 / shape_wr(v)); }
 
@@ -240,6 +240,172 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
           }
         }
       }
+  }
+}
+
+// LDS-staged variant (tile shape 5): a workgroup tile of 32 rows x 64
+// columns, waves 1 x 4 (each 32 rows x 16 columns).  Per chunk of 16 k the
+// 256 threads stage A (32 x 16) and B (16 x 64) in LDS with coalesced loads
+// (A column-major: along the rows; A^T and B: along k), double-buffered: the
+// next chunk's global loads are in flight while the waves run the current
+// chunk's MFMAs from LDS, one barrier per chunk.  A is read from L2 once per
+// workgroup instead of once per wave.  Each output element sums the same
+// products in the same order as k_gemm (steps k0 + 4 s + l / 16, zero
+// operands past k), so the results are bitwise those of the other shapes.
+// Every wave takes part in the loads and barriers, also where its columns
+// lie past the block; only the stores are masked.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_lds(const c2 *__restrict__ A, const c2 *__restrict__ B,
+                                                  c2 *__restrict__ C, const Tile *__restrict__ tiles,
+                                                  const Term *__restrict__ terms, int ncols, int ntiles, int ny,
+                                                  int xcd_order) {
+  constexpr int TN = 64, KC = 16, AP = TM + 1, BP = KC + 1;   // LDS row pitches (c2), padded
+  __shared__ c2 sA[2][KC * AP];        // [k][row]
+  __shared__ c2 sB[2][TN * BP];        // [col][k]
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (xcd_order) {
+    const int q = (int)(blockIdx.x >> 3);
+    by = q % ny;
+    bx = 8 * (q / ny) + (int)(blockIdx.x & 7);
+    if (bx >= ntiles) return;            // whole workgroup: uniform
+  }
+  const Tile t = tiles[bx];
+  int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
+  if (t.r0 < 0) {
+    nsc = (t.n + TN - 1) / TN;
+    nsub = ((t.m + TM - 1) / TM) * nsc;
+    st0 = by;
+    sstep = ny;
+  } else if (t.c0 < 0) {
+    tn = ncols;
+    cb0 = by * TN;
+    if (cb0 >= tn) return;
+  } else if (by > 0) {
+    return;
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  for (int st = st0; st < nsub; st += sstep) {
+    int rb = rb0, cb = cb0;
+    if (t.r0 < 0) {
+      rb = (st / nsc) * TM;
+      cb = (st % nsc) * TN;
+    }
+    const int col0 = cb + 16 * wave;                 // this wave's 16 columns
+    c2 cold[2][4];
+    if (MODE != 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int crow = rb + 16 * i + lg + 4 * r, ccol = col0 + li;
+          cold[i][r] = make_double2(0.0, 0.0);
+          if (ccol < tn && crow < t.m) cold[i][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+        }
+    }
+    d4 rr[2], ii[2], ss[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) rr[i] = ii[i] = ss[i] = d4{0.0, 0.0, 0.0, 0.0};
+    // chunk cursor: term q, first k k0 (terms with k = 0 contribute nothing)
+    int q = t.t_begin, k0 = 0;
+    while (q < t.t_end && terms[q].k <= 0) ++q;
+    c2 ra[2], rbv[4];                                  // staged global loads of one chunk
+    auto gload = [&](int qq, int kk0) {
+      const Term tm = terms[qq];
+      const c2 *Ab = A + tm.a_off;
+      if (tm.trans) {                                  // A^T[row][k] = Ab[row lda + k]: along k
+        const int kk = tid & 15, row = tid >> 4;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr_ = rb + row + 16 * h, k = kk0 + kk;
+          ra[h] = (rr_ < t.m && k < tm.k) ? Ab[(int64_t)rr_ * tm.lda + k] : make_double2(0.0, 0.0);
+        }
+      } else {                                         // A[row][k] = Ab[k lda + row]: along the rows
+        const int row = tid & 31, kk = tid >> 5;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr_ = rb + row, k = kk0 + kk + 8 * h;
+          ra[h] = (rr_ < t.m && k < tm.k) ? Ab[(int64_t)k * tm.lda + rr_] : make_double2(0.0, 0.0);
+        }
+      }
+      const int kk = tid & 15, cl = tid >> 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = cb + cl + 16 * j, k = kk0 + kk;
+        rbv[j] = (col < tn && k < tm.k) ? B[tm.b_off + (int64_t)col * tm.ldb + k] : make_double2(0.0, 0.0);
+      }
+    };
+    auto lstore = [&](int buf, int trans) {
+      if (trans) {
+        const int kk = tid & 15, row = tid >> 4;
+        sA[buf][kk * AP + row] = ra[0];
+        sA[buf][kk * AP + row + 16] = ra[1];
+      } else {
+        const int row = tid & 31, kk = tid >> 5;
+        sA[buf][kk * AP + row] = ra[0];
+        sA[buf][(kk + 8) * AP + row] = ra[1];
+      }
+      const int kk = tid & 15, cl = tid >> 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sB[buf][(cl + 16 * j) * BP + kk] = rbv[j];
+    };
+    int buf = 0;
+    if (q < t.t_end) {
+      gload(q, 0);
+      lstore(0, terms[q].trans);
+    }
+    __syncthreads();
+    while (q < t.t_end) {
+      // next chunk
+      int nq = q, nk0 = k0 + KC;
+      if (nk0 >= terms[q].k) {
+        nk0 = 0;
+        ++nq;
+        while (nq < t.t_end && terms[nq].k <= 0) ++nq;
+      }
+      const bool more = nq < t.t_end;
+      if (more) gload(nq, nk0);                        // in flight during the products
+      const c2 *pa = sA[buf], *pb = sB[buf];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + lg;
+        const c2 bv = pb[(16 * wave + li) * BP + kk];
+        const double bs = bv.x + bv.y;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const c2 av = pa[kk * AP + 16 * i + li];
+          rr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, rr[i], 0, 0, 0);
+          ii[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, ii[i], 0, 0, 0);
+          ss[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, bs, ss[i], 0, 0, 0);
+        }
+      }
+      if (more) lstore(buf ^ 1, terms[nq].trans);
+      __syncthreads();
+      buf ^= 1;
+      q = nq;
+      k0 = nk0;
+    }
+    // the next sub-tile's first stores must not overwrite LDS still being read
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ccol = col0 + li;
+      if (ccol >= tn) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int crow = rb + 16 * i + lg + 4 * r;
+        if (crow >= t.m) continue;
+        const c2 acc = make_double2(rr[i][r] - ii[i][r], ss[i][r] - rr[i][r] - ii[i][r]);
+        c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+        if (MODE == 0) {
+          *p = acc;
+        } else if (MODE == 1) {
+          *p = make_double2(cold[i][r].x - acc.x, cold[i][r].y - acc.y);
+        } else {
+          *p = make_double2(cold[i][r].x + acc.x, cold[i][r].y + acc.y);
+        }
+      }
+    }
   }
 }
 
@@ -1463,6 +1629,76 @@ __global__ void k_aca_pack(const AcaBlock *__restrict__ blocks, const int32_t *_
   for (int64_t e = threadIdx.x; e < B.n * k; e += blockDim.x) o[B.m * k + e] = V[e];
 }
 
+// Recompression on the device, step 1: Gram matrices G_U = U^H U and
+// G_V = V^H V (k x k, column-major) of each block's packed ACA factors (U
+// m x k then V n x k at pack[b]), into gram[goff[b]] (G_U then G_V).  Each
+// wave takes entries (p, c), p <= c, in turn; lanes stride over the rows and
+// the wave sums them in a fixed order; the lower triangle is the conjugate.
+__global__ __launch_bounds__(256) void k_gram(const AcaBlock *__restrict__ blocks, const int32_t *__restrict__ rank,
+                                              const int64_t *__restrict__ pack, const int64_t *__restrict__ goff,
+                                              const c2 *__restrict__ packed, c2 *__restrict__ gram) {
+  const AcaBlock B = blocks[blockIdx.x];
+  const int k = rank[blockIdx.x];
+  if (k <= 0) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ne = k * (k + 1) / 2;
+  for (int side = 0; side < 2; ++side) {
+    const c2 *F = packed + pack[blockIdx.x] + (side ? B.m * k : 0);
+    const int64_t rows = side ? B.n : B.m;
+    c2 *G = gram + goff[blockIdx.x] + (int64_t)side * k * k;
+    for (int e = wave; e < ne; e += 4) {
+      // e -> (p, c), p <= c, column by column
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= e) ++c;
+      const int p = e - c * (c + 1) / 2;
+      const c2 *fp = F + (int64_t)p * rows, *fc = F + (int64_t)c * rows;
+      double re = 0.0, im = 0.0;
+      for (int64_t i = lane; i < rows; i += 64) {      // conj(f_p) f_c
+        const c2 a = fp[i], b = fc[i];
+        re = fma(a.x, b.x, re);
+        re = fma(a.y, b.y, re);
+        im = fma(a.x, b.y, im);
+        im = fma(-a.y, b.x, im);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+      }
+      if (lane == 0) {
+        G[(int64_t)c * k + p] = make_double2(re, im);
+        G[(int64_t)p * k + c] = make_double2(re, -im);
+      }
+    }
+  }
+}
+
+// Step 3 (after the host has formed T_U, T_V from the Gram matrices): the
+// recompressed factors U' = U T_U (m x r) and V' = V T_V (n x r) into
+// out[fpack[b]] (U' then V').  T at tofs[b]: T_U (k x r) then T_V (k x r).
+// One row of U or V per thread; T is read from L1 (the same for every row).
+__global__ __launch_bounds__(256) void k_apply(const AcaBlock *__restrict__ blocks, const int32_t *__restrict__ rank,
+                                               const int32_t *__restrict__ rnew, const int64_t *__restrict__ pack,
+                                               const int64_t *__restrict__ tofs, const int64_t *__restrict__ fpack,
+                                               const c2 *__restrict__ packed, const c2 *__restrict__ T,
+                                               c2 *__restrict__ out) {
+  const AcaBlock B = blocks[blockIdx.x];
+  const int k = rank[blockIdx.x], r = rnew[blockIdx.x];
+  if (k <= 0 || r <= 0) return;
+  for (int side = 0; side < 2; ++side) {
+    const c2 *F = packed + pack[blockIdx.x] + (side ? B.m * k : 0);
+    const c2 *Ts = T + tofs[blockIdx.x] + (int64_t)side * k * r;
+    const int64_t rows = side ? B.n : B.m;
+    c2 *o = out + fpack[blockIdx.x] + (side ? B.m * r : 0);
+    for (int64_t i = threadIdx.x; i < rows; i += blockDim.x)
+      for (int c = 0; c < r; ++c) {
+        c2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < k; ++q) cmac(acc, F[(int64_t)q * rows + i], Ts[(int64_t)c * k + q]);
+        o[(int64_t)c * rows + i] = acc;
+      }
+  }
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -1577,6 +1813,7 @@ static void gemm64_launch(int shape, dim3 g, hipStream_t s, const c2 *A, const c
     case 2: hipLaunchKernelGGL((k_gemm<MODE, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 3: hipLaunchKernelGGL((k_gemm<MODE, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 4: hipLaunchKernelGGL((k_gemm<MODE, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 5: hipLaunchKernelGGL((k_gemm_lds<MODE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
   }
 }
@@ -1590,6 +1827,7 @@ static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 2:
+    case 5:       // the LDS-staged shape has no FP32 kernel: the same 32 x 64 tile without LDS
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 3:
@@ -1886,8 +2124,10 @@ struct DeviceState::Impl {
   int shape_of[TC_COUNT] = {0, 0, 0, 0, 0, 0};
   int pick_shape(int cls, int64_t R) const {
     const double g = P.M > 0 ? (double)N / (double)P.M : 0.0;
+    const int pr = cls == TC_SCHUR ? 0 : precision;     // the setup is FP64 in every form
     for (const TuneEntry &e : tune)
-      if (e.cls == cls && R <= e.rhs_max && g <= e.group_max) return e.shape;
+      if (e.cls == cls && R <= e.rhs_max && g <= e.group_max && (e.precision < 0 || e.precision == pr))
+        return e.shape;
     return 0;
   }
   void launch(const Built &b, int mode, const c2 *A, const c2 *B, c2 *C) {
@@ -3284,6 +3524,29 @@ void DeviceState::near_fill(const Mesh &m, double freq_hz, int cfie, double alph
   HIP_CHECK(hipStreamSynchronize(I.s));
 }
 
+// f(q) for q in [0, n) on all host cores (blocks handed out in order).
+template <class F>
+static void parallel_blocks(int64_t n, F &&f) {
+  const int nt = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), (int)((n + 63) / 64)));
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::mutex emu;
+  auto work = [&]() {
+    try {
+      for (int64_t q; (q = next.fetch_add(1)) < n;) f(q);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(emu);
+      if (!err) err = std::current_exception();
+      next.store(n);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
+
 void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alpha, const HMatrix &H, double eps,
                              const FarEmit &emit) {
   HIP_CHECK(hipSetDevice(device));
@@ -3297,10 +3560,10 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alp
   // (no fewer than 4096) so that the host recompression starts early
   const int64_t cap_elems = (int64_t)1 << 28;
   const int64_t cap_blocks = std::max<int64_t>(4096, (nf + 15) / 16);
-  DevArray<c2> scratch, packed;
+  DevArray<c2> scratch, packed, gram, dT, finals;
   DevArray<AcaBlock> dblk;
-  DevArray<int32_t> drank;
-  DevArray<int64_t> dpack;
+  DevArray<int32_t> drank, drnew;
+  DevArray<int64_t> dpack, dgoff, dtofs, dfpack;
   int64_t b0 = 0;
   while (b0 < nf) {
     std::vector<AcaBlock> blk;
@@ -3336,15 +3599,66 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alp
       ch.off[q] = tot;
       if (ch.rank[q] > 0) tot += (blk[q].m + blk[q].n) * ch.rank[q];
     }
-    ch.uv.resize(tot);
     if (tot > 0) {
       dpack.upload(ch.off, I.s);
       packed.alloc((size_t)tot);
       hipLaunchKernelGGL(k_aca_pack, dim3((unsigned)nb), dim3(256), 0, I.s, dblk.p, drank.p, dpack.p, scratch.p,
                          packed.p);
       HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipMemcpyAsync((void *)ch.uv.data(), packed.p, (size_t)tot * sizeof(c2), hipMemcpyDeviceToHost, I.s));
+      // recompression: Gram matrices on the device, the k x k eigenproblems
+      // on host threads, the recompressed factors U T_U, V T_V on the device
+      std::vector<int64_t> goff(nb, 0);
+      int64_t gtot = 0;
+      for (int64_t q = 0; q < nb; ++q) {
+        goff[q] = gtot;
+        if (ch.rank[q] > 0) gtot += 2 * (int64_t)ch.rank[q] * ch.rank[q];
+      }
+      dgoff.upload(goff, I.s);
+      gram.alloc((size_t)std::max<int64_t>(gtot, 1));
+      hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(256), 0, I.s, dblk.p, drank.p, dpack.p, dgoff.p, packed.p,
+                         gram.p);
+      HIP_CHECK(hipGetLastError());
+      std::vector<cplx> hg((size_t)std::max<int64_t>(gtot, 1));
+      HIP_CHECK(hipMemcpyAsync((void *)hg.data(), gram.p, (size_t)gtot * sizeof(c2), hipMemcpyDeviceToHost, I.s));
+      HIP_CHECK(hipStreamSynchronize(I.s));
+      std::vector<std::vector<cplx>> TU(nb), TV(nb);
+      std::vector<int32_t> rnew(nb, 0);
+      parallel_blocks(nb, [&](int64_t q) {
+        const int k = ch.rank[q];
+        if (k <= 0) return;
+        int r = 0;
+        recompress_from_grams(k, &hg[goff[q]], &hg[goff[q] + (int64_t)k * k], eps, TU[q], TV[q], r);
+        rnew[q] = r;
+      });
+      std::vector<int64_t> tofs(nb, 0), fpack(nb, 0);
+      int64_t ttot = 0, ftot = 0;
+      for (int64_t q = 0; q < nb; ++q) {
+        tofs[q] = ttot;
+        fpack[q] = ftot;
+        ttot += 2 * (int64_t)TU[q].size();
+        ftot += (blk[q].m + blk[q].n) * (int64_t)rnew[q];
+      }
+      std::vector<c2> ht((size_t)std::max<int64_t>(ttot, 1));
+      for (int64_t q = 0; q < nb; ++q) {
+        std::memcpy(&ht[tofs[q]], TU[q].data(), TU[q].size() * sizeof(c2));
+        std::memcpy(&ht[tofs[q] + (int64_t)TU[q].size()], TV[q].data(), TV[q].size() * sizeof(c2));
+      }
+      dT.upload(ht, I.s);
+      dtofs.upload(tofs, I.s);
+      dfpack.upload(fpack, I.s);
+      drnew.upload(rnew, I.s);
+      finals.alloc((size_t)std::max<int64_t>(ftot, 1));
+      hipLaunchKernelGGL(k_apply, dim3((unsigned)nb), dim3(256), 0, I.s, dblk.p, drank.p, drnew.p, dpack.p, dtofs.p,
+                         dfpack.p, packed.p, dT.p, finals.p);
+      HIP_CHECK(hipGetLastError());
+      ch.uv.resize(ftot);
+      HIP_CHECK(hipMemcpyAsync((void *)ch.uv.data(), finals.p, (size_t)ftot * sizeof(c2), hipMemcpyDeviceToHost, I.s));
+      for (int64_t q = 0; q < nb; ++q) {
+        ch.off[q] = fpack[q];
+        if (ch.rank[q] > 0) ch.rank[q] = rnew[q];
+      }
     }
+    ch.final = true;
     HIP_CHECK(hipStreamSynchronize(I.s));
     emit(std::move(ch));
     b0 = b;

@@ -116,6 +116,7 @@ using NearFill = std::function<void(HMatrix &H)>;
 // term cap).
 struct FarChunk {
   int64_t b0 = 0, b1 = 0;
+  bool final = false;     // true: factors already recompressed (rank = final rank)
   std::vector<int32_t> rank;
   std::vector<int64_t> off;
   std::vector<cplx> uv;
@@ -135,6 +136,11 @@ void build_hmatrix(const Mesh &mesh, const hps_params &p, HMatrix &H, const Near
 // Small dense complex linear algebra used by the ACA recompression.
 void householder_qr(int64_t m, int64_t n, cplx *A /* m x n col-major, in/out */,
                     std::vector<cplx> &Q /* m x k */, std::vector<cplx> &R /* k x n */, int64_t &k);
+// T_U, T_V (k x r, column-major) of the recompressed factors U T_U, V T_V of a
+// block U V^T, from G_U = U^H U and G_V = V^H V (k x k, column-major); r by
+// the recompression's truncation rule at eps.
+void recompress_from_grams(int64_t k, const cplx *GU, const cplx *GV, double eps, std::vector<cplx> &TU,
+                           std::vector<cplx> &TV, int &rank);
 void jacobi_svd(int64_t n, const cplx *A /* n x n col-major */, std::vector<cplx> &W,
                 std::vector<double> &s, std::vector<cplx> &Y);  // A = W diag(s) Y^H, s descending
 

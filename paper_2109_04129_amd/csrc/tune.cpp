@@ -1,11 +1,11 @@
 // Tile-shape tuning table: reads the JSON file the autotuner writes.
 //
 //   {"arch": "gfx950",
-//    "entries": [{"class": "sweep", "rhs_max": 256, "group_max": 64, "shape": 3}, ...]}
+//    "entries": [{"class": "sweep", "rhs_max": 256, "group_max": 64, "precision": 0, "shape": 3}, ...]}
 //
-// Entries are matched in file order (first match wins); "rhs_max" and
-// "group_max" may be omitted (no bound).  Other keys are ignored.  A small
-// recursive-descent reader of the JSON subset the file uses (objects,
+// Entries are matched in file order (first match wins); "rhs_max",
+// "group_max" and "precision" may be omitted (no bound / any precision).
+// Other keys are ignored.  A small recursive-descent reader of the JSON subset the file uses (objects,
 // arrays, strings without unicode escapes, numbers, true / false / null).
 #include <cerrno>
 #include <cmath>
@@ -166,10 +166,11 @@ std::vector<TuneEntry> read_tuning(const std::string &path) {
   for (const JVal &e : ent->arr) {
     if (e.kind != JVal::OBJ) throw Error{HPS_EINVAL, "tuning file: an entry is not an object"};
     const JVal *c = e.get("class"), *sh = e.get("shape"), *rm = e.get("rhs_max"), *gm = e.get("group_max");
+    const JVal *pr = e.get("precision");
     if (!c || c->kind != JVal::STR || class_id(c->str) < 0)
       throw Error{HPS_EINVAL, "tuning file: entry without a known \"class\" (sweep, dinv, far1, far2, near, schur)"};
     if (!sh || sh->kind != JVal::NUM || sh->num != std::floor(sh->num) || sh->num < 0 || sh->num >= TUNE_SHAPES)
-      throw Error{HPS_EINVAL, "tuning file: \"shape\" must be an integer 0-4"};
+      throw Error{HPS_EINVAL, "tuning file: \"shape\" must be an integer 0-5"};
     TuneEntry t;
     t.cls = class_id(c->str);
     t.shape = (int)sh->num;
@@ -182,6 +183,11 @@ std::vector<TuneEntry> read_tuning(const std::string &path) {
     if (gm && gm->kind != JVal::NUL) {
       if (gm->kind != JVal::NUM || gm->num < 0) throw Error{HPS_EINVAL, "tuning file: bad \"group_max\""};
       t.group_max = gm->num;
+    }
+    if (pr && pr->kind != JVal::NUL) {
+      if (pr->kind != JVal::NUM || pr->num != std::floor(pr->num) || pr->num < 0 || pr->num > 2)
+        throw Error{HPS_EINVAL, "tuning file: \"precision\" must be 0, 1 or 2"};
+      t.precision = (int)pr->num;
     }
     out.push_back(t);
   }

@@ -501,12 +501,13 @@ def test_tuning_table_reader(tmp_path):
     try:
         assert status(path=tmp_path / "absent.json")[0] == -6
         for bad in ('{"entries": [', '[1, 2]', '{"entries": 3}', '{"entries": [{"class": "gemm", "shape": 0}]}',
-                    '{"entries": [{"class": "sweep", "shape": 5}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
-                    '{"entries": [{"class": "sweep", "shape": 0, "rhs_max": -1}]}', '{"entries": []} x'):
+                    '{"entries": [{"class": "sweep", "shape": 6}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
+                    '{"entries": [{"class": "sweep", "shape": 0, "rhs_max": -1}]}', '{"entries": []} x',
+                    '{"entries": [{"class": "sweep", "shape": 0, "precision": 3}]}'):
             st, msg = status(bad)
             assert st == -1, (bad, st, msg)
         ok = ('{"arch": "gfx950", "shapes": {"0": "32 x 32"}, "entries": ['
-              '{"class": "sweep", "rhs_max": 64, "group_max": 48.5, "shape": 3}, '
+              '{"class": "sweep", "rhs_max": 64, "group_max": 48.5, "precision": 1, "shape": 3}, '
               '{"class": "schur", "rhs_max": null, "group_max": null, "shape": 2}], "measured": [1, true, null]}')
         st, msg = status(ok)
         assert st == -3 and "host-only" in msg, (st, msg)

@@ -330,11 +330,13 @@ def test_open_plate():
 
 
 def test_device_hmatrix_build(c0_workload, c0_hmatrix, c0_dense):
-    """hps_build_hmatrix on a device context computes the near blocks and the
-    ACA samples of the far blocks on the GPU (the host recompresses): near
-    entries equal the oracle's and the host build's (host_near = 1) to
-    rounding; the far field approximates the dense matrix to the ACA bound,
-    like the host build, with the same structure."""
+    """hps_build_hmatrix on a device context computes the near blocks, the
+    ACA samples of the far blocks and their recompression on the GPU (Gram
+    matrices and recompressed factors on the device, k x k eigenproblems on
+    host threads): near entries equal the oracle's and the host build's
+    (host_near = 1: QR + SVD recompression on the host) to rounding; the far
+    field approximates the dense matrix to the ACA bound (2 eps), like the
+    host build, with the same structure and mean rank within 10%."""
     w, H = c0_workload, c0_hmatrix
     print("case: sphere 1,920 unknowns, H-matrix build on the device", flush=True)
     out = {}
