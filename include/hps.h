@@ -97,7 +97,7 @@ typedef struct {
   int32_t host_near;       /* 0 (default): with a device, hps_build_hmatrix computes the
                               near blocks, the ACA samples of the far blocks and
                               their recompression on it (host threads solve only
-                              the k x k eigenproblems of the recompression, k <= 48);
+                              the k x k eigenproblems of the recompression, k <= 96);
                               1: the whole build on host threads */
   int32_t formulation;     /* 0 (default): EFIE (eqs. 2-3), symmetric matrix, right
                               coefficients only.  1: CFIE of eq. (8),
@@ -303,7 +303,11 @@ hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
    "schur" (setup Schur updates); S 0-4 = workgroup tiles of 32 rows x 32, 64,
    64, 128, 128 columns (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32,
    16 x 64 outputs), 5 = 32 x 64 with both operands staged in LDS,
-   double-buffered (FP64 launches; FP32 ones take shape 2 for it).  A launch takes the first entry of its class whose
+   double-buffered (FP64 launches; FP32 ones take shape 2 for it), 6 = a
+   vector-ALU matrix-vector kernel for one-column FP64 solves (other launches
+   take shape 0 for it; its sums are in another order, so one-column results
+   differ from the other shapes' by rounding), 7 and 8 = shapes 2 and 1 built
+   for 3 waves per SIMD (FP64; FP32 launches take 2 and 1).  A launch takes the first entry of its class whose
    rhs_max bounds its column count, whose group_max bounds the mean pivot
    size (unknowns per group) and whose precision (0, 1, 2 as in hps_params;
    the setup counts as 0) matches; shape 0 when none does.  NULL or "" restores

@@ -49,9 +49,11 @@ struct GemmBatch {
 // Shapes 0-4: workgroup tiles of 32 rows x 32, 64, 64, 128, 128 columns
 // (waves of 16 x 16, 16 x 32, 32 x 16, 32 x 32, 16 x 64); shape 5: 32 x 64
 // with the operands staged in LDS, double-buffered (FP64; the FP32 kernels
-// take shape 2 for it).
+// take shape 2 for it); shape 6: a vector-ALU matrix-vector kernel for
+// one-column FP64 solves (any other launch takes shape 0 for it); shapes 7
+// and 8: shapes 2 and 1 built for 3 waves per SIMD (FP64; FP32 takes 2, 1).
 enum { TC_SWEEP = 0, TC_DINV, TC_FAR1, TC_FAR2, TC_NEAR, TC_SCHUR, TC_COUNT };
-constexpr int TUNE_SHAPES = 6;
+constexpr int TUNE_SHAPES = 9;
 struct TuneEntry {
   int cls;
   int64_t rhs_max;

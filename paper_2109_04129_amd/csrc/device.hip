@@ -73,18 +73,21 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // from L2 (no LDS).  The tile shape of each launch class is a run-time choice
 // (a tuning table written by the autotuner); every shape gives bitwise the
 // same result (each output element sums the same products in the same order).
+// WPE > 1 builds the kernel for at least WPE waves per SIMD (registers capped
+// accordingly; the C tile of the read-modify-write modes is then fetched
+// after the products, so fewer registers stay live through them).
 constexpr int TM = 32;
 constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops over its share of sub-tiles)
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // tile shapes: (WR, NB) and the workgroup tile's column count
-static_assert(TUNE_SHAPES == 6, "tile shapes 0-5 (5: the LDS-staged 32 x 64 kernel)");
-__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 ? 1 : 2; }
-__host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 ? 2 : (v == 4 ? 4 : 1); }
+static_assert(TUNE_SHAPES == 9, "tile shapes 0-8 (5: LDS-staged 32 x 64, 6: one-column vector kernel, 7-8: shapes 2 and 1 built for 3 waves per SIMD)");
+__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 || v == 7 ? 1 : 2; }
+__host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 || v == 8 ? 2 : (v == 4 ? 4 : 1); }
 __host__ __device__ constexpr int shape_tn(int v) { return 16 * shape_nb(v) * (4 / shape_wr(v)); }
 
-template <int MODE, int WR, int NB>
-__global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
+template <int MODE, int WR, int NB, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm(const c2 *__restrict__ A, const c2 *__restrict__ B,
                                               c2 *__restrict__ C, const Tile *__restrict__ tiles,
                                               const Term *__restrict__ terms, int ncols, int ntiles, int ny,
                                               int xcd_order) {
@@ -136,9 +139,11 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
     bool arow_ok[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) arow_ok[i] = row0 + 16 * i + li < t.m;
-    // read-modify-write modes: fetch C now, so its latency hides behind the products
+    // read-modify-write modes: fetch C now, so its latency hides behind the
+    // products (after them when the kernel is built for more waves per SIMD:
+    // fewer registers live through the products)
     c2 cold[RB][NB][4];
-    if (MODE != 0) {
+    auto fetch_c = [&]() {
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -151,7 +156,8 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
             if (ccol < tn && crow < t.m) cold[i][j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
           }
         }
-    }
+    };
+    if (MODE != 0 && WPE == 1) fetch_c();
     d4 rr[RB][NB], ii[RB][NB], ss[RB][NB];      // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -219,6 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm(const c2 *__restrict__ A, const c2
         }
       }
     }
+    if (MODE != 0 && WPE > 1) fetch_c();
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -405,6 +412,68 @@ __global__ __launch_bounds__(256) void k_gemm_lds(const c2 *__restrict__ A, cons
           *p = make_double2(cold[i][r].x + acc.x, cold[i][r].y + acc.y);
         }
       }
+    }
+  }
+}
+
+// One right-hand side (tile shape 6): a matrix-vector product per tile of
+// 32 rows, on the vector ALU; with one column the MFMA tile would compute
+// 31 padding columns and the product is bound by streaming A.  256 threads
+// = 32 rows x 8 lanes along k; A^T terms (A read along k) take row = t / 8,
+// plain terms (A read along its columns) row = t % 32, so every load of A is
+// coalesced.  Each thread sums its share of k in order; the 8 partial sums
+// of a row are added in a fixed order through LDS (deterministic).  Solve
+// tiles only (c0 < 0, ncols = 1).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemv(const c2 *__restrict__ A, const c2 *__restrict__ B,
+                                              c2 *__restrict__ C, const Tile *__restrict__ tiles,
+                                              const Term *__restrict__ terms, int ntiles) {
+  __shared__ c2 part[2][TM][9];
+  // one-dimensional grid of ntiles workgroups (the host launches it so)
+  const int bx = (int)blockIdx.x;
+  if (bx >= ntiles) return;
+  const Tile t = tiles[bx];
+  const int tid = threadIdx.x;
+  const int rT = tid >> 3, kT = tid & 7;      // A^T terms
+  const int rN = tid & 31, kN = tid >> 5;     // plain terms
+  c2 accT = make_double2(0.0, 0.0), accN = make_double2(0.0, 0.0);
+  const int rowT = t.r0 + rT, rowN = t.r0 + rN;
+  for (int q = t.t_begin; q < t.t_end; ++q) {
+    const Term tm = terms[q];
+    const c2 *Ab = A + tm.a_off, *Bb = B + tm.b_off;
+    if (tm.trans) {
+      if (rowT < t.m) {
+#pragma unroll 4
+        for (int k = kT; k < tm.k; k += 8) cmac(accT, Ab[(int64_t)rowT * tm.lda + k], Bb[k]);
+      }
+    } else {
+      if (rowN < t.m) {
+#pragma unroll 4
+        for (int k = kN; k < tm.k; k += 8) cmac(accN, Ab[(int64_t)k * tm.lda + rowN], Bb[k]);
+      }
+    }
+  }
+  part[0][rT][kT] = accT;
+  part[1][rN][kN] = accN;
+  __syncthreads();
+  if (tid < TM) {
+    const int row = t.r0 + tid;
+    c2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      acc.x += part[0][tid][j].x;
+      acc.y += part[0][tid][j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      acc.x += part[1][tid][j].x;
+      acc.y += part[1][tid][j].y;
+    }
+    if (row < t.m) {
+      c2 *p = C + t.c_off + row;
+      if (MODE == 0) *p = acc;
+      else if (MODE == 1) *p = make_double2(p->x - acc.x, p->y - acc.y);
+      else *p = make_double2(p->x + acc.x, p->y + acc.y);
     }
   }
 }
@@ -1449,7 +1518,7 @@ __global__ __launch_bounds__(256) void k_near(NearMesh M, const int64_t *__restr
 // stay in the workgroup's scratch; rank -1 hands the block back to the host
 // (rank limit m n / (m + n) reached, more than kAcaCap terms, or m too
 // large for the row bitmap).  Recompression happens on the host.
-constexpr int kAcaCap = 48;
+constexpr int kAcaCap = 96;
 constexpr int kAcaMaxRows = 65536;
 
 struct AcaBlock {
@@ -1814,6 +1883,8 @@ static void gemm64_launch(int shape, dim3 g, hipStream_t s, const c2 *A, const c
     case 3: hipLaunchKernelGGL((k_gemm<MODE, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 4: hipLaunchKernelGGL((k_gemm<MODE, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 5: hipLaunchKernelGGL((k_gemm_lds<MODE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 7: hipLaunchKernelGGL((k_gemm<MODE, 1, 1, 3>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 8: hipLaunchKernelGGL((k_gemm<MODE, 2, 2, 3>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
   }
 }
@@ -1824,10 +1895,12 @@ static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const
   const dim3 blk(256);
   switch (shape) {
     case 1:
+    case 8:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 2:
     case 5:       // the LDS-staged shape has no FP32 kernel: the same 32 x 64 tile without LDS
+    case 7:       // FP32 kernels are not built for 3 waves per SIMD: the same tile
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 3:
@@ -2107,7 +2180,13 @@ struct DeviceState::Impl {
     dim3 g = xo ? dim3((unsigned)nwg) : dim3((unsigned)n_tiles, (unsigned)sub);
     const int nt = (int)n_tiles;
     const int64_t pr = prof_begin(mode, flops, bytes, n_tiles, cls);
-    if (mode == 0)
+    if (shape == 6 && !(wide && ncols == 1)) shape = 0;    // the vector kernel serves one-column solve tiles only
+    if (shape == 6) {
+      const dim3 g1((unsigned)n_tiles), blk(256);
+      if (mode == 0) hipLaunchKernelGGL(k_gemv<0>, g1, blk, 0, s, A, B, C, tiles, terms, nt);
+      else if (mode == 1) hipLaunchKernelGGL(k_gemv<1>, g1, blk, 0, s, A, B, C, tiles, terms, nt);
+      else hipLaunchKernelGGL(k_gemv<2>, g1, blk, 0, s, A, B, C, tiles, terms, nt);
+    } else if (mode == 0)
       gemm64_launch<0>(shape, g, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
     else if (mode == 1)
       gemm64_launch<1>(shape, g, s, A, B, C, tiles, terms, ncols, nt, sub, xo);
@@ -2180,6 +2259,7 @@ struct DeviceState::Impl {
     if (ncols < 0) ncols = cur_R;
     const int64_t pr = prof_begin(MODE, flops, bytes, n, cls);
     // store mode (far field, D^-1) in the XCD-aware order, as in launch_tiles
+    if (shape == 6) shape = 0;                          // no FP32 vector kernel: the 32 x 32 tile
     const int ny = (int)cdiv(ncols, shape_tn(shape)), xo = MODE == 0 ? 1 : 0;
     const int64_t nwg = cdiv(n, 8) * 8 * (int64_t)ny;
     if (n > INT32_MAX || nwg * 256 > (int64_t)UINT32_MAX) throw Error{HPS_EINVAL, "launch too large"};
@@ -2599,7 +2679,10 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   I.ready = false;
   I.built_R = -1;
   I.tune = tune;
-  const int schur_shape = I.pick_shape(TC_SCHUR, 0);
+  // the Schur updates' tile shape (explicit tiles: the one-column vector
+  // kernel does not apply, the width is the shape's)
+  const int schur_shape = I.pick_shape(TC_SCHUR, 0) == 6 ? 0 : I.pick_shape(TC_SCHUR, 0);
+  const int64_t schur_tn = shape_tn(schur_shape);
   I.shape_of[TC_SCHUR] = schur_shape;
   const int64_t N = I.N, M = I.M;
   // working and factor panels; a non-symmetric near field (CFIE) also keeps
@@ -2931,12 +3014,17 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       const bool next = P.level[j] == l + 1;
       std::vector<Tile> &tl = next ? o.stiles : o.stiles2;
       GemmLaunch &gl = next ? o.schur : o.schur2;
-      tl.push_back(Tile{coff, (int32_t)P.size[j], -1, -1, (int32_t)P.size[j], (int32_t)cols, start[x], start[x + 1]});
+      // one explicit tile per (32 x shape-width) sub-tile of the target, so
+      // every workgroup of the launch has work (a whole-block tile would be
+      // given as many workgroups as the launch's largest target needs)
+      for (int64_t r0 = 0; r0 < P.size[j]; r0 += TM)
+        for (int64_t c0 = 0; c0 < cols; c0 += schur_tn)
+          tl.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j], (int32_t)cols,
+                            start[x], start[x + 1]});
       gl.flops += tflop[x];
       for (int32_t q = start[x]; q < start[x + 1]; ++q)
         gl.bytes += 16.0 * o.sterms[q].k * ((double)P.size[j] + (double)cols);
       gl.bytes += 32.0 * P.size[j] * cols;
-      gl.sub = std::max<int>(gl.sub, (int)(cdiv(P.size[j], TM) * cdiv(cols, TM)));
       slot[id] = -1;
     }
     tgt.clear();
