@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--only-headline", action="store_true",
                     help="headline leg only (for profiler runs): no secondary legs, no baseline")
     ap.add_argument("--batch-workload", default="ellipsoids32_600MHz")
+    ap.add_argument("--only-single-rhs", action="store_true",
+                    help="the single-RHS leg of --workload only (for profiler runs); prints its own JSON line")
     ap.add_argument("--leaf-study", action="store_true",
                     help="run only the leaf-size study (Sec. V.A): two-term and converged-series error against "
                          "the direct solution vs leaf size, EFIE and CFIE; prints its own JSON line")
@@ -124,6 +126,18 @@ def install(hps, ctx, p, g):
                         g["far_rng"], g["far_rank"], g["far_off"], g["far_uv"])
 
 
+def copy_calib(args):
+    """With --copy-calib: one 256 MiB device copy (a scale reference for the
+    HBM byte counters of a profiler run)."""
+    import torch
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)                   # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def gpu_leg(args, w, g, steps, warmup, precision=0, refine=0, reference_terms=None, extra=None,
             reference_tol=0.0, profile=True):
     """`steps` timed steps (hps_setup + the whole sweep's hps_solve_planewaves)
@@ -134,12 +148,7 @@ def gpu_leg(args, w, g, steps, warmup, precision=0, refine=0, reference_terms=No
     from paper_2109_04129_amd import hps
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    if args.copy_calib:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)                   # 256 MiB read + 256 MiB written
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calib(args)
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
     set_mesh(hps, ctx, w)
@@ -223,6 +232,7 @@ def single_rhs_leg(args, w, g, precision=0, reps=10):
     one profiled solve for the per-kernel algorithmic bytes."""
     import torch
     from paper_2109_04129_amd import hps
+    copy_calib(args)
     stream = torch.cuda.current_stream()
     ctx = hps.hps_create(0, stream.cuda_stream)
     try:
@@ -678,6 +688,13 @@ def main():
         sys.exit(2)
     if args.leaf_study:
         print(json.dumps(leaf_study(args)), flush=True)
+        return
+    if args.only_single_rhs:
+        from workloads import workload
+        w = workload(args.workload)
+        w["name"] = args.workload
+        hm, _ = build_hmatrix(w)
+        print(json.dumps(single_rhs_leg(args, w, hm)), flush=True)
         return
     from workloads import workload
     w = workload(args.workload)

@@ -307,7 +307,9 @@ hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
    vector-ALU matrix-vector kernel for one-column FP64 solves (other launches
    take shape 0 for it; its sums are in another order, so one-column results
    differ from the other shapes' by rounding), 7 and 8 = shapes 2 and 1 built
-   for 3 waves per SIMD (FP64; FP32 launches take 2 and 1).  A launch takes the first entry of its class whose
+   for 3 waves per SIMD (FP64; FP32 launches take 2 and 1), 9 = shape 0
+   built for 5 waves per SIMD (FP64; FP32 takes 0), 10 = shape 3 built for 4
+   waves per SIMD (FP32; FP64 takes 3).  A launch takes the first entry of its class whose
    rhs_max bounds its column count, whose group_max bounds the mean pivot
    size (unknowns per group) and whose precision (0, 1, 2 as in hps_params;
    the setup counts as 0) matches; shape 0 when none does.  NULL or "" restores

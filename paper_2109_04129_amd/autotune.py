@@ -33,14 +33,16 @@ import time
 
 CLASSES = ["sweep", "dinv", "far1", "far2", "near", "schur"]
 SOLVE_CLASSES = CLASSES[:5]
-SHAPES = 9
-SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16", 1: "32 x 64 tile, waves 2 x 2 of 16 x 32",
+SHAPES = 11
+SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16 (FP64 built for 4 waves per SIMD)", 1: "32 x 64 tile, waves 2 x 2 of 16 x 32",
              2: "32 x 64 tile, waves 1 x 4 of 32 x 16", 3: "32 x 128 tile, waves 1 x 4 of 32 x 32",
              4: "32 x 128 tile, waves 2 x 2 of 16 x 64",
              5: "32 x 64 tile, waves 1 x 4 of 32 x 16, operands staged in LDS (FP64; FP32 takes shape 2)",
              6: "one-column FP64 solves: vector-ALU matrix-vector kernel (else shape 0)",
              7: "as 2, built for 3 waves per SIMD (FP64; FP32 takes 2)",
-             8: "as 1, built for 3 waves per SIMD (FP64; FP32 takes 1)"}
+             8: "as 1, built for 3 waves per SIMD (FP64; FP32 takes 1)",
+             9: "as 0, built for 5 waves per SIMD (FP64; FP32 takes 0)",
+             10: "as 3, built for 4 waves per SIMD (FP32; FP64 takes 3)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning", "gfx950.json")
 

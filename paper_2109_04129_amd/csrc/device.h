@@ -51,9 +51,12 @@ struct GemmBatch {
 // with the operands staged in LDS, double-buffered (FP64; the FP32 kernels
 // take shape 2 for it); shape 6: a vector-ALU matrix-vector kernel for
 // one-column FP64 solves (any other launch takes shape 0 for it); shapes 7
-// and 8: shapes 2 and 1 built for 3 waves per SIMD (FP64; FP32 takes 2, 1).
+// and 8: shapes 2 and 1 built for 3 waves per SIMD (FP64; FP32 takes 2, 1);
+// shape 9: shape 0 built for 5 waves per SIMD (FP64; FP32 takes 0); shape
+// 10: shape 3 built for 4 waves per SIMD (FP32; FP64 takes 3).  The FP64
+// shape 0 itself is built for 4.
 enum { TC_SWEEP = 0, TC_DINV, TC_FAR1, TC_FAR2, TC_NEAR, TC_SCHUR, TC_COUNT };
-constexpr int TUNE_SHAPES = 9;
+constexpr int TUNE_SHAPES = 11;
 struct TuneEntry {
   int cls;
   int64_t rhs_max;

@@ -81,9 +81,9 @@ constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops ove
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // tile shapes: (WR, NB) and the workgroup tile's column count
-static_assert(TUNE_SHAPES == 9, "tile shapes 0-8 (5: LDS-staged 32 x 64, 6: one-column vector kernel, 7-8: shapes 2 and 1 built for 3 waves per SIMD)");
-__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 || v == 7 ? 1 : 2; }
-__host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 || v == 8 ? 2 : (v == 4 ? 4 : 1); }
+static_assert(TUNE_SHAPES == 11, "tile shapes 0-10");
+__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 || v == 7 || v == 10 ? 1 : 2; }
+__host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 || v == 8 || v == 10 ? 2 : (v == 4 ? 4 : 1); }
 __host__ __device__ constexpr int shape_tn(int v) { return 16 * shape_nb(v) * (4 / shape_wr(v)); }
 
 template <int MODE, int WR, int NB, int WPE = 1>
@@ -495,8 +495,8 @@ __device__ __forceinline__ float2 load_a(const void *__restrict__ A, int64_t i) 
   return make_float2(__low2float(h), __high2float(h));
 }
 
-template <int MODE, int AT, int WR, int NB>
-__global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
+template <int MODE, int AT, int WR, int NB, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm32(const void *__restrict__ A, const float2 *__restrict__ B,
                                                 float2 *__restrict__ C, const Tile *__restrict__ tiles,
                                                 const Term *__restrict__ terms, const float *__restrict__ scales,
                                                 const int32_t *__restrict__ rowpart, int ncols, int ntiles, int ny,
@@ -542,9 +542,10 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
     if (AT != 0 && rowpart != nullptr && arow_ok[i] && t.t_begin < t.t_end && terms[t.t_begin].sidx == -2)
       sc_row[i] = scales[rowpart[t.c_off + arow]];
   }
-  // read-modify-write modes: fetch C now, so its latency hides behind the products
+  // read-modify-write modes: fetch C now, so its latency hides behind the
+  // products (after them in the builds for more waves per SIMD)
   float2 cold[RB][NB][4];
-  if (MODE != 0) {
+  auto fetch_c = [&]() {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -557,7 +558,8 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
           if (ccol < tn && crow < t.m) cold[i][j][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
         }
       }
-  }
+  };
+  if (MODE != 0 && WPE == 1) fetch_c();
   f4 rr[RB][NB], ii[RB][NB], ss[RB][NB];          // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
   for (int i = 0; i < RB; ++i)
@@ -637,6 +639,7 @@ __global__ __launch_bounds__(256) void k_gemm32(const void *__restrict__ A, cons
       }
     }
   }
+  if (MODE != 0 && WPE > 1) fetch_c();
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -1885,7 +1888,9 @@ static void gemm64_launch(int shape, dim3 g, hipStream_t s, const c2 *A, const c
     case 5: hipLaunchKernelGGL((k_gemm_lds<MODE>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 7: hipLaunchKernelGGL((k_gemm<MODE, 1, 1, 3>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 8: hipLaunchKernelGGL((k_gemm<MODE, 2, 2, 3>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
-    default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 9: hipLaunchKernelGGL((k_gemm<MODE, 2, 1, 5>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 10: hipLaunchKernelGGL((k_gemm<MODE, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1, 4>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
   }
 }
 template <int MODE, int AT>
@@ -1905,6 +1910,9 @@ static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const
       break;
     case 3:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
+      break;
+    case 10:      // shape 3 built for 4 waves per SIMD
+      hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 4:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 4>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
