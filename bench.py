@@ -82,6 +82,10 @@ def parse():
     ap.add_argument("--batch-workload", default="ellipsoids32_600MHz")
     ap.add_argument("--only-single-rhs", action="store_true",
                     help="the single-RHS leg of --workload only (for profiler runs); prints its own JSON line")
+    ap.add_argument("--tuning", default=None,
+                    help="tile-shape table (JSON, as the autotuner writes) to use instead of the library's")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the batching leg (--batch-workload); prints its own JSON line")
     ap.add_argument("--leaf-study", action="store_true",
                     help="run only the leaf-size study (Sec. V.A): two-term and converged-series error against "
                          "the direct solution vs leaf size, EFIE and CFIE; prints its own JSON line")
@@ -101,7 +105,7 @@ def build_hmatrix(w, **extra):
     installed in every leg.  ``extra`` selects e.g. the CFIE formulation."""
     import torch
     from paper_2109_04129_amd import hps
-    h = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
+    h = tuned(hps.hps_create(0, torch.cuda.current_stream().cuda_stream))
     try:
         set_mesh(hps, h, w)
         p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], verbose=1,
@@ -150,7 +154,7 @@ def gpu_leg(args, w, g, steps, warmup, precision=0, refine=0, reference_terms=No
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     copy_calib(args)
     stream = torch.cuda.current_stream()
-    ctx = hps.hps_create(0, stream.cuda_stream)
+    ctx = tuned(hps.hps_create(0, stream.cuda_stream))
     set_mesh(hps, ctx, w)
     kw = dict(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2, precision=precision,
               refine_passes=refine)
@@ -204,7 +208,7 @@ def gpu_leg(args, w, g, steps, warmup, precision=0, refine=0, reference_terms=No
         Xm = X.cpu().numpy()
         del X
         p.precision, p.refine_passes, p.terms, p.series_tol = 0, 0, reference_terms, reference_tol
-        ref = hps.hps_create(0, stream.cuda_stream)
+        ref = tuned(hps.hps_create(0, stream.cuda_stream))
         set_mesh(hps, ref, w)
         install(hps, ref, p, g)
         hps.hps_setup(ref)
@@ -234,7 +238,7 @@ def single_rhs_leg(args, w, g, precision=0, reps=10):
     from paper_2109_04129_amd import hps
     copy_calib(args)
     stream = torch.cuda.current_stream()
-    ctx = hps.hps_create(0, stream.cuda_stream)
+    ctx = tuned(hps.hps_create(0, stream.cuda_stream))
     try:
         set_mesh(hps, ctx, w)
         p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=w["aca_tol"], terms=2,
@@ -304,7 +308,7 @@ def batch_leg(args):
     # on host threads; not timed as setup)
     parts, build_s = [], 0.0
     for p, (xyz, tri) in enumerate(bw["meshes"]):
-        h = hps.hps_create(0, stream)
+        h = tuned(hps.hps_create(0, stream))
         hps.hps_set_mesh(h, xyz, tri)
         t0 = time.perf_counter()
         hps.hps_build_hmatrix(h, prm)
@@ -317,15 +321,15 @@ def batch_leg(args):
     Ns = [a["N"] for a in parts]
     NT = sum(Ns)
 
-    def batch_ctx(precision):
-        c = hps.hps_batch_create(P, 0, stream)
+    def batch_ctx(precision, graphs=1):
+        c = tuned(hps.hps_batch_create(P, 0, stream))
         for p, (xyz, tri) in enumerate(bw["meshes"]):
             hps.hps_batch_set_mesh(c, p, xyz, tri)
-        prm.precision, prm.refine_passes = precision, (1 if precision else 0)
+        prm.precision, prm.refine_passes, prm.graphs = precision, (1 if precision else 0), graphs
         for p, a in enumerate(parts):
             hps.hps_batch_set_hmatrix(c, p, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
                                       a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
-        prm.precision, prm.refine_passes = 0, 0
+        prm.precision, prm.refine_passes, prm.graphs = 0, 0, 1
         return c
 
     def timed(c, Xp, steps):
@@ -341,9 +345,9 @@ def batch_leg(args):
 
     K = args.leg_steps
 
-    def run_batch(c, precision):
+    def run_batch(c, precision, warm=1):
         Xb = torch.zeros(R * NT, dtype=torch.complex128, device="cuda")
-        timed(c, Xb, 1)
+        timed(c, Xb, warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         su, so, rcs, ratio = timed(c, Xb, K)
@@ -355,6 +359,14 @@ def batch_leg(args):
     st = hps.hps_stats(ctx)
     hps.hps_destroy(ctx)
     print("[bench] batched FP64 done", file=sys.stderr, flush=True)
+    # graphs = 2: the first setup runs eagerly and is recorded, the second
+    # captures it; the timed setups replay that graph (every level recomputed
+    # on the device from the installed values, no host scheduling)
+    ctx = batch_ctx(0, graphs=2)
+    res["g"] = run_batch(ctx, 0, warm=2)
+    res["g"]["replays"] = hps.hps_stats(ctx)["device"].get("setup_replays")
+    hps.hps_destroy(ctx)
+    print("[bench] batched FP64 with setup graph done", file=sys.stderr, flush=True)
     ctx = batch_ctx(2)                       # precision form of the batch, same H-matrices
     res[2] = run_batch(ctx, 2)
     dev = dict(hps.hps_stats(ctx).get("device", {}))
@@ -365,7 +377,7 @@ def batch_leg(args):
     seq_total, seq_setup, seq_solve, worst, worst_db = 0.0, 0.0, 0.0, 0.0, 0.0
     off = 0
     for p, (xyz, tri) in enumerate(bw["meshes"]):
-        c = hps.hps_create(0, stream)
+        c = tuned(hps.hps_create(0, stream))
         hps.hps_set_mesh(c, xyz, tri)
         a = parts[p]
         hps.hps_set_hmatrix(c, prm, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
@@ -406,12 +418,17 @@ def batch_leg(args):
            "unknowns_min_max": [min(Ns), max(Ns)], "hmatrix_build_s": build_s,
            "plain_sequential": {"rhs_per_s_step": P * R * K / seq_total, "setup_s": seq_setup,
                                 "solve_rhs_per_s": P * R / seq_solve}}
-    for form, name in ((0, "batched_fp64"), (2, "batched_mixed_fp16_far")):
+    for form, name in ((0, "batched_fp64"), ("g", "batched_fp64_setup_graph"), (2, "batched_mixed_fp16_far")):
         r = res[form]
         out[name] = {"rhs_per_s_step": P * R * K / r["total"], "setup_s": float(np.median(r["setup"])),
                      "solve_rhs_per_s": P * R / float(np.median(r["solve"])),
                      "speedup_step_vs_plain": (P * R * K / r["total"]) / (P * R * K / seq_total)}
     out["batched_fp64"]["current_rel_err_vs_plain"] = worst
+    g = out["batched_fp64_setup_graph"]
+    g["setup"] = ("graphs = 2: the timed setups replay the first setup's launches from one captured HIP graph "
+                  "(same structure; every level recomputed on the device)")
+    g["setup_replays"] = res["g"]["replays"]
+    g["currents_bitwise_equal_to_eager_batch"] = bool(np.array_equal(res["g"]["X"], res[0]["X"]))
     out["batched_mixed_fp16_far"]["current_rel_err_vs_fp64_terms4"] = res[2].get("err")
     out["batched_mixed_fp16_far"]["rcs_db_err_vs_fp64_terms4"] = worst_db
     out["batched_mixed_fp16_far"]["per_problem"] = res[2].get("per_problem")
@@ -617,27 +634,29 @@ def secondary_leg(args, name):
 def leaf_study(args):
     """Sec. V.A (Fig. 4): accuracy of the two-term series against the direct
     solution of the same discretisation as the leaves grow, with the eq. (45)
-    ratio.  Sphere r = 1 m, icosphere subdivision 4 (7,680 unknowns) at
-    400 MHz (edges about lambda/10).  The direct solution is the library's own
-    with eta = 0 (nothing admissible: Z_F = 0, every leaf pair a near block,
-    so the setup is a block LDL^T of the full MoM matrix and one series term
-    solves exactly).  Leaves by unknown count (octree split while a cell has
-    more than leaf_max) and by electrical size (cells never narrower than
-    leaf_box_min).  Error = max over RHS of ||x - x_dir|| / ||x_dir||, for two
-    terms and for the series run until ||it_t|| / ||it_0|| < 1e-8 (at most 60
-    terms; it only converges where the ratio is below one)."""
+    ratio.  Sphere r = 1 m, icosphere subdivision 5 (30,720 unknowns) at
+    800 MHz (edges about lambda/10, the sphere 5.3 wavelengths across).  The
+    direct solution is the library's own with eta = 0 (nothing admissible:
+    Z_F = 0, every leaf pair a near block, so the setup is a block LDL^T of
+    the full MoM matrix and one series term solves exactly), on cells of at
+    least 0.5 m cut into pivots of at most 128 unknowns.  Leaves by unknown
+    count (octree split while a cell has more than leaf_max) and by
+    electrical size (leaf_max 16, cells never narrower than leaf_box_min).
+    Error = max over RHS of ||x - x_dir|| / ||x_dir||, for two terms and for
+    the series run until ||it_t|| / ||it_0|| < 1e-8 (at most 60 terms; it
+    only converges where the ratio is below one)."""
     import torch
     from paper_2109_04129_amd import hps
     from workloads import icosphere, monostatic_angles
-    freq = 400e6
+    freq = 800e6
     lam = 299792458.0 / freq
-    xyz, tri = icosphere(4, 1.0)
+    xyz, tri = icosphere(5, 1.0)
     khat, pol = monostatic_angles([0.0, 45.0, 90.0, 135.0, 180.0], [0.0, 0.0, 0.0, 0.0, 0.0])
     R = len(khat)
     stream = torch.cuda.current_stream().cuda_stream
 
     def solve(form, leaf, box, eta, terms, tol=0.0):
-        ctx = hps.hps_create(0, stream)
+        ctx = tuned(hps.hps_create(0, stream))
         try:
             hps.hps_set_mesh(ctx, xyz, tri)
             p = hps.hps_params_default(freq_hz=freq, leaf_max=leaf, aca_tol=1e-3, terms=terms, series_tol=tol,
@@ -659,35 +678,53 @@ def leaf_study(args):
         return float(np.max(np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)))
 
     rows = []
-    cases = [("count", lf, 0.0) for lf in (32, 64, 128, 256, 512)] + \
-            [("box", 1024, f * lam) for f in (0.25, 0.5, 0.75, 1.0)]
+    cases = [("count", lf, 0.0) for lf in (16, 32, 64, 128)] + \
+            [("box", 16, f * lam) for f in (0.15, 0.3, 0.6, 1.2)]
     for form, fname in ((0, "EFIE"), (1, "CFIE alpha 0.5")):
-        xd, _, rcs_d, _ = solve(form, 128, 0.0, 0.0, 1)
+        xd, _, rcs_d, _ = solve(form, 128, 0.5, 0.0, 1)
         log("leaf study %s: direct solution done" % fname)
         for kind, leaf, box in cases:
             x2, ratio, rcs2, info = solve(form, leaf, box, 2.0, 2)
             xc, _, _, infoc = solve(form, leaf, box, 2.0, 60, 1e-8)
             rows.append({"formulation": fname, "leaves": kind, "leaf_max": leaf, "leaf_box_min_lambda": box / lam,
-                         "groups": info["groups"], "mean_unknowns_per_group": 7680.0 / max(info["groups"] or 1, 1),
+                         "groups": info["groups"], "far_blocks": info["far_blocks"],
+                         "mean_unknowns_per_group": float(xd.shape[1]) / max(info["groups"] or 1, 1),
                          "ratio_eq45_max": float(np.max(ratio)), "ratio_eq45_median": float(np.median(ratio)),
                          "two_term_err_vs_direct": err(x2, xd),
                          "two_term_rcs_db_err_max": float(np.max(np.abs(10 * np.log10(rcs2 / rcs_d)))),
                          "series_1e-8_err_vs_direct": err(xc, xd), "series_terms_used": infoc["terms_used"]})
             log("leaf study %s %s %s done" % (fname, kind, leaf if kind == "count" else box / lam))
-    return {"study": "leaf size (Sec. V.A, Fig. 4 metric)", "workload": "sphere r=1 m, icosphere subdiv 4, "
-            "7,680 unknowns, 400 MHz (lambda %.4f m), ACA 1e-3, 5 monostatic RHS theta = 0..180 step 45" % lam,
-            "direct": "library, eta = 0 (no far blocks: block LDL^T of the full MoM matrix, one term)",
+    return {"study": "leaf size (Sec. V.A, Fig. 4 metric)", "workload": "sphere r=1 m, icosphere subdiv 5, "
+            "30,720 unknowns, 800 MHz (lambda %.4f m), ACA 1e-3, 5 monostatic RHS theta = 0..180 step 45" % lam,
+            "direct": "library, eta = 0 on cells of at least 0.5 m cut into pivots of at most 128 unknowns "
+                      "(no far blocks: block LDL^T of the full MoM matrix, one term)",
             "rows": rows}
 
 
+TUNING_PATH = None
+
+
+def tuned(ctx):
+    """A new context with the --tuning table in place of the library's own."""
+    if TUNING_PATH:
+        from paper_2109_04129_amd import hps
+        hps.hps_set_tuning(ctx, TUNING_PATH)
+    return ctx
+
+
 def main():
+    global TUNING_PATH
     args = parse()
+    TUNING_PATH = args.tuning
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.leaf_study:
         print(json.dumps(leaf_study(args)), flush=True)
+        return
+    if args.only_batch:
+        print(json.dumps(batch_leg(args)), flush=True)
         return
     if args.only_single_rhs:
         from workloads import workload

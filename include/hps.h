@@ -79,8 +79,17 @@ typedef struct {
                               the scaled unknowns, does. */
   int32_t graphs;          /* 1 (default): the device part of a solve is captured once
                               per RHS count into a HIP graph and replayed; 0: every
-                              kernel is launched from the host on each call.  Same
-                              results either way.  Solves run eagerly while
+                              kernel is launched from the host on each call.  2: as 1,
+                              and the setup too: an hps_setup whose elimination plan,
+                              H-matrix structure (groups, near and far block lists,
+                              ranks), device buffers, form and tile shape equal those
+                              of the last eager setup replays that setup's launches on
+                              the values now installed (same structure, new values:
+                              hps_set_hmatrix with arrays of the same sizes), from a
+                              graph captured at the first replay; the solve schedules
+                              and captured solves are kept.  Anything else runs the
+                              setup eagerly and records it again.  Same results in
+                              every mode.  Setups and solves run eagerly while
                               hps_profile is on. */
   int32_t verbose;         /* 1: the host H-matrix build reports its progress on
                               stderr; 0 (default): silent */
@@ -314,7 +323,11 @@ hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
    size (unknowns per group) and whose precision (0, 1, 2 as in hps_params;
    the setup counts as 0) matches; shape 0 when none does.  NULL or "" restores
    the built-in table (shape 0 everywhere).  Every shape gives bitwise the
-   same results.  hps_create loads tuning/gfx950.json from the library's
+   same results.  An optional top-level "sweep_pull_kmax": K (integer >= 0,
+   default 0) makes every sweep target whose summed contraction is at most K
+   take all its terms in one tile set (pull) instead of one per source level
+   (push); the sums then run in another order (results equal to rounding);
+   it applies from the next hps_setup.  hps_create loads tuning/gfx950.json from the library's
    directory when that file exists (a malformed one fails hps_create with
    HPS_EINVAL).  Takes effect at the next hps_setup / solve.  Errors:
    HPS_EIO (file), HPS_EINVAL (content), HPS_EDEVICE (host-only context). */

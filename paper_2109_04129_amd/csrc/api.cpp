@@ -74,7 +74,7 @@ hps_status check_params(hps_ctx *c, const hps_params *p) {
   if (p->refine_passes < 0) return fail(c, HPS_EINVAL, "refine_passes must be >= 0");
   if (p->precision < 0 || p->precision > 2) return fail(c, HPS_EINVAL, "precision must be 0, 1 or 2");
   if (p->ordering != 0 && p->ordering != 1) return fail(c, HPS_EINVAL, "ordering must be 0 or 1");
-  if (p->graphs != 0 && p->graphs != 1) return fail(c, HPS_EINVAL, "graphs must be 0 or 1");
+  if (p->graphs < 0 || p->graphs > 2) return fail(c, HPS_EINVAL, "graphs must be 0, 1 or 2");
   if (!(p->leaf_box_min >= 0.0) || !std::isfinite(p->leaf_box_min))
     return fail(c, HPS_EINVAL, "leaf_box_min must be >= 0");
   if (!(p->series_tol >= 0.0) || !std::isfinite(p->series_tol))
@@ -733,7 +733,7 @@ hps_status hps_set_tuning(hps_ctx *c, const char *path) {
   if (!c) return HPS_EINVAL;
   return guarded(c, [&]() {
     // the file is read and checked first, so a bad table is reported as such
-    std::vector<hps::TuneEntry> t;
+    hps::TuneTable t;
     if (path && *path) t = hps::read_tuning(path);
     if (!c->dev) return fail(c, HPS_EDEVICE, "host-only context");
     c->dev->set_tuning(t, (path && *path) ? std::string(path) : std::string("built-in (all 32 x 32)"));

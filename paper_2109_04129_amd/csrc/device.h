@@ -65,8 +65,16 @@ struct TuneEntry {
   int precision = -1;     // solve arithmetic the entry applies to (0 FP64, 1-2 FP32); -1 any
 };
 
+// A tuning table: tile shapes per launch class, and the sweeps' pull
+// threshold (the longest contraction a sweep target takes in one tile set;
+// -1: the built-in value).
+struct TuneTable {
+  std::vector<TuneEntry> entries;
+  int64_t sweep_pull_kmax = -1;
+};
+
 // Reads a tuning table (JSON, see tune.cpp); throws Error.
-std::vector<TuneEntry> read_tuning(const std::string &path);
+TuneTable read_tuning(const std::string &path);
 
 struct StageTimes {
   double setup_ms = 0, inverse_ms = 0, coef_ms = 0, schur_ms = 0, symbolic_ms = 0;
@@ -103,8 +111,8 @@ class DeviceState {
                   const FarEmit &emit);
   void set_profiling(bool on);
   // tile-shape table (applies from the next hps_setup / solve) and where it came from
-  void set_tuning(const std::vector<TuneEntry> &t, const std::string &src);
-  std::vector<TuneEntry> tune;
+  void set_tuning(const TuneTable &t, const std::string &src);
+  TuneTable tune;
   std::string tune_src = "built-in (all 32 x 32)";
 
   int device;

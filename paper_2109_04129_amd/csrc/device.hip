@@ -976,6 +976,12 @@ __global__ void k_fill(c2 *p, int64_t n) {
   if (i < n) p[i] = make_double2(0.0, 0.0);
 }
 
+// Sets one flag word from a kernel rather than a memset, so that the work
+// around it can be captured into a graph.
+__global__ void k_set_i32(int *p, int v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
 // Scatter the near blocks (row-major m x n, tree order) into the panels.
 struct Scatter {
   int64_t src, dst;
@@ -2080,6 +2086,152 @@ struct DeviceState::Impl {
       (void)hipStreamDestroy(s2);
     }
   }
+  // One elimination level of the setup as launches over device arrays: the
+  // inverses of its pivots by size class, the right coefficients, and the
+  // Schur updates into rows of the next level (main stream) and of the
+  // levels after it (second stream).
+  struct LevelLaunch {
+    struct Inv { int nc; int64_t count; const int64_t *off; const int32_t *n, *id; double flops; };
+    std::vector<Inv> inv;
+    const Term *terms = nullptr;
+    const Tile *coef = nullptr, *schur = nullptr, *schur2 = nullptr;
+    int64_t n_coef = 0, n_schur = 0, n_schur2 = 0;
+    int sub = 1, sub2 = 1;
+    double f_coef = 0.0, b_coef = 0.0, f_schur = 0.0, b_schur = 0.0, f_schur2 = 0.0, b_schur2 = 0.0;
+  };
+  // Orders between the streams: S2(l) after COEF(l); INV(l) after S2(l - 2)
+  // (the last update of its rows from the second stream); S1(l) after
+  // S2(l - 1) (both write rows of level l + 1).
+  void launch_level(const LevelLaunch &v, int l, c2 *Wd, int shape) {
+    if (l >= 2) HIP_CHECK(hipStreamWaitEvent(s, lev_ev[2 * (l - 2) + 1], 0));
+    for (const LevelLaunch::Inv &li : v.inv) {
+      const unsigned nb = (unsigned)li.count;
+      const int64_t pr = prof_begin(3, li.flops, 0.0, li.count);
+      if (li.nc == 32)
+        hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, F.p, li.off, li.n, li.id, status.p);
+      else if (li.nc == 64)
+        hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(512), 0, s, Wd, F.p, li.off, li.n, li.id, status.p);
+      else
+        hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(1024), 0, s, Wd, F.p, li.off, li.n, li.id, status.p);
+      HIP_CHECK(hipGetLastError());
+      prof_end(pr);
+    }
+    launch_tiles(v.coef, v.terms, v.n_coef, 0, F.p, Wd, F.p, 1, v.f_coef, v.b_coef);
+    HIP_CHECK(hipEventRecord(lev_ev[2 * l], s));
+    if (l >= 1) HIP_CHECK(hipStreamWaitEvent(s, lev_ev[2 * (l - 1) + 1], 0));
+    launch_tiles(v.schur, v.terms, v.n_schur, 1, Wd, F.p, Wd, std::min(v.sub, SUB_Y), v.f_schur, v.b_schur, false, 0,
+                 shape, TC_SCHUR);
+    HIP_CHECK(hipStreamWaitEvent(s2, lev_ev[2 * l], 0));
+    const hipStream_t main_s = s;
+    s = s2;                          // launch_tiles and its timing events use s
+    try {
+      launch_tiles(v.schur2, v.terms, v.n_schur2, 1, Wd, F.p, Wd, std::min(v.sub2, SUB_Y), v.f_schur2, v.b_schur2,
+                   false, 0, shape, TC_SCHUR);
+    } catch (...) {
+      s = main_s;
+      throw;
+    }
+    s = main_s;
+    HIP_CHECK(hipEventRecord(lev_ev[2 * l + 1], s2));
+  }
+  // The setup's device work before the levels: panels cleared, near blocks
+  // scattered into them, the singular-block flag cleared.
+  DevArray<Scatter> dsc;           // scatter descriptors of the last setup
+  int64_t n_scatter = 0;
+  void setup_front(c2 *Wd, int64_t PEt) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, Wd, PEt);
+    HIP_CHECK(hipGetLastError());
+    if (n_scatter > 0) {
+      hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_scatter), dim3(256), 0, s, near.p, Wd, dsc.p);
+      HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, status.p, 0);
+    HIP_CHECK(hipGetLastError());
+  }
+  // Precision form, after the levels: FP32 copies of the factor panels, near
+  // blocks and far factors, and the 16-bit far factors with one FP32 scale
+  // per factor and block (buffers allocated by the caller).
+  DevArray<FarPart> dparts;        // far-factor parts of the last setup
+  int64_t n_parts = 0;
+  void precision_convert(int64_t PEt) {
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, F.p, F32.p, PEt);
+    HIP_CHECK(hipGetLastError());
+    const int64_t nn = std::max<int64_t>((int64_t)near.n, 1);
+    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, s, near.p, near32.p, (int64_t)near.n);
+    HIP_CHECK(hipGetLastError());
+    if (faruv.n) {
+      hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv((int64_t)faruv.n, 256)), dim3(256), 0, s, faruv.p, farf32.p,
+                         (int64_t)faruv.n);
+      HIP_CHECK(hipGetLastError());
+    }
+    if (n_parts > 0) {
+      if (precision == 1)
+        hipLaunchKernelGGL(k_far16<1>, dim3((unsigned)n_parts), dim3(256), 0, s, faruv.p, far16.p, fscale.p, dparts.p);
+      else
+        hipLaunchKernelGGL(k_far16<2>, dim3((unsigned)n_parts), dim3(256), 0, s, faruv.p, far16.p, fscale.p, dparts.p);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+  // Setup replay (graphs == 2): the launches of the last eager setup, over
+  // device arrays that stay allocated, with what they were built from.  A
+  // later setup with the same plan, H-matrix structure, buffers, form and
+  // tile shape runs the same launches on the values now in the buffers, from
+  // one graph captured at its first replay.
+  bool setup_graphs = false;
+  struct SetupRec {
+    bool valid = false;
+    std::vector<LevelLaunch> levels;
+    Plan plan;
+    HMatrix hs;                      // structure only
+    std::vector<int64_t> soff;
+    const void *near_p = nullptr, *faruv_p = nullptr;
+    size_t near_n = 0, faruv_n = 0;
+    int64_t PEt = 0;
+    int precision = 0, shape = 0;
+    int64_t kpull = 0;
+    bool nonsym = false;
+    double flops = 0.0;
+    int64_t replays = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    void reset() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      x = nullptr;
+      g = nullptr;
+      valid = false;
+      levels.clear();
+      plan = Plan();
+      hs = HMatrix();
+      soff.clear();
+    }
+    ~SetupRec() { reset(); }
+  } srec;
+  bool setup_replayable(const Plan &P, int shape) const {
+    const Plan &a = srec.plan;
+    const HMatrix &h = srec.hs;
+    return setup_graphs && !prof && srec.valid && srec.precision == precision && srec.shape == shape &&
+           srec.kpull == sweep_pull_kmax &&
+           srec.nonsym == nonsym && srec.near_p == (const void *)near.p && srec.near_n == near.n &&
+           srec.faruv_p == (const void *)faruv.p && srec.faruv_n == faruv.n && srec.soff == soff &&
+           h.N == hcopy.N && h.M == hcopy.M && h.nonsym == hcopy.nonsym && h.perm == hcopy.perm &&
+           h.gptr == hcopy.gptr && h.near_ts == hcopy.near_ts && h.near_off == hcopy.near_off &&
+           h.far_rng == hcopy.far_rng && h.far_rank == hcopy.far_rank && h.far_off == hcopy.far_off &&
+           a.M == P.M && a.N == P.N && a.order == P.order && a.pos == P.pos && a.size == P.size && a.uoff == P.uoff &&
+           a.later_ptr == P.later_ptr && a.later == P.later && a.col_off == P.col_off && a.width == P.width &&
+           a.panel_off == P.panel_off && a.panel_elems == P.panel_elems && a.level == P.level &&
+           a.n_levels == P.n_levels && a.level_ptr == P.level_ptr && a.level_piv == P.level_piv &&
+           a.n_upper_blocks == P.n_upper_blocks;
+  }
+  // The whole device part of a setup whose level launches are recorded.
+  void setup_device_work() {
+    c2 *Wd = Wk.p;
+    setup_front(Wd, srec.PEt);
+    const int L = (int)srec.levels.size();
+    for (int l = 0; l < L; ++l) launch_level(srec.levels[l], l, Wd, srec.shape);
+    if (L > 0) HIP_CHECK(hipStreamWaitEvent(s, lev_ev[2 * (L - 1) + 1], 0));   // join the second stream
+    if (precision > 0) precision_convert(srec.PEt);
+  }
   Pool spool;                      // solve schedules (independent of R)
   int64_t built_R = -1;
   std::vector<Built> b_fwd, b_bwd;
@@ -2208,6 +2360,7 @@ struct DeviceState::Impl {
   // entry of the class whose rhs_max and group_max bound R and the mean
   // pivot size; shape 0 (32 x 32) when none does.
   std::vector<TuneEntry> tune;
+  int64_t sweep_pull_kmax = 0;     // sweep targets with a contraction up to this take one tile set (pull)
   int shape_of[TC_COUNT] = {0, 0, 0, 0, 0, 0};
   int pick_shape(int cls, int64_t R) const {
     const double g = P.M > 0 ? (double)N / (double)P.M : 0.0;
@@ -2576,6 +2729,7 @@ void DeviceState::upload(const Mesh &mesh, const HMatrix &H, const hps_params &p
   I.ratio_warn = p.ratio_warn;
   I.mem_cap = p.device_mem_cap;
   I.use_graphs = p.graphs != 0;
+  I.setup_graphs = p.graphs == 2;
   graphs = p.graphs;
   I.drop_graphs();
   const uint64_t need = (H.near_vals.size() + H.far_uv.size()) * sizeof(c2) + (uint64_t)H.N * 14 * kQD * 8;
@@ -2682,16 +2836,60 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   Impl &I = *impl;
   HIP_CHECK(hipSetDevice(device));
   hipStream_t s = I.s;
-  I.drop_graphs();
   I.P = P;
-  I.ready = false;
-  I.built_R = -1;
-  I.tune = tune;
+  I.tune = tune.entries;
+  I.sweep_pull_kmax = tune.sweep_pull_kmax >= 0 ? tune.sweep_pull_kmax : 0;
   // the Schur updates' tile shape (explicit tiles: the one-column vector
   // kernel does not apply, the width is the shape's)
   const int schur_shape = I.pick_shape(TC_SCHUR, 0) == 6 ? 0 : I.pick_shape(TC_SCHUR, 0);
   const int64_t schur_tn = shape_tn(schur_shape);
   I.shape_of[TC_SCHUR] = schur_shape;
+  if (I.setup_replayable(P, schur_shape)) {
+    // same structure as the recorded setup: its launches on the current
+    // values, from the graph (captured here the first time); the solve
+    // schedules and captured solves stay valid
+    I.ready = false;
+    const auto th0 = std::chrono::steady_clock::now();
+    if (!I.srec.x) {
+      HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        I.setup_device_work();
+      } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(s, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+      }
+      HIP_CHECK(hipStreamEndCapture(s, &I.srec.g));
+      HIP_CHECK(hipGraphInstantiate(&I.srec.x, I.srec.g, nullptr, nullptr, 0));
+    }
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventRecord(e0, s));
+    HIP_CHECK(hipGraphLaunch(I.srec.x, s));
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    HIP_CHECK(hipEventDestroy(e0));
+    HIP_CHECK(hipEventDestroy(e1));
+    times.schur_ms = ms;
+    times.inverse_ms = 0.0;
+    sched_split[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+    for (int q = 1; q < 5; ++q) sched_split[q] = 0.0;
+    int st = 0;
+    HIP_CHECK(hipMemcpy(&st, I.status.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (st > 0) throw Error{HPS_ESINGULAR, "singular scaled diagonal block of group " + std::to_string(P.order[st - 1])};
+    I.P.setup_flops = I.srec.flops;
+    I.srec.replays += 1;
+    I.ready = true;
+    return;
+  }
+  I.srec.reset();
+  I.drop_graphs();
+  I.ready = false;
+  I.built_R = -1;
   const int64_t N = I.N, M = I.M;
   // working and factor panels; a non-symmetric near field (CFIE) also keeps
   // the lower blocks, stored transposed in a second copy of the panel layout
@@ -2716,14 +2914,39 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         sc.t_ptr.push_back((int32_t)sc.terms.size());
       };
       auto close = [](Impl::Sched &sc) { sc.t_ptr.push_back((int32_t)sc.terms.size()); };
-      // Right-looking (push) sweeps: the launch of level l applies the blocks of
-      // the pivots at level l to every group they couple to, one term per pivot,
-      // so a launch has many short tiles instead of a few long ones.
-      //   forward (eq. 25), levels ascending:   b_f -= C_ef^T b_e, e at level l, f in N+(e);
-      //   back (eq. 26), levels descending:     x_e -= C_ef x_f,  f at level l, f in N+(e).
+      // Sweeps (eqs. 25-26), one launch per level.  A group whose whole
+      // contraction in a sweep (the summed sizes of the groups it receives
+      // terms from) is at most sweep_pull_kmax takes all its terms in one tile
+      // set, in the launch before its own level is needed (pull: its rows are
+      // read and written once); the others take one tile set per source level
+      // (push: many short tiles).  Sources of a launch are final at its start
+      // and no group of a launch is both a source and a target.
+      //   forward, levels ascending, launch l: b_f -= C_ef^T b_e for e at level l
+      //     and push targets f in N+(e); and for pull targets f at level l + 1,
+      //     every e with f in N+(e), e ascending;
+      //   back, levels descending, launch l: x_e -= C_ef x_f for f at level l
+      //     and push targets e with f in N+(e); and for pull targets e at level
+      //     l - 1, every f in N+(e), f ascending.
       std::vector<std::vector<std::pair<int32_t, int64_t>>> contrib(M);
       for (int64_t e = 0; e < M; ++e)
         for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) contrib[P.later[a]].push_back({(int32_t)e, P.col_off[a]});
+      const int64_t kpull = I.sweep_pull_kmax;
+      std::vector<char> pull_f(M, 0), pull_b(M, 0);
+      for (int64_t g = 0; g < M; ++g) {
+        int64_t kf = 0;
+        for (const auto &ce : contrib[g]) kf += P.size[ce.first];
+        pull_f[g] = kf > 0 && kf <= kpull;
+        const int64_t kb = P.width[g] - P.size[g];
+        pull_b[g] = kb > 0 && kb <= kpull;
+      }
+      auto fwd_term = [&](int32_t e, int64_t coff) {
+        return Term{(I.nonsym ? PE : 0) + P.panel_off[e] + coff * P.size[e], P.uoff[e], (int32_t)P.size[e],
+                    (int32_t)N, (int32_t)P.size[e], 1};
+      };
+      auto bwd_term = [&](int32_t e, int64_t coff, int32_t f) {
+        return Term{P.panel_off[e] + coff * P.size[e], P.uoff[f], (int32_t)P.size[e], (int32_t)N,
+                    (int32_t)P.size[f], 0};
+      };
       I.fwd.assign(L, Impl::Sched());
       I.bwd.assign(L, Impl::Sched());
       std::vector<int32_t> slot(M, -1), tgt;
@@ -2747,18 +2970,26 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
           const int32_t e = P.level_piv[i];
           for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a)
-            put(P.later[a], Term{(I.nonsym ? PE : 0) + P.panel_off[e] + P.col_off[a] * P.size[e], P.uoff[e],
-                                 (int32_t)P.size[e], (int32_t)N, (int32_t)P.size[e], 1});
+            if (!pull_f[P.later[a]]) put(P.later[a], fwd_term(e, P.col_off[a]));
         }
+        if (l + 1 < L)
+          for (int64_t i = P.level_ptr[l + 1]; i < P.level_ptr[l + 2]; ++i) {
+            const int32_t f = P.level_piv[i];
+            if (pull_f[f])
+              for (const auto &ce : contrib[f]) put(f, fwd_term(ce.first, ce.second));
+          }
         flush(I.fwd[l]);
         for (int64_t i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
           const int32_t f = P.level_piv[i];
-          for (auto &ce : contrib[f]) {
-            const int32_t e = ce.first;
-            put(e, Term{P.panel_off[e] + ce.second * P.size[e], P.uoff[f], (int32_t)P.size[e], (int32_t)N,
-                        (int32_t)P.size[f], 0});
-          }
+          for (const auto &ce : contrib[f])
+            if (!pull_b[ce.first]) put(ce.first, bwd_term(ce.first, ce.second, f));
         }
+        if (l >= 1)
+          for (int64_t i = P.level_ptr[l - 1]; i < P.level_ptr[l]; ++i) {
+            const int32_t e = P.level_piv[i];
+            if (pull_b[e])
+              for (int64_t a = P.later_ptr[e]; a < P.later_ptr[e + 1]; ++a) put(e, bwd_term(e, P.col_off[a], P.later[a]));
+          }
         flush(I.bwd[l]);
       }
       I.dinv = Impl::Sched();
@@ -3116,8 +3347,6 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   I.Wk.alloc(PEt);
   I.F.alloc(PEt);
   c2 *Wd = I.Wk.p;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, Wd, PEt);
-  HIP_CHECK(hipGetLastError());
   std::vector<Scatter> sc(H.n_near());
   for (int64_t b = 0; b < H.n_near(); ++b) {
     const int32_t t = H.near_ts[2 * b], u = H.near_ts[2 * b + 1];
@@ -3140,12 +3369,9 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       throw Error{HPS_EINVAL, "internal descriptor out of range (scatter)"};
     sc[b] = d;
   }
-  DevArray<Scatter> dsc;
-  dsc.upload(sc, s);
-  if (!sc.empty()) {
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)sc.size()), dim3(256), 0, s, I.near.p, Wd, dsc.p);
-    HIP_CHECK(hipGetLastError());
-  }
+  I.dsc.upload(sc, s);
+  I.n_scatter = (int64_t)sc.size();
+  I.setup_front(Wd, PEt);
 
   std::vector<int> cut{0};
   for (int w = 1; cut.back() < L; w *= 2) cut.push_back(std::min(L, cut.back() + w));
@@ -3154,7 +3380,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   double flops = 0.0, wait_ms = 0.0, stage_ms = 0.0;
   int64_t n_tiles_all = 0, n_terms_all = 0;
   const int ncls[3] = {32, 64, 128};
-  HIP_CHECK(hipMemsetAsync(I.status.p, 0, sizeof(int), s));
+  const bool record = I.setup_graphs && !I.prof;
+  if (record) I.srec.levels.resize(L);
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
@@ -3229,48 +3456,30 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     if (c == 0) HIP_CHECK(hipEventRecord(e0, s));
     size_t q = 0;
     for (int l = lo; l < hi; ++l) {
-      // The Schur updates of level l into rows of level l + 1 (S1) run on the
-      // main stream; the rest (S2, rows of levels >= l + 2) on the second
-      // stream, overlapping the inverses and coefficients of the next level.
-      // Orders: S2(l) after COEF(l); INV(l) after S2(l - 2) (the last update
-      // of its rows from the second stream); S1(l) after S2(l - 1) (both write
-      // rows of level l + 1).
-      if (l >= 2) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (l - 2) + 1], 0));
+      Impl::LevelLaunch v;
       for (; q < invl.size() && invl[q].level == l; ++q) {
         const InvLaunch &li = invl[q];
-        const unsigned nb = (unsigned)li.count;
-        const int64_t *po = ch.d_inv_off.p + li.start;
-        const int32_t *pn = ch.d_inv_n.p + li.start, *pi = ch.d_inv_id.p + li.start;
-        const int64_t pr = I.prof_begin(3, li.flops, 0.0, li.count);
-        if (li.nc == 32)
-          hipLaunchKernelGGL(k_inverse<32>, dim3(nb), dim3(256), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-        else if (li.nc == 64)
-          hipLaunchKernelGGL(k_inverse<64>, dim3(nb), dim3(512), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-        else
-          hipLaunchKernelGGL(k_inverse<128>, dim3(nb), dim3(1024), 0, s, Wd, I.F.p, po, pn, pi, I.status.p);
-        HIP_CHECK(hipGetLastError());
-        I.prof_end(pr);
+        v.inv.push_back(Impl::LevelLaunch::Inv{li.nc, li.count, ch.d_inv_off.p + li.start, ch.d_inv_n.p + li.start,
+                                               ch.d_inv_id.p + li.start, li.flops});
       }
       const GemmLaunch &cl = coefl[l - lo], &sl = schurl[l - lo], &sl2 = schur2l[l - lo];
-      I.launch_tiles(ch.d_tiles.p + cl.t0, ch.d_terms.p, cl.n, 0, I.F.p, Wd, I.F.p, 1, cl.flops, cl.bytes);
-      HIP_CHECK(hipEventRecord(I.lev_ev[2 * l], s));
-      if (l >= 1) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (l - 1) + 1], 0));
-      I.launch_tiles(ch.d_tiles.p + sl.t0, ch.d_terms.p, sl.n, 1, Wd, I.F.p, Wd, std::min(sl.sub, SUB_Y), sl.flops,
-                     sl.bytes, false, 0, schur_shape, TC_SCHUR);
-      HIP_CHECK(hipStreamWaitEvent(I.s2, I.lev_ev[2 * l], 0));
-      {
-        const hipStream_t main_s = I.s;
-        I.s = I.s2;                      // launch_tiles and its timing events use I.s
-        try {
-          I.launch_tiles(ch.d_tiles.p + sl2.t0, ch.d_terms.p, sl2.n, 1, Wd, I.F.p, Wd, std::min(sl2.sub, SUB_Y),
-                         sl2.flops, sl2.bytes, false, 0, schur_shape, TC_SCHUR);
-        } catch (...) {
-          I.s = main_s;
-          throw;
-        }
-        I.s = main_s;
-      }
-      HIP_CHECK(hipEventRecord(I.lev_ev[2 * l + 1], I.s2));
+      v.terms = ch.d_terms.p;
+      v.coef = ch.d_tiles.p + cl.t0;
+      v.n_coef = cl.n;
+      v.f_coef = cl.flops;
+      v.b_coef = cl.bytes;
+      v.schur = ch.d_tiles.p + sl.t0;
+      v.n_schur = sl.n;
+      v.sub = sl.sub;
+      v.f_schur = sl.flops;
+      v.b_schur = sl.bytes;
+      v.schur2 = ch.d_tiles.p + sl2.t0;
+      v.n_schur2 = sl2.n;
+      v.sub2 = sl2.sub;
+      v.f_schur2 = sl2.flops;
+      v.b_schur2 = sl2.bytes;
+      I.launch_level(v, l, Wd, schur_shape);
+      if (record) I.srec.levels[l] = std::move(v);
     }
   }
   if (L > 0) HIP_CHECK(hipStreamWaitEvent(s, I.lev_ev[2 * (L - 1) + 1], 0));   // join the second stream
@@ -3301,12 +3510,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // far factors to 16-bit pairs with one FP32 scale per factor per block
   if (I.precision > 0) {
     I.F32.alloc(PEt);
-    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(PEt, 256)), dim3(256), 0, s, I.F.p, I.F32.p, PEt);
-    HIP_CHECK(hipGetLastError());
-    const int64_t nn = std::max<int64_t>((int64_t)I.near.n, 1);
-    I.near32.alloc(nn);
-    hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, s, I.near.p, I.near32.p, (int64_t)I.near.n);
-    HIP_CHECK(hipGetLastError());
+    I.near32.alloc(std::max<int64_t>((int64_t)I.near.n, 1));
     const HMatrix &Hf = I.hcopy;
     std::vector<FarPart> parts(2 * Hf.n_far());
     for (int64_t b = 0; b < Hf.n_far(); ++b) {
@@ -3318,25 +3522,32 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         throw Error{HPS_EINVAL, "internal descriptor out of range (far16)"};
     }
     I.farf32.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
-    if (I.faruv.n) {
-      hipLaunchKernelGGL(k_to32, dim3((unsigned)cdiv((int64_t)I.faruv.n, 256)), dim3(256), 0, s, I.faruv.p, I.farf32.p,
-                         (int64_t)I.faruv.n);
-      HIP_CHECK(hipGetLastError());
-    }
     I.far16.alloc(std::max<int64_t>((int64_t)I.faruv.n, 1));
     I.fscale.alloc(std::max<size_t>(parts.size(), 1));
-    if (!parts.empty()) {
-      DevArray<FarPart> dparts;
-      dparts.upload(parts, s);
-      if (I.precision == 1)
-        hipLaunchKernelGGL(k_far16<1>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
-      else
-        hipLaunchKernelGGL(k_far16<2>, dim3((unsigned)parts.size()), dim3(256), 0, s, I.faruv.p, I.far16.p, I.fscale.p, dparts.p);
-      HIP_CHECK(hipGetLastError());
-      HIP_CHECK(hipStreamSynchronize(s));
-    }
+    I.dparts.upload(parts, s);
+    I.n_parts = (int64_t)parts.size();
+    I.precision_convert(PEt);
+    HIP_CHECK(hipStreamSynchronize(s));
   }
-
+  if (record) {                  // what a later setup of the same structure replays
+    Impl::SetupRec &r = I.srec;
+    r.plan = P;
+    r.hs.N = I.hcopy.N; r.hs.M = I.hcopy.M; r.hs.nonsym = I.hcopy.nonsym; r.hs.perm = I.hcopy.perm;
+    r.hs.gptr = I.hcopy.gptr; r.hs.near_ts = I.hcopy.near_ts; r.hs.near_off = I.hcopy.near_off;
+    r.hs.far_rng = I.hcopy.far_rng; r.hs.far_rank = I.hcopy.far_rank; r.hs.far_off = I.hcopy.far_off;
+    r.soff = I.soff;
+    r.near_p = I.near.p;
+    r.near_n = I.near.n;
+    r.faruv_p = I.faruv.p;
+    r.faruv_n = I.faruv.n;
+    r.PEt = PEt;
+    r.precision = I.precision;
+    r.shape = schur_shape;
+    r.kpull = I.sweep_pull_kmax;
+    r.nonsym = I.nonsym;
+    r.flops = flops;
+    r.valid = true;
+  }
   I.upload_solve_pool();
   I.ready = true;
 }
@@ -3761,12 +3972,12 @@ void DeviceState::far_sample(const Mesh &m, double freq_hz, int cfie, double alp
   }
 }
 
-void DeviceState::set_tuning(const std::vector<TuneEntry> &t, const std::string &src) {
+void DeviceState::set_tuning(const TuneTable &t, const std::string &src) {
   Impl &I = *impl;
   HIP_CHECK(hipStreamSynchronize(I.s));
   tune = t;
   tune_src = src;
-  I.tune = t;
+  I.tune = t.entries;             // the sweep pull threshold applies from the next setup
   if (I.ready) {                 // re-resolve the solve shapes at the next solve (captured graphs dropped)
     I.drop_graphs();
     I.built_R = -1;
@@ -3796,11 +4007,13 @@ std::string DeviceState::stats_json() const {
   o << ", \"near_elems\": " << I.near.n << ", \"far_elems\": " << I.faruv.n;
   {
     const char *cn[TC_COUNT] = {"sweep", "dinv", "far1", "far2", "near", "schur"};
-    o << ", \"tuning\": {\"source\": \"" << tune_src << "\", \"entries\": " << tune.size() << ", \"shapes\": {";
+    o << ", \"tuning\": {\"source\": \"" << tune_src << "\", \"entries\": " << tune.entries.size()
+      << ", \"sweep_pull_kmax\": " << I.sweep_pull_kmax << ", \"shapes\": {";
     for (int c = 0; c < TC_COUNT; ++c) o << (c ? ", " : "") << "\"" << cn[c] << "\": " << I.shape_of[c];
     o << "}}";
   }
   o << ", \"terms\": " << I.terms << ", \"series_tol\": " << I.series_tol << ", \"terms_used\": " << I.terms_used;
+  o << ", \"setup_replays\": " << I.srec.replays << ", \"setup_recorded\": " << (I.srec.valid ? "true" : "false");
   o << ", \"schedule_split\": {\"levels_built_ms\": " << sched_split[0] << ", \"wait_ms\": " << sched_split[1]
     << ", \"stage_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
   o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms

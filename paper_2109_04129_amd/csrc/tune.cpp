@@ -1,10 +1,11 @@
 // Tile-shape tuning table: reads the JSON file the autotuner writes.
 //
-//   {"arch": "gfx950",
+//   {"arch": "gfx950", "sweep_pull_kmax": 4096,
 //    "entries": [{"class": "sweep", "rhs_max": 256, "group_max": 64, "precision": 0, "shape": 3}, ...]}
 //
 // Entries are matched in file order (first match wins); "rhs_max",
 // "group_max" and "precision" may be omitted (no bound / any precision).
+// "sweep_pull_kmax" (optional, integer >= 0) sets the sweeps' pull threshold.
 // Other keys are ignored.  A small recursive-descent reader of the JSON subset the file uses (objects,
 // arrays, strings without unicode escapes, numbers, true / false / null).
 #include <cerrno>
@@ -148,7 +149,7 @@ int class_id(const std::string &c) {
 
 }  // namespace
 
-std::vector<TuneEntry> read_tuning(const std::string &path) {
+TuneTable read_tuning(const std::string &path) {
   std::ifstream f(path, std::ios::binary);
   if (!f) throw Error{HPS_EIO, "cannot open tuning file " + path};
   std::stringstream buf;
@@ -162,7 +163,14 @@ std::vector<TuneEntry> read_tuning(const std::string &path) {
   if (root.kind != JVal::OBJ) throw Error{HPS_EINVAL, "tuning file: top level is not an object"};
   const JVal *ent = root.get("entries");
   if (!ent || ent->kind != JVal::ARR) throw Error{HPS_EINVAL, "tuning file: no \"entries\" array"};
-  std::vector<TuneEntry> out;
+  TuneTable table;
+  const JVal *pk = root.get("sweep_pull_kmax");
+  if (pk && pk->kind != JVal::NUL) {
+    if (pk->kind != JVal::NUM || pk->num != std::floor(pk->num) || pk->num < 0 || pk->num > 1.0e15)
+      throw Error{HPS_EINVAL, "tuning file: \"sweep_pull_kmax\" must be an integer >= 0"};
+    table.sweep_pull_kmax = (int64_t)pk->num;
+  }
+  std::vector<TuneEntry> &out = table.entries;
   for (const JVal &e : ent->arr) {
     if (e.kind != JVal::OBJ) throw Error{HPS_EINVAL, "tuning file: an entry is not an object"};
     const JVal *c = e.get("class"), *sh = e.get("shape"), *rm = e.get("rhs_max"), *gm = e.get("group_max");
@@ -191,7 +199,7 @@ std::vector<TuneEntry> read_tuning(const std::string &path) {
     }
     out.push_back(t);
   }
-  return out;
+  return table;
 }
 
 }  // namespace hps

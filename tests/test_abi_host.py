@@ -49,7 +49,11 @@ def test_host_context_and_errors():
         p = hps.hps_params_default(freq_hz=0.0)
         with pytest.raises(hps.HpsError):
             hps.hps_build_hmatrix(ctx, p)               # freq must be > 0
-        p = hps.hps_params_default(freq_hz=300e6, leaf_max=16)
+        for bad in (-1, 3):                             # graphs: 0, 1 or 2
+            with pytest.raises(hps.HpsError) as e:
+                hps.hps_build_hmatrix(ctx, hps.hps_params_default(freq_hz=300e6, leaf_max=16, graphs=bad))
+            assert e.value.status == -1
+        p = hps.hps_params_default(freq_hz=300e6, leaf_max=16, graphs=2)
         hps.hps_build_hmatrix(ctx, p)
         with pytest.raises(hps.HpsError) as e:
             hps.hps_setup(ctx)                          # host-only context
@@ -503,10 +507,12 @@ def test_tuning_table_reader(tmp_path):
         for bad in ('{"entries": [', '[1, 2]', '{"entries": 3}', '{"entries": [{"class": "gemm", "shape": 0}]}',
                     '{"entries": [{"class": "sweep", "shape": 11}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
                     '{"entries": [{"class": "sweep", "shape": 0, "rhs_max": -1}]}', '{"entries": []} x',
-                    '{"entries": [{"class": "sweep", "shape": 0, "precision": 3}]}'):
+                    '{"entries": [{"class": "sweep", "shape": 0, "precision": 3}]}',
+                    '{"sweep_pull_kmax": -1, "entries": []}', '{"sweep_pull_kmax": 2.5, "entries": []}',
+                    '{"sweep_pull_kmax": "all", "entries": []}'):
             st, msg = status(bad)
             assert st == -1, (bad, st, msg)
-        ok = ('{"arch": "gfx950", "shapes": {"0": "32 x 32"}, "entries": ['
+        ok = ('{"arch": "gfx950", "shapes": {"0": "32 x 32"}, "sweep_pull_kmax": 4096, "entries": ['
               '{"class": "sweep", "rhs_max": 64, "group_max": 48.5, "precision": 1, "shape": 3}, '
               '{"class": "schur", "rhs_max": null, "group_max": null, "shape": 2}], "measured": [1, true, null]}')
         st, msg = status(ok)

@@ -90,3 +90,41 @@ def test_one_column_vector_kernel(c0_workload, c0_hmatrix, tmp_path):
     b = excitation(H.rwg, w["freq_hz"], khat, pol)
     x_ref, _ = PowerSeries(H, schur_scaling(H, min_degree_order(group_graph(H)))).solve_rwg(b, 2)
     assert per_rhs_rel(X6.T, x_ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("kpull", [64, 10 ** 9])
+def test_pull_sweeps(c0_workload, c0_hmatrix, kpull, tmp_path):
+    """Sweep targets whose contraction is at most sweep_pull_kmax take all
+    their terms in one tile set (pull) instead of one per source level
+    (push): the sums run in another order, so currents, RCS, ratios and the
+    H-matrix product agree with the push form to rounding (1e-12) and with
+    the oracle's two-term series (1e-10).  kpull = 64 mixes both forms in one
+    launch; 10^9 pulls every target."""
+    w, H = c0_workload, c0_hmatrix
+    print("case: pull sweeps (kmax %d) vs push, sphere 1,920 unknowns, 37 RHS" % kpull, flush=True)
+    X0, Y0, rcs0, ratio0, khat, pol = _run(w, H, 0, 0, tmp_path)
+    path = tmp_path / "pull.json"
+    path.write_text(json.dumps({"sweep_pull_kmax": kpull, "entries": []}))
+    ctx = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        hps.hps_set_tuning(ctx, str(path))
+        hps.hps_set_mesh(ctx, w["xyz"], w["tri"])
+        p = hps.hps_params_default(freq_hz=w["freq_hz"], leaf_max=w["leaf_max"], aca_tol=1e-3, terms=2)
+        a = hmatrix_arrays(H)
+        hps.hps_set_hmatrix(ctx, p, a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"], a["near_vals"],
+                            a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+        hps.hps_setup(ctx)
+        X = torch.zeros((len(khat), H.N), dtype=torch.complex128, device="cuda")
+        _, rcs, ratio = hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr())
+        torch.cuda.synchronize()
+        assert hps.hps_stats(ctx)["device"]["tuning"]["sweep_pull_kmax"] == kpull
+        X = X.cpu().numpy()
+    finally:
+        hps.hps_destroy(ctx)
+    e_push = per_rhs_rel(X.T, X0.T).max()
+    b = excitation(H.rwg, w["freq_hz"], khat, pol)
+    x_ref, _ = PowerSeries(H, schur_scaling(H, min_degree_order(group_graph(H)))).solve_rwg(b, 2)
+    e_or = per_rhs_rel(X.T, x_ref).max()
+    print("pull vs push %.2e, vs oracle %.2e" % (e_push, e_or), flush=True)
+    assert e_push < 1e-12 and e_or < 1e-10
+    assert np.max(np.abs(rcs / rcs0 - 1)) < 1e-10 and np.max(np.abs(ratio / ratio0 - 1)) < 1e-10
