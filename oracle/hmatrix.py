@@ -116,7 +116,8 @@ def _far_job(pairs):
     return out
 
 
-def _one_blas_thread():
+def _init_worker(job):
+    _JOB.update(job)
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
@@ -125,12 +126,16 @@ def _one_blas_thread():
 
 
 def _run(job, items, workers, chunk=64):
+    """Independent blocks over worker processes.  The workers come from a
+    fork server (a fresh interpreter), never from a fork of the caller, which
+    may hold a GPU runtime with live threads and device mappings; the
+    operator and permutation reach them through the pool's initializer."""
     chunks = [items[i:i + chunk] for i in range(0, len(items), chunk)]
     if workers <= 1:
         res = [job(c) for c in chunks]
     else:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers, initializer=_one_blas_thread) as pool:
+        with mp.get_context("forkserver").Pool(workers, initializer=_init_worker, initargs=(dict(_JOB),)) as pool:
             res = pool.map(job, chunks)
     return [r for c in res for r in c]
 
@@ -142,7 +147,7 @@ def build_hmatrix(xyz, tri, freq_hz, leaf_max, aca_tol, eta_far=True, workers=1,
     With ``eta_far=False`` nothing is admissible: every leaf pair becomes a
     near block (Z_F = 0), used to pin the series against a dense LU solve.
     ``eta`` is the admissibility constant of eq. (10) (any value >= sqrt(3):
-    far = cells that do not touch).  ``workers`` > 1 evaluates independent blocks in forked processes (the
+    far = cells that do not touch).  ``workers`` > 1 evaluates independent blocks in worker processes (the
     arithmetic of each block is unchanged).  ``box_min`` > 0 stops the octree
     at cells of at least that side (metres), whatever their unknown count.
     ``open_surface`` accepts boundary edges (an open PEC sheet such as the

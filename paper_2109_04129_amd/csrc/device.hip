@@ -15,6 +15,7 @@
 // workgroup and sums its terms in a fixed order (deterministic, no atomics).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <chrono>
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   } else if (by > 0) {
     return;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const int wr = WR == 2 ? (wave >> 1) : 0, wc = WR == 2 ? (wave & 1) : wave;
   for (int st = st0; st < nsub; st += sstep) {
@@ -139,6 +140,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     bool arow_ok[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) arow_ok[i] = row0 + 16 * i + li < t.m;
+    // a wave of two 16-row blocks whose second block lies wholly past the
+    // target's edge computes the first only (wave-uniform choice)
+    const bool one_rb = RB > 1 && row0 + 16 >= t.m;
     // read-modify-write modes: fetch C now, so its latency hides behind the
     // products (after them when the kernel is built for more waves per SIMD:
     // fewer registers live through the products)
@@ -163,68 +167,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) rr[i][j] = ii[i][j] = ss[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int q = t.t_begin; q < t.t_end; ++q) {
-      const Term tm = terms[q];
-      const c2 *Ab = A + tm.a_off;
-      // full chunks of 16: in step s lane group g reads k = k0 + 4 s + g
-      const int kfull = tm.k & ~15;
-      for (int k0 = 0; k0 < kfull; k0 += 16) {
-        c2 av[RB][4], bv[NB][4];
+    auto products = [&](auto rbe) {
+      constexpr int RBE = decltype(rbe)::value;
+      for (int q = t.t_begin; q < t.t_end; ++q) {
+        const Term tm = terms[q];
+        const c2 *Ab = A + tm.a_off;
+        // full chunks of 16: in step s lane group g reads k = k0 + 4 s + g
+        const int kfull = tm.k & ~15;
+        for (int k0 = 0; k0 < kfull; k0 += 16) {
+          c2 av[RB][4], bv[NB][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = k0 + 4 * s + lg;
+          for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * s + lg;
 #pragma unroll
-          for (int i = 0; i < RB; ++i) {
+            for (int i = 0; i < RBE; ++i) {
+              const int arow = row0 + 16 * i + li;
+              av[i][s] = make_double2(0.0, 0.0);
+              if (arow_ok[i]) av[i][s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              const int bcol = col0 + 16 * j + li;
+              bv[j][s] = make_double2(0.0, 0.0);
+              if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              const double bs = bv[j][s].x + bv[j][s].y;
+#pragma unroll
+              for (int i = 0; i < RBE; ++i) {
+                rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
+                ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
+                ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+              }
+            }
+          }
+        }
+        // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
+        for (int kt = kfull; kt < tm.k; kt += 4) {
+          const int k = kt + lg;
+          const bool kok = k < tm.k;
+          c2 av[RB];
+#pragma unroll
+          for (int i = 0; i < RBE; ++i) {
             const int arow = row0 + 16 * i + li;
-            av[i][s] = make_double2(0.0, 0.0);
-            if (arow_ok[i]) av[i][s] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+            av[i] = make_double2(0.0, 0.0);
+            if (kok && arow_ok[i]) av[i] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
           }
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
             const int bcol = col0 + 16 * j + li;
-            bv[j][s] = make_double2(0.0, 0.0);
-            if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-          }
-        }
+            c2 bv = make_double2(0.0, 0.0);
+            if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const double bs = bv[j][s].x + bv[j][s].y;
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-              rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
-              ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
-              ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+            for (int i = 0; i < RBE; ++i) {
+              rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i][j], 0, 0, 0);
+              ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv.y, ii[i][j], 0, 0, 0);
+              ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
             }
           }
         }
       }
-      // tail (k % 16): steps of 4, lane group g takes k = kt + g; empty steps skipped
-      for (int kt = kfull; kt < tm.k; kt += 4) {
-        const int k = kt + lg;
-        const bool kok = k < tm.k;
-        c2 av[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int arow = row0 + 16 * i + li;
-          av[i] = make_double2(0.0, 0.0);
-          if (kok && arow_ok[i]) av[i] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int bcol = col0 + 16 * j + li;
-          c2 bv = make_double2(0.0, 0.0);
-          if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-#pragma unroll
-          for (int i = 0; i < RB; ++i) {
-            rr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i][j], 0, 0, 0);
-            ii[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv.y, ii[i][j], 0, 0, 0);
-            ss[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
-          }
-        }
-      }
-    }
+    };
+    if (one_rb)
+      products(std::integral_constant<int, 1>{});
+    else
+      products(std::integral_constant<int, RB>{});
     if (MODE != 0 && WPE > 1) fetch_c();
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -525,7 +536,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   } else if (by > 0) {
     return;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int wr = WR == 2 ? (wave >> 1) : 0, wc = WR == 2 ? (wave & 1) : wave;
   const int row0 = rb + 16 * RB * wr, col0 = cb + 16 * NB * wc;
   if (row0 >= t.m || col0 >= tn) return;
@@ -565,80 +576,90 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) rr[i][j] = ii[i][j] = ss[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int q = t.t_begin; q < t.t_end; ++q) {
-    const Term tm = terms[q];
-    float sc[RB];
+  // a wave of two 16-row blocks whose second block lies wholly past the
+  // target's edge computes the first only (wave-uniform choice)
+  const bool one_rb = RB > 1 && row0 + 16 >= t.m;
+  auto products = [&](auto rbe) {
+    constexpr int RBE = decltype(rbe)::value;
+    for (int q = t.t_begin; q < t.t_end; ++q) {
+      const Term tm = terms[q];
+      float sc[RB];
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
-      sc[i] = AT == 0 ? 1.0f : (tm.sidx >= 0 ? scales[tm.sidx] : (tm.sidx == -2 ? sc_row[i] : 1.0f));
-    const int kfull = tm.k & ~15;
-    for (int k0 = 0; k0 < kfull; k0 += 16) {
-      float2 av[RB][4], bv[NB][4];
+      for (int i = 0; i < RBE; ++i)
+        sc[i] = AT == 0 ? 1.0f : (tm.sidx >= 0 ? scales[tm.sidx] : (tm.sidx == -2 ? sc_row[i] : 1.0f));
+      const int kfull = tm.k & ~15;
+      for (int k0 = 0; k0 < kfull; k0 += 16) {
+        float2 av[RB][4], bv[NB][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * s + lg;
+        for (int s = 0; s < 4; ++s) {
+          const int k = k0 + 4 * s + lg;
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
+          for (int i = 0; i < RBE; ++i) {
+            const int arow = row0 + 16 * i + li;
+            av[i][s] = make_float2(0.f, 0.f);
+            if (arow_ok[i]) {
+              const int64_t idx =
+                  tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+              av[i][s] = load_a<AT>(A, idx);
+              av[i][s].x *= sc[i];
+              av[i][s].y *= sc[i];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int bcol = col0 + 16 * j + li;
+            bv[j][s] = make_float2(0.f, 0.f);
+            if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const float bs = bv[j][s].x + bv[j][s].y;
+#pragma unroll
+            for (int i = 0; i < RBE; ++i) {
+              rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
+              ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
+              ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+            }
+          }
+        }
+      }
+      for (int kt = kfull; kt < tm.k; kt += 4) {
+        const int k = kt + lg;
+        const bool kok = k < tm.k;
+        float2 av[RB];
+#pragma unroll
+        for (int i = 0; i < RBE; ++i) {
           const int arow = row0 + 16 * i + li;
-          av[i][s] = make_float2(0.f, 0.f);
-          if (arow_ok[i]) {
-            const int64_t idx =
-                tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
-            av[i][s] = load_a<AT>(A, idx);
-            av[i][s].x *= sc[i];
-            av[i][s].y *= sc[i];
+          av[i] = make_float2(0.f, 0.f);
+          if (kok && arow_ok[i]) {
+            const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
+            av[i] = load_a<AT>(A, idx);
+            av[i].x *= sc[i];
+            av[i].y *= sc[i];
           }
         }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           const int bcol = col0 + 16 * j + li;
-          bv[j][s] = make_float2(0.f, 0.f);
-          if (bcol < tn) bv[j][s] = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-        }
-      }
+          float2 bv = make_float2(0.f, 0.f);
+          if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const float bs = bv[j][s].x + bv[j][s].y;
-#pragma unroll
-          for (int i = 0; i < RB; ++i) {
-            rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x, bv[j][s].x, rr[i][j], 0, 0, 0);
-            ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].y, bv[j][s].y, ii[i][j], 0, 0, 0);
-            ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s].x + av[i][s].y, bs, ss[i][j], 0, 0, 0);
+          for (int i = 0; i < RBE; ++i) {
+            rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv.x, rr[i][j], 0, 0, 0);
+            ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv.y, ii[i][j], 0, 0, 0);
+            ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
           }
         }
       }
     }
-    for (int kt = kfull; kt < tm.k; kt += 4) {
-      const int k = kt + lg;
-      const bool kok = k < tm.k;
-      float2 av[RB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int arow = row0 + 16 * i + li;
-        av[i] = make_float2(0.f, 0.f);
-        if (kok && arow_ok[i]) {
-          const int64_t idx = tm.trans ? tm.a_off + (int64_t)arow * tm.lda + k : tm.a_off + (int64_t)k * tm.lda + arow;
-          av[i] = load_a<AT>(A, idx);
-          av[i].x *= sc[i];
-          av[i].y *= sc[i];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int bcol = col0 + 16 * j + li;
-        float2 bv = make_float2(0.f, 0.f);
-        if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv.x, rr[i][j], 0, 0, 0);
-          ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv.y, ii[i][j], 0, 0, 0);
-          ss[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x + av[i].y, bv.x + bv.y, ss[i][j], 0, 0, 0);
-        }
-      }
-    }
-  }
+  };
+  if (one_rb)
+    products(std::integral_constant<int, 1>{});
+  else
+    products(std::integral_constant<int, RB>{});
   if (MODE != 0 && WPE > 1) fetch_c();
 #pragma unroll
   for (int i = 0; i < RB; ++i)
@@ -2080,6 +2101,9 @@ struct DeviceState::Impl {
     }
   }
   ~Impl() {
+    // captured graphs go first: they were recorded on s2 and the level events
+    srec.reset();
+    drop_graphs();
     for (hipEvent_t e : lev_ev) (void)hipEventDestroy(e);
     if (s2) {
       (void)hipStreamSynchronize(s2);
