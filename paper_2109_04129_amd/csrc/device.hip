@@ -71,12 +71,13 @@ __device__ __forceinline__ c2 cinv(c2 a) {
 // D[l / 16 + 4 r][l % 16].  In step s of a chunk of 16 the lane groups take
 // k = k0 + 4 s + l / 16, so one load instruction reads four consecutive
 // elements of each of 16 rows (A) or columns (B).  Operands come straight
-// from L2 (no LDS).  The tile shape of each launch class is a run-time choice
+// from L2; the read-modify-write modes of the multi-wave builds stage their
+// C sub-tile in LDS (below).  The tile shape of each launch class is a run-time choice
 // (a tuning table written by the autotuner); every shape gives bitwise the
 // same result (each output element sums the same products in the same order).
 // WPE > 1 builds the kernel for at least WPE waves per SIMD (registers capped
-// accordingly; the C tile of the read-modify-write modes is then fetched
-// after the products, so fewer registers stay live through them).
+// accordingly; the C tile of the read-modify-write modes then goes through
+// LDS instead of registers).
 constexpr int TM = 32;
 constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops over its share of sub-tiles)
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -129,6 +130,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   const int wr = WR == 2 ? (wave >> 1) : 0, wc = WR == 2 ? (wave & 1) : wave;
+  // The read-modify-write modes built for several waves per SIMD stage the
+  // wave's C sub-tile (16 RB rows x 16 NB columns) in LDS with direct-to-LDS
+  // loads issued before the products, so its latency hides behind them with
+  // no registers held, and read it back after them.  Load q of the wave
+  // fills slots 64 q .. 64 q + 63, lane l slot 64 q + l; element (c, r) of
+  // the sub-tile sits at slot c RW + (r + 2 c) mod RW (the rotation spreads
+  // the read-back of one row over the banks).
+  constexpr bool LDS_C = MODE != 0 && WPE > 1;
+  constexpr int RW = 16 * RB, CW = 16 * NB, NQ = RW * CW / 64;
+  __shared__ c2 cbuf[LDS_C ? 4 * RW * CW : 1];
+  c2 *const cw = cbuf + (LDS_C ? wave * RW * CW : 0);
   for (int st = st0; st < nsub; st += sstep) {
     int rb = rb0, cb = cb0;
     if (t.r0 < 0) {
@@ -162,6 +174,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
     };
     if (MODE != 0 && WPE == 1) fetch_c();
+    if constexpr (LDS_C) {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");    // the previous sub-tile's read-back is done
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int e = 64 * q + lane, c = e / RW, r = (e - c * RW - 2 * c) & (RW - 1);
+        const int ccol = col0 + c, crow = row0 + r;
+        if (ccol < tn && crow < t.m)
+          __builtin_amdgcn_global_load_lds((const void *)(C + t.c_off + (int64_t)ccol * t.ldc + crow),
+                                           (__attribute__((address_space(3))) void *)(cw + 64 * q), 16, 0, 0);
+      }
+    }
     d4 rr[RB][NB], ii[RB][NB], ss[RB][NB];      // 3M: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -236,7 +259,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       products(std::integral_constant<int, 1>{});
     else
       products(std::integral_constant<int, RB>{});
-    if (MODE != 0 && WPE > 1) fetch_c();
+    if constexpr (LDS_C) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");      // the staged C sub-tile has landed
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = 16 * j + li, rw = 16 * i + lg + 4 * r;
+            cold[i][j][r] = cw[c * RW + ((rw + 2 * c) & (RW - 1))];
+          }
+    } else if (MODE != 0 && WPE > 1) {
+      fetch_c();
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
