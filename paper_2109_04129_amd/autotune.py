@@ -33,7 +33,7 @@ import time
 
 CLASSES = ["sweep", "dinv", "far1", "far2", "near", "schur"]
 SOLVE_CLASSES = CLASSES[:5]
-SHAPES = 11
+SHAPES = 13
 SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16 (FP64 built for 4 waves per SIMD)", 1: "32 x 64 tile, waves 2 x 2 of 16 x 32",
              2: "32 x 64 tile, waves 1 x 4 of 32 x 16", 3: "32 x 128 tile, waves 1 x 4 of 32 x 32",
              4: "32 x 128 tile, waves 2 x 2 of 16 x 64",
@@ -42,7 +42,10 @@ SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16 (FP64 built for 4 waves pe
              7: "as 2, built for 3 waves per SIMD (FP64; FP32 takes 2)",
              8: "as 1, built for 3 waves per SIMD (FP64; FP32 takes 1)",
              9: "as 0, built for 5 waves per SIMD (FP64; FP32 takes 0)",
-             10: "as 3, built for 4 waves per SIMD (FP32; FP64 takes 3)"}
+             10: "as 3, built for 4 waves per SIMD (FP32; FP64 takes 3)",
+             11: "as 2, full 16-k chunks staged in LDS one chunk ahead by direct-to-LDS loads, target tile in LDS "
+                 "(FP64; FP32 takes 2)",
+             12: "as 11, target tile fetched after the products (FP64; FP32 takes 2)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning", "gfx950.json")
 

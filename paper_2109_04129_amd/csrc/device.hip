@@ -83,8 +83,10 @@ constexpr int SUB_Y = 16;     // workgroups per whole-block tile (each loops ove
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // tile shapes: (WR, NB) and the workgroup tile's column count
-static_assert(TUNE_SHAPES == 11, "tile shapes 0-10");
-__host__ __device__ constexpr int shape_wr(int v) { return v == 2 || v == 3 || v == 5 || v == 7 || v == 10 ? 1 : 2; }
+static_assert(TUNE_SHAPES == 13, "tile shapes 0-12");
+__host__ __device__ constexpr int shape_wr(int v) {
+  return v == 2 || v == 3 || v == 5 || v == 7 || v == 10 || v == 11 || v == 12 ? 1 : 2;
+}
 __host__ __device__ constexpr int shape_nb(int v) { return v == 1 || v == 3 || v == 8 || v == 10 ? 2 : (v == 4 ? 4 : 1); }
 __host__ __device__ constexpr int shape_tn(int v) { return 16 * shape_nb(v) * (4 / shape_wr(v)); }
 
@@ -448,6 +450,231 @@ __global__ __launch_bounds__(256) void k_gemm_lds(const c2 *__restrict__ A, cons
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int crow = rb + 16 * i + lg + 4 * r;
+        if (crow >= t.m) continue;
+        const c2 acc = make_double2(rr[i][r] - ii[i][r], ss[i][r] - rr[i][r] - ii[i][r]);
+        c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+        if (MODE == 0) {
+          *p = acc;
+        } else if (MODE == 1) {
+          *p = make_double2(cold[i][r].x - acc.x, cold[i][r].y - acc.y);
+        } else {
+          *p = make_double2(cold[i][r].x + acc.x, cold[i][r].y + acc.y);
+        }
+      }
+    }
+  }
+}
+
+// Pipelined variant (tile shapes 11 and 12): the 32 x 64 workgroup tile of
+// shape 7 (four waves of 32 rows x 16 columns), with every full 16-k chunk
+// of a term staged in LDS by direct-to-LDS loads one chunk ahead, so the
+// loads of chunk c + 1 are in flight while the products of chunk c run.
+// The workgroup shares the A chunk (32 rows x 16 k, each wave loads a
+// quarter); each wave loads its own B chunk (16 k x 16 columns); both are
+// double-buffered.  LDS slots of a load instruction are consecutive (lane l
+// writes slot 64 q + l), so the layouts follow the coalesced lane order:
+//   A, plain (A read along its columns): slot k 32 + r;
+//   A^T (A read along k): slot r 16 + (k + r) mod 16;
+//   B: slot c 16 + (k + c) mod 16 of the wave's block;
+// the rotations keep the MFMA operand reads (16 rows or columns at one k)
+// on distinct banks.  Rows and columns past the tile's edge are not loaded:
+// their slots feed only outputs that are never stored.  The k % 16 tail and
+// the target tile are handled as in k_gemm (CL = 1: the target tile staged
+// in LDS too, CL = 0: fetched after the products).  The products are
+// k_gemm's, in the same order, so the results are bitwise the same.  Every
+// wave of the workgroup takes part in every barrier (the chunk loop and its
+// bounds are uniform over the workgroup); waves past the tile's last column
+// skip their loads of B, their products and their stores.
+template <int MODE, int CL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_pipe(
+    const c2 *__restrict__ A, const c2 *__restrict__ B, c2 *__restrict__ C, const Tile *__restrict__ tiles,
+    const Term *__restrict__ terms, int ncols, int ntiles, int ny, int xcd_order) {
+  constexpr int RB = 2, TN = 64;
+  __shared__ c2 abuf[2][512];
+  __shared__ c2 bbuf[2][4][256];
+  __shared__ c2 cbuf[CL ? 4 * 512 : 1];
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (xcd_order) {
+    const int q = (int)(blockIdx.x >> 3);
+    by = q % ny;
+    bx = 8 * (q / ny) + (int)(blockIdx.x & 7);
+    if (bx >= ntiles) return;
+  }
+  const Tile t = tiles[bx];
+  int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
+  if (t.r0 < 0) {
+    nsc = (t.n + TN - 1) / TN;
+    nsub = ((t.m + TM - 1) / TM) * nsc;
+    st0 = by;
+    sstep = ny;
+  } else if (t.c0 < 0) {
+    tn = ncols;
+    cb0 = by * TN;
+    if (cb0 >= tn) return;
+  } else if (by > 0) {
+    return;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  c2 *const cw = cbuf + (CL ? wave * 512 : 0);
+  for (int st = st0; st < nsub; st += sstep) {
+    int rb = rb0, cb = cb0;
+    if (t.r0 < 0) {
+      rb = (st / nsc) * TM;
+      cb = (st % nsc) * TN;
+    }
+    const int row0 = rb, col0 = cb + 16 * wave;
+    if (row0 >= t.m) continue;                          // uniform over the workgroup
+    const bool cols = col0 < tn;                        // uniform over the wave
+    __syncthreads();                                    // the previous sub-tile's LDS reads are done
+    bool arow_ok[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) arow_ok[i] = row0 + 16 * i + li < t.m;
+    const bool one_rb = row0 + 16 >= t.m;
+    if (CL && MODE != 0 && cols) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = 64 * q + lane, c = e >> 5, r = (e - 32 * c - 2 * c) & 31;
+        const int ccol = col0 + c, crow = row0 + r;
+        if (ccol < tn && crow < t.m)
+          __builtin_amdgcn_global_load_lds((const void *)(C + t.c_off + (int64_t)ccol * t.ldc + crow),
+                                           (lds_ptr)(cw + 64 * q), 16, 0, 0);
+      }
+    }
+    d4 rr[RB], ii[RB], ss[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) rr[i] = ii[i] = ss[i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = t.t_begin; q < t.t_end; ++q) {
+      const Term tm = terms[q];
+      const c2 *Ab = A + tm.a_off;
+      const int nchunk = tm.k >> 4;
+      // chunk ch of this term into buffer b: the wave's quarter of A and its own B
+      auto stage = [&](int ch, int b) {
+        const int k0 = ch * 16;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int qa = 2 * wave + h, e = 64 * qa + lane;
+          int r, k;
+          if (tm.trans) {
+            r = e >> 4;
+            k = ((e & 15) - r) & 15;
+          } else {
+            k = e >> 5;
+            r = e & 31;
+          }
+          if (row0 + r < t.m)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(tm.trans ? Ab + (int64_t)(row0 + r) * tm.lda + k0 + k
+                                        : Ab + (int64_t)(k0 + k) * tm.lda + row0 + r),
+                (lds_ptr)(&abuf[b][64 * qa]), 16, 0, 0);
+        }
+        if (cols) {
+#pragma unroll
+          for (int qb = 0; qb < 4; ++qb) {
+            const int e = 64 * qb + lane, c = e >> 4, k = ((e & 15) - c) & 15;
+            if (col0 + c < tn)
+              __builtin_amdgcn_global_load_lds((const void *)(B + tm.b_off + (int64_t)(col0 + c) * tm.ldb + k0 + k),
+                                               (lds_ptr)(&bbuf[b][wave][64 * qb]), 16, 0, 0);
+          }
+        }
+      };
+      __syncthreads();                                  // the previous term's chunk reads are done
+      if (nchunk > 0) stage(0, 0);
+      for (int ch = 0; ch < nchunk; ++ch) {
+        const int b = ch & 1;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of chunk ch have landed
+        __syncthreads();                                    // every wave's have; chunk ch - 1 is read
+        if (ch + 1 < nchunk) stage(ch + 1, b ^ 1);
+        if (cols) {
+          auto prod = [&](auto rbe) {
+            constexpr int RBE = decltype(rbe)::value;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int k = 4 * s + lg;
+              c2 av[RB];
+#pragma unroll
+              for (int i = 0; i < RBE; ++i) {
+                const int r = 16 * i + li;
+                av[i] = tm.trans ? abuf[b][r * 16 + ((k + r) & 15)] : abuf[b][k * 32 + r];
+              }
+              const c2 bv = bbuf[b][wave][li * 16 + ((k + li) & 15)];
+              const double bs = bv.x + bv.y;
+#pragma unroll
+              for (int i = 0; i < RBE; ++i) {
+                rr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i], 0, 0, 0);
+                ii[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv.y, ii[i], 0, 0, 0);
+                ss[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x + av[i].y, bs, ss[i], 0, 0, 0);
+              }
+            }
+          };
+          if (one_rb)
+            prod(std::integral_constant<int, 1>{});
+          else
+            prod(std::integral_constant<int, RB>{});
+        }
+      }
+      // tail (k % 16): steps of 4 from global memory, as in k_gemm
+      if (cols) {
+        auto tail = [&](auto rbe) {
+          constexpr int RBE = decltype(rbe)::value;
+          for (int kt = nchunk * 16; kt < tm.k; kt += 4) {
+            const int k = kt + lg;
+            const bool kok = k < tm.k;
+            c2 av[RB];
+#pragma unroll
+            for (int i = 0; i < RBE; ++i) {
+              const int arow = row0 + 16 * i + li;
+              av[i] = make_double2(0.0, 0.0);
+              if (kok && arow_ok[i]) av[i] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+            }
+            const int bcol = col0 + li;
+            c2 bv = make_double2(0.0, 0.0);
+            if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+#pragma unroll
+            for (int i = 0; i < RBE; ++i) {
+              rr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i], 0, 0, 0);
+              ii[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv.y, ii[i], 0, 0, 0);
+              ss[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x + av[i].y, bv.x + bv.y, ss[i], 0, 0, 0);
+            }
+          }
+        };
+        if (one_rb)
+          tail(std::integral_constant<int, 1>{});
+        else
+          tail(std::integral_constant<int, RB>{});
+      }
+    }
+    if (!cols) continue;
+    c2 cold[RB][4];
+    if (MODE != 0) {
+      if (CL) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rw = 16 * i + lg + 4 * r;
+            cold[i][r] = cw[li * 32 + ((rw + 2 * li) & 31)];
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int crow = row0 + 16 * i + lg + 4 * r, ccol = col0 + li;
+            cold[i][r] = make_double2(0.0, 0.0);
+            if (ccol < tn && crow < t.m) cold[i][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+          }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int ccol = col0 + li;
+      if (ccol >= tn) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int crow = row0 + 16 * i + lg + 4 * r;
         if (crow >= t.m) continue;
         const c2 acc = make_double2(rr[i][r] - ii[i][r], ss[i][r] - rr[i][r] - ii[i][r]);
         c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
@@ -1953,6 +2180,8 @@ static void gemm64_launch(int shape, dim3 g, hipStream_t s, const c2 *A, const c
     case 8: hipLaunchKernelGGL((k_gemm<MODE, 2, 2, 3>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 9: hipLaunchKernelGGL((k_gemm<MODE, 2, 1, 5>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     case 10: hipLaunchKernelGGL((k_gemm<MODE, 1, 2>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 11: hipLaunchKernelGGL((k_gemm_pipe<MODE, 1>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
+    case 12: hipLaunchKernelGGL((k_gemm_pipe<MODE, 0>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
     default: hipLaunchKernelGGL((k_gemm<MODE, 2, 1, 4>), g, blk, 0, s, A, B, C, tiles, terms, ncols, nt, ny, xo); break;
   }
 }
@@ -1969,6 +2198,8 @@ static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const
     case 2:
     case 5:       // the LDS-staged shape has no FP32 kernel: the same 32 x 64 tile without LDS
     case 7:       // FP32 kernels are not built for 3 waves per SIMD: the same tile
+    case 11:      // the pipelined shapes have no FP32 kernel: the same tile
+    case 12:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 3:

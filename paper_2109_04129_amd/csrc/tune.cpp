@@ -178,7 +178,7 @@ TuneTable read_tuning(const std::string &path) {
     if (!c || c->kind != JVal::STR || class_id(c->str) < 0)
       throw Error{HPS_EINVAL, "tuning file: entry without a known \"class\" (sweep, dinv, far1, far2, near, schur)"};
     if (!sh || sh->kind != JVal::NUM || sh->num != std::floor(sh->num) || sh->num < 0 || sh->num >= TUNE_SHAPES)
-      throw Error{HPS_EINVAL, "tuning file: \"shape\" must be an integer 0-10"};
+      throw Error{HPS_EINVAL, "tuning file: \"shape\" must be an integer 0-12"};
     TuneEntry t;
     t.cls = class_id(c->str);
     t.shape = (int)sh->num;

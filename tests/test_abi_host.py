@@ -505,7 +505,7 @@ def test_tuning_table_reader(tmp_path):
     try:
         assert status(path=tmp_path / "absent.json")[0] == -6
         for bad in ('{"entries": [', '[1, 2]', '{"entries": 3}', '{"entries": [{"class": "gemm", "shape": 0}]}',
-                    '{"entries": [{"class": "sweep", "shape": 11}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
+                    '{"entries": [{"class": "sweep", "shape": 13}]}', '{"entries": [{"class": "sweep", "shape": 1.5}]}',
                     '{"entries": [{"class": "sweep", "shape": 0, "rhs_max": -1}]}', '{"entries": []} x',
                     '{"entries": [{"class": "sweep", "shape": 0, "precision": 3}]}',
                     '{"sweep_pull_kmax": -1, "entries": []}', '{"sweep_pull_kmax": 2.5, "entries": []}',

@@ -1,5 +1,5 @@
 """Tile shapes of the grouped complex GEMM (the autotuner's choices, shape 5
-the LDS-staged kernel): every
+the LDS-staged kernel, 11 and 12 the pipelined ones): every
 shape sums the same products in the same order for each output element, so
 setup and solve results are bitwise those of the 32 x 32 shape.  Checked on
 the oracle's H-matrix of the 1,920-unknown sphere with 37 RHS (two column
@@ -58,9 +58,9 @@ def _run(w, H, shape, precision, tmp_path, nrhs=37):
 @pytest.mark.parametrize("precision", [0, 2])
 def test_tile_shapes_bitwise(c0_workload, c0_hmatrix, precision, tmp_path):
     w, H = c0_workload, c0_hmatrix
-    print("case: tile shapes 0-10, sphere 1,920 unknowns, 37 RHS, precision %d" % precision, flush=True)
+    print("case: tile shapes 0-12, sphere 1,920 unknowns, 37 RHS, precision %d" % precision, flush=True)
     X0, Y0, rcs0, ratio0, khat, pol = _run(w, H, 0, precision, tmp_path)
-    for shape in range(1, 11):          # 6 (the one-column kernel) falls back to 0 for 37 columns
+    for shape in range(1, 13):          # 6 (the one-column kernel) falls back to 0 for 37 columns
         X, Y, rcs, ratio, _, _ = _run(w, H, shape, precision, tmp_path)
         assert np.array_equal(X, X0), "shape %d: currents differ (max %.3e)" % (shape, np.max(np.abs(X - X0)))
         assert np.array_equal(Y, Y0), "shape %d: H x differs" % shape
