@@ -33,13 +33,17 @@ DOMINANT = "gemm_sub"
 
 
 def kernel_hash():
-    """sha256 prefix of the k_gemm template's source (the function itself),
-    to tie the counted traffic to it."""
+    """sha256 prefix of the grouped GEMM templates' source (k_gemm and the
+    pipelined k_gemm_pipe, the functions themselves), to tie the counted
+    traffic to them."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2109_04129_amd", "csrc", "device.hip")).read()
-    a = src.rindex("template <", 0, src.index("void k_gemm("))
-    b = src.index("\n}\n", a) + 3
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("void k_gemm(", "void k_gemm_pipe("):
+        a = src.rindex("template <", 0, src.index(name))
+        b = src.index("\n}\n", a) + 3
+        h.update(src[a:b].encode())
+    return h.hexdigest()[:16]
 
 
 def counted_traffic(workload):
@@ -276,7 +280,7 @@ def single_rhs_leg(args, w, g, precision=0, reps=10):
     k = ks.get("gemm_sub", {})
     sub = None
     if k.get("ms"):
-        sub = {"kernel": "k_gemm<1> (sweeps)", "bound": "hbm", "achieved": k["bytes"] / (k["ms"] * 1e-3) / 1e9,
+        sub = {"kernel": "grouped GEMM, subtract mode (the sweeps; one column: k_gemv)", "bound": "hbm", "achieved": k["bytes"] / (k["ms"] * 1e-3) / 1e9,
                "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
                "frac": k["bytes"] / (k["ms"] * 1e-3) / PEAK["hbm"],
                "launches": k["launches"], "avg_launch_us": 1e3 * k["ms"] / k["launches"],
@@ -542,7 +546,8 @@ def roofline_from(stats, steps=1):
                             "achieved_tflops": f / t / 1e12, "intensity_flop_per_byte": f / b})
     sec = k["ms"] * 1e-3
     flop_rate, byte_rate = k["flops"] / sec, k["bytes"] / sec
-    return {"kernel": "k_gemm<1> (grouped complex GEMM on FP64 MFMA, subtract)", "bound": "mfma",
+    return {"kernel": "grouped complex GEMM on FP64 MFMA, subtract mode (k_gemm / k_gemm_pipe by tile shape)",
+            "bound": "mfma",
             "achieved": flop_rate / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
             "frac": flop_rate / PEAK["fp64"],
             "flops_per_launch": k["flops"] / k["launches"],

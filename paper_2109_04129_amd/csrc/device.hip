@@ -947,6 +947,175 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     }
 }
 
+// Pipelined FP32 variant (tile shapes 11 and 12 of launches with FP32 A
+// operands): k_gemm32's 32 x 64 tile of four 32 x 16 waves, with every full
+// 16-k chunk staged in LDS one chunk ahead as in k_gemm_pipe.  A lane's
+// direct-to-LDS load moves 16 bytes, two complex floats: a pair of rows
+// (plain A) or of k (A^T, and B).  LDS slot layouts (16-byte slots; slot e
+// holds elements 2 e and 2 e + 1 of the buffer):
+//   A, plain: slot k 16 + p holds rows 2 p, 2 p + 1 at k (element k 32 + r);
+//   A^T: slot r 8 + (m + r) mod 8 holds k = 2 m, 2 m + 1 of row r;
+//   B: slot c 8 + (m + c) mod 8 holds k = 2 m, 2 m + 1 of column c.
+// A row pair that straddles the tile's last row takes a plain load of its
+// valid row and an LDS store (no read past the operand).  The target tile is
+// fetched after the products.  Same products in the same order as k_gemm32,
+// so the results are bitwise the same.
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm32_pipe(
+    const float2 *__restrict__ A, const float2 *__restrict__ B, float2 *__restrict__ C,
+    const Tile *__restrict__ tiles, const Term *__restrict__ terms, int ncols, int ntiles, int ny, int xcd_order) {
+  constexpr int RB = 2, TN = 64;
+  __shared__ float2 abuf[2][512];
+  __shared__ float2 bbuf[2][4][256];
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (xcd_order) {
+    const int q = (int)(blockIdx.x >> 3);
+    by = q % ny;
+    bx = 8 * (q / ny) + (int)(blockIdx.x & 7);
+    if (bx >= ntiles) return;
+  }
+  const Tile t = tiles[bx];
+  int rb = t.r0, cb = t.c0, tn = t.n;
+  if (t.r0 < 0) {
+    const int nsc = (t.n + TN - 1) / TN, nsr = (t.m + TM - 1) / TM;
+    if (by >= nsr * nsc) return;
+    rb = (by / nsc) * TM;
+    cb = (by % nsc) * TN;
+  } else if (t.c0 < 0) {
+    tn = ncols;
+    cb = by * TN;
+    if (cb >= tn) return;
+  } else if (by > 0) {
+    return;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  const int row0 = rb, col0 = cb + 16 * wave;
+  if (row0 >= t.m) return;                              // uniform over the workgroup
+  const bool cols = col0 < tn;                          // uniform over the wave
+  bool arow_ok[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) arow_ok[i] = row0 + 16 * i + li < t.m;
+  const bool one_rb = row0 + 16 >= t.m;
+  f4 rr[RB], ii[RB], ss[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) rr[i] = ii[i] = ss[i] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int q = t.t_begin; q < t.t_end; ++q) {
+    const Term tm = terms[q];
+    const float2 *Ab = A + tm.a_off;
+    const int nchunk = tm.k >> 4;
+    auto stage = [&](int ch, int b) {
+      const int k0 = ch * 16, e = 64 * wave + lane;          // this wave's 64 slots of A
+      if (tm.trans) {
+        const int r = e >> 3, m = ((e & 7) - r) & 7;
+        if (row0 + r < t.m)
+          __builtin_amdgcn_global_load_lds((const void *)(Ab + (int64_t)(row0 + r) * tm.lda + k0 + 2 * m),
+                                           (lds_ptr)(&abuf[b][128 * wave]), 16, 0, 0);
+      } else {
+        const int k = e >> 4, r = 2 * (e & 15);
+        if (row0 + r + 1 < t.m)
+          __builtin_amdgcn_global_load_lds((const void *)(Ab + (int64_t)(k0 + k) * tm.lda + row0 + r),
+                                           (lds_ptr)(&abuf[b][128 * wave]), 16, 0, 0);
+        else if (row0 + r < t.m)
+          abuf[b][2 * e] = Ab[(int64_t)(k0 + k) * tm.lda + row0 + r];
+      }
+      if (cols) {
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+          const int eb = 64 * qb + lane, c = eb >> 3, m = ((eb & 7) - c) & 7;
+          if (col0 + c < tn)
+            __builtin_amdgcn_global_load_lds((const void *)(B + tm.b_off + (int64_t)(col0 + c) * tm.ldb + k0 + 2 * m),
+                                             (lds_ptr)(&bbuf[b][wave][128 * qb]), 16, 0, 0);
+        }
+      }
+    };
+    __syncthreads();                                    // the previous term's chunk reads are done
+    if (nchunk > 0) stage(0, 0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int b = ch & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of chunk ch have landed
+      __syncthreads();                                    // every wave's have; chunk ch - 1 is read
+      if (ch + 1 < nchunk) stage(ch + 1, b ^ 1);
+      if (cols) {
+        auto prod = [&](auto rbe) {
+          constexpr int RBE = decltype(rbe)::value;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + lg;
+            float2 av[RB];
+#pragma unroll
+            for (int i = 0; i < RBE; ++i) {
+              const int r = 16 * i + li;
+              av[i] = tm.trans ? abuf[b][2 * (r * 8 + (((k >> 1) + r) & 7)) + (k & 1)] : abuf[b][k * 32 + r];
+            }
+            const float2 bv = bbuf[b][wave][2 * (li * 8 + (((k >> 1) + li) & 7)) + (k & 1)];
+#pragma unroll
+            for (int i = 0; i < RBE; ++i) {
+              rr[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv.x, rr[i], 0, 0, 0);
+              ii[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv.y, ii[i], 0, 0, 0);
+              ss[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x + av[i].y, bv.x + bv.y, ss[i], 0, 0, 0);
+            }
+          }
+        };
+        if (one_rb)
+          prod(std::integral_constant<int, 1>{});
+        else
+          prod(std::integral_constant<int, RB>{});
+      }
+    }
+    if (cols) {                                         // tail (k % 16) from global memory, as in k_gemm32
+      auto tail = [&](auto rbe) {
+        constexpr int RBE = decltype(rbe)::value;
+        for (int kt = nchunk * 16; kt < tm.k; kt += 4) {
+          const int k = kt + lg;
+          const bool kok = k < tm.k;
+          float2 av[RB];
+#pragma unroll
+          for (int i = 0; i < RBE; ++i) {
+            const int arow = row0 + 16 * i + li;
+            av[i] = make_float2(0.f, 0.f);
+            if (kok && arow_ok[i]) av[i] = tm.trans ? Ab[(int64_t)arow * tm.lda + k] : Ab[(int64_t)k * tm.lda + arow];
+          }
+          const int bcol = col0 + li;
+          float2 bv = make_float2(0.f, 0.f);
+          if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+#pragma unroll
+          for (int i = 0; i < RBE; ++i) {
+            rr[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv.x, rr[i], 0, 0, 0);
+            ii[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv.y, ii[i], 0, 0, 0);
+            ss[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x + av[i].y, bv.x + bv.y, ss[i], 0, 0, 0);
+          }
+        }
+      };
+      if (one_rb)
+        tail(std::integral_constant<int, 1>{});
+      else
+        tail(std::integral_constant<int, RB>{});
+    }
+  }
+  if (!cols) return;
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int ccol = col0 + li;
+    if (ccol >= tn) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int crow = row0 + 16 * i + 4 * lg + r;
+      if (crow >= t.m) continue;
+      const float2 acc = make_float2(rr[i][r] - ii[i][r], ss[i][r] - rr[i][r] - ii[i][r]);
+      float2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+      if (MODE == 0) {
+        *p = acc;
+      } else {
+        const float2 o = *p;
+        *p = MODE == 1 ? make_float2(o.x - acc.x, o.y - acc.y) : make_float2(o.x + acc.x, o.y + acc.y);
+      }
+    }
+  }
+}
+
+
 __global__ void k_to32(const c2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -2195,11 +2364,17 @@ static void gemm32_launch(int shape, dim3 g, hipStream_t s, const void *A, const
     case 8:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 2, 2>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
+    case 11:      // the pipelined shapes: FP32 A operands only, else the same tile unpipelined
+    case 12:
+      if (AT == 0) {
+        hipLaunchKernelGGL((k_gemm32_pipe<MODE>), g, blk, 0, s, (const float2 *)A, B, C, tiles, terms, ncols, nt, ny,
+                           xo);
+        break;
+      }
+      [[fallthrough]];
     case 2:
     case 5:       // the LDS-staged shape has no FP32 kernel: the same 32 x 64 tile without LDS
     case 7:       // FP32 kernels are not built for 3 waves per SIMD: the same tile
-    case 11:      // the pipelined shapes have no FP32 kernel: the same tile
-    case 12:
       hipLaunchKernelGGL((k_gemm32<MODE, AT, 1, 1>), g, blk, 0, s, A, B, C, tiles, terms, sc, rp, ncols, nt, ny, xo);
       break;
     case 3:
