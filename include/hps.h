@@ -320,7 +320,9 @@ hps_status hps_hmatvec_noalloc(hps_ctx *ctx, int64_t R, const void *X, void *Y);
    built for 5 waves per SIMD (FP64; FP32 takes 0), 10 = shape 3 built for 4
    waves per SIMD (FP32; FP64 takes 3), 11 and 12 = the tile of shape 7 with
    every full 16-k chunk of a term staged in LDS one chunk ahead by
-   direct-to-LDS loads (11 also stages the target tile; FP64; FP32 takes 2).  A launch takes the first entry of its class whose
+   direct-to-LDS loads (FP64: 11 also stages the target tile; FP32 launches
+   with FP32 factors take the pipelined FP32 kernel for both, those with
+   16-bit factors take 2).  A launch takes the first entry of its class whose
    rhs_max bounds its column count, whose group_max bounds the mean pivot
    size (unknowns per group) and whose precision (0, 1, 2 as in hps_params;
    the setup counts as 0) matches; shape 0 when none does.  NULL or "" restores

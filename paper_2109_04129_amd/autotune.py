@@ -44,8 +44,8 @@ SHAPE_DOC = {0: "32 x 32 tile, waves 2 x 2 of 16 x 16 (FP64 built for 4 waves pe
              9: "as 0, built for 5 waves per SIMD (FP64; FP32 takes 0)",
              10: "as 3, built for 4 waves per SIMD (FP32; FP64 takes 3)",
              11: "as 2, full 16-k chunks staged in LDS one chunk ahead by direct-to-LDS loads, target tile in LDS "
-                 "(FP64; FP32 takes 2)",
-             12: "as 11, target tile fetched after the products (FP64; FP32 takes 2)"}
+                 "(FP64; FP32 with FP32 factors: the pipelined FP32 kernel; 16-bit factors: 2)",
+             12: "as 11, target tile fetched after the products (FP32 as for 11)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning", "gfx950.json")
 

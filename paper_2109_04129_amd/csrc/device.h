@@ -56,8 +56,9 @@ struct GemmBatch {
 // 10: shape 3 built for 4 waves per SIMD (FP32; FP64 takes 3).  The FP64
 // shape 0 itself is built for 4.  Shapes 11 and 12: the tile of shape 7 with
 // every full 16-k chunk staged in LDS one chunk ahead by direct-to-LDS loads
-// (11: the target tile staged in LDS too, 12: fetched after the products;
-// FP64; FP32 takes 2).
+// (FP64: 11 stages the target tile in LDS too, 12 fetches it after the
+// products; FP32 launches with FP32 factors take the pipelined FP32 kernel
+// for both, those with 16-bit factors take 2).
 enum { TC_SWEEP = 0, TC_DINV, TC_FAR1, TC_FAR2, TC_NEAR, TC_SCHUR, TC_COUNT };
 constexpr int TUNE_SHAPES = 13;
 struct TuneEntry {
