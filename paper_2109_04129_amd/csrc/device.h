@@ -19,6 +19,16 @@ struct Tile {
   int32_t ldc, r0, c0, m, n, t_begin, t_end;
 };
 
+// c0 == TILE_PACKED marks a packed tile (the pipelined shapes 11 and 12 only,
+// in the setup's Schur updates): rows r0 .. r0 + 31 of targets that share
+// one row band (m rows, leading dimension ldc) and one term, whose A rows
+// (terms[t_begin]; its b_off and ldb unused) multiply n <= 4 column blocks of
+// up to 16 columns, one per wave.  Block w is terms[t_begin + 1 + w]: a_off =
+// element offset of its first C column, b_off = of its first B column, ldb =
+// B's leading dimension, lda = its valid columns (1..16), k = the term's k;
+// t_end = t_begin + 1 + n, c_off unused.
+constexpr int32_t TILE_PACKED = -2;
+
 // One term op(A) B: A at a_off (column-major, lda), B at b_off (column-major,
 // ldb), contraction length k; trans = 1 uses A^T (never the conjugate).
 // sidx >= 0: A is a 16-bit far factor whose values are multiplied by

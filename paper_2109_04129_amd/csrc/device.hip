@@ -502,8 +502,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (bx >= ntiles) return;
   }
   const Tile t = tiles[bx];
+  const bool packed = t.c0 == TILE_PACKED;
   int rb0 = t.r0, cb0 = t.c0, tn = t.n, nsub = 1, nsc = 1, st0 = 0, sstep = 1;
-  if (t.r0 < 0) {
+  if (packed) {
+    if (by > 0) return;
+  } else if (t.r0 < 0) {
     nsc = (t.n + TN - 1) / TN;
     nsub = ((t.m + TM - 1) / TM) * nsc;
     st0 = by;
@@ -518,13 +521,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
   c2 *const cw = cbuf + (CL ? wave * 512 : 0);
+  // A packed tile gives each wave a column block of its own (C and B start,
+  // B's leading dimension, valid columns): one term's A rows times blocks of
+  // several targets.  Otherwise the wave's columns start at col0 of t.c_off.
+  int64_t cbase = t.c_off, wb_off = 0;
+  int wldb = 0, q_end = t.t_end;
+  if (packed) {
+    tn = 0;
+    q_end = t.t_begin + 1;
+    if (wave < t.n) {
+      const Term wd = terms[t.t_begin + 1 + wave];
+      cbase = wd.a_off;
+      wb_off = wd.b_off;
+      wldb = wd.ldb;
+      tn = wd.lda;
+    }
+  }
   for (int st = st0; st < nsub; st += sstep) {
     int rb = rb0, cb = cb0;
     if (t.r0 < 0) {
       rb = (st / nsc) * TM;
       cb = (st % nsc) * TN;
     }
-    const int row0 = rb, col0 = cb + 16 * wave;
+    const int row0 = rb, col0 = packed ? 0 : cb + 16 * wave;
     if (row0 >= t.m) continue;                          // uniform over the workgroup
     const bool cols = col0 < tn;                        // uniform over the wave
     __syncthreads();                                    // the previous sub-tile's LDS reads are done
@@ -538,16 +557,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int e = 64 * q + lane, c = e >> 5, r = (e - 32 * c - 2 * c) & 31;
         const int ccol = col0 + c, crow = row0 + r;
         if (ccol < tn && crow < t.m)
-          __builtin_amdgcn_global_load_lds((const void *)(C + t.c_off + (int64_t)ccol * t.ldc + crow),
+          __builtin_amdgcn_global_load_lds((const void *)(C + cbase + (int64_t)ccol * t.ldc + crow),
                                            (lds_ptr)(cw + 64 * q), 16, 0, 0);
       }
     }
     d4 rr[RB], ii[RB], ss[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) rr[i] = ii[i] = ss[i] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int q = t.t_begin; q < t.t_end; ++q) {
+    for (int q = t.t_begin; q < q_end; ++q) {
       const Term tm = terms[q];
       const c2 *Ab = A + tm.a_off;
+      const c2 *Bw = B + (packed ? wb_off : tm.b_off);     // the wave's B columns start at column col0 of Bw
+      const int ldb = packed ? wldb : tm.ldb;
       const int nchunk = tm.k >> 4;
       // chunk ch of this term into buffer b: the wave's quarter of A and its own B
       auto stage = [&](int ch, int b) {
@@ -574,7 +595,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           for (int qb = 0; qb < 4; ++qb) {
             const int e = 64 * qb + lane, c = e >> 4, k = ((e & 15) - c) & 15;
             if (col0 + c < tn)
-              __builtin_amdgcn_global_load_lds((const void *)(B + tm.b_off + (int64_t)(col0 + c) * tm.ldb + k0 + k),
+              __builtin_amdgcn_global_load_lds((const void *)(Bw + (int64_t)(col0 + c) * ldb + k0 + k),
                                                (lds_ptr)(&bbuf[b][wave][64 * qb]), 16, 0, 0);
           }
         }
@@ -630,7 +651,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
             const int bcol = col0 + li;
             c2 bv = make_double2(0.0, 0.0);
-            if (kok && bcol < tn) bv = B[tm.b_off + (int64_t)bcol * tm.ldb + k];
+            if (kok && bcol < tn) bv = Bw[(int64_t)bcol * ldb + k];
 #pragma unroll
             for (int i = 0; i < RBE; ++i) {
               rr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv.x, rr[i], 0, 0, 0);
@@ -664,7 +685,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           for (int r = 0; r < 4; ++r) {
             const int crow = row0 + 16 * i + lg + 4 * r, ccol = col0 + li;
             cold[i][r] = make_double2(0.0, 0.0);
-            if (ccol < tn && crow < t.m) cold[i][r] = C[t.c_off + (int64_t)ccol * t.ldc + crow];
+            if (ccol < tn && crow < t.m) cold[i][r] = C[cbase + (int64_t)ccol * t.ldc + crow];
           }
       }
     }
@@ -677,7 +698,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int crow = row0 + 16 * i + lg + 4 * r;
         if (crow >= t.m) continue;
         const c2 acc = make_double2(rr[i][r] - ii[i][r], ss[i][r] - rr[i][r] - ii[i][r]);
-        c2 *p = C + t.c_off + (int64_t)ccol * t.ldc + crow;
+        c2 *p = C + cbase + (int64_t)ccol * t.ldc + crow;
         if (MODE == 0) {
           *p = acc;
         } else if (MODE == 1) {
@@ -2307,6 +2328,24 @@ void validate(const Tile *tiles, size_t ntiles, const std::vector<Term> &terms, 
               int64_t nc, const char *what) {
   for (size_t it = 0; it < ntiles; ++it) {
     const Tile &t0 = tiles[it];
+    if (t0.c0 == TILE_PACKED) {
+      if (t0.m <= 0 || t0.ldc < t0.m || t0.r0 < 0 || t0.r0 >= t0.m || t0.n < 1 || t0.n > 4 || t0.t_begin < 0 ||
+          t0.t_end != t0.t_begin + 1 + t0.n || t0.t_end > (int64_t)terms.size())
+        throw Error{HPS_EINVAL, std::string("internal: packed tile in ") + what};
+      const Term &a = terms[t0.t_begin];
+      const int64_t amax = a.trans ? a.a_off + (int64_t)(t0.m - 1) * a.lda + (a.k - 1)
+                                   : a.a_off + (int64_t)(a.k - 1) * a.lda + (t0.m - 1);
+      if (a.k <= 0 || a.a_off < 0 || amax >= na || (a.trans ? a.lda < a.k : a.lda < t0.m))
+        throw Error{HPS_EINVAL, std::string("internal descriptor out of range (packed A) in ") + what};
+      for (int w = 0; w < t0.n; ++w) {
+        const Term &d = terms[t0.t_begin + 1 + w];
+        if (d.lda < 1 || d.lda > 16 || d.k != a.k || d.ldb < a.k || d.a_off < 0 || d.b_off < 0 ||
+            d.a_off + (int64_t)(d.lda - 1) * t0.ldc + (t0.m - 1) >= nc ||
+            d.b_off + (int64_t)(d.lda - 1) * d.ldb + (a.k - 1) >= nb)
+          throw Error{HPS_EINVAL, std::string("internal descriptor out of range (packed block) in ") + what};
+      }
+      continue;
+    }
     Tile t = t0;
     if (t0.n < 0) {
       if (t0.ldc != nc) throw Error{HPS_EINVAL, std::string("internal: column stride of C in ") + what};
@@ -3309,6 +3348,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   // kernel does not apply, the width is the shape's)
   const int schur_shape = I.pick_shape(TC_SCHUR, 0) == 6 ? 0 : I.pick_shape(TC_SCHUR, 0);
   const int64_t schur_tn = shape_tn(schur_shape);
+  const bool schur_packed = schur_shape == 11 || schur_shape == 12;   // packed tiles: k_gemm_pipe only
   I.shape_of[TC_SCHUR] = schur_shape;
   if (I.setup_replayable(P, schur_shape)) {
     // same structure as the recorded setup: its launches on the current
@@ -3701,6 +3741,32 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     o.sterms.resize(start[tgt.size()]);
     std::vector<int32_t> fillp(start.begin(), start.end() - 1);
     for (size_t x = 0; x < pair_id.size(); ++x) o.sterms[fillp[pair_id[x]]++] = pair_term[x];
+    // Packed tiles (pipelined shapes): the 16-column blocks of the targets
+    // with a single term are grouped by that term's A (one pivot, one row
+    // band; targets of one group are consecutive here) and dealt four to a
+    // tile, one per wave, so a target whose width is not a multiple of 64
+    // leaves no wave of the launch idle.
+    struct PackRun {
+      int64_t a_off = -1, j = -1;
+      bool next = false;
+      Term at{};
+      std::vector<Term> blocks;
+    } run;
+    auto flush = [&]() {
+      if (run.blocks.empty()) return;
+      std::vector<Tile> &tl = run.next ? o.stiles : o.stiles2;
+      const int64_t mj = P.size[run.j];
+      for (size_t i = 0; i < run.blocks.size(); i += 4) {
+        const int32_t nw = (int32_t)std::min<size_t>(4, run.blocks.size() - i);
+        const int32_t tb = (int32_t)o.sterms.size();
+        o.sterms.push_back(run.at);
+        for (int32_t w = 0; w < nw; ++w) o.sterms.push_back(run.blocks[i + w]);
+        for (int64_t r0 = 0; r0 < mj; r0 += TM)
+          tl.push_back(Tile{run.blocks[i].a_off, (int32_t)mj, (int32_t)r0, TILE_PACKED, (int32_t)mj, nw, tb,
+                            tb + 1 + nw});
+      }
+      run.blocks.clear();
+    };
     for (size_t x = 0; x < tgt.size(); ++x) {
       const int64_t id = tgt[x], j = tjrow[x];
       int64_t coff, cols;
@@ -3719,19 +3785,34 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       const bool next = P.level[j] == l + 1;
       std::vector<Tile> &tl = next ? o.stiles : o.stiles2;
       GemmLaunch &gl = next ? o.schur : o.schur2;
-      // one explicit tile per (32 x shape-width) sub-tile of the target, so
-      // every workgroup of the launch has work (a whole-block tile would be
-      // given as many workgroups as the launch's largest target needs)
-      for (int64_t r0 = 0; r0 < P.size[j]; r0 += TM)
-        for (int64_t c0 = 0; c0 < cols; c0 += schur_tn)
-          tl.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j], (int32_t)cols,
-                            start[x], start[x + 1]});
+      if (schur_packed && start[x + 1] - start[x] == 1) {
+        const Term tm = o.sterms[start[x]];
+        if (tm.a_off != run.a_off || j != run.j) {
+          flush();
+          run.a_off = tm.a_off;
+          run.j = j;
+          run.next = next;
+          run.at = tm;
+        }
+        for (int64_t c0 = 0; c0 < cols; c0 += 16)
+          run.blocks.push_back(Term{coff + c0 * P.size[j], tm.b_off + c0 * tm.ldb,
+                                    (int32_t)std::min<int64_t>(16, cols - c0), tm.ldb, tm.k, 0});
+      } else {
+        // one explicit tile per (32 x shape-width) sub-tile of the target, so
+        // every workgroup of the launch has work (a whole-block tile would be
+        // given as many workgroups as the launch's largest target needs)
+        for (int64_t r0 = 0; r0 < P.size[j]; r0 += TM)
+          for (int64_t c0 = 0; c0 < cols; c0 += schur_tn)
+            tl.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j],
+                              (int32_t)cols, start[x], start[x + 1]});
+      }
       gl.flops += tflop[x];
       for (int32_t q = start[x]; q < start[x + 1]; ++q)
         gl.bytes += 16.0 * o.sterms[q].k * ((double)P.size[j] + (double)cols);
       gl.bytes += 32.0 * P.size[j] * cols;
       slot[id] = -1;
     }
+    flush();
     tgt.clear();
     tcount.clear();
     tjrow.clear();
