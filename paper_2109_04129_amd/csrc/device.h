@@ -136,8 +136,9 @@ class DeviceState {
   int terms = 2;
   double last_solve_flops = 0.0;
   // setup schedule: ms until every level was built, ms the launching thread
-  // waited for builds, ms it spent staging and enqueueing, tiles, terms
-  double sched_split[5] = {0, 0, 0, 0, 0};
+  // waited for builds, ms it spent staging and enqueueing, tiles, terms, and
+  // the Schur tiles' 16-column block slots x 16-k chunks, all and used
+  double sched_split[7] = {0, 0, 0, 0, 0, 0, 0};
 
   struct Impl;
   std::unique_ptr<Impl> impl;

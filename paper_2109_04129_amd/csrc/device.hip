@@ -3633,6 +3633,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     std::vector<Term> cterms, sterms;
     GemmLaunch coef, schur, schur2;
     double flops = 0.0;
+    double col_slots = 0.0, col_active = 0.0;    // Schur tiles: 16-column block slots x 16-k chunks, and the used ones
     std::string err;
   };
   std::vector<LevelOut> lv_out(L);
@@ -3764,6 +3765,9 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         for (int64_t r0 = 0; r0 < mj; r0 += TM)
           tl.push_back(Tile{run.blocks[i].a_off, (int32_t)mj, (int32_t)r0, TILE_PACKED, (int32_t)mj, nw, tb,
                             tb + 1 + nw});
+        const double ch = (double)((run.at.k + 15) / 16) * (double)cdiv(mj, TM);
+        o.col_slots += 4.0 * ch;
+        o.col_active += nw * ch;
       }
       run.blocks.clear();
     };
@@ -3805,6 +3809,11 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
           for (int64_t c0 = 0; c0 < cols; c0 += schur_tn)
             tl.push_back(Tile{coff, (int32_t)P.size[j], (int32_t)r0, (int32_t)c0, (int32_t)P.size[j],
                               (int32_t)cols, start[x], start[x + 1]});
+        double ch = 0.0;
+        for (int32_t q = start[x]; q < start[x + 1]; ++q) ch += (double)((o.sterms[q].k + 15) / 16);
+        ch *= (double)cdiv(P.size[j], TM);
+        o.col_slots += (double)(cdiv(cols, schur_tn) * (schur_tn / 16)) * ch;
+        o.col_active += (double)cdiv(cols, 16) * ch;
       }
       gl.flops += tflop[x];
       for (int32_t q = start[x]; q < start[x + 1]; ++q)
@@ -3926,6 +3935,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   if ((int)I.chunks.size() < n_chunks) I.chunks.resize(n_chunks);
   double flops = 0.0, wait_ms = 0.0, stage_ms = 0.0;
   int64_t n_tiles_all = 0, n_terms_all = 0;
+  double col_slots = 0.0, col_active = 0.0;
   const int ncls[3] = {32, 64, 128};
   const bool record = I.setup_graphs && !I.prof;
   if (record) I.srec.levels.resize(L);
@@ -3995,6 +4005,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       append_tiles(o.stiles, sb, schurl[l - lo], o.schur);
       append_tiles(o.stiles2, sb, schur2l[l - lo], o.schur2);
       flops += o.flops;
+      col_slots += o.col_slots;
+      col_active += o.col_active;
     }
     ch.upload(nt, nm, ni, s);
     n_tiles_all += nt;
@@ -4035,6 +4047,8 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
   sched_split[2] = stage_ms;
   sched_split[3] = (double)n_tiles_all;
   sched_split[4] = (double)n_terms_all;
+  sched_split[5] = col_slots;
+  sched_split[6] = col_active;
   times.inverse_ms = wait_ms + stage_ms;
   HIP_CHECK(hipEventRecord(e1, s));
 
@@ -4562,7 +4576,8 @@ std::string DeviceState::stats_json() const {
   o << ", \"terms\": " << I.terms << ", \"series_tol\": " << I.series_tol << ", \"terms_used\": " << I.terms_used;
   o << ", \"setup_replays\": " << I.srec.replays << ", \"setup_recorded\": " << (I.srec.valid ? "true" : "false");
   o << ", \"schedule_split\": {\"levels_built_ms\": " << sched_split[0] << ", \"wait_ms\": " << sched_split[1]
-    << ", \"stage_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4] << "}";
+    << ", \"stage_ms\": " << sched_split[2] << ", \"tiles\": " << sched_split[3] << ", \"terms\": " << sched_split[4]
+    << ", \"schur_col_slots\": " << sched_split[5] << ", \"schur_col_active\": " << sched_split[6] << "}";
   o << ", \"times_ms\": {\"setup_numeric\": " << times.schur_ms << ", \"setup_schedule\": " << times.inverse_ms
     << ", \"symbolic\": " << times.symbolic_ms
     << ", \"solve\": " << times.solve_ms << ", \"rhs\": " << times.rhs_ms << ", \"series\": " << times.sweep_ms

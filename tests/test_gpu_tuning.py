@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 CLASSES = ["sweep", "dinv", "far1", "far2", "near", "schur"]
 
 
-def _run(w, H, shape, precision, tmp_path, nrhs=37):
+def _run(w, H, shape, precision, tmp_path, nrhs=37, stats=None):
     path = tmp_path / ("shape%d.json" % shape)
     path.write_text(json.dumps({"entries": [{"class": c, "shape": shape} for c in CLASSES]}))
     ctx = hps.hps_create(0, torch.cuda.current_stream().cuda_stream)
@@ -47,7 +47,10 @@ def _run(w, H, shape, precision, tmp_path, nrhs=37):
         Y = torch.zeros_like(X)
         hps.hps_hmatvec(ctx, nrhs, X.data_ptr(), Y.data_ptr())
         torch.cuda.synchronize()
-        used = hps.hps_stats(ctx)["device"]["tuning"]["shapes"]
+        dev = hps.hps_stats(ctx)["device"]
+        if stats is not None:
+            stats.append(dev)
+        used = dev["tuning"]["shapes"]
         # the setup's Schur updates have no one-column launches: shape 6 means 0 there
         assert all(v == (0 if (c == "schur" and shape == 6) else shape) for c, v in used.items()), used
         return X.cpu().numpy(), Y.cpu().numpy(), rcs, ratio, khat, pol
@@ -71,6 +74,23 @@ def test_tile_shapes_bitwise(c0_workload, c0_hmatrix, precision, tmp_path):
         err = per_rhs_rel(X0.T, x_ref).max()
         print("shape 0 vs oracle: %.2e" % err, flush=True)
         assert err < 1e-10
+
+
+def test_packed_schur_tiles(c0_workload, c0_hmatrix, tmp_path):
+    """The pipelined shape deals the 16-column blocks of single-term Schur
+    targets four to a tile: the same blocks in fewer tile slots than the
+    unpacked 32 x 64 tile of shape 7, and bitwise the same results."""
+    w, H = c0_workload, c0_hmatrix
+    print("case: packed Schur tiles, shape 12 vs 7, sphere 1,920 unknowns", flush=True)
+    s7, s12 = [], []
+    X7, Y7, rcs7, _, _, _ = _run(w, H, 7, 0, tmp_path, stats=s7)
+    X12, Y12, rcs12, _, _, _ = _run(w, H, 12, 0, tmp_path, stats=s12)
+    a7, a12 = s7[0]["schedule_split"], s12[0]["schedule_split"]
+    print("column-block slots: shape 7 %d of %d used, shape 12 %d of %d used" % (
+        a7["schur_col_active"], a7["schur_col_slots"], a12["schur_col_active"], a12["schur_col_slots"]), flush=True)
+    assert a12["schur_col_active"] == a7["schur_col_active"] > 0
+    assert a12["schur_col_slots"] < a7["schur_col_slots"]
+    assert np.array_equal(X12, X7) and np.array_equal(Y12, Y7) and np.array_equal(rcs12, rcs7)
 
 
 def test_one_column_vector_kernel(c0_workload, c0_hmatrix, tmp_path):
