@@ -3744,16 +3744,19 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
     for (size_t x = 0; x < pair_id.size(); ++x) o.sterms[fillp[pair_id[x]]++] = pair_term[x];
     // Packed tiles (pipelined shapes): the 16-column blocks of the targets
     // with a single term are grouped by that term's A (one pivot, one row
-    // band; targets of one group are consecutive here) and dealt four to a
-    // tile, one per wave, so a target whose width is not a multiple of 64
-    // leaves no wave of the launch idle.
+    // band: the targets of one row band are consecutive here, and a
+    // non-symmetric field interleaves two such groups, upper and lower
+    // blocks) and dealt four to a tile, one per wave, so a target whose width
+    // is not a multiple of 64 leaves no wave of the launch idle.
     struct PackRun {
       int64_t a_off = -1, j = -1;
       bool next = false;
       Term at{};
       std::vector<Term> blocks;
-    } run;
-    auto flush = [&]() {
+    };
+    std::vector<PackRun> runs;          // the open groups of the current row band
+    int64_t runs_j = -1;
+    auto flush = [&](PackRun &run) {
       if (run.blocks.empty()) return;
       std::vector<Tile> &tl = run.next ? o.stiles : o.stiles2;
       const int64_t mj = P.size[run.j];
@@ -3770,6 +3773,10 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
         o.col_active += nw * ch;
       }
       run.blocks.clear();
+    };
+    auto flush_all = [&]() {
+      for (PackRun &r : runs) flush(r);
+      runs.clear();
     };
     for (size_t x = 0; x < tgt.size(); ++x) {
       const int64_t id = tgt[x], j = tjrow[x];
@@ -3791,13 +3798,20 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       GemmLaunch &gl = next ? o.schur : o.schur2;
       if (schur_packed && start[x + 1] - start[x] == 1) {
         const Term tm = o.sterms[start[x]];
-        if (tm.a_off != run.a_off || j != run.j) {
-          flush();
-          run.a_off = tm.a_off;
-          run.j = j;
-          run.next = next;
-          run.at = tm;
+        if (j != runs_j) {
+          flush_all();
+          runs_j = j;
         }
+        size_t r = 0;
+        while (r < runs.size() && runs[r].a_off != tm.a_off) ++r;
+        if (r == runs.size()) {
+          runs.emplace_back();
+          runs[r].a_off = tm.a_off;
+          runs[r].j = j;
+          runs[r].next = next;
+          runs[r].at = tm;
+        }
+        PackRun &run = runs[r];
         for (int64_t c0 = 0; c0 < cols; c0 += 16)
           run.blocks.push_back(Term{coff + c0 * P.size[j], tm.b_off + c0 * tm.ldb,
                                     (int32_t)std::min<int64_t>(16, cols - c0), tm.ldb, tm.k, 0});
@@ -3821,7 +3835,7 @@ void DeviceState::setup(const Plan &P, const HMatrix &H) {
       gl.bytes += 32.0 * P.size[j] * cols;
       slot[id] = -1;
     }
-    flush();
+    flush_all();
     tgt.clear();
     tcount.clear();
     tjrow.clear();

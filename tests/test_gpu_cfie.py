@@ -292,3 +292,41 @@ def test_cfie_arbitrary_rhs_and_graph_replay(oracle_cfie):
     err = per_rhs_rel(outs[1][0], x).max()
     print("current err %.2e" % err, flush=True)
     assert err < 1e-10
+
+
+def test_cfie_tile_shapes_bitwise(oracle_cfie, tmp_path):
+    """The non-symmetric setup on the pipelined shapes (packed Schur tiles of
+    upper and lower blocks) and on the plain-register 32 x 64 tile gives
+    bitwise the currents of the 32 x 32 tile; packing uses fewer 16-column
+    block slots for the same blocks."""
+    import json
+    xyz, tri, H = oracle_cfie
+    khat, pol = _angles()
+    print("case: CFIE ellipsoid 480 unknowns, tile shapes 0, 7, 11, 12", flush=True)
+    a = hmatrix_arrays(H)
+    out, split = {}, {}
+    for shape in (0, 7, 11, 12):
+        path = tmp_path / ("shape%d.json" % shape)
+        path.write_text(json.dumps({"entries": [{"class": c, "shape": shape}
+                                                for c in ("sweep", "dinv", "far1", "far2", "near", "schur")]}))
+        ctx = _ctx()
+        try:
+            hps.hps_set_tuning(ctx, str(path))
+            hps.hps_set_mesh(ctx, xyz, tri)
+            hps.hps_set_hmatrix(ctx, _params(), a["N"], a["perm"], a["group_ptr"], a["near_ts"], a["near_off"],
+                                a["near_vals"], a["far_rng"], a["far_rank"], a["far_off"], a["far_uv"])
+            hps.hps_setup(ctx)
+            out[shape] = _solve(ctx, H.N, khat, pol)
+            dev = hps.hps_stats(ctx)["device"]
+            assert dev["tuning"]["shapes"]["schur"] == shape
+            split[shape] = dev["schedule_split"]
+        finally:
+            hps.hps_destroy(ctx)
+    for shape in (7, 11, 12):
+        assert np.array_equal(out[shape][1], out[0][1]), "shape %d" % shape
+        assert np.array_equal(out[shape][2], out[0][2]), "shape %d" % shape
+    s7, s12 = split[7], split[12]
+    print("column-block slots: shape 7 %d of %d used, shape 12 %d of %d used" % (
+        s7["schur_col_active"], s7["schur_col_slots"], s12["schur_col_active"], s12["schur_col_slots"]), flush=True)
+    assert s12["schur_col_active"] == s7["schur_col_active"] > 0
+    assert s12["schur_col_slots"] < s7["schur_col_slots"]
