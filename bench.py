@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--leaf-study", action="store_true",
                     help="run only the leaf-size study (Sec. V.A): two-term and converged-series error against "
                          "the direct solution vs leaf size, EFIE and CFIE; prints its own JSON line")
+    ap.add_argument("--scaling-study", action="store_true",
+                    help="run only the scaling study (Sec. IV, Figs. 3 and 5): setup time, factor memory and "
+                         "solve time vs unknowns on spheres of constant mesh density; prints its own JSON line")
     return ap.parse_args()
 
 
@@ -706,6 +709,71 @@ def leaf_study(args):
             "rows": rows}
 
 
+def scaling_study(args):
+    """Sec. IV (eqs. 46-56) and Figs. 3 and 5: setup time and the memory of the
+    scaling coefficients and scaled near-field blocks grow as O(N), the
+    solution as O(N log N).  Spheres of constant mesh density (icosphere
+    subdivision s, radius 2^(s-5) m, 790 MHz: the 30,720-unknown sphere's
+    edge length at every size), leaf <= 128, ACA 1e-3, plain FP64, two terms.
+    Per size: the setup (mean of two after a warm-up), the factor panels'
+    bytes, a 32-RHS solve per RHS and a one-RHS solve (means of two after a
+    warm-up, device work synchronised); the log-log slopes over the sizes."""
+    import torch
+    from paper_2109_04129_amd import hps
+    from workloads import icosphere, monostatic_angles
+    freq = 790e6
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for sub in (3, 4, 5, 6):
+        xyz, tri = icosphere(sub, 2.0 ** (sub - 5))
+        ctx = tuned(hps.hps_create(0, stream))
+        try:
+            hps.hps_set_mesh(ctx, xyz, tri)
+            p = hps.hps_params_default(freq_hz=freq, leaf_max=128, aca_tol=1e-3, terms=2)
+            t0 = time.perf_counter()
+            hps.hps_build_hmatrix(ctx, p)
+            t_build = time.perf_counter() - t0
+            N = hps.hps_num_unknowns(ctx)
+
+            def timed(fn, reps=2):
+                fn()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t) / reps
+
+            t_setup = timed(lambda: hps.hps_setup(ctx))
+            res = {}
+            for R in (32, 1):
+                th = np.linspace(0.0, 180.0, R) if R > 1 else np.array([90.0])
+                khat, pol = monostatic_angles(th, np.zeros_like(th))
+                X = torch.zeros((R, N), dtype=torch.complex128, device="cuda")
+                res[R] = timed(lambda: hps.hps_solve_planewaves(ctx, khat, pol, X.data_ptr()))
+            d = hps.hps_stats(ctx)
+            dev = d.get("device", {})
+            rows.append({"subdivision": sub, "radius_m": 2.0 ** (sub - 5), "N": int(N),
+                         "groups": (d.get("hmatrix") or {}).get("groups"),
+                         "hmatrix_build_s": t_build, "setup_s": t_setup,
+                         "factor_gb": dev.get("factor_bytes", 0) / 1e9,
+                         "solve_ms_per_rhs_32": 1e3 * res[32] / 32, "solve_ms_1rhs": 1e3 * res[1]})
+            log("scaling study: N = %d done (setup %.3f s)" % (N, t_setup))
+        finally:
+            hps.hps_destroy(ctx)
+    lg = np.log([r["N"] for r in rows])
+
+    def slope(key):
+        return float(np.polyfit(lg, np.log([r[key] for r in rows]), 1)[0])
+
+    return {"study": "scaling (Sec. IV, Figs. 3 and 5)",
+            "workload": "spheres of constant mesh density: icosphere subdivision 3-6, radius 2^(s-5) m, 790 MHz, "
+                        "leaf <= 128, ACA 1e-3, plain FP64, two terms",
+            "rows": rows,
+            "loglog_slope_vs_N": {k: slope(k) for k in ("setup_s", "factor_gb", "solve_ms_per_rhs_32",
+                                                       "solve_ms_1rhs")}}
+
+
 TUNING_PATH = None
 
 
@@ -727,6 +795,9 @@ def main():
         sys.exit(2)
     if args.leaf_study:
         print(json.dumps(leaf_study(args)), flush=True)
+        return
+    if args.scaling_study:
+        print(json.dumps(scaling_study(args)), flush=True)
         return
     if args.only_batch:
         print(json.dumps(batch_leg(args)), flush=True)
