@@ -349,7 +349,10 @@ hps_status hps_set_tuning(hps_ctx *ctx, const char *path);
 hps_status hps_profile(hps_ctx *ctx, int enable);
 
 /* JSON statistics (sizes, ranks, fill, bytes, per-stage device times of the
-   last setup / solve in ms) into buf (NUL-terminated, truncated to len). */
+   last setup / solve in ms, the tile shapes in use, and the last setup's
+   schedule: "schedule_split" with its build times, tile and term counts and
+   the Schur tiles' 16-column block slots x 16-k chunks, all and used) into
+   buf (NUL-terminated, truncated to len). */
 hps_status hps_stats(const hps_ctx *ctx, char *buf, size_t len);
 
 /* ------------------------------------------------------------------ batches
