@@ -211,16 +211,23 @@ def test_near_singular_block_reported(small):
         hps.hps_destroy(ctx)
 
 
-@pytest.mark.parametrize("precision,refine,bar", [(2, 0, 1e-3), (2, 1, 1e-3), (1, 0, 5e-3), (1, 1, 1e-3)])
+BF16_TWO_TERM = pytest.mark.xfail(
+    strict=True, reason="BF16 far factors without the residual pass: measured 2.7e-3 against 1e-3 (the two-term "
+                        "series carries the 2^-9 unit roundoff of BF16 unreduced); one FP32 residual pass meets 1e-3")
+
+
+@pytest.mark.parametrize("precision,refine,bar", [(2, 0, 1e-3), (2, 1, 1e-3),
+                                                  pytest.param(1, 0, 1e-3, marks=BF16_TWO_TERM), (1, 1, 1e-3)])
 def test_precision_form(c0_workload, c0_hmatrix, precision, refine, bar):
     """Precision form (FP32 solve on MFMA, 16-bit far factors with per-block
     FP32 scale, optional FP32 residual pass) against the FP64 oracle at the
     matching number of terms: one residual pass with the two-term operator P
     gives x + P(b - Hx) = (I - K + K^2 - K^3) Z_N^-1 b, the four-term series.
-    With one pass (FP32 far factors in the residual and its correction) both
-    16-bit formats are held to the 1e-3 / 0.1 dB target.  The two-term series
-    alone carries the far-factor rounding unreduced: FP16 (unit roundoff
-    2^-12) meets 1e-3, BF16 (2^-9) is held to 5e-3."""
+    Every case is held to the 1e-3 / 0.1 dB target.  With one pass (FP32 far
+    factors in the residual and its correction) both 16-bit formats meet it.
+    The two-term series alone carries the far-factor rounding unreduced: FP16
+    (unit roundoff 2^-12) meets it, BF16 (2^-9) does not (an expected
+    failure, with the measured error)."""
     w, H = c0_workload, c0_hmatrix
     print("case: sphere 1,920, precision %d, refine %d" % (precision, refine), flush=True)
     khat, pol = monostatic_angles(np.linspace(0.0, 180.0, 7), np.zeros(7))
